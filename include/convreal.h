@@ -1,0 +1,139 @@
+/*
+ * convreal.h - C ABI of libconvreal, the real-space half of a split spherical
+ * convolution on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Sutter, Wandelt & Elsner, "Using hybrid GPU/CPU kernel
+ * splitting to accelerate spherical convolutions", Estimating Errors
+ * section, Eq. 1): a radially symmetric kernel is split into a band-limited
+ * harmonic part (l <= l_cut, applied elsewhere by spherical-harmonic
+ * transforms) and a compact real-space part truncated at theta_cut. This
+ * library applies the real-space part to maps on the equal-area iso-latitude
+ * ring grid the paper assumes (HEALPix, ring order, Results section):
+ *
+ *     y_p = Omega * sum_{q : d_pq <= d_cut} Ktilde(d_pq) * x_q
+ *
+ *   Omega  = 4 pi / Npix, Npix = 12 nside^2 (pixel area; equal for all pixels)
+ *   d_pq   = |v_p - v_q|, chord between pixel-centre unit vectors
+ *   d_cut  = 2 sin(theta_cut / 2); pairs with d_pq == d_cut are included
+ *   Ktilde = K interpolated from a table on a uniform chord grid (the paper's
+ *            real-space convolver interpolates its kernel from tabulated
+ *            nodes; discussion of Fig. 4).
+ *
+ * Pixel layout: ring order as in the HEALPix library. Ring i = 1..4N-1 from
+ * the north pole; caps (i < N or i > 3N) hold 4k pixels (k = distance in
+ * rings from the nearer pole) at phi = (pi/2k)(a + 1/2); belt rings hold 4N
+ * pixels at phi = (pi/2N)(a + s/2), s = (i - N + 1) mod 2.
+ *
+ * Kernel table convention: n_tab values T[k] = K(d_k), d_k = k * h,
+ * h = d_cut / (n_tab - 3), k = 0..n_tab-1 (the last two nodes lie beyond
+ * d_cut). Ktilde(d) is the 4-point Lagrange interpolant on nodes
+ * k-1..k+2 of segment k = floor(d/h) (k clamped to n_tab-3), with ghost
+ * node T[-1] = T[1] (K is even in d). K is in continuous normalisation;
+ * the library multiplies by Omega.
+ *
+ * Error behaviour: every entry point returns CONV_REAL_OK (0) or a
+ * negative code. Arguments are validated on the host before any device call;
+ * an invalid argument leaves all outputs untouched. conv_real_last_error()
+ * returns a message for the calling thread's most recent failure.
+ */
+#ifndef CONVREAL_H
+#define CONVREAL_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct conv_real_plan conv_real_plan;
+
+/* Precision modes. */
+#define CONV_REAL_F64   0  /* maps FP64 in/out; every pixel pair evaluated and accumulated in FP64 */
+#define CONV_REAL_F32   1  /* maps FP32 in/out; every pixel pair evaluated and accumulated in FP64 */
+#define CONV_REAL_MIXED 2  /* maps FP32 in/out; ring-pair weight blocks in split hi/lo FP16 on the
+                              matrix cores, FP32 products summed per ring pair, FP64 across ring pairs */
+
+/* Error codes. */
+#define CONV_REAL_OK           0
+#define CONV_REAL_EINVAL      -1  /* bad argument value (nside, n_tab, theta_cut, precision, nmaps, NULL) */
+#define CONV_REAL_ENOMEM      -2  /* device or host allocation failed */
+#define CONV_REAL_EHIP        -3  /* a HIP runtime call failed; see conv_real_last_error() */
+#define CONV_REAL_EALIAS      -4  /* maps_in and maps_out overlap */
+#define CONV_REAL_ENODEV      -5  /* no usable gfx950 device */
+
+/* Limits. */
+#define CONV_REAL_MAX_NSIDE  8192
+#define CONV_REAL_MAX_NTAB   8192
+#define CONV_REAL_MAX_LMAX   32768
+
+/*
+ * conv_real_tabulate - sample a radial kernel given by its harmonic
+ * coefficients on the chord grid used by conv_real_init.
+ *
+ *   K(theta) = sum_{l=0}^{lmax} (2l+1)/(4 pi) * k_ell[l] * P_l(cos theta)
+ *
+ * (the Legendre transformation operator that links l-space and real-space
+ * kernels, Eq. 1), summed in FP64 on the device with the three-term Legendre
+ * recurrence written in u = 1 - cos(theta) = d^2/2, so that no cancellation
+ * occurs near theta = 0.
+ *
+ *   k_ell      host pointer, lmax+1 doubles (read only, caller-owned)
+ *   lmax       0 <= lmax <= CONV_REAL_MAX_LMAX
+ *   theta_cut  truncation radius in radians, 0 < theta_cut <= pi
+ *   n_tab      4 <= n_tab <= CONV_REAL_MAX_NTAB
+ *   table      host pointer, n_tab doubles written (caller-owned)
+ *
+ * Synchronous: returns after the table has been copied back.
+ */
+int conv_real_tabulate(const double* k_ell, int lmax, double theta_cut, int n_tab, double* table);
+
+/*
+ * conv_real_init - build a plan for one (nside, kernel table, theta_cut, precision).
+ *
+ *   plan       out: opaque handle, owned by the caller until conv_real_destroy
+ *   nside      1 <= nside <= CONV_REAL_MAX_NSIDE
+ *   table      host pointer, n_tab doubles in the convention above (copied)
+ *   n_tab      4 <= n_tab <= CONV_REAL_MAX_NTAB
+ *   theta_cut  0 < theta_cut <= pi
+ *   precision  CONV_REAL_F64, CONV_REAL_F32 or CONV_REAL_MIXED
+ *
+ * Binds the plan to the current HIP device. Computes the ring-pair windows
+ * (ring_window pass), the exact pair count and the device tables; for
+ * CONV_REAL_MIXED also the split-FP16 weight blocks. Synchronous.
+ */
+int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_tab,
+                   double theta_cut, int precision);
+
+/*
+ * conv_real_apply - y = A x for nmaps maps.
+ *
+ *   maps_in    device pointer, [nmaps][12 nside^2] contiguous, FP64 for
+ *              CONV_REAL_F64, FP32 otherwise (read only)
+ *   maps_out   device pointer, same shape and type (written); must not
+ *              overlap maps_in (CONV_REAL_EALIAS)
+ *   nmaps      >= 1
+ *   stream     hipStream_t to launch on (NULL = default stream)
+ *
+ * Asynchronous on stream; no host synchronisation, no allocation.
+ */
+int conv_real_apply(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps,
+                    void* stream);
+
+/*
+ * conv_real_pairs - exact number of ordered pixel pairs (p, q) with
+ * d_pq <= d_cut over the whole map (counted on the device at init).
+ */
+int conv_real_pairs(const conv_real_plan* plan, long long* pairs);
+
+/* conv_real_destroy - free a plan and its device memory. NULL is accepted. */
+int conv_real_destroy(conv_real_plan* plan);
+
+/* conv_real_strerror - static description of an error code. */
+const char* conv_real_strerror(int code);
+
+/* conv_real_last_error - message for this thread's most recent failure ("" if none). */
+const char* conv_real_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CONVREAL_H */

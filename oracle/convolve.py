@@ -3,7 +3,8 @@
     y_p = Omega * sum_{q : d_pq <= d_cut} Ktilde(d_pq) * x_q
 
 (the real-space half of the split kernel of Eq. 1, applied to a pixelized map;
-Omega = 4 pi / Npix). Pairs with d exactly equal to d_cut are included.
+Omega = 4 pi / Npix). Pairs with d exactly equal to d_cut are included; a cut of
+theta_cut = pi keeps every pair (no chord exceeds 2, so ties at d = 2 are inside).
 The chord is |v_p - v_q| from the pixel-centre unit vectors, component by
 component (no 1 - v.v form).
 
@@ -18,6 +19,11 @@ from __future__ import annotations
 import numpy as np
 
 from . import geometry, kernel
+
+
+def _pair_limit(theta_cut: float) -> float:
+    """Largest chord kept: d_cut, or no limit for a cut of pi."""
+    return np.inf if theta_cut >= np.pi else kernel.chord_cut(theta_cut)
 
 
 def _as_maps(x):
@@ -35,7 +41,7 @@ def convolve_bruteforce(nside: int, table: np.ndarray, theta_cut: float, x,
     npix = v.shape[0]
     assert xm.shape[1] == npix
     omega = geometry.pixel_area(nside)
-    dcut = kernel.chord_cut(theta_cut)
+    dcut = _pair_limit(theta_cut)
     h = kernel.node_spacing(theta_cut, len(table))
     if chunk <= 0:
         chunk = max(1, int(2.0e6 // npix))
@@ -69,7 +75,7 @@ def convolve_sampled(nside: int, table: np.ndarray, theta_cut: float, x,
     rt = geometry.ring_table(nside)
     z, st, phi, _ = geometry.pixel_angles(nside)
     omega = geometry.pixel_area(nside)
-    dcut = kernel.chord_cut(theta_cut)
+    dcut = _pair_limit(theta_cut)
     h = kernel.node_spacing(theta_cut, len(table))
     out = np.zeros((xm.shape[0], len(pix)))
     cache = {}
@@ -94,7 +100,8 @@ def pair_counts_sampled(nside: int, theta_cut: float, pix: np.ndarray):
     pix = np.asarray(pix, dtype=np.int64)
     rt = geometry.ring_table(nside)
     z, st, phi, _ = geometry.pixel_angles(nside)
-    dcut = kernel.chord_cut(theta_cut)
+    dcut = _pair_limit(theta_cut)
+    dref = kernel.chord_cut(theta_cut)
     counts = np.zeros(len(pix), dtype=np.int64)
     margin = np.inf
     for idx, p in enumerate(pix):
@@ -104,7 +111,8 @@ def pair_counts_sampled(nside: int, theta_cut: float, pix: np.ndarray):
         vz = z[lo:hi] - z[p]
         d = np.sqrt(vx * vx + vy * vy + vz * vz)
         counts[idx] = int(np.count_nonzero(d <= dcut))
-        margin = min(margin, float(np.min(np.abs(d - dcut))) / dcut)
+        if np.isfinite(dcut):
+            margin = min(margin, float(np.min(np.abs(d - dcut))) / dref)
     return counts, margin
 
 

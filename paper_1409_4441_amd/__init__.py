@@ -1,0 +1,162 @@
+"""paper_1409_4441_amd - real-space half of a split spherical convolution on MI355X.
+
+Thin ctypes binding of libconvreal.so (declared in include/convreal.h): argument
+marshalling only. Every step of the convolution runs in the library's HIP
+kernels; PyTorch supplies device memory and streams. There is no CPU fallback:
+if the library is missing, importing this package raises.
+
+    import paper_1409_4441_amd as cr
+    table = cr.tabulate(k_ell, theta_cut, n_tab)           # K on chord nodes (device FP64)
+    plan = cr.Plan(nside, table, theta_cut, "f32")          # ring windows, pair count, tables
+    y = plan.apply(x)                                       # x: cuda tensor [nmaps, 12 nside^2]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libconvreal.so")
+
+F64 = 0
+F32 = 1
+MIXED = 2
+_PRECISIONS = {"f64": F64, "f32": F32, "mixed": MIXED}
+
+OK = 0
+EINVAL = -1
+ENOMEM = -2
+EHIP = -3
+EALIAS = -4
+ENODEV = -5
+
+# Every entry point that include/convreal.h declares.
+EXPORTS = ("conv_real_tabulate", "conv_real_init", "conv_real_apply", "conv_real_pairs",
+           "conv_real_destroy", "conv_real_strerror", "conv_real_last_error")
+
+
+class ConvRealError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        text = msg if msg.startswith(where) else f"{where}: {msg}"
+        super().__init__(f"{text} (code {code})")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1409_4441_amd.build` "
+                          "(the convolution has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_double, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+    dptr = ctypes.POINTER(ctypes.c_double)
+    lib.conv_real_tabulate.argtypes = [dptr, c_int, c_double, c_int, dptr]
+    lib.conv_real_tabulate.restype = c_int
+    lib.conv_real_init.argtypes = [ctypes.POINTER(c_void_p), c_int, dptr, c_int, c_double, c_int]
+    lib.conv_real_init.restype = c_int
+    lib.conv_real_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p]
+    lib.conv_real_apply.restype = c_int
+    lib.conv_real_pairs.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_longlong)]
+    lib.conv_real_pairs.restype = c_int
+    lib.conv_real_destroy.argtypes = [c_void_p]
+    lib.conv_real_destroy.restype = c_int
+    lib.conv_real_strerror.argtypes = [c_int]
+    lib.conv_real_strerror.restype = ctypes.c_char_p
+    lib.conv_real_last_error.argtypes = []
+    lib.conv_real_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        msg = lib.conv_real_last_error().decode() or lib.conv_real_strerror(code).decode()
+        raise ConvRealError(code, where, msg)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def tabulate(k_ell, theta_cut: float, n_tab: int) -> np.ndarray:
+    """K(d_k) = sum_l (2l+1)/(4 pi) k_l P_l(cos theta_k) on the plan's chord nodes (device FP64)."""
+    k = np.ascontiguousarray(k_ell, dtype=np.float64)
+    out = np.empty(int(n_tab), dtype=np.float64)
+    _check(lib.conv_real_tabulate(_dptr(k), len(k) - 1, float(theta_cut), int(n_tab), _dptr(out)),
+           "conv_real_tabulate")
+    return out
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+class Plan:
+    """One (nside, kernel table, theta_cut, precision) on the current device."""
+
+    def __init__(self, nside: int, table, theta_cut: float, precision: str = "f64"):
+        if precision not in _PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
+        t = np.ascontiguousarray(table, dtype=np.float64)
+        handle = ctypes.c_void_p()
+        _check(lib.conv_real_init(ctypes.byref(handle), int(nside), _dptr(t), len(t),
+                                  float(theta_cut), _PRECISIONS[precision]), "conv_real_init")
+        self._h = handle
+        self.nside = int(nside)
+        self.npix = 12 * self.nside * self.nside
+        self.theta_cut = float(theta_cut)
+        self.precision = precision
+        self.n_tab = len(t)
+
+    @property
+    def dtype(self):
+        import torch
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def pairs(self) -> int:
+        n = ctypes.c_longlong()
+        _check(lib.conv_real_pairs(self._h, ctypes.byref(n)), "conv_real_pairs")
+        return int(n.value)
+
+    def apply(self, x, out=None, stream=None):
+        """y = A x. x: CUDA tensor [npix] or [nmaps, npix], contiguous, plan dtype."""
+        import torch
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError("x must be a CUDA tensor")
+        if x.dtype != self.dtype:
+            raise TypeError(f"x must be {self.dtype}")
+        if x.shape[-1] != self.npix or x.dim() not in (1, 2):
+            raise ValueError(f"x must have shape [nmaps, {self.npix}]")
+        if not x.is_contiguous():
+            raise ValueError("x must be contiguous")
+        if out is None:
+            out = torch.empty_like(x)
+        elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError("out must match x")
+        nmaps = 1 if x.dim() == 1 else x.shape[0]
+        _check(lib.conv_real_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   int(nmaps), _stream_handle(stream)), "conv_real_apply")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.conv_real_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,351 @@
+// C entry points of libconvreal: validation, plan construction, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace convreal {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+// HEALPix ring scheme with integer numerators (Gorski et al. 2005; library ordering):
+//   caps, ring k from the nearer pole: 4k pixels, |z| = 1 - k^2/(3N^2), phi = (pi/2k)(a + 1/2)
+//   belt, ring i = N..3N: 4N pixels, z = (2N - i) 2/(3N), phi = (pi/2N)(a + s/2), s = (i-N+1) mod 2
+RingGrid make_ring_grid(int nside) {
+  RingGrid g;
+  const long long N = nside;
+  const long long q = 3 * N * N;
+  g.nside = nside;
+  g.nrings = static_cast<int>(4 * N - 1);
+  g.Z.resize(g.nrings);
+  g.z.resize(g.nrings);
+  g.s.resize(g.nrings);
+  g.n.resize(g.nrings);
+  g.c.resize(g.nrings);
+  g.start.resize(g.nrings);
+  long long pos = 0;
+  for (long long i = 1; i <= 4 * N - 1; ++i) {
+    long long Z;
+    int n, c;
+    if (i < N) {
+      Z = q - i * i;
+      n = static_cast<int>(4 * i);
+      c = 1;
+    } else if (i <= 3 * N) {
+      Z = 2 * N * (2 * N - i);
+      n = static_cast<int>(4 * N);
+      c = static_cast<int>((i - N + 1) & 1);
+    } else {
+      const long long k = 4 * N - i;
+      Z = -(q - k * k);
+      n = static_cast<int>(4 * k);
+      c = 1;
+    }
+    const int r = static_cast<int>(i - 1);
+    g.Z[r] = Z;
+    g.z[r] = static_cast<double>(Z) / static_cast<double>(q);
+    // (q - Z)(q + Z) is exact in 64-bit integers for nside <= 8192.
+    const long long S = (q - Z) * (q + Z);
+    g.s[r] = std::sqrt(static_cast<double>(S)) / static_cast<double>(q);
+    g.n[r] = n;
+    g.c[r] = c;
+    g.start[r] = pos;
+    pos += n;
+  }
+  g.npix = pos;
+  return g;
+}
+
+// Squared chord between rings r and t at equal azimuth: (z_r - z_t)^2 + (s_r - s_t)^2,
+// with both differences formed from exact integer numerators.
+static double ring_gap2(const RingGrid& g, int r, int t) {
+  const double q = 3.0 * g.nside * static_cast<double>(g.nside);
+  const long long dZ = g.Z[r] - g.Z[t];
+  const long long sZ = g.Z[r] + g.Z[t];
+  const double dz = static_cast<double>(dZ) / q;
+  // s_r - s_t = (s_r^2 - s_t^2) / (s_r + s_t) = -(Z_r - Z_t)(Z_r + Z_t) / (q^2 (s_r + s_t))
+  const double ds = -(static_cast<double>(dZ) * static_cast<double>(sZ)) / (q * q * (g.s[r] + g.s[t]));
+  return dz * dz + ds * ds;
+}
+
+void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std::vector<int>& jhi) {
+  // Slack so that rounding never drops a ring; the per-pair chord test is exact.
+  const double lim = dcut2 * (1.0 + 1e-9) + 1e-300;
+  jlo.assign(g.nrings, 0);
+  jhi.assign(g.nrings, 0);
+  for (int r = 0; r < g.nrings; ++r) {
+    int lo = r, hi = r;
+    while (lo - 1 >= 0 && ring_gap2(g, r, lo - 1) <= lim) --lo;
+    while (hi + 1 < g.nrings && ring_gap2(g, r, hi + 1) <= lim) ++hi;
+    jlo[r] = lo;
+    jhi[r] = hi;
+  }
+}
+
+}  // namespace convreal
+
+using convreal::set_error;
+
+namespace {
+
+constexpr int kMagic = 0x43565231;  // "CVR1"
+constexpr int kTile = 256;          // output pixels per workgroup of the plain kernel
+
+bool finite_all(const double* v, long long n) {
+  for (long long i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  return e == hipErrorOutOfMemory ? CONV_REAL_ENOMEM : CONV_REAL_EHIP;
+}
+
+template <typename T>
+hipError_t dev_alloc(conv_real_plan* p, T** out, size_t count) {
+  *out = nullptr;
+  if (count == 0) count = 1;
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+  if (e != hipSuccess) return e;
+  p->owned.push_back(ptr);
+  *out = static_cast<T*>(ptr);
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t dev_upload(conv_real_plan* p, T** out, const std::vector<T>& host) {
+  hipError_t e = dev_alloc(p, out, host.size());
+  if (e != hipSuccess) return e;
+  if (host.empty()) return hipSuccess;
+  return hipMemcpy(*out, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_plan(conv_real_plan* p) {
+  for (void* ptr : p->owned) (void)hipFree(ptr);
+  p->owned.clear();
+  p->magic = 0;
+  delete p;
+}
+
+int check_device(int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    set_error(std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+    return CONV_REAL_ENODEV;
+  }
+  *dev_out = dev;
+  return CONV_REAL_OK;
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  hipError_t enter(int dev) {
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != dev) {
+      e = hipSetDevice(dev);
+      if (e != hipSuccess) return e;
+      changed = true;
+    }
+    return hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* conv_real_strerror(int code) {
+  switch (code) {
+    case CONV_REAL_OK: return "success";
+    case CONV_REAL_EINVAL: return "invalid argument";
+    case CONV_REAL_ENOMEM: return "out of memory";
+    case CONV_REAL_EHIP: return "HIP runtime error";
+    case CONV_REAL_EALIAS: return "input and output maps overlap";
+    case CONV_REAL_ENODEV: return "no usable gfx950 device";
+    default: return "unknown error";
+  }
+}
+
+const char* conv_real_last_error(void) { return convreal::g_last_error.c_str(); }
+
+int conv_real_tabulate(const double* k_ell, int lmax, double theta_cut, int n_tab, double* table) {
+  if (!k_ell || !table) { set_error("conv_real_tabulate: NULL pointer"); return CONV_REAL_EINVAL; }
+  if (lmax < 0 || lmax > CONV_REAL_MAX_LMAX) { set_error("conv_real_tabulate: lmax out of range"); return CONV_REAL_EINVAL; }
+  if (!(theta_cut > 0.0) || !(theta_cut <= M_PI)) { set_error("conv_real_tabulate: theta_cut must be in (0, pi]"); return CONV_REAL_EINVAL; }
+  if (n_tab < 4 || n_tab > CONV_REAL_MAX_NTAB) { set_error("conv_real_tabulate: n_tab out of range"); return CONV_REAL_EINVAL; }
+  if (!finite_all(k_ell, lmax + 1)) { set_error("conv_real_tabulate: non-finite k_ell"); return CONV_REAL_EINVAL; }
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc != CONV_REAL_OK) return rc;
+  const double dcut = 2.0 * std::sin(0.5 * theta_cut);
+  const double h = dcut / (n_tab - 3);
+  hipError_t e = convreal::tabulate_device(k_ell, lmax, h, n_tab, table);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_tabulate");
+  return CONV_REAL_OK;
+}
+
+int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_tab,
+                   double theta_cut, int precision) {
+  if (!plan) { set_error("conv_real_init: NULL plan pointer"); return CONV_REAL_EINVAL; }
+  *plan = nullptr;
+  if (!table) { set_error("conv_real_init: NULL table"); return CONV_REAL_EINVAL; }
+  if (nside < 1 || nside > CONV_REAL_MAX_NSIDE) { set_error("conv_real_init: nside out of range"); return CONV_REAL_EINVAL; }
+  if (n_tab < 4 || n_tab > CONV_REAL_MAX_NTAB) { set_error("conv_real_init: n_tab out of range"); return CONV_REAL_EINVAL; }
+  if (!(theta_cut > 0.0) || !(theta_cut <= M_PI)) { set_error("conv_real_init: theta_cut must be in (0, pi]"); return CONV_REAL_EINVAL; }
+  if (precision != CONV_REAL_F64 && precision != CONV_REAL_F32 && precision != CONV_REAL_MIXED) {
+    set_error("conv_real_init: unknown precision"); return CONV_REAL_EINVAL;
+  }
+  if (!finite_all(table, n_tab)) { set_error("conv_real_init: non-finite table entry"); return CONV_REAL_EINVAL; }
+  if (precision == CONV_REAL_MIXED) {
+    set_error("conv_real_init: CONV_REAL_MIXED is not available in this build");
+    return CONV_REAL_EINVAL;
+  }
+
+  int dev = 0;
+  int rc = check_device(&dev);
+  if (rc != CONV_REAL_OK) return rc;
+
+  auto* p = new (std::nothrow) conv_real_plan();
+  if (!p) { set_error("conv_real_init: host allocation failed"); return CONV_REAL_ENOMEM; }
+  p->magic = kMagic;
+  p->device = dev;
+  p->nside = nside;
+  p->precision = precision;
+  p->n_tab = n_tab;
+  p->theta_cut = theta_cut;
+  p->dcut = 2.0 * std::sin(0.5 * theta_cut);
+  // A cut of pi keeps every pair: no chord exceeds 2, and antipodal pairs must not be lost to
+  // rounding of d^2 at the tie d = d_cut = 2.
+  p->dcut2 = theta_cut >= M_PI ? 4.0 * (1.0 + 1e-12) : p->dcut * p->dcut;
+  p->h = p->dcut / (n_tab - 3);
+  p->inv_h = 1.0 / p->h;
+  p->npix = 12LL * nside * nside;
+  p->omega = 4.0 * M_PI / static_cast<double>(p->npix);
+
+  const convreal::RingGrid g = convreal::make_ring_grid(nside);
+  p->nrings = g.nrings;
+  std::vector<int> jlo, jhi;
+  convreal::neighbour_rings(g, p->dcut2, jlo, jhi);
+
+  std::vector<long long> poff(g.nrings + 1, 0);
+  for (int r = 0; r < g.nrings; ++r) poff[r + 1] = poff[r] + (jhi[r] - jlo[r] + 1);
+  p->npairs_ring = poff[g.nrings];
+  std::vector<int> pi(p->npairs_ring), pj(p->npairs_ring);
+  for (int r = 0; r < g.nrings; ++r)
+    for (long long k = poff[r]; k < poff[r + 1]; ++k) {
+      pi[k] = r;
+      pj[k] = jlo[r] + static_cast<int>(k - poff[r]);
+    }
+  std::vector<double> rcd(g.nrings), rsd(g.nrings);
+  for (int r = 0; r < g.nrings; ++r) {
+    rcd[r] = std::cos(M_PI / g.n[r]);
+    rsd[r] = std::sin(M_PI / g.n[r]);
+  }
+  std::vector<int> tile_ring, tile_a0;
+  for (int r = 0; r < g.nrings; ++r)
+    for (int a0 = 0; a0 < g.n[r]; a0 += kTile) {
+      tile_ring.push_back(r);
+      tile_a0.push_back(a0);
+    }
+  p->ntiles = static_cast<int>(tile_ring.size());
+  std::vector<double> tab(table, table + n_tab);
+
+  hipError_t e = hipSuccess;
+  if ((e = dev_upload(p, &p->d_table, tab)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rn, g.n)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rc, g.c)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rstart, g.start)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rcd, rcd)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rsd, rsd)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_Z, g.Z)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_s, g.s)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_poff, poff)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_jlo, jlo)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_pi, pi)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_pj, pj)) != hipSuccess ||
+      (e = dev_alloc(p, &p->d_pA, p->npairs_ring)) != hipSuccess ||
+      (e = dev_alloc(p, &p->d_pB, p->npairs_ring)) != hipSuccess ||
+      (e = dev_alloc(p, &p->d_phw, p->npairs_ring)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_tile_ring, tile_ring)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_tile_a0, tile_a0)) != hipSuccess ||
+      (e = dev_alloc(p, &p->d_count, 1)) != hipSuccess) {
+    rc = hip_fail(e, "conv_real_init: device allocation/upload");
+    free_plan(p);
+    return rc;
+  }
+  if ((e = convreal::launch_ring_window(p, nullptr)) != hipSuccess ||
+      (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
+      (e = convreal::launch_pair_count(p, nullptr)) != hipSuccess ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
+    rc = hip_fail(e, "conv_real_init: window/count kernels");
+    free_plan(p);
+    return rc;
+  }
+  unsigned long long cnt = 0;
+  if ((e = hipMemcpy(&cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost)) != hipSuccess) {
+    rc = hip_fail(e, "conv_real_init: count readback");
+    free_plan(p);
+    return rc;
+  }
+  p->pairs = static_cast<long long>(cnt);
+  *plan = p;
+  return CONV_REAL_OK;
+}
+
+int conv_real_apply(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps, void* stream) {
+  if (!plan || plan->magic != kMagic) { set_error("conv_real_apply: invalid plan"); return CONV_REAL_EINVAL; }
+  if (!maps_in || !maps_out) { set_error("conv_real_apply: NULL map pointer"); return CONV_REAL_EINVAL; }
+  if (nmaps < 1) { set_error("conv_real_apply: nmaps must be >= 1"); return CONV_REAL_EINVAL; }
+  const size_t elem = plan->precision == CONV_REAL_F64 ? sizeof(double) : sizeof(float);
+  const size_t bytes = static_cast<size_t>(nmaps) * static_cast<size_t>(plan->npix) * elem;
+  const char* in0 = static_cast<const char*>(maps_in);
+  const char* out0 = static_cast<const char*>(maps_out);
+  if (in0 < out0 + bytes && out0 < in0 + bytes) {
+    set_error("conv_real_apply: maps_in and maps_out overlap");
+    return CONV_REAL_EALIAS;
+  }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_apply: hipSetDevice");
+  e = convreal::launch_pair_accumulate(plan, maps_in, maps_out, nmaps, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "conv_real_apply: launch");
+  return CONV_REAL_OK;
+}
+
+int conv_real_pairs(const conv_real_plan* plan, long long* pairs) {
+  if (!plan || plan->magic != kMagic || !pairs) { set_error("conv_real_pairs: invalid argument"); return CONV_REAL_EINVAL; }
+  *pairs = plan->pairs;
+  return CONV_REAL_OK;
+}
+
+int conv_real_destroy(conv_real_plan* plan) {
+  if (!plan) return CONV_REAL_OK;
+  if (plan->magic != kMagic) { set_error("conv_real_destroy: invalid plan"); return CONV_REAL_EINVAL; }
+  DeviceGuard guard;
+  (void)guard.enter(plan->device);
+  free_plan(plan);
+  return CONV_REAL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Private declarations of libconvreal: the plan and the host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/convreal.h"
+
+namespace convreal {
+
+// Per-thread message for conv_real_last_error().
+void set_error(const std::string& msg);
+
+// Device buffer owned by a plan.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Ring grid of the ring-ordered pixelization, host side, FP64 plus exact integers.
+// z_i = Z_i / (3 N^2) with Z_i an integer; sin(theta_i) = sqrt((3N^2 - Z_i)(3N^2 + Z_i)) / (3N^2);
+// pixel a of ring i sits at phi = pi (2a + c_i) / n_i with c_i in {0, 1}.
+struct RingGrid {
+  int nside = 0;
+  int nrings = 0;
+  long long npix = 0;
+  std::vector<long long> Z;     // numerator of z
+  std::vector<double> z;        // z_i
+  std::vector<double> s;        // sin(theta_i)
+  std::vector<int> n;           // pixels in ring
+  std::vector<int> c;           // azimuth offset numerator
+  std::vector<long long> start; // first pixel index
+};
+
+RingGrid make_ring_grid(int nside);
+
+// Neighbour ring ranges: ring r sees rings jlo[r]..jhi[r] (0-based, contiguous).
+void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std::vector<int>& jhi);
+
+struct conv_real_plan_impl;
+
+}  // namespace convreal
+
+// The opaque plan of the C ABI.
+struct conv_real_plan {
+  int magic = 0;
+  int device = 0;
+  int nside = 0;
+  int precision = 0;
+  int n_tab = 0;
+  int nrings = 0;
+  long long npix = 0;
+  double theta_cut = 0.0;
+  double dcut = 0.0;
+  double dcut2 = 0.0;
+  double h = 0.0;
+  double inv_h = 0.0;
+  double omega = 0.0;
+  long long pairs = 0;
+  long long npairs_ring = 0;   // number of (output ring, neighbour ring) pairs
+  int ntiles = 0;              // output tiles of the plain kernel
+
+  // device arrays (plain path)
+  double* d_table = nullptr;   // n_tab
+  int* d_rn = nullptr;         // per ring
+  int* d_rc = nullptr;
+  long long* d_rstart = nullptr;
+  double* d_rcd = nullptr;     // cos(pi / n)
+  double* d_rsd = nullptr;     // sin(pi / n)
+  long long* d_Z = nullptr;
+  double* d_s = nullptr;
+  long long* d_poff = nullptr; // nrings + 1, CSR offsets into ring-pair arrays
+  int* d_jlo = nullptr;        // per ring
+  int* d_pi = nullptr;         // per ring pair: output ring
+  int* d_pj = nullptr;         // per ring pair: neighbour ring
+  double* d_pA = nullptr;      // per ring pair: (dz)^2 + (ds)^2
+  double* d_pB = nullptr;      // per ring pair: 4 s_i s_j
+  double* d_phw = nullptr;     // per ring pair: window half-width in pixels of ring j
+  int* d_tile_ring = nullptr;  // per tile
+  int* d_tile_a0 = nullptr;    // per tile
+  unsigned long long* d_count = nullptr;
+
+  std::vector<void*> owned;    // every device allocation, freed by destroy
+};
+
+namespace convreal {
+
+// Launchers (each in the translation unit that defines its kernel).
+hipError_t launch_ring_window(const conv_real_plan* p, hipStream_t st);
+hipError_t launch_pair_count(const conv_real_plan* p, hipStream_t st);
+hipError_t launch_pair_accumulate(const conv_real_plan* p, const void* x, void* y, int nmaps,
+                                  hipStream_t st);
+hipError_t tabulate_device(const double* k_ell, int lmax, double h, int n_tab, double* table_host);
+
+}  // namespace convreal

@@ -1,0 +1,93 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects bad
+arguments on the host before any device call (runs without a GPU)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1409_4441_amd as cr
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "convreal.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(conv_real_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 7
+    for n in names:
+        assert hasattr(cr.lib, n), n
+    assert sorted(cr.EXPORTS) == names
+
+
+def test_strerror():
+    for code in [cr.OK, cr.EINVAL, cr.ENOMEM, cr.EHIP, cr.EALIAS, cr.ENODEV]:
+        assert cr.lib.conv_real_strerror(code)
+    assert cr.lib.conv_real_strerror(-99) == b"unknown error"
+
+
+def _init(nside, table, n_tab, theta_cut, precision):
+    h = ctypes.c_void_p()
+    t = None if table is None else np.ascontiguousarray(table, dtype=np.float64)
+    tp = None if t is None else t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rc = cr.lib.conv_real_init(ctypes.byref(h), nside, tp, n_tab, theta_cut, precision)
+    return rc, h
+
+
+@pytest.mark.parametrize("nside,n_tab,theta_cut,precision", [
+    (0, 16, 0.1, 0), (-3, 16, 0.1, 0), (8193, 16, 0.1, 0),
+    (8, 3, 0.1, 0), (8, 8193, 0.1, 0),
+    (8, 16, 0.0, 0), (8, 16, -0.1, 0), (8, 16, 3.2, 0), (8, 16, float("nan"), 0),
+    (8, 16, 0.1, 7), (8, 16, 0.1, -1),
+])
+def test_init_rejects_bad_arguments(nside, n_tab, theta_cut, precision):
+    rc, h = _init(nside, np.ones(max(n_tab, 4)), n_tab, theta_cut, precision)
+    assert rc == cr.EINVAL
+    assert h.value is None
+
+
+def test_init_rejects_null_and_nonfinite():
+    rc, _ = _init(8, None, 16, 0.1, 0)
+    assert rc == cr.EINVAL
+    t = np.ones(16)
+    t[5] = np.inf
+    rc, _ = _init(8, t, 16, 0.1, 0)
+    assert rc == cr.EINVAL
+    assert b"non-finite" in cr.lib.conv_real_last_error()
+    assert cr.lib.conv_real_init(None, 8, None, 16, 0.1, 0) == cr.EINVAL
+
+
+def test_apply_and_pairs_reject_bad_plan():
+    x = ctypes.c_void_p(16)
+    assert cr.lib.conv_real_apply(None, x, ctypes.c_void_p(32), 1, None) == cr.EINVAL
+    n = ctypes.c_longlong()
+    assert cr.lib.conv_real_pairs(None, ctypes.byref(n)) == cr.EINVAL
+    assert cr.lib.conv_real_destroy(None) == cr.OK
+
+
+def test_tabulate_rejects_bad_arguments():
+    k = np.ones(10)
+    out = np.empty(16)
+    kp = k.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    op = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert cr.lib.conv_real_tabulate(kp, -1, 0.1, 16, op) == cr.EINVAL
+    assert cr.lib.conv_real_tabulate(kp, 9, 0.0, 16, op) == cr.EINVAL
+    assert cr.lib.conv_real_tabulate(kp, 9, math.pi + 0.1, 16, op) == cr.EINVAL
+    assert cr.lib.conv_real_tabulate(kp, 9, 0.1, 2, op) == cr.EINVAL
+    assert cr.lib.conv_real_tabulate(None, 9, 0.1, 16, op) == cr.EINVAL
+    assert cr.lib.conv_real_tabulate(kp, 9, 0.1, 16, None) == cr.EINVAL
+
+
+def test_python_binding_validates():
+    with pytest.raises(ValueError):
+        cr.Plan(8, np.ones(16), 0.1, "f16")
+    with pytest.raises(cr.ConvRealError) as e:
+        cr.Plan(0, np.ones(16), 0.1, "f64")
+    assert e.value.code == cr.EINVAL

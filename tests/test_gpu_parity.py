@@ -1,0 +1,195 @@
+"""GPU parity of the plain FP64 path (CONV_REAL_F64 / CONV_REAL_F32) against the CPU oracle.
+
+Both sides receive the same seeded inputs and the same kernel table (tabulated by
+the oracle). Tolerances:
+  * FP64 maps: rel rms <= 1e-12 and max |dy| <= 1e-12 max |y| (rounding order only);
+  * FP32 maps: output rounded once from an FP64 sum, rel rms <= 2e-7;
+  * pair counts and per-pixel neighbour counts: exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import convolve as oc
+from oracle import geometry as og
+from oracle import kernel as ok
+
+torch = pytest.importorskip("torch")
+cr = pytest.importorskip("paper_1409_4441_amd")
+
+pytestmark = pytest.mark.gpu
+
+DEG = math.pi / 180
+
+
+def _dev():
+    return torch.device("cuda:0")
+
+
+def _run(plan, x_np):
+    x = torch.from_numpy(np.ascontiguousarray(x_np)).to(_dev())
+    y = plan.apply(x)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def _gauss_table(sigma, tc, n_tab=2048, lmax=512):
+    return ok.tabulate(synth.gaussian_beam_sigma(lmax, sigma), tc, n_tab)
+
+
+def test_tabulate_matches_oracle(cuda_device):
+    cases = [(synth.gaussian_beam_sigma(512, 1.5 * DEG), 7.5 * DEG, 2048)]
+    for name in ["resid512", "resid2048"]:
+        w = synth.workload(name)
+        cases.append((w.k_ell(), w.theta_cut, w.n_tab))
+    cases.append((np.ones(4097), 0.3, 777))
+    for k_ell, tc, n_tab in cases:
+        ref = ok.tabulate(k_ell, tc, n_tab)
+        got = cr.tabulate(k_ell, tc, n_tab)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_f64_full_map_gauss32(cuda_device):
+    w = synth.workload("gauss32")
+    T = ok.tabulate(w.k_ell(), w.theta_cut, w.n_tab)
+    x = synth.white_noise(w.nside, 2, seed=w.seed)
+    with cr.Plan(w.nside, T, w.theta_cut, "f64") as plan:
+        y = _run(plan, x)
+        assert plan.pairs() == oc.pair_count_total(w.nside, w.theta_cut)
+    ref = oc.convolve_sampled(w.nside, T, w.theta_cut, x, np.arange(x.shape[1]))
+    for m in range(2):
+        assert oc.rel_rms(y[m], ref[m]) <= 1e-12
+        assert np.max(np.abs(y[m] - ref[m])) <= 1e-12 * np.max(np.abs(ref[m]))
+
+
+@pytest.mark.parametrize("nside", [1, 2, 3, 8, 16])
+@pytest.mark.parametrize("tc_deg", [0.5, 9.0, 40.0, 100.0, 180.0])
+def test_f64_small_grids_all_cuts(cuda_device, nside, tc_deg):
+    """Tiny rings, windows wrapping whole rings near the poles, cut = pi (every pair)."""
+    tc = tc_deg * DEG
+    T = _gauss_table(max(tc / 3, 0.05), tc, n_tab=64, lmax=64)
+    x = synth.white_noise(nside, 1, seed=100 + nside)
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        y = _run(plan, x)
+        pairs = plan.pairs()
+    npix = x.shape[1]
+    counts, margin = oc.pair_counts_sampled(nside, tc, np.arange(npix))
+    assert pairs == int(counts.sum())
+    if tc_deg == 180.0:
+        assert pairs == npix * npix
+    ref = oc.convolve_sampled(nside, T, tc, x, np.arange(npix))
+    assert oc.rel_rms(y, ref) <= 1e-12
+
+
+def test_per_pixel_counts(cuda_device):
+    """With K = 1, y_p / Omega is the number of neighbours of p (exact in FP64)."""
+    nside, tc = 16, 0.3
+    T = np.ones(32)
+    npix = 12 * nside * nside
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        y = _run(plan, np.ones((1, npix)))
+    counts, _ = oc.pair_counts_sampled(nside, tc, np.arange(npix))
+    got = np.rint(y[0] / og.pixel_area(nside)).astype(np.int64)
+    assert np.array_equal(got, counts)
+
+
+def test_f32_maps(cuda_device):
+    w = synth.workload("gauss32")
+    T = ok.tabulate(w.k_ell(), w.theta_cut, w.n_tab)
+    x = synth.white_noise(w.nside, 1, seed=w.seed + 7, dtype=np.float32)
+    with cr.Plan(w.nside, T, w.theta_cut, "f32") as plan:
+        y = _run(plan, x)
+    assert y.dtype == np.float32
+    ref = oc.convolve_sampled(w.nside, T, w.theta_cut, x.astype(np.float64), np.arange(x.shape[1]))
+    assert oc.rel_rms(y, ref) <= 2e-7
+
+
+@pytest.mark.parametrize("nmaps", [1, 3, 4, 5, 9])
+def test_batched_maps_equal_single(cuda_device, nmaps):
+    nside, tc = 16, 8 * DEG
+    T = _gauss_table(2 * DEG, tc)
+    x = synth.white_noise(nside, nmaps, seed=nmaps)
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        y = _run(plan, x)
+        for m in range(nmaps):
+            ym = _run(plan, x[m:m + 1])
+            assert np.array_equal(ym[0], y[m])
+
+
+def test_deterministic_and_stream(cuda_device):
+    nside, tc = 32, 6 * DEG
+    T = _gauss_table(1.5 * DEG, tc)
+    x = torch.from_numpy(synth.white_noise(nside, 2, seed=3)).to(_dev())
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        y1 = plan.apply(x)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            y2 = plan.apply(x, stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        assert torch.equal(y1, y2)
+
+
+def test_alias_rejected(cuda_device):
+    nside, tc = 8, 10 * DEG
+    T = _gauss_table(3 * DEG, tc, n_tab=64, lmax=64)
+    x = torch.zeros(2, 12 * nside * nside, dtype=torch.float64, device=_dev())
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        with pytest.raises(cr.ConvRealError) as e:
+            plan.apply(x[0:1], out=x[0:1])
+        assert e.value.code == cr.EALIAS
+        with pytest.raises(TypeError):
+            plan.apply(x.float())
+
+
+def test_symmetry_and_harmonic_response_gpu(cuda_device):
+    """The GPU operator is symmetric and returns k_l^trunc * P_l(n . n0) for degree-l inputs."""
+    nside = 64
+    sigma = 1.5 * DEG
+    tc = 5 * sigma
+    T = _gauss_table(sigma, tc)
+    npix = 12 * nside * nside
+    g = np.random.default_rng(9)
+    u = g.standard_normal(npix)
+    v = g.standard_normal(npix)
+    vec = og.pixel_vectors(nside)
+    n0 = np.array([0.3, -0.5, 0.81])
+    n0 /= np.linalg.norm(n0)
+    ells = [0, 10, 30]
+    harm = np.stack([ok.legendre_p(30, vec @ n0)[l] for l in ells])
+    kt = ok.truncated_transfer(T, tc, 30)
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        Au, Av = _run(plan, np.stack([u, v]))
+        yh = _run(plan, harm)
+    assert abs(u @ Av - Au @ v) <= 1e-13 * np.linalg.norm(u) * np.linalg.norm(Av)
+    for k, l in enumerate(ells):
+        assert oc.rel_rms(yh[k], kt[l] * harm[k]) <= 1.5e-3
+
+
+@pytest.mark.parametrize("name,nsamp", [("resid512", 400), ("resid2048", 300)])
+def test_full_size_sampled(cuda_device, name, nsamp):
+    """Full-size grids, plain FP64-accumulate kernel with FP32 maps, at sampled output pixels;
+    neighbour counts of the sampled pixels exact."""
+    w = synth.workload(name)
+    T = ok.tabulate(w.k_ell(), w.theta_cut, w.n_tab)
+    x = synth.white_noise(w.nside, 1, seed=w.seed, dtype=np.float32)
+    npix = x.shape[1]
+    g = np.random.default_rng(w.seed)
+    pix = np.concatenate([g.choice(npix, nsamp - 8, replace=False),
+                          [0, 1, 2, 3, npix - 1, npix // 2, 2 * w.nside * (w.nside - 1), npix // 2 - 1]])
+    with cr.Plan(w.nside, T, w.theta_cut, "f32") as plan:
+        y = _run(plan, x)
+        pairs = plan.pairs()
+    ref = oc.convolve_sampled(w.nside, T, w.theta_cut, x.astype(np.float64), pix)
+    assert oc.rel_rms(y[0, pix], ref) <= 2e-7
+    counts, margin = oc.pair_counts_sampled(w.nside, w.theta_cut, pix)
+    assert margin > 1e-10
+    with cr.Plan(w.nside, np.ones(16), w.theta_cut, "f64") as plan1:
+        yc = _run(plan1, np.ones((1, npix)))
+    got = np.rint(yc[0, pix] / og.pixel_area(w.nside)).astype(np.int64)
+    assert np.array_equal(got, counts)
+    # the total pair count agrees with the per-pixel counts summed over the whole map
+    assert pairs == int(np.rint(yc[0].astype(np.float64) / og.pixel_area(w.nside)).sum())
