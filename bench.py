@@ -1,18 +1,20 @@
 """Throughput of the real-space convolution on one MI355X: pixel-pairs/s and maps/s.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload resid2048] [--precision f32]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload resid2048] [--precision mixed]
 
-One step = one conv_real_apply over the workload's maps, inputs already in HBM.
-Prints ONE JSON line. The roofline object is for the kernel that does the
-pair sums; its average launch duration comes from HIP events recorded on the
-stream it runs on. The cpu_baseline object times the CPU oracle on a bounded
-sample of output pixels of the same workload.
+One step = one conv_real_apply over the workload's maps (the whole real-space convolution),
+inputs already in HBM. Prints ONE JSON line:
+  value          pixel pairs per second of the timed path (exact pair count x maps / wall time)
+  maps_per_s     maps per second
+  plain_fp64     the plain FP64 per-pair kernel on the same map, timed beside it
+  roofline       the kernel that takes most of the step, timed with HIP events recorded between
+                 the library's kernels on the stream they run on (conv_real_profile)
+  cpu_baseline   the CPU oracle timed on a bounded sample of output pixels of the same workload
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -37,9 +39,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="resid2048")
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "f32", "f64"])
+    ap.add_argument("--plain-steps", type=int, default=3, help="timed applies of the plain kernel")
+    ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=400, help="output pixels the oracle sums")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     return ap.parse_args()
 
 
@@ -47,6 +52,47 @@ def make_map(w, nmaps):
     import synth
     dt = np.float64 if w.dtype == "f64" else np.float32
     return synth.white_noise(w.nside, nmaps, seed=w.seed, dtype=dt), "white N(0,1)"
+
+
+def time_applies(plan, x, y, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        plan.apply(x, out=y, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.apply(x, out=y, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ev0.elapsed_time(ev1) / steps
+
+
+def kernel_table(plan, x, y, reps, stream):
+    """Average per-kernel milliseconds and pixel pairs over reps profiled applies."""
+    acc = {}
+    for _ in range(reps):
+        _, stages = plan.profile(x, out=y, stream=stream)
+        for name, ms, work in stages:
+            a = acc.setdefault(name, [0.0, 0])
+            a[0] += ms
+            a[1] = work
+    return {k: {"ms": v[0] / reps, "pairs": v[1]} for k, v in acc.items()}
+
+
+def roofline_for(name, ms, pairs):
+    if "mfma" in name:
+        achieved = 2.0 * pairs / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP16_MFMA_TFLOPS, "traffic": None, "kernel": name, "kernel_ms": ms,
+                "algorithmic": "2 flop per pixel pair per map (FP16 matrix peak)"}
+    achieved = 2.0 * pairs / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": name, "kernel_ms": ms,
+            "algorithmic": "2 flop per pixel pair per map (FP64 vector peak)"}
 
 
 def cpu_baseline(w, table, x, y_gpu, nsamp):
@@ -96,58 +142,56 @@ def main():
     x = torch.from_numpy(x_np).to(dev)
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
-
-    for _ in range(args.warmup):
-        plan.apply(x, out=y, stream=stream)
-    torch.cuda.synchronize()
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.apply(x, out=y, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall0
-    kern_ms = ev0.elapsed_time(ev1) / args.steps
-    ms_per_step = 1e3 * wall / args.steps
-
     nmaps = x.shape[0]
-    total_pairs = pairs_per_map * nmaps
-    value = total_pairs * args.steps / wall
+
+    wall, apply_ms = time_applies(plan, x, y, args.steps, args.warmup, stream)
+    value = pairs_per_map * nmaps * args.steps / wall
     maps_per_s = nmaps * args.steps / wall
 
-    # Dominant kernel: the per-pair FP64 sum. Algorithmic work: one multiply-add (2 flops) per
-    # pixel pair per map, against the FP64 vector peak (the path is FP64 ALU-bound).
-    achieved_tflops = 2.0 * total_pairs / (kern_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": None,
-                "kernel": "pair_accumulate_kernel", "kernel_ms": kern_ms,
-                "algorithmic": "2 flop per pixel pair per map"}
-    elem = x.element_size()
-    hbm_gbs = 2.0 * elem * w.nside * w.nside * 12 * nmaps / (kern_ms * 1e-3) / 1e9
+    kernels = kernel_table(plan, x, y, args.profile_steps, stream)
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    roofline = roofline_for(dom, kernels[dom]["ms"], kernels[dom]["pairs"])
+    hbm_gbs = 2.0 * x.element_size() * x.numel() / (apply_ms * 1e-3) / 1e9
 
+    plan.apply(x, out=y, stream=stream)
+    torch.cuda.synchronize()
     y_np = y.cpu().numpy()
+
+    plain = None
+    if not args.no_plain and args.precision != "f64":
+        with cr.Plan(w.nside, table, w.theta_cut, "f32") as pf:
+            yf = torch.empty_like(x)
+            wall_f, ms_f = time_applies(pf, x, yf, args.plain_steps, 1, stream)
+            diff = torch.sqrt(torch.sum((y.double() - yf.double()) ** 2) / torch.sum(yf.double() ** 2)).item()
+        plain = {"ms_per_map": 1e3 * wall_f / (args.plain_steps * nmaps),
+                 "pixel_pairs_per_s": pairs_per_map * nmaps * args.plain_steps / wall_f,
+                 "maps_per_s": nmaps * args.plain_steps / wall_f,
+                 "speedup_of_timed_path": (wall_f / args.plain_steps) / (wall / args.steps),
+                 "rel_rms_timed_path_vs_plain": diff,
+                 "kernel": "pair_accumulate_kernel<float> (FP64 per pair)"}
+
     cpu = None
     err = None
     if not args.no_cpu:
         cpu, err = cpu_baseline(w, table, x_np, y_np, args.cpu_sample)
 
+    path = {"mixed": "split-FP16 matrix cores for belt ring pairs + FP64 per-pair for cap pairs",
+            "f32": "plain FP64 per-pair (FP32 maps)", "f64": "plain FP64 per-pair (FP64 maps)"}[args.precision]
     out = {
         "metric": METRIC, "value": value, "unit": "pixel-pairs/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
+        "dtype": {"mixed": "f16", "f32": "f64", "f64": "f64"}[args.precision],
+        "data": "synthetic",
         "config": {"workload": w.name, "nside": w.nside, "npix": 12 * w.nside ** 2, "nmaps": nmaps,
                    "theta_cut_arcmin": w.theta_cut / synth.ARCMIN, "fwhm_arcmin": w.fwhm / synth.ARCMIN,
                    "ell_cut": w.ell_cut, "lmax": w.lmax, "n_tab": w.n_tab, "map": map_desc,
-                   "maps_dtype": args.precision if args.precision == "f64" else "f32",
-                   "path": "plain FP64 per-pair (CONV_REAL_%s)" % args.precision.upper()},
+                   "maps_dtype": "f64" if args.precision == "f64" else "f32", "path": path},
         "maps_per_s": maps_per_s, "pairs_per_map": pairs_per_map, "init_s": init_s,
-        "achieved_hbm_gbs": hbm_gbs,
+        "apply_ms_events": apply_ms, "achieved_hbm_gbs": hbm_gbs,
+        "kernels": kernels,
         "rel_rms_vs_oracle_sample": err,
+        "plain_fp64": plain,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -123,6 +123,21 @@ int conv_real_apply(conv_real_plan* plan, const void* maps_in, void* maps_out, i
  */
 int conv_real_pairs(const conv_real_plan* plan, long long* pairs);
 
+/*
+ * conv_real_profile - run conv_real_apply once with HIP events recorded on `stream` between the
+ * library's kernels, wait for it, and report per kernel (tracing and benchmarks).
+ *
+ *   names      out: up to *nstages static kernel names (caller-owned array of pointers)
+ *   ms         out: up to *nstages durations in milliseconds (launches of the same kernel in a
+ *              row are merged)
+ *   work       out: up to *nstages pixel pairs summed by the kernel (0 for auxiliary kernels)
+ *   nstages    in: capacity of the three arrays; out: number of entries written
+ *
+ * Same arguments and errors as conv_real_apply; synchronous.
+ */
+int conv_real_profile(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps,
+                      void* stream, const char** names, float* ms, long long* work, int* nstages);
+
 /* conv_real_destroy - free a plan and its device memory. NULL is accepted. */
 int conv_real_destroy(conv_real_plan* plan);
 

@@ -34,7 +34,7 @@ ENODEV = -5
 
 # Every entry point that include/convreal.h declares.
 EXPORTS = ("conv_real_tabulate", "conv_real_init", "conv_real_apply", "conv_real_pairs",
-           "conv_real_destroy", "conv_real_strerror", "conv_real_last_error")
+           "conv_real_profile", "conv_real_destroy", "conv_real_strerror", "conv_real_last_error")
 
 
 class ConvRealError(RuntimeError):
@@ -59,6 +59,10 @@ def _load():
     lib.conv_real_apply.restype = c_int
     lib.conv_real_pairs.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_longlong)]
     lib.conv_real_pairs.restype = c_int
+    lib.conv_real_profile.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p,
+                                      ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_int)]
+    lib.conv_real_profile.restype = c_int
     lib.conv_real_destroy.argtypes = [c_void_p]
     lib.conv_real_destroy.restype = c_int
     lib.conv_real_strerror.argtypes = [c_int]
@@ -143,6 +147,34 @@ class Plan:
         _check(lib.conv_real_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                    int(nmaps), _stream_handle(stream)), "conv_real_apply")
         return out
+
+    def _check_maps(self, x, out):
+        import torch
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError("x must be a CUDA tensor")
+        if x.dtype != self.dtype:
+            raise TypeError(f"x must be {self.dtype}")
+        if x.shape[-1] != self.npix or x.dim() not in (1, 2) or not x.is_contiguous():
+            raise ValueError(f"x must be contiguous with shape [nmaps, {self.npix}]")
+        if out is None:
+            out = torch.empty_like(x)
+        elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError("out must match x")
+        return out, (1 if x.dim() == 1 else x.shape[0])
+
+    def profile(self, x, out=None, stream=None):
+        """Run one apply with events between the library's kernels (synchronous).
+        Returns (out, [(kernel_name, milliseconds, pixel_pairs), ...])."""
+        out, nmaps = self._check_maps(x, out)
+        cap = 32
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_float * cap)()
+        work = (ctypes.c_longlong * cap)()
+        n = ctypes.c_int(cap)
+        _check(lib.conv_real_profile(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                     int(nmaps), _stream_handle(stream), names, ms, work, ctypes.byref(n)),
+               "conv_real_profile")
+        return out, [(names[k].decode(), float(ms[k]), int(work[k])) for k in range(n.value)]
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

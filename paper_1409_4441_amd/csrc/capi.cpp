@@ -171,6 +171,124 @@ struct DeviceGuard {
   }
 };
 
+// Mixed path set-up: belt bands, window width, split-FP16 weight blocks, and the list of ring
+// pairs left to the per-pair kernel (every pair touching a polar cap).
+hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std::vector<int>& jlo,
+                       const std::vector<int>& jhi, const std::vector<long long>& poff,
+                       const std::vector<int>& pj) {
+  hipError_t e;
+  const int N = p->nside;
+  const int blo = N - 1, bhi = 3 * N - 1;  // belt rings, 0-based
+  std::vector<double> hw(p->npairs_ring);
+  if ((e = hipMemcpy(hw.data(), p->d_phw, sizeof(double) * hw.size(), hipMemcpyDeviceToHost)) != hipSuccess)
+    return e;
+  // Bands of 16 belt output rings; per (band, input ring j) the tight range of window offsets
+  // m = b - a over the band's rows, from the same windows the per-pair kernel walks:
+  // m in [ceil(delta/2 - hw - eps), floor(delta/2 + hw + eps)], delta = c_i - c_j.
+  const int nbelt = bhi - blo + 1;
+  const int nbands = (nbelt + 15) / 16;
+  std::vector<int> band_jf(nbands), band_nj(nbands), band_woff(nbands);
+  std::vector<int> blk_koff, blk_nk, blk_mlo, chunk_band, chunk_j, chunk_m0;
+  bool ok = true;
+  int nk_max = 1;
+  for (int b = 0; b < nbands && ok; ++b) {
+    const int r0 = blo + 16 * b;
+    const int r1 = std::min(r0 + 15, bhi);
+    int lo = jlo[r0], hi = jhi[r0];
+    for (int r = r0; r <= r1; ++r) {
+      lo = std::min(lo, jlo[r]);
+      hi = std::max(hi, jhi[r]);
+    }
+    lo = std::max(lo, blo);
+    hi = std::min(hi, bhi);
+    band_jf[b] = lo;
+    band_nj[b] = hi - lo + 1;
+    band_woff[b] = static_cast<int>(blk_nk.size());
+    for (int j = lo; j <= hi && ok; ++j) {
+      int mmin = 1 << 30, mmax = -(1 << 30);
+      for (int r = r0; r <= r1; ++r) {
+        if (j < jlo[r] || j > jhi[r]) continue;
+        const long long k = poff[r] + (j - jlo[r]);
+        if (2.0 * hw[k] >= 4.0 * N) { ok = false; break; }  // window wraps the whole ring
+        const double half_delta = 0.5 * (g.c[r] - g.c[j]);
+        mmin = std::min(mmin, static_cast<int>(std::ceil(half_delta - hw[k] - 1e-7)));
+        mmax = std::max(mmax, static_cast<int>(std::floor(half_delta + hw[k] + 1e-7)));
+      }
+      if (!ok) break;
+      if (mmax < mmin) { mmin = 0; mmax = 0; }
+      const int nk = (mmax - mmin + 1 + 31) / 32;
+      if (nk > 4 || 32 * nk > 4 * N) { ok = false; break; }
+      nk_max = std::max(nk_max, nk);
+      blk_koff.push_back(static_cast<int>(chunk_band.size()));
+      blk_nk.push_back(nk);
+      blk_mlo.push_back(mmin);
+      for (int q = 0; q < nk; ++q) {
+        chunk_band.push_back(b);
+        chunk_j.push_back(j);
+        chunk_m0.push_back(mmin + 32 * q);
+      }
+    }
+  }
+  p->belt_enabled = ok ? 1 : 0;
+
+  if (p->belt_enabled) {
+    p->belt_lo = blo;
+    p->belt_hi = bhi;
+    p->belt_nk = nk_max;
+    p->belt_nbands = nbands;
+    p->belt_nsegs = (4 * N + 255) / 256;
+    p->n_wblk = static_cast<long long>(blk_nk.size());
+    p->n_chunks = static_cast<long long>(chunk_band.size());
+    // weight scale: power of two with Omega * max|T| * s_w < 2^12 (interpolation overshoot stays
+    // far below the FP16 maximum)
+    double tmax = 0.0;
+    std::vector<double> tab(p->n_tab);
+    if ((e = hipMemcpy(tab.data(), p->d_table, sizeof(double) * p->n_tab, hipMemcpyDeviceToHost)) != hipSuccess)
+      return e;
+    for (double v : tab) tmax = std::max(tmax, std::fabs(v));
+    int ex = 0;
+    std::frexp(std::max(tmax * p->omega, 1e-300), &ex);
+    p->belt_sw = std::ldexp(1.0, 12 - ex);
+    if ((e = dev_upload(p, &p->d_band_jf, band_jf)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_band_nj, band_nj)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_band_woff, band_woff)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_blk_koff, blk_koff)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_blk_nk, blk_nk)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_blk_mlo, blk_mlo)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_chunk_band, chunk_band)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_chunk_j, chunk_j)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_chunk_m0, chunk_m0)) != hipSuccess ||
+        (e = dev_alloc(p, &p->d_wt, static_cast<size_t>(p->n_chunks) * 1024)) != hipSuccess ||
+        (e = convreal::build_belt_weights(p)) != hipSuccess)
+      return e;
+  } else {
+    p->belt_lo = 1;
+    p->belt_hi = 0;
+  }
+  if ((e = dev_alloc(p, &p->d_amax, convreal::kMaxMixedMaps)) != hipSuccess) return e;
+
+  std::vector<long long> roff(g.nrings + 1, 0), ridx;
+  std::vector<int> rtile_ring, rtile_a0;
+  for (int r = 0; r < g.nrings; ++r) {
+    const bool belt_row = p->belt_enabled && r >= blo && r <= bhi;
+    for (long long k = poff[r]; k < poff[r + 1]; ++k)
+      if (!belt_row || pj[k] < blo || pj[k] > bhi) ridx.push_back(k);
+    roff[r + 1] = static_cast<long long>(ridx.size());
+    if (roff[r + 1] > roff[r])
+      for (int a0 = 0; a0 < g.n[r]; a0 += kTile) {
+        rtile_ring.push_back(r);
+        rtile_a0.push_back(a0);
+      }
+  }
+  p->n_rtiles = static_cast<int>(rtile_ring.size());
+  if ((e = dev_upload(p, &p->d_rest_off, roff)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rest_idx, ridx)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rtile_ring, rtile_ring)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rtile_a0, rtile_a0)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -217,10 +335,6 @@ int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_
     set_error("conv_real_init: unknown precision"); return CONV_REAL_EINVAL;
   }
   if (!finite_all(table, n_tab)) { set_error("conv_real_init: non-finite table entry"); return CONV_REAL_EINVAL; }
-  if (precision == CONV_REAL_MIXED) {
-    set_error("conv_real_init: CONV_REAL_MIXED is not available in this build");
-    return CONV_REAL_EINVAL;
-  }
 
   int dev = 0;
   int rc = check_device(&dev);
@@ -296,7 +410,7 @@ int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_
   }
   if ((e = convreal::launch_ring_window(p, nullptr)) != hipSuccess ||
       (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
-      (e = convreal::launch_pair_count(p, nullptr)) != hipSuccess ||
+      (e = convreal::launch_pair_count(p, false, nullptr)) != hipSuccess ||
       (e = hipDeviceSynchronize()) != hipSuccess) {
     rc = hip_fail(e, "conv_real_init: window/count kernels");
     free_plan(p);
@@ -309,6 +423,18 @@ int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_
     return rc;
   }
   p->pairs = static_cast<long long>(cnt);
+  if (precision == CONV_REAL_MIXED) {
+    if ((e = setup_mixed(p, g, jlo, jhi, poff, pj)) != hipSuccess ||
+        (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
+        (e = convreal::launch_pair_count(p, true, nullptr)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess ||
+        (e = hipMemcpy(&cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost)) != hipSuccess) {
+      rc = hip_fail(e, "conv_real_init: mixed-precision set-up");
+      free_plan(p);
+      return rc;
+    }
+    p->pairs_rest = static_cast<long long>(cnt);
+  }
   *plan = p;
   return CONV_REAL_OK;
 }
@@ -328,9 +454,66 @@ int conv_real_apply(conv_real_plan* plan, const void* maps_in, void* maps_out, i
   DeviceGuard guard;
   hipError_t e = guard.enter(plan->device);
   if (e != hipSuccess) return hip_fail(e, "conv_real_apply: hipSetDevice");
-  e = convreal::launch_pair_accumulate(plan, maps_in, maps_out, nmaps, static_cast<hipStream_t>(stream));
+  if (plan->precision == CONV_REAL_MIXED)
+    e = convreal::launch_mixed(plan, static_cast<const float*>(maps_in), static_cast<float*>(maps_out), nmaps,
+                               static_cast<hipStream_t>(stream));
+  else
+    e = convreal::launch_pair_accumulate(plan, maps_in, maps_out, nmaps, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "conv_real_apply: launch");
   return CONV_REAL_OK;
+}
+
+int conv_real_profile(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps,
+                      void* stream, const char** names, float* ms, long long* work, int* nstages) {
+  if (!names || !ms || !work || !nstages || *nstages < 1) {
+    set_error("conv_real_profile: NULL output or zero capacity");
+    return CONV_REAL_EINVAL;
+  }
+  if (!plan || plan->magic != kMagic) { set_error("conv_real_profile: invalid plan"); return CONV_REAL_EINVAL; }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_profile: hipSetDevice");
+  convreal::Recorder rec;
+  int made = 0;
+  for (; made <= convreal::Recorder::kMax; ++made)
+    if ((e = hipEventCreate(&rec.ev[made])) != hipSuccess) break;
+  int rc = CONV_REAL_OK;
+  if (e != hipSuccess) {
+    rc = hip_fail(e, "conv_real_profile: hipEventCreate");
+  } else {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((e = hipEventRecord(rec.ev[0], st)) != hipSuccess) {
+      rc = hip_fail(e, "conv_real_profile: hipEventRecord");
+    } else {
+      plan->rec = &rec;
+      rc = conv_real_apply(plan, maps_in, maps_out, nmaps, stream);
+      plan->rec = nullptr;
+      if (rc == CONV_REAL_OK && (e = hipStreamSynchronize(st)) != hipSuccess)
+        rc = hip_fail(e, "conv_real_profile: hipStreamSynchronize");
+    }
+    if (rc == CONV_REAL_OK) {
+      int out = 0;
+      for (int k = 0; k < rec.n; ++k) {
+        float t = 0.0f;
+        if ((e = hipEventElapsedTime(&t, rec.ev[k], rec.ev[k + 1])) != hipSuccess) {
+          rc = hip_fail(e, "conv_real_profile: hipEventElapsedTime");
+          break;
+        }
+        if (out > 0 && std::strcmp(names[out - 1], rec.name[k]) == 0) {
+          ms[out - 1] += t;
+          work[out - 1] += rec.work[k];
+        } else if (out < *nstages) {
+          names[out] = rec.name[k];
+          ms[out] = t;
+          work[out] = rec.work[k];
+          ++out;
+        }
+      }
+      *nstages = out;
+    }
+  }
+  for (int k = 0; k < made; ++k) (void)hipEventDestroy(rec.ev[k]);
+  return rc;
 }
 
 int conv_real_pairs(const conv_real_plan* plan, long long* pairs) {

@@ -40,7 +40,14 @@ RingGrid make_ring_grid(int nside);
 // Neighbour ring ranges: ring r sees rings jlo[r]..jhi[r] (0-based, contiguous).
 void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std::vector<int>& jhi);
 
-struct conv_real_plan_impl;
+// Events recorded between kernels by conv_real_profile.
+struct Recorder {
+  static constexpr int kMax = 32;
+  hipEvent_t ev[kMax + 1];
+  const char* name[kMax];
+  long long work[kMax];
+  int n = 0;
+};
 
 }  // namespace convreal
 
@@ -83,16 +90,63 @@ struct conv_real_plan {
   int* d_tile_a0 = nullptr;    // per tile
   unsigned long long* d_count = nullptr;
 
+  // mixed path: belt ring pairs on the matrix cores, the rest (cap-touching pairs) per pair
+  int belt_enabled = 0;
+  int belt_lo = 1;             // belt output rings [belt_lo, belt_hi] (0-based); empty if disabled
+  int belt_hi = 0;
+  int belt_nk = 0;             // largest number of K-chunks (32 window offsets) of any block
+  int belt_nbands = 0;         // bands of 16 output rings
+  int belt_nsegs = 0;          // 256-pixel segments per ring
+  long long n_wblk = 0;        // weight blocks (band, input ring)
+  long long n_chunks = 0;      // K-chunks over all weight blocks
+  double belt_sw = 1.0;        // power-of-two weight scale
+  int* d_band_jf = nullptr;    // per band: first input ring
+  int* d_band_nj = nullptr;    // per band: number of input rings
+  int* d_band_woff = nullptr;  // per band: first weight block
+  int* d_blk_koff = nullptr;   // per weight block: first K-chunk
+  int* d_blk_nk = nullptr;     // per weight block: K-chunks
+  int* d_blk_mlo = nullptr;    // per weight block: first window offset m = b - a
+  int* d_chunk_band = nullptr; // per K-chunk
+  int* d_chunk_j = nullptr;
+  int* d_chunk_m0 = nullptr;
+  _Float16* d_wt = nullptr;    // n_chunks * 1024 FP16
+  unsigned* d_amax = nullptr;  // per map (up to kMaxMixedMaps): max |x| bits
+  long long* d_rest_off = nullptr;   // per ring: CSR offsets into d_rest_idx
+  long long* d_rest_idx = nullptr;   // ring-pair indices handled per pair
+  int* d_rtile_ring = nullptr;
+  int* d_rtile_a0 = nullptr;
+  int n_rtiles = 0;
+  long long pairs_rest = 0;    // pixel pairs per map summed by the per-pair remainder kernel
+
+  convreal::Recorder* rec = nullptr;  // set only inside conv_real_profile
   std::vector<void*> owned;    // every device allocation, freed by destroy
 };
 
 namespace convreal {
+// Record a profiling event after a kernel launch (no-op unless conv_real_profile is running).
+inline void mark(const conv_real_plan* p, hipStream_t st, const char* name, long long work) {
+  Recorder* r = p->rec;
+  if (!r || r->n >= Recorder::kMax) return;
+  if (hipEventRecord(r->ev[r->n + 1], st) != hipSuccess) return;
+  r->name[r->n] = name;
+  r->work[r->n] = work;
+  r->n += 1;
+}
+}  // namespace convreal
+
+namespace convreal {
+
+constexpr int kMaxMixedMaps = 64;  // maps per mixed-path launch (larger batches are chunked)
 
 // Launchers (each in the translation unit that defines its kernel).
 hipError_t launch_ring_window(const conv_real_plan* p, hipStream_t st);
-hipError_t launch_pair_count(const conv_real_plan* p, hipStream_t st);
+hipError_t launch_pair_count(const conv_real_plan* p, bool remainder, hipStream_t st);
 hipError_t launch_pair_accumulate(const conv_real_plan* p, const void* x, void* y, int nmaps,
                                   hipStream_t st);
+hipError_t launch_remainder(const conv_real_plan* p, const float* x, float* y, int nmaps,
+                            hipStream_t st);
+hipError_t build_belt_weights(conv_real_plan* p);
+hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st);
 hipError_t tabulate_device(const double* k_ell, int lmax, double h, int n_tab, double* table_host);
 
 }  // namespace convreal

@@ -1,18 +1,23 @@
-// pair_accumulate (plain path): every pixel pair evaluated and accumulated in FP64.
+// pair_accumulate: every pixel pair evaluated and accumulated in FP64.
 //
 //   y_p = Omega * sum_{q : d_pq <= d_cut} Ktilde(d_pq) x_q
 //
 // One thread per output pixel a of ring i; a workgroup owns a tile of up to 256 consecutive pixels
-// of one ring, and the kernel table sits in LDS. For each neighbour ring j (from the ring_window
-// pass) the thread walks the candidate pixels b of its azimuthal window. The half-angle
-// alpha = (phi_a - phi_b) / 2 = (pi / 2) * num / (n_i n_j) has the exact integer numerator
-// num = (2a + c_i) n_j - (2b + c_j) n_i; sin(alpha) is seeded from that numerator and advanced by
-// the rotation alpha -> alpha - pi / n_j from one pixel to the next (re-seeded every 64 steps).
-// The chord is d^2 = A_ij + B_ij sin^2(alpha); pairs with d^2 <= d_cut^2 are interpolated from the
-// table (4-point Lagrange, segment k = floor(d/h) clamped to n_tab - 3, ghost T[-1] = T[1]) and
-// accumulated in FP64.
+// of one ring, and the kernel table sits in LDS. For each listed neighbour ring j (from the
+// ring_window pass) the thread walks the candidate pixels b of its azimuthal window. The
+// half-angle alpha = (phi_a - phi_b) / 2 = (pi / 2) * num / (n_i n_j) has the exact integer
+// numerator num = (2a + c_i) n_j - (2b + c_j) n_i; sin(alpha) is seeded from that numerator and
+// advanced by the rotation alpha -> alpha - pi / n_j from one pixel to the next (re-seeded every
+// 64 steps). The chord is d^2 = A_ij + B_ij sin^2(alpha); pairs with d^2 <= d_cut^2 are
+// interpolated from the table and accumulated in FP64.
+//
+// The same loop serves two callers:
+//   * the plain path (CONV_REAL_F64 / F32): every ring pair of every output ring, stored;
+//   * the mixed path's remainder: only ring pairs that touch a polar cap, listed by index; the
+//     result is stored for cap output rings and added to the matrix-core result for belt rings.
 #include <hip/hip_runtime.h>
 
+#include "common.h"
 #include "internal.h"
 
 namespace {
@@ -26,8 +31,9 @@ struct PairArgs {
   const long long* rstart;
   const double* rcd;
   const double* rsd;
-  const long long* poff;
-  const int* jlo;
+  const long long* off;   // per ring: CSR offsets into the (listed) ring pairs
+  const long long* idx;   // listed pair -> ring-pair index, or nullptr for the identity
+  const int* pj;          // per ring pair: neighbour ring
   const double* pA;
   const double* pB;
   const double* phw;
@@ -35,57 +41,26 @@ struct PairArgs {
   const int* tile_a0;
   int ntiles;
   int n_tab;
+  int belt_lo;            // rings [belt_lo, belt_hi] get y += (remainder mode); others y =
+  int belt_hi;
+  int accumulate_belt;
   double inv_h;
   double dcut2;
   double omega;
   long long npix;
 };
 
-// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of tiles so that
-// tiles sharing neighbour rings share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
-  const int xcd = b & 7;
-  const int idx = b >> 3;
-  const int base = ntiles >> 3;
-  const int rem = ntiles & 7;
-  return xcd * base + min(xcd, rem) + idx;
-}
-
-__device__ __forceinline__ double interp(const double* __restrict__ s_tab, int n_tab, double d,
-                                         double inv_h) {
-  const double t = d * inv_h;
-  int k = static_cast<int>(t);
-  if (k > n_tab - 3) k = n_tab - 3;
-  const double f = t - static_cast<double>(k);
-  const double tm1 = s_tab[k == 0 ? 1 : k - 1];
-  const double t0 = s_tab[k];
-  const double t1 = s_tab[k + 1];
-  const double t2 = s_tab[k + 2];
-  const double fm1 = f - 1.0;
-  const double fm2 = f - 2.0;
-  const double fp1 = f + 1.0;
-  const double ff1 = f * fm1;
-  const double g = fp1 * fm2;
-  const double wm1 = -(ff1 * fm2) * (1.0 / 6.0);
-  const double w2 = (fp1 * ff1) * (1.0 / 6.0);
-  const double w0 = (g * fm1) * 0.5;
-  const double w1 = -(g * f) * 0.5;
-  return wm1 * tm1 + w0 * t0 + w1 * t1 + w2 * t2;
-}
-
-// Visits the candidate pixels of every neighbour ring of output pixel (ring r, pixel a) and calls
-// body(kt_or_unused, input_pixel_index, in_cut) for each pair inside the cut.
 template <bool kCount, int kMaxMaps, typename T>
 __device__ __forceinline__ void pair_loop(const PairArgs& a, const double* __restrict__ s_tab, int r,
                                           int ai, const T* __restrict__ x, int nm, double* acc,
                                           unsigned long long* cnt) {
   const int ni = a.rn[r];
   const long long twoa_ci = 2LL * ai + a.rc[r];
-  const long long k0 = a.poff[r];
-  const long long k1 = a.poff[r + 1];
-  const int j0 = a.jlo[r];
-  for (long long k = k0; k < k1; ++k) {
-    const int j = j0 + static_cast<int>(k - k0);
+  const long long k0 = a.off[r];
+  const long long k1 = a.off[r + 1];
+  for (long long kk = k0; kk < k1; ++kk) {
+    const long long k = a.idx ? a.idx[kk] : kk;
+    const int j = a.pj[k];
     const int nj = a.rn[j];
     const long long cj = a.rc[j];
     const long long sj = a.rstart[j];
@@ -125,7 +100,7 @@ __device__ __forceinline__ void pair_loop(const PairArgs& a, const double* __res
         if constexpr (kCount) {
           *cnt += 1;
         } else {
-          const double kt = interp(s_tab, a.n_tab, sqrt(d2), a.inv_h);
+          const double kt = convreal::interp_f64(s_tab, a.n_tab, sqrt(d2), a.inv_h);
           const T* xp = x + sj + bm;
 #pragma unroll
           for (int m = 0; m < kMaxMaps; ++m)
@@ -144,7 +119,7 @@ template <int kMaxMaps, typename T>
 __global__ __launch_bounds__(kTile) void pair_accumulate_kernel(PairArgs a, const T* __restrict__ x,
                                                                 T* __restrict__ y, int nm) {
   extern __shared__ double s_tab[];
-  const int tile = xcd_tile(blockIdx.x, a.ntiles);
+  const int tile = convreal::xcd_remap(blockIdx.x, a.ntiles);
   for (int k = threadIdx.x; k < a.n_tab; k += blockDim.x) s_tab[k] = a.table[k];
   __syncthreads();
   const int r = a.tile_ring[tile];
@@ -155,20 +130,25 @@ __global__ __launch_bounds__(kTile) void pair_accumulate_kernel(PairArgs a, cons
   for (int m = 0; m < kMaxMaps; ++m) acc[m] = 0.0;
   pair_loop<false, kMaxMaps, T>(a, s_tab, r, ai, x, nm, acc, nullptr);
   const long long out = a.rstart[r] + ai;
+  const bool add = a.accumulate_belt && r >= a.belt_lo && r <= a.belt_hi;
 #pragma unroll
-  for (int m = 0; m < kMaxMaps; ++m)
-    if (m < nm) y[m * a.npix + out] = static_cast<T>(a.omega * acc[m]);
+  for (int m = 0; m < kMaxMaps; ++m) {
+    if (m < nm) {
+      T* yp = y + m * a.npix + out;
+      const double v = a.omega * acc[m];
+      *yp = add ? static_cast<T>(static_cast<double>(*yp) + v) : static_cast<T>(v);
+    }
+  }
 }
 
 __global__ __launch_bounds__(kTile) void pair_count_kernel(PairArgs a,
                                                            unsigned long long* __restrict__ total) {
-  extern __shared__ double s_tab[];
   __shared__ unsigned long long s_red[kTile];
-  const int tile = xcd_tile(blockIdx.x, a.ntiles);
+  const int tile = convreal::xcd_remap(blockIdx.x, a.ntiles);
   const int r = a.tile_ring[tile];
   const int ai = a.tile_a0[tile] + threadIdx.x;
   unsigned long long cnt = 0;
-  if (ai < a.rn[r]) pair_loop<true, 1, float>(a, s_tab, r, ai, nullptr, 0, nullptr, &cnt);
+  if (ai < a.rn[r]) pair_loop<true, 1, float>(a, nullptr, r, ai, nullptr, 0, nullptr, &cnt);
   s_red[threadIdx.x] = cnt;
   __syncthreads();
   for (int w = kTile / 2; w > 0; w >>= 1) {
@@ -178,7 +158,7 @@ __global__ __launch_bounds__(kTile) void pair_count_kernel(PairArgs a,
   if (threadIdx.x == 0) atomicAdd(total, s_red[0]);
 }
 
-PairArgs make_args(const conv_real_plan* p) {
+PairArgs make_args(const conv_real_plan* p, bool remainder) {
   PairArgs a;
   a.table = p->d_table;
   a.rn = p->d_rn;
@@ -186,14 +166,27 @@ PairArgs make_args(const conv_real_plan* p) {
   a.rstart = p->d_rstart;
   a.rcd = p->d_rcd;
   a.rsd = p->d_rsd;
-  a.poff = p->d_poff;
-  a.jlo = p->d_jlo;
+  a.pj = p->d_pj;
   a.pA = p->d_pA;
   a.pB = p->d_pB;
   a.phw = p->d_phw;
-  a.tile_ring = p->d_tile_ring;
-  a.tile_a0 = p->d_tile_a0;
-  a.ntiles = p->ntiles;
+  if (remainder) {
+    a.off = p->d_rest_off;
+    a.idx = p->d_rest_idx;
+    a.tile_ring = p->d_rtile_ring;
+    a.tile_a0 = p->d_rtile_a0;
+    a.ntiles = p->n_rtiles;
+    a.accumulate_belt = 1;
+  } else {
+    a.off = p->d_poff;
+    a.idx = nullptr;
+    a.tile_ring = p->d_tile_ring;
+    a.tile_a0 = p->d_tile_a0;
+    a.ntiles = p->ntiles;
+    a.accumulate_belt = 0;
+  }
+  a.belt_lo = p->belt_lo;
+  a.belt_hi = p->belt_hi;
   a.n_tab = p->n_tab;
   a.inv_h = p->inv_h;
   a.dcut2 = p->dcut2;
@@ -202,42 +195,54 @@ PairArgs make_args(const conv_real_plan* p) {
   return a;
 }
 
+template <typename T>
+hipError_t launch_loop(const conv_real_plan* p, const PairArgs& a, const T* x, T* y, int nmaps,
+                       size_t lds, hipStream_t st, const char* name, long long pairs_per_map) {
+  constexpr int kChunk = 4;
+  if (a.ntiles == 0) return hipSuccess;
+  for (int m0 = 0; m0 < nmaps; m0 += kChunk) {
+    const int nm = nmaps - m0 < kChunk ? nmaps - m0 : kChunk;
+    const T* xi = x + static_cast<size_t>(m0) * p->npix;
+    T* yo = y + static_cast<size_t>(m0) * p->npix;
+    if (nm == 1)
+      hipLaunchKernelGGL((pair_accumulate_kernel<1, T>), dim3(a.ntiles), dim3(kTile), lds, st, a, xi, yo, nm);
+    else
+      hipLaunchKernelGGL((pair_accumulate_kernel<kChunk, T>), dim3(a.ntiles), dim3(kTile), lds, st, a, xi, yo, nm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    convreal::mark(p, st, name, pairs_per_map * nm);
+  }
+  return hipSuccess;
+}
+
 }  // namespace
 
 namespace convreal {
 
-hipError_t launch_pair_count(const conv_real_plan* p, hipStream_t st) {
-  const PairArgs a = make_args(p);
-  hipLaunchKernelGGL(pair_count_kernel, dim3(p->ntiles), dim3(kTile), 0, st, a, p->d_count);
+hipError_t launch_pair_count(const conv_real_plan* p, bool remainder, hipStream_t st) {
+  const PairArgs a = make_args(p, remainder);
+  if (a.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(pair_count_kernel, dim3(a.ntiles), dim3(kTile), 0, st, a, p->d_count);
   return hipGetLastError();
 }
 
 hipError_t launch_pair_accumulate(const conv_real_plan* p, const void* x, void* y, int nmaps,
                                   hipStream_t st) {
-  const PairArgs a = make_args(p);
+  const PairArgs a = make_args(p, false);
   const size_t lds = sizeof(double) * static_cast<size_t>(p->n_tab);
-  constexpr int kChunk = 4;
-  for (int m0 = 0; m0 < nmaps; m0 += kChunk) {
-    const int nm = nmaps - m0 < kChunk ? nmaps - m0 : kChunk;
-    if (p->precision == CONV_REAL_F64) {
-      const double* xi = static_cast<const double*>(x) + static_cast<size_t>(m0) * p->npix;
-      double* yo = static_cast<double*>(y) + static_cast<size_t>(m0) * p->npix;
-      if (nm == 1)
-        hipLaunchKernelGGL((pair_accumulate_kernel<1, double>), dim3(p->ntiles), dim3(kTile), lds, st, a, xi, yo, nm);
-      else
-        hipLaunchKernelGGL((pair_accumulate_kernel<kChunk, double>), dim3(p->ntiles), dim3(kTile), lds, st, a, xi, yo, nm);
-    } else {
-      const float* xi = static_cast<const float*>(x) + static_cast<size_t>(m0) * p->npix;
-      float* yo = static_cast<float*>(y) + static_cast<size_t>(m0) * p->npix;
-      if (nm == 1)
-        hipLaunchKernelGGL((pair_accumulate_kernel<1, float>), dim3(p->ntiles), dim3(kTile), lds, st, a, xi, yo, nm);
-      else
-        hipLaunchKernelGGL((pair_accumulate_kernel<kChunk, float>), dim3(p->ntiles), dim3(kTile), lds, st, a, xi, yo, nm);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  if (p->precision == CONV_REAL_F64)
+    return launch_loop(p, a, static_cast<const double*>(x), static_cast<double*>(y), nmaps, lds, st,
+                       "pair_accumulate_kernel<double>", p->pairs);
+  return launch_loop(p, a, static_cast<const float*>(x), static_cast<float*>(y), nmaps, lds, st,
+                     "pair_accumulate_kernel<float>", p->pairs);
+}
+
+hipError_t launch_remainder(const conv_real_plan* p, const float* x, float* y, int nmaps,
+                            hipStream_t st) {
+  const PairArgs a = make_args(p, true);
+  const size_t lds = sizeof(double) * static_cast<size_t>(p->n_tab);
+  return launch_loop(p, a, x, y, nmaps, lds, st, "pair_accumulate_kernel<float> (cap pairs)",
+                     p->pairs_rest);
 }
 
 }  // namespace convreal

@@ -7,6 +7,7 @@
 // in pixels of ring j is dphi_max * n_j / (2 pi); a value >= n_j / 2 means the whole ring.
 #include <hip/hip_runtime.h>
 
+#include "common.h"
 #include "internal.h"
 
 namespace {
@@ -23,14 +24,8 @@ __global__ __launch_bounds__(256) void ring_window_kernel(long long npairs, cons
   if (k >= npairs) return;
   const int i = pi[k];
   const int j = pj[k];
-  // z and s differences from exact integer numerators: z = Z / q,
-  // s_i - s_j = (s_i^2 - s_j^2) / (s_i + s_j) = -(Z_i - Z_j)(Z_i + Z_j) / (q^2 (s_i + s_j)).
-  const long long dZ = Z[i] - Z[j];
-  const long long sZ = Z[i] + Z[j];
-  const double dz = static_cast<double>(dZ) / q;
-  const double ds = -static_cast<double>(dZ * sZ) / (q * q * (s[i] + s[j]));
-  const double A = dz * dz + ds * ds;
-  const double B = 4.0 * s[i] * s[j];
+  double A, B;
+  convreal::chord_constants(Z[i], Z[j], s[i], s[j], q, &A, &B);
   const int nj = rn[j];
   const double s2 = (dcut2 - A) / B;
   double hw;
