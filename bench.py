@@ -50,8 +50,11 @@ def parse():
 
 def make_map(w, nmaps):
     import synth
-    dt = np.float64 if w.dtype == "f64" else np.float32
-    return synth.white_noise(w.nside, nmaps, seed=w.seed, dtype=dt), "white N(0,1)"
+    desc = {"white": "white N(0,1)",
+            "red": f"Gaussian random field C_l = 1/(l(l+1)), 2 <= l <= {w.map_lmax}",
+            "red+noise": f"Gaussian random field C_l = 1/(l(l+1)), 2 <= l <= {w.map_lmax}, "
+                         f"plus white noise of {w.noise_frac:g} x the field's rms"}[w.map_kind]
+    return synth.workload_maps(w, nmaps), desc
 
 
 def time_applies(plan, x, y, steps, warmup, stream):
@@ -84,7 +87,7 @@ def kernel_table(plan, x, y, reps, stream):
 
 
 def roofline_for(name, ms, pairs):
-    if "mfma" in name:
+    if "mfma" in name or "persistent" in name:
         achieved = 2.0 * pairs / (ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP16_MFMA_TFLOPS, "traffic": None, "kernel": name, "kernel_ms": ms,

@@ -138,6 +138,59 @@ int conv_real_pairs(const conv_real_plan* plan, long long* pairs);
 int conv_real_profile(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps,
                       void* stream, const char** names, float* ms, long long* work, int* nstages);
 
+/*
+ * Launch configuration of the mixed path (CONV_REAL_MIXED). All of a mixed apply's pair sums run
+ * in one persistent kernel that drains a work queue of belt items (a band of 16 output rings x
+ * `seg` output pixels, matrix-core bound) and cap items (64 output pixels with their 16 symmetric
+ * images each, bound by on-the-fly weight evaluation).
+ *   seg        belt output pixels per work item: 256 or 512
+ *   wg_per_cu  resident workgroups per compute unit (persistent grid = CUs x wg_per_cu): 1..4
+ *   order      0: items by decreasing estimated cost; 1: belt and cap items alternating
+ */
+typedef struct conv_real_tuning {
+  int seg;
+  int wg_per_cu;
+  int order;
+} conv_real_tuning;
+
+/* conv_real_set_tuning / conv_real_get_tuning - set or read a mixed plan's launch configuration
+ * (EINVAL for other precisions or out-of-range fields). Synchronous; not while an apply on the
+ * plan may still be running. */
+int conv_real_set_tuning(conv_real_plan* plan, const conv_real_tuning* t);
+int conv_real_get_tuning(const conv_real_plan* plan, conv_real_tuning* t);
+
+/*
+ * conv_real_autotune - time every launch configuration on the caller's maps (each configuration
+ * once warm, then three timed applies with HIP events on `stream`), keep the fastest on the plan
+ * and return it in *best. Same map arguments as conv_real_apply; maps_out is overwritten.
+ * Synchronous. Mixed plans only.
+ */
+int conv_real_autotune(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps, void* stream,
+                       conv_real_tuning* best);
+
+/*
+ * Batches: maps of different grids and kernels (each with its own mixed plan) in one persistent
+ * launch, so that small maps fill the GPU alongside large ones.
+ *
+ * conv_real_batch_create - count (1..64) mixed plans on the current device; the batch keeps the
+ *   plan pointers (the plans must outlive it) and builds one cost-sorted work queue.
+ * conv_real_batch_apply - maps_in[k], maps_out[k]: host arrays of device pointers, one FP32 map of
+ *   plan k each (12 nside_k^2 values); no overlaps between any input and output. Asynchronous on
+ *   stream, no allocation, no host synchronisation (capturable in a HIP graph).
+ * conv_real_batch_set_tuning / conv_real_batch_autotune - as for plans.
+ * conv_real_batch_pairs - total pixel pairs of one batch apply.
+ * conv_real_batch_destroy - free the batch (not its plans). NULL is accepted.
+ */
+typedef struct conv_real_batch conv_real_batch;
+int conv_real_batch_create(conv_real_batch** batch, conv_real_plan* const* plans, int count);
+int conv_real_batch_apply(conv_real_batch* batch, const float* const* maps_in, float* const* maps_out,
+                          void* stream);
+int conv_real_batch_set_tuning(conv_real_batch* batch, const conv_real_tuning* t);
+int conv_real_batch_autotune(conv_real_batch* batch, const float* const* maps_in, float* const* maps_out,
+                             void* stream, conv_real_tuning* best);
+int conv_real_batch_pairs(const conv_real_batch* batch, long long* pairs);
+int conv_real_batch_destroy(conv_real_batch* batch);
+
 /* conv_real_destroy - free a plan and its device memory. NULL is accepted. */
 int conv_real_destroy(conv_real_plan* plan);
 

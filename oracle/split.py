@@ -1,0 +1,131 @@
+"""Kernel splitting: error estimate, weighted least-squares split, cost model, split search (oracle).
+
+Test infrastructure (see the package docstring). Follows the paper's Estimating Errors section:
+
+* Eq. 1   K~_l = K^_l + P_{l theta} K^_theta: the approximate kernel is the truncated harmonic part
+          (l <= l_cut) plus the Legendre transform of the truncated real-space part.
+* Eq. 2   sigma_rms^2 = (1 / 4 pi) sum_{l=0}^{lmax} (K_l - K~_l)^2 C_l^in (2l + 1).
+* Eq. 3-5 A^T W A x = A^T W K_l with x = [K^_l (l <= l_cut); K^_theta (z_cut samples)],
+          A = [delta_{l,j} for the harmonic columns | P_{l,k} for the real-space columns],
+          W = diag((2l + 1) C_l^in), solved by SVD dropping singular values below 1e-6.
+* Eq. 6   sigma^2 = alpha^2 sigma_rms^2 / ((1 / 4 pi) sum (2l + 1) K_l^2).
+* Eq. 7-8 cost models (the paper's GTX 480 / one-core fits, seconds, theta_cut in arcmin).
+* Search  linear scan over theta_cut; for each, binary search for the smallest l_cut meeting the
+          error bound; keep the cheapest pair, the wall time being that of the slower of the two
+          convolutions that run in parallel (Fig. 1).
+
+Readings (the paper is silent or garbled on these):
+* the Legendre operator acts on the real-space kernel sampled at Gauss-Legendre nodes of an
+  (lmax + 1)-point rule: P_{l,k} = 2 pi w_k P_l(z_k), for the nodes with z_k > cos(theta_cut)
+  (their count is z_cut; the printed definition "lmax - l_cos(theta_cut)" is garbled);
+* A has lmax + 1 rows (l = 0..lmax, as in the sums of Eqs. 2 and 6) and l_cut + 1 harmonic columns;
+* W includes C_l^in (the printed W omits it; identical for the flat C_l^in = 1 the paper uses);
+* the singular-value cutoff is relative to the largest singular value.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import kernel
+
+
+def gauss_legendre(lmax: int):
+    """Nodes and weights of the (lmax + 1)-point Gauss-Legendre rule on [-1, 1]."""
+    return np.polynomial.legendre.leggauss(lmax + 1)
+
+
+def real_space_nodes(lmax: int, theta_cut: float):
+    """The Gauss-Legendre nodes inside the cut (z > cos theta_cut) and their weights."""
+    z, w = gauss_legendre(lmax)
+    sel = z > math.cos(theta_cut)
+    return z[sel], w[sel]
+
+
+def legendre_operator(lmax: int, z: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """P_{l,k} = 2 pi w_k P_l(z_k), shape [lmax + 1, len(z)]."""
+    return 2.0 * math.pi * kernel.legendre_p(lmax, z) * w[None, :]
+
+
+def design_matrix(lmax: int, ell_cut: int, theta_cut: float):
+    """A of Eq. 5: identity block for l <= l_cut, Legendre operator for the real-space samples."""
+    z, w = real_space_nodes(lmax, theta_cut)
+    P = legendre_operator(lmax, z, w)
+    A = np.zeros((lmax + 1, ell_cut + 1 + len(z)))
+    A[: ell_cut + 1, : ell_cut + 1] = np.eye(ell_cut + 1)
+    A[:, ell_cut + 1:] = P
+    return A, z, w
+
+
+def lsq_split(K_ell: np.ndarray, C_in: np.ndarray, ell_cut: int, theta_cut: float,
+              sv_cut: float = 1e-6):
+    """Solve A^T W A x = A^T W K (Eq. 3) by SVD, dropping singular values below sv_cut times the
+    largest. Returns (K_hat_ell, K_hat_theta, z_nodes, K_tilde_ell)."""
+    lmax = len(K_ell) - 1
+    A, z, w = design_matrix(lmax, ell_cut, theta_cut)
+    Wd = (2.0 * np.arange(lmax + 1) + 1.0) * C_in
+    M = A.T @ (Wd[:, None] * A)
+    rhs = A.T @ (Wd * K_ell)
+    U, s, Vt = np.linalg.svd(M)
+    keep = s >= sv_cut * s[0]
+    x = Vt[keep].T @ ((U[:, keep].T @ rhs) / s[keep])
+    K_tilde = A @ x
+    return x[: ell_cut + 1], x[ell_cut + 1:], z, K_tilde
+
+
+def rms_error(K_ell, K_tilde, C_in) -> float:
+    """sigma_rms of Eq. 2."""
+    ell = np.arange(len(K_ell))
+    return math.sqrt(np.sum((K_ell - K_tilde) ** 2 * C_in * (2 * ell + 1)) / (4.0 * math.pi))
+
+
+def fractional_error(K_ell, K_tilde, C_in, alpha: float = 5.0) -> float:
+    """sigma of Eq. 6."""
+    ell = np.arange(len(K_ell))
+    norm = np.sum((2 * ell + 1) * K_ell ** 2) / (4.0 * math.pi)
+    return alpha * rms_error(K_ell, K_tilde, C_in) / math.sqrt(norm)
+
+
+def cost_gpu_paper(theta_cut_arcmin: float) -> float:
+    """Eq. 7: real-space GPU convolution, seconds (GTX 480, Nside 2048, lmax 4096)."""
+    return 0.0232 * theta_cut_arcmin + 2.428
+
+
+def cost_cpu_paper(ell_cut: float, lmax: int = 4096) -> float:
+    """Eq. 8: harmonic-space convolution on one CPU core, seconds."""
+    return 160.0 * ell_cut ** 2 * lmax / 4096.0 ** 3
+
+
+def wall_time(t_gpu: float, t_cpu: float) -> float:
+    """The two convolutions run concurrently (Fig. 1): the slower one sets the wall time."""
+    return max(t_gpu, t_cpu)
+
+
+def split_search(K_ell, C_in, bound: float, theta_grid, t_gpu, t_cpu, alpha: float = 5.0,
+                 sv_cut: float = 1e-6):
+    """Scan theta_cut; binary-search the smallest feasible l_cut for each; keep the cheapest.
+    Returns (theta_cut, ell_cut, wall, error) or None if no pair meets the bound."""
+    lmax = len(K_ell) - 1
+
+    def err(lc, tc):
+        _, _, _, kt = lsq_split(K_ell, C_in, lc, tc, sv_cut)
+        return fractional_error(K_ell, kt, C_in, alpha)
+
+    best = None
+    for tc in theta_grid:
+        if err(lmax, tc) > bound:
+            continue
+        lo, hi = 0, lmax
+        if err(lo, tc) <= bound:
+            hi = lo
+        while hi - lo > 1:
+            mid = (lo + hi) // 2
+            if err(mid, tc) <= bound:
+                hi = mid
+            else:
+                lo = mid
+        wall = wall_time(t_gpu(tc), t_cpu(hi))
+        if best is None or wall < best[2]:
+            best = (tc, hi, wall, err(hi, tc))
+    return best

@@ -34,7 +34,18 @@ ENODEV = -5
 
 # Every entry point that include/convreal.h declares.
 EXPORTS = ("conv_real_tabulate", "conv_real_init", "conv_real_apply", "conv_real_pairs",
-           "conv_real_profile", "conv_real_destroy", "conv_real_strerror", "conv_real_last_error")
+           "conv_real_profile", "conv_real_set_tuning", "conv_real_get_tuning", "conv_real_autotune",
+           "conv_real_batch_create", "conv_real_batch_apply", "conv_real_batch_set_tuning",
+           "conv_real_batch_autotune", "conv_real_batch_pairs", "conv_real_batch_destroy",
+           "conv_real_destroy", "conv_real_strerror", "conv_real_last_error")
+
+
+class Tuning(ctypes.Structure):
+    """conv_real_tuning: seg (256|512), wg_per_cu (1..4), order (0|1)."""
+    _fields_ = [("seg", ctypes.c_int), ("wg_per_cu", ctypes.c_int), ("order", ctypes.c_int)]
+
+    def as_dict(self):
+        return {"seg": self.seg, "wg_per_cu": self.wg_per_cu, "order": self.order}
 
 
 class ConvRealError(RuntimeError):
@@ -63,6 +74,21 @@ def _load():
                                       ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(c_int)]
     lib.conv_real_profile.restype = c_int
+    tp = ctypes.POINTER(Tuning)
+    fpp = ctypes.POINTER(c_void_p)
+    lib.conv_real_set_tuning.argtypes = [c_void_p, tp]
+    lib.conv_real_get_tuning.argtypes = [c_void_p, tp]
+    lib.conv_real_autotune.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p, tp]
+    lib.conv_real_batch_create.argtypes = [ctypes.POINTER(c_void_p), fpp, c_int]
+    lib.conv_real_batch_apply.argtypes = [c_void_p, fpp, fpp, c_void_p]
+    lib.conv_real_batch_set_tuning.argtypes = [c_void_p, tp]
+    lib.conv_real_batch_autotune.argtypes = [c_void_p, fpp, fpp, c_void_p, tp]
+    lib.conv_real_batch_pairs.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_longlong)]
+    lib.conv_real_batch_destroy.argtypes = [c_void_p]
+    for name in ("conv_real_set_tuning", "conv_real_get_tuning", "conv_real_autotune", "conv_real_batch_create",
+                 "conv_real_batch_apply", "conv_real_batch_set_tuning", "conv_real_batch_autotune",
+                 "conv_real_batch_pairs", "conv_real_batch_destroy"):
+        getattr(lib, name).restype = c_int
     lib.conv_real_destroy.argtypes = [c_void_p]
     lib.conv_real_destroy.restype = c_int
     lib.conv_real_strerror.argtypes = [c_int]
@@ -176,9 +202,133 @@ class Plan:
                "conv_real_profile")
         return out, [(names[k].decode(), float(ms[k]), int(work[k])) for k in range(n.value)]
 
+    def set_tuning(self, seg: int = 256, wg_per_cu: int = 2, order: int = 0):
+        t = Tuning(seg, wg_per_cu, order)
+        _check(lib.conv_real_set_tuning(self._h, ctypes.byref(t)), "conv_real_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        _check(lib.conv_real_get_tuning(self._h, ctypes.byref(t)), "conv_real_get_tuning")
+        return t.as_dict()
+
+    def autotune(self, x, out=None, stream=None, cache: str | None = None) -> dict:
+        """Fastest launch configuration for maps like x (timed by the library), kept on the plan.
+        With `cache`, a JSON file keyed by (nside, theta_cut, precision, nmaps bucket) is read
+        first and updated after a search."""
+        out, nmaps = self._check_maps(x, out)
+        key = f"{self.nside}|{self.theta_cut:.6g}|{self.precision}|{1 if nmaps == 1 else 2 ** (nmaps - 1).bit_length()}"
+        if cache is not None:
+            found = _cache_get(cache, key)
+            if found is not None:
+                self.set_tuning(**found)
+                return found
+        t = Tuning()
+        _check(lib.conv_real_autotune(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                      int(nmaps), _stream_handle(stream), ctypes.byref(t)), "conv_real_autotune")
+        if cache is not None:
+            _cache_put(cache, key, t.as_dict())
+        return t.as_dict()
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib.conv_real_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _cache_get(path, key):
+    import json
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        t = data.get(key)
+        if isinstance(t, dict) and set(t) == {"seg", "wg_per_cu", "order"}:
+            return {k: int(v) for k, v in t.items()}
+    except (OSError, ValueError):
+        pass                                     # missing or corrupt cache: search again
+    return None
+
+
+def _cache_put(path, key, value):
+    import json
+    import os
+    data = {}
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        if not isinstance(data, dict):
+            data = {}
+    except (OSError, ValueError):
+        data = {}
+    data[key] = value
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+class Batch:
+    """Maps of different grids and kernels (one mixed plan each) in one persistent launch."""
+
+    def __init__(self, plans):
+        if not plans or len(plans) > 64:
+            raise ValueError("need 1..64 plans")
+        self.plans = list(plans)                 # keeps the plans alive
+        arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+        h = ctypes.c_void_p()
+        _check(lib.conv_real_batch_create(ctypes.byref(h), arr, len(plans)), "conv_real_batch_create")
+        self._h = h
+
+    def _ptrs(self, xs, outs):
+        import torch
+        if len(xs) != len(self.plans):
+            raise ValueError("one map per plan")
+        if outs is None:
+            outs = [torch.empty_like(x) for x in xs]
+        for p, x, o in zip(self.plans, xs, outs):
+            if not (x.is_cuda and o.is_cuda and x.dtype == torch.float32 and o.dtype == torch.float32):
+                raise TypeError("maps must be float32 CUDA tensors")
+            if x.numel() != p.npix or o.numel() != p.npix or not x.is_contiguous() or not o.is_contiguous():
+                raise ValueError("map k must hold 12 nside_k^2 contiguous values")
+        pin = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        pout = (ctypes.c_void_p * len(xs))(*[o.data_ptr() for o in outs])
+        return outs, pin, pout
+
+    def apply(self, xs, outs=None, stream=None):
+        outs, pin, pout = self._ptrs(xs, outs)
+        _check(lib.conv_real_batch_apply(self._h, pin, pout, _stream_handle(stream)), "conv_real_batch_apply")
+        return outs
+
+    def pairs(self) -> int:
+        n = ctypes.c_longlong()
+        _check(lib.conv_real_batch_pairs(self._h, ctypes.byref(n)), "conv_real_batch_pairs")
+        return int(n.value)
+
+    def set_tuning(self, seg: int = 256, wg_per_cu: int = 2, order: int = 0):
+        t = Tuning(seg, wg_per_cu, order)
+        _check(lib.conv_real_batch_set_tuning(self._h, ctypes.byref(t)), "conv_real_batch_set_tuning")
+
+    def autotune(self, xs, outs=None, stream=None) -> dict:
+        outs, pin, pout = self._ptrs(xs, outs)
+        t = Tuning()
+        _check(lib.conv_real_batch_autotune(self._h, pin, pout, _stream_handle(stream), ctypes.byref(t)),
+               "conv_real_batch_autotune")
+        return t.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.conv_real_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -107,6 +107,7 @@ bool finite_all(const double* v, long long n) {
 
 int hip_fail(hipError_t e, const char* what) {
   set_error(std::string(what) + ": " + hipGetErrorString(e));
+  (void)hipGetLastError();  // clear the runtime's sticky error so that later calls are not blamed
   return e == hipErrorOutOfMemory ? CONV_REAL_ENOMEM : CONV_REAL_EHIP;
 }
 
@@ -171,6 +172,60 @@ struct DeviceGuard {
   }
 };
 
+// Work items of one map for the persistent kernel, in the order the tuning asks for. An item is
+// (slot, kind << 30 | index): kind 0 = belt (band x pixel segment), kind 1 = cap (4 tiles).
+struct QueueItem {
+  double cost;
+  int kind;
+  int idx;
+};
+
+std::vector<QueueItem> queue_of(const conv_real_plan* p, const convreal::Tuning& t) {
+  std::vector<QueueItem> belt, cap, out;
+  if (p->belt_enabled) {
+    const int nsegs = (4 * p->nside + t.seg - 1) / t.seg;
+    for (int b = 0; b < p->belt_nbands; ++b)
+      for (int s = 0; s < nsegs; ++s) belt.push_back({p->cost_belt[b] * (t.seg / 64), 0, b * nsegs + s});
+  }
+  if (p->cap_mode)
+    for (int k = 0; k < static_cast<int>(p->cost_cap.size()); ++k) cap.push_back({p->cost_cap[k], 1, k});
+  auto desc = [](const QueueItem& a, const QueueItem& b) { return a.cost > b.cost; };
+  std::stable_sort(belt.begin(), belt.end(), desc);
+  std::stable_sort(cap.begin(), cap.end(), desc);
+  if (t.order == 1) {
+    size_t i = 0, j = 0;
+    while (i < belt.size() || j < cap.size()) {
+      if (i < belt.size()) out.push_back(belt[i++]);
+      if (j < cap.size()) out.push_back(cap[j++]);
+    }
+  } else {
+    out = belt;
+    out.insert(out.end(), cap.begin(), cap.end());
+    std::stable_sort(out.begin(), out.end(), desc);
+  }
+  return out;
+}
+
+void release(conv_real_plan* p, void* ptr) {
+  if (!ptr) return;
+  for (auto it = p->owned.begin(); it != p->owned.end(); ++it)
+    if (*it == ptr) {
+      (void)hipFree(ptr);
+      p->owned.erase(it);
+      return;
+    }
+}
+
+hipError_t build_items(conv_real_plan* p) {
+  const std::vector<QueueItem> q = queue_of(p, p->tune);
+  std::vector<int2> items(q.size());
+  for (size_t k = 0; k < q.size(); ++k) items[k] = make_int2(0, (q[k].kind << 30) | q[k].idx);
+  release(p, p->d_items);
+  p->d_items = nullptr;
+  p->n_items = static_cast<int>(items.size());
+  return dev_upload(p, &p->d_items, items);
+}
+
 // Mixed path set-up: belt bands, window width, split-FP16 weight blocks, and the list of ring
 // pairs left to the per-pair kernel (every pair touching a polar cap).
 hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std::vector<int>& jlo,
@@ -231,6 +286,17 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
   }
   p->belt_enabled = ok ? 1 : 0;
 
+  // weight scale: power of two with Omega * max|T| * s_w < 2^12 (interpolation overshoot stays
+  // far below the FP16 maximum)
+  std::vector<double> tab(p->n_tab);
+  if ((e = hipMemcpy(tab.data(), p->d_table, sizeof(double) * p->n_tab, hipMemcpyDeviceToHost)) != hipSuccess)
+    return e;
+  double tmax = 0.0;
+  for (double v : tab) tmax = std::max(tmax, std::fabs(v));
+  int ex = 0;
+  std::frexp(std::max(tmax * p->omega, 1e-300), &ex);
+  p->belt_sw = std::ldexp(1.0, 12 - ex);
+
   if (p->belt_enabled) {
     p->belt_lo = blo;
     p->belt_hi = bhi;
@@ -239,16 +305,6 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
     p->belt_nsegs = (4 * N + 255) / 256;
     p->n_wblk = static_cast<long long>(blk_nk.size());
     p->n_chunks = static_cast<long long>(chunk_band.size());
-    // weight scale: power of two with Omega * max|T| * s_w < 2^12 (interpolation overshoot stays
-    // far below the FP16 maximum)
-    double tmax = 0.0;
-    std::vector<double> tab(p->n_tab);
-    if ((e = hipMemcpy(tab.data(), p->d_table, sizeof(double) * p->n_tab, hipMemcpyDeviceToHost)) != hipSuccess)
-      return e;
-    for (double v : tab) tmax = std::max(tmax, std::fabs(v));
-    int ex = 0;
-    std::frexp(std::max(tmax * p->omega, 1e-300), &ex);
-    p->belt_sw = std::ldexp(1.0, 12 - ex);
     if ((e = dev_upload(p, &p->d_band_jf, band_jf)) != hipSuccess ||
         (e = dev_upload(p, &p->d_band_nj, band_nj)) != hipSuccess ||
         (e = dev_upload(p, &p->d_band_woff, band_woff)) != hipSuccess ||
@@ -286,7 +342,118 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
       (e = dev_upload(p, &p->d_rtile_ring, rtile_ring)) != hipSuccess ||
       (e = dev_upload(p, &p->d_rtile_a0, rtile_a0)) != hipSuccess)
     return e;
-  return hipSuccess;
+
+  // Cap-touching pairs on the matrix cores when the coefficient table fits in 64 KB of LDS.
+  p->cap_mode = (p->n_tab - 2) * 16 <= 65536 ? 1 : 0;
+  std::vector<int> ring_add(g.nrings, 0);
+  std::vector<int> citem_ring, citem_a0;
+  if (p->cap_mode) {
+    // 4-point Lagrange interpolant of segment k (nodes k-1..k+2, ghost T[-1] = T[1]) in the
+    // monomial basis of the local coordinate f, scaled by Omega s_w.
+    const int nseg = p->n_tab - 2;
+    std::vector<float> coef(4 * static_cast<size_t>(nseg));
+    const double sc = p->omega * p->belt_sw;
+    for (int k = 0; k < nseg; ++k) {
+      const double tm1 = tab[k == 0 ? 1 : k - 1], t0 = tab[k], t1 = tab[k + 1], t2 = tab[k + 2];
+      coef[4 * k + 0] = static_cast<float>(sc * t0);
+      coef[4 * k + 1] = static_cast<float>(sc * (-tm1 / 3.0 - t0 / 2.0 + t1 - t2 / 6.0));
+      coef[4 * k + 2] = static_cast<float>(sc * (tm1 / 2.0 - t0 + t1 / 2.0));
+      coef[4 * k + 3] = static_cast<float>(sc * (-tm1 / 6.0 + t0 / 2.0 - t1 / 2.0 + t2 / 6.0));
+    }
+    // work items: 16-pixel tiles of the symmetry group's fundamental domain [0, F) of every
+    // north-half output ring that has cap-touching pairs (its mirror ring is produced alongside)
+    std::vector<double> ring_cost(g.nrings, 0.0);
+    for (int r = 0; r <= (g.nrings - 1) / 2; ++r) {
+      if (roff[r + 1] == roff[r]) continue;
+      const int F = (g.n[r] / 4 - g.c[r]) / 2 + 1;
+      for (int a0 = 0; a0 < F; a0 += 16) {
+        citem_ring.push_back(r);
+        citem_a0.push_back(a0);
+      }
+      // estimated cycles of one tile: per neighbour ring, K-chunks x (weights + inputs) work
+      double c = 0.0;
+      for (long long kk = roff[r]; kk < roff[r + 1]; ++kk) {
+        const long long k = ridx[kk];
+        const int nj = g.n[pj[k]];
+        const double K = std::min(static_cast<double>(nj) + 16.0 * nj / g.n[r], 16.0 * nj / g.n[r] + 2.0 * hw[k] + 2.0);
+        c += std::ceil(K / 32.0) * 1200.0 + 150.0;
+      }
+      ring_cost[r] = c;
+    }
+    for (int r = 0; r < g.nrings; ++r)
+      ring_add[r] = (p->belt_enabled && r >= blo && r <= bhi && roff[r + 1] > roff[r]) ? 1 : 0;
+    p->n_citems = static_cast<int>(citem_ring.size());
+    p->cap_nseg = nseg;
+    p->cost_cap.clear();
+    for (int t = 0; t < p->n_citems; t += 4) {
+      double c = 0.0;
+      for (int u = t; u < std::min(t + 4, p->n_citems); ++u) c = std::max(c, ring_cost[citem_ring[u]]);
+      p->cost_cap.push_back(c);
+    }
+    if ((e = dev_upload(p, &p->d_coef, coef)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_citem_ring, citem_ring)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_citem_a0, citem_a0)) != hipSuccess)
+      return e;
+  }
+  if ((e = dev_upload(p, &p->d_ring_add, ring_add)) != hipSuccess) return e;
+
+  // belt band costs: per 16-pixel column block, K-chunks x 3 products x 16 cycles plus staging
+  p->cost_belt.assign(p->belt_enabled ? p->belt_nbands : 0, 0.0);
+  for (int b = 0; b < static_cast<int>(p->cost_belt.size()); ++b) {
+    double c = 0.0;
+    for (int jj = 0; jj < band_nj[b]; ++jj) c += blk_nk[band_woff[b] + jj] * 48.0 + 12.0;
+    p->cost_belt[b] = c;
+  }
+
+  // rows receiving both contributions: one contiguous run of rings in each hemisphere
+  convreal::MixedDesc d{};
+  d.zero_lo[0] = d.zero_hi[0] = d.zero_lo[1] = d.zero_hi[1] = 0;
+  int half = 0;
+  for (int r = 0; r < g.nrings && half < 2; ++r) {
+    if (!ring_add[r]) continue;
+    int r1 = r;
+    while (r1 + 1 < g.nrings && ring_add[r1 + 1]) ++r1;
+    d.zero_lo[half] = g.start[r];
+    d.zero_hi[half] = g.start[r1] + g.n[r1];
+    ++half;
+    r = r1;
+  }
+  d.rn = p->d_rn;
+  d.rc = p->d_rc;
+  d.rstart = p->d_rstart;
+  d.nrings = g.nrings;
+  d.ring_n = 4 * N;
+  d.npix = p->npix;
+  d.wt = p->d_wt;
+  d.band_jf = p->d_band_jf;
+  d.band_nj = p->d_band_nj;
+  d.band_woff = p->d_band_woff;
+  d.blk_koff = p->d_blk_koff;
+  d.blk_nk = p->d_blk_nk;
+  d.blk_mlo = p->d_blk_mlo;
+  d.belt_lo = p->belt_lo;
+  d.belt_hi = p->belt_hi;
+  d.ring_add = p->d_ring_add;
+  d.coef = p->d_coef;
+  d.nseg = p->cap_nseg;
+  d.n_citems = p->n_citems;
+  d.citem_ring = p->d_citem_ring;
+  d.citem_a0 = p->d_citem_a0;
+  d.rest_off = p->d_rest_off;
+  d.rest_idx = p->d_rest_idx;
+  d.pj = p->d_pj;
+  d.pA = p->d_pA;
+  d.pB = p->d_pB;
+  d.phw = p->d_phw;
+  d.inv_h = p->inv_h;
+  d.dcut2 = p->dcut2;
+  d.inv_sw = static_cast<float>(1.0 / p->belt_sw);
+  std::vector<convreal::MixedDesc> dv(1, d);
+  if ((e = dev_upload(p, &p->d_desc, dv)) != hipSuccess ||
+      (e = dev_alloc(p, &p->d_counter, 1)) != hipSuccess ||
+      (e = convreal::set_lds_limits(p->cap_nseg)) != hipSuccess)
+    return e;
+  return build_items(p);
 }
 
 }  // namespace
@@ -350,8 +517,8 @@ int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_
   p->theta_cut = theta_cut;
   p->dcut = 2.0 * std::sin(0.5 * theta_cut);
   // A cut of pi keeps every pair: no chord exceeds 2, and antipodal pairs must not be lost to
-  // rounding of d^2 at the tie d = d_cut = 2.
-  p->dcut2 = theta_cut >= M_PI ? 4.0 * (1.0 + 1e-12) : p->dcut * p->dcut;
+  // rounding of d^2 (or the sin^2 polynomial of the mixed path) at the tie d = d_cut = 2.
+  p->dcut2 = theta_cut >= M_PI ? 4.0 * (1.0 + 1e-9) : p->dcut * p->dcut;
   p->h = p->dcut / (n_tab - 3);
   p->inv_h = 1.0 / p->h;
   p->npix = 12LL * nside * nside;
@@ -528,6 +695,291 @@ int conv_real_destroy(conv_real_plan* plan) {
   DeviceGuard guard;
   (void)guard.enter(plan->device);
   free_plan(plan);
+  return CONV_REAL_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ tuning, autotune, batches
+struct conv_real_batch {
+  int magic = 0;
+  int device = 0;
+  int count = 0;
+  conv_real_plan* plans[convreal::kMaxSlots] = {};
+  convreal::Tuning tune;
+  int2* d_items = nullptr;
+  int n_items = 0;
+  unsigned* d_amax = nullptr;
+  unsigned* d_counter = nullptr;
+  int max_nseg = 0;
+  long long npix_max = 0;
+  long long pairs = 0;
+};
+
+namespace {
+
+constexpr int kBatchMagic = 0x43564231;  // "CVB1"
+
+bool tuning_ok(const conv_real_tuning* t) {
+  return t && (t->seg == 256 || t->seg == 512) && t->wg_per_cu >= 1 && t->wg_per_cu <= 4 &&
+         (t->order == 0 || t->order == 1);
+}
+
+convreal::Tuning to_internal(const conv_real_tuning* t) {
+  convreal::Tuning r;
+  r.seg = t->seg;
+  r.wg_per_cu = t->wg_per_cu;
+  r.order = t->order;
+  return r;
+}
+
+void to_public(const convreal::Tuning& r, conv_real_tuning* t) {
+  t->seg = r.seg;
+  t->wg_per_cu = r.wg_per_cu;
+  t->order = r.order;
+}
+
+std::vector<conv_real_tuning> candidate_tunings() {
+  std::vector<conv_real_tuning> c;
+  for (int seg : {256, 512})
+    for (int wg : {1, 2, 3})
+      for (int order : {0, 1}) c.push_back({seg, wg, order});
+  return c;
+}
+
+hipError_t build_batch_items(conv_real_batch* b) {
+  std::vector<std::pair<QueueItem, int>> all;
+  std::vector<QueueItem> belt, cap;
+  for (int k = 0; k < b->count; ++k)
+    for (const QueueItem& q : queue_of(b->plans[k], b->tune)) all.push_back({q, k});
+  auto desc = [](const std::pair<QueueItem, int>& x, const std::pair<QueueItem, int>& y) {
+    return x.first.cost > y.first.cost;
+  };
+  std::stable_sort(all.begin(), all.end(), desc);
+  std::vector<std::pair<QueueItem, int>> ordered;
+  if (b->tune.order == 1) {
+    std::vector<std::pair<QueueItem, int>> bl, cp;
+    for (auto& e : all) (e.first.kind == 0 ? bl : cp).push_back(e);
+    size_t i = 0, j = 0;
+    while (i < bl.size() || j < cp.size()) {
+      if (i < bl.size()) ordered.push_back(bl[i++]);
+      if (j < cp.size()) ordered.push_back(cp[j++]);
+    }
+  } else {
+    ordered = all;
+  }
+  std::vector<int2> items(ordered.size());
+  for (size_t k = 0; k < ordered.size(); ++k)
+    items[k] = make_int2(ordered[k].second, (ordered[k].first.kind << 30) | ordered[k].first.idx);
+  if (b->d_items) (void)hipFree(b->d_items);
+  b->d_items = nullptr;
+  b->n_items = static_cast<int>(items.size());
+  hipError_t e = hipMalloc(&b->d_items, sizeof(int2) * std::max<size_t>(items.size(), 1));
+  if (e != hipSuccess) return e;
+  if (!items.empty()) e = hipMemcpy(b->d_items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+hipError_t batch_launch(conv_real_batch* b, const float* const* in, float* const* out, hipStream_t st) {
+  convreal::Slots S;
+  for (int k = 0; k < b->count; ++k) {
+    S.desc[k] = b->plans[k]->d_desc;
+    S.x[k] = in[k];
+    S.y[k] = out[k];
+  }
+  return convreal::launch_mixed_queue(b->plans[0], S, b->count, b->d_items, b->n_items, 1, b->d_amax, b->d_counter,
+                                      b->tune, b->max_nseg, b->npix_max, b->pairs, st);
+}
+
+// Mean milliseconds of `reps` runs of fn() on st, after one untimed run.
+template <typename F>
+int time_runs(F fn, hipStream_t st, int reps, float* ms_out) {
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return hip_fail(e, "autotune: hipEventCreate");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "autotune: hipEventCreate");
+  }
+  int rc = fn();
+  if (rc == CONV_REAL_OK && (e = hipEventRecord(e0, st)) != hipSuccess) rc = hip_fail(e, "autotune: record");
+  for (int r = 0; r < reps && rc == CONV_REAL_OK; ++r) rc = fn();
+  if (rc == CONV_REAL_OK && (e = hipEventRecord(e1, st)) != hipSuccess) rc = hip_fail(e, "autotune: record");
+  if (rc == CONV_REAL_OK && (e = hipEventSynchronize(e1)) != hipSuccess) rc = hip_fail(e, "autotune: sync");
+  float ms = 0.0f;
+  if (rc == CONV_REAL_OK && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) rc = hip_fail(e, "autotune: elapsed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_out = ms / reps;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int conv_real_set_tuning(conv_real_plan* plan, const conv_real_tuning* t) {
+  if (!plan || plan->magic != kMagic) { set_error("conv_real_set_tuning: invalid plan"); return CONV_REAL_EINVAL; }
+  if (plan->precision != CONV_REAL_MIXED) { set_error("conv_real_set_tuning: mixed plans only"); return CONV_REAL_EINVAL; }
+  if (!tuning_ok(t)) { set_error("conv_real_set_tuning: field out of range"); return CONV_REAL_EINVAL; }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_set_tuning: hipSetDevice");
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "conv_real_set_tuning: sync");
+  plan->tune = to_internal(t);
+  if ((e = build_items(plan)) != hipSuccess) return hip_fail(e, "conv_real_set_tuning: work queue");
+  return CONV_REAL_OK;
+}
+
+int conv_real_get_tuning(const conv_real_plan* plan, conv_real_tuning* t) {
+  if (!plan || plan->magic != kMagic || !t) { set_error("conv_real_get_tuning: invalid argument"); return CONV_REAL_EINVAL; }
+  to_public(plan->tune, t);
+  return CONV_REAL_OK;
+}
+
+int conv_real_autotune(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps, void* stream,
+                       conv_real_tuning* best) {
+  if (!plan || plan->magic != kMagic || !best) { set_error("conv_real_autotune: invalid argument"); return CONV_REAL_EINVAL; }
+  if (plan->precision != CONV_REAL_MIXED) { set_error("conv_real_autotune: mixed plans only"); return CONV_REAL_EINVAL; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float best_ms = 1e30f;
+  conv_real_tuning chosen;
+  to_public(plan->tune, &chosen);
+  for (const conv_real_tuning& c : candidate_tunings()) {
+    int rc = conv_real_set_tuning(plan, &c);
+    if (rc != CONV_REAL_OK) return rc;
+    float ms = 0.0f;
+    rc = time_runs([&]() { return conv_real_apply(plan, maps_in, maps_out, nmaps, stream); }, st, 3, &ms);
+    if (rc != CONV_REAL_OK) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
+      chosen = c;
+    }
+  }
+  *best = chosen;
+  return conv_real_set_tuning(plan, &chosen);
+}
+
+int conv_real_batch_create(conv_real_batch** batch, conv_real_plan* const* plans, int count) {
+  if (!batch) { set_error("conv_real_batch_create: NULL batch pointer"); return CONV_REAL_EINVAL; }
+  *batch = nullptr;
+  if (!plans || count < 1 || count > convreal::kMaxSlots) {
+    set_error("conv_real_batch_create: need 1..64 plans");
+    return CONV_REAL_EINVAL;
+  }
+  for (int k = 0; k < count; ++k) {
+    const conv_real_plan* p = plans[k];
+    if (!p || p->magic != kMagic || p->precision != CONV_REAL_MIXED || !p->cap_mode || p->device != plans[0]->device) {
+      set_error("conv_real_batch_create: every plan must be a mixed plan on one device with n_tab <= 4098");
+      return CONV_REAL_EINVAL;
+    }
+  }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plans[0]->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_batch_create: hipSetDevice");
+  auto* b = new (std::nothrow) conv_real_batch();
+  if (!b) { set_error("conv_real_batch_create: host allocation failed"); return CONV_REAL_ENOMEM; }
+  b->magic = kBatchMagic;
+  b->device = plans[0]->device;
+  b->count = count;
+  for (int k = 0; k < count; ++k) {
+    b->plans[k] = plans[k];
+    b->max_nseg = std::max(b->max_nseg, plans[k]->cap_nseg);
+    b->npix_max = std::max(b->npix_max, plans[k]->npix);
+    b->pairs += plans[k]->pairs;
+  }
+  if ((e = hipMalloc(&b->d_amax, sizeof(unsigned) * convreal::kMaxSlots)) != hipSuccess ||
+      (e = hipMalloc(&b->d_counter, sizeof(unsigned))) != hipSuccess ||
+      (e = build_batch_items(b)) != hipSuccess) {
+    const int rc = hip_fail(e, "conv_real_batch_create");
+    if (b->d_amax) (void)hipFree(b->d_amax);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    if (b->d_items) (void)hipFree(b->d_items);
+    delete b;
+    return rc;
+  }
+  *batch = b;
+  return CONV_REAL_OK;
+}
+
+int conv_real_batch_apply(conv_real_batch* batch, const float* const* maps_in, float* const* maps_out, void* stream) {
+  if (!batch || batch->magic != kBatchMagic) { set_error("conv_real_batch_apply: invalid batch"); return CONV_REAL_EINVAL; }
+  if (!maps_in || !maps_out) { set_error("conv_real_batch_apply: NULL map arrays"); return CONV_REAL_EINVAL; }
+  for (int k = 0; k < batch->count; ++k) {
+    if (!maps_in[k] || !maps_out[k]) { set_error("conv_real_batch_apply: NULL map pointer"); return CONV_REAL_EINVAL; }
+  }
+  for (int k = 0; k < batch->count; ++k) {
+    const char* o0 = reinterpret_cast<const char*>(maps_out[k]);
+    const char* o1 = o0 + sizeof(float) * batch->plans[k]->npix;
+    for (int m = 0; m < batch->count; ++m) {
+      const char* i0 = reinterpret_cast<const char*>(maps_in[m]);
+      const char* i1 = i0 + sizeof(float) * batch->plans[m]->npix;
+      if (i0 < o1 && o0 < i1) { set_error("conv_real_batch_apply: an output overlaps an input"); return CONV_REAL_EALIAS; }
+      if (m != k) {
+        const char* p0 = reinterpret_cast<const char*>(maps_out[m]);
+        const char* p1 = p0 + sizeof(float) * batch->plans[m]->npix;
+        if (p0 < o1 && o0 < p1) { set_error("conv_real_batch_apply: outputs overlap"); return CONV_REAL_EALIAS; }
+      }
+    }
+  }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(batch->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_batch_apply: hipSetDevice");
+  if ((e = batch_launch(batch, maps_in, maps_out, static_cast<hipStream_t>(stream))) != hipSuccess)
+    return hip_fail(e, "conv_real_batch_apply: launch");
+  return CONV_REAL_OK;
+}
+
+int conv_real_batch_set_tuning(conv_real_batch* batch, const conv_real_tuning* t) {
+  if (!batch || batch->magic != kBatchMagic) { set_error("conv_real_batch_set_tuning: invalid batch"); return CONV_REAL_EINVAL; }
+  if (!tuning_ok(t)) { set_error("conv_real_batch_set_tuning: field out of range"); return CONV_REAL_EINVAL; }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(batch->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_batch_set_tuning: hipSetDevice");
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "conv_real_batch_set_tuning: sync");
+  batch->tune = to_internal(t);
+  if ((e = build_batch_items(batch)) != hipSuccess) return hip_fail(e, "conv_real_batch_set_tuning: work queue");
+  return CONV_REAL_OK;
+}
+
+int conv_real_batch_autotune(conv_real_batch* batch, const float* const* maps_in, float* const* maps_out,
+                             void* stream, conv_real_tuning* best) {
+  if (!batch || batch->magic != kBatchMagic || !best) { set_error("conv_real_batch_autotune: invalid argument"); return CONV_REAL_EINVAL; }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float best_ms = 1e30f;
+  conv_real_tuning chosen;
+  to_public(batch->tune, &chosen);
+  for (const conv_real_tuning& c : candidate_tunings()) {
+    int rc = conv_real_batch_set_tuning(batch, &c);
+    if (rc != CONV_REAL_OK) return rc;
+    float ms = 0.0f;
+    rc = time_runs([&]() { return conv_real_batch_apply(batch, maps_in, maps_out, stream); }, st, 3, &ms);
+    if (rc != CONV_REAL_OK) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
+      chosen = c;
+    }
+  }
+  *best = chosen;
+  return conv_real_batch_set_tuning(batch, &chosen);
+}
+
+int conv_real_batch_pairs(const conv_real_batch* batch, long long* pairs) {
+  if (!batch || batch->magic != kBatchMagic || !pairs) { set_error("conv_real_batch_pairs: invalid argument"); return CONV_REAL_EINVAL; }
+  *pairs = batch->pairs;
+  return CONV_REAL_OK;
+}
+
+int conv_real_batch_destroy(conv_real_batch* batch) {
+  if (!batch) return CONV_REAL_OK;
+  if (batch->magic != kBatchMagic) { set_error("conv_real_batch_destroy: invalid batch"); return CONV_REAL_EINVAL; }
+  DeviceGuard guard;
+  (void)guard.enter(batch->device);
+  if (batch->d_items) (void)hipFree(batch->d_items);
+  if (batch->d_amax) (void)hipFree(batch->d_amax);
+  if (batch->d_counter) (void)hipFree(batch->d_counter);
+  batch->magic = 0;
+  delete batch;
   return CONV_REAL_OK;
 }
 

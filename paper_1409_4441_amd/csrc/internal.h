@@ -40,6 +40,61 @@ RingGrid make_ring_grid(int nside);
 // Neighbour ring ranges: ring r sees rings jlo[r]..jhi[r] (0-based, contiguous).
 void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std::vector<int>& jhi);
 
+constexpr int kMaxSlots = 64;  // maps per persistent mixed-path launch
+
+// Everything the mixed path's device routines read about one plan (lives in device memory).
+struct MixedDesc {
+  // geometry
+  const int* rn;
+  const int* rc;
+  const long long* rstart;
+  int nrings;
+  int ring_n;                 // 4N
+  long long npix;
+  // belt ring pairs
+  const _Float16* wt;
+  const int* band_jf;
+  const int* band_nj;
+  const int* band_woff;
+  const int* blk_koff;
+  const int* blk_nk;
+  const int* blk_mlo;
+  int belt_lo;
+  int belt_hi;
+  const int* ring_add;        // per ring: receives a belt and a cap-pair contribution
+  long long zero_lo[2];       // pixel ranges of such rows (zeroed before the launch)
+  long long zero_hi[2];
+  // cap-touching ring pairs
+  const float* coef;          // per segment: 4 FP32 cubic coefficients x Omega x s_w
+  int nseg;
+  int n_citems;
+  const int* citem_ring;
+  const int* citem_a0;
+  const long long* rest_off;
+  const long long* rest_idx;
+  const int* pj;
+  const double* pA;
+  const double* pB;
+  const double* phw;
+  double inv_h;
+  double dcut2;
+  float inv_sw;
+};
+
+// Per-launch map slots of the persistent kernel (passed by value).
+struct Slots {
+  const MixedDesc* desc[kMaxSlots];
+  const float* x[kMaxSlots];
+  float* y[kMaxSlots];
+};
+
+// Launch configuration of the persistent kernel (see conv_real_tuning).
+struct Tuning {
+  int seg = 256;       // belt output pixels per work item: 256 or 512
+  int wg_per_cu = 2;   // resident workgroups per compute unit
+  int order = 0;       // 0: all items by decreasing cost; 1: belt and cap items alternating
+};
+
 // Events recorded between kernels by conv_real_profile.
 struct Recorder {
   static constexpr int kMax = 32;
@@ -116,7 +171,22 @@ struct conv_real_plan {
   int* d_rtile_ring = nullptr;
   int* d_rtile_a0 = nullptr;
   int n_rtiles = 0;
-  long long pairs_rest = 0;    // pixel pairs per map summed by the per-pair remainder kernel
+  long long pairs_rest = 0;    // pixel pairs per map that touch a polar cap
+  // cap-touching ring pairs on the matrix cores (on-the-fly FP32 weights, 16 symmetric images)
+  int cap_mode = 0;            // 1: cap_mfma_kernel; 0: FP64 per-pair remainder kernel
+  float* d_coef = nullptr;     // (n_tab - 2) x 4: per-segment cubic coefficients x Omega x s_w
+  int* d_citem_ring = nullptr; // per work item: output ring (north half)
+  int* d_citem_a0 = nullptr;   // per work item: first pixel of a 16-pixel tile
+  int n_citems = 0;
+  int* d_ring_add = nullptr;   // per ring: 1 if it gets a belt and a cap-pair contribution
+  int cap_nseg = 0;            // coefficient segments (n_tab - 2) if cap_mode
+  convreal::MixedDesc* d_desc = nullptr;  // device copy of the plan's descriptor
+  convreal::Tuning tune;
+  int2* d_items = nullptr;     // work queue of one map (slot 0)
+  int n_items = 0;
+  unsigned* d_counter = nullptr;
+  std::vector<double> cost_belt;   // per belt band: estimated cycles per 16-pixel column block
+  std::vector<double> cost_cap;    // per cap work item (4 tiles): estimated cycles
 
   convreal::Recorder* rec = nullptr;  // set only inside conv_real_profile
   std::vector<void*> owned;    // every device allocation, freed by destroy
@@ -146,6 +216,11 @@ hipError_t launch_pair_accumulate(const conv_real_plan* p, const void* x, void* 
 hipError_t launch_remainder(const conv_real_plan* p, const float* x, float* y, int nmaps,
                             hipStream_t st);
 hipError_t build_belt_weights(conv_real_plan* p);
+size_t belt_stage_bytes(int seg);
+hipError_t set_lds_limits(int nseg);
+hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, int nslots, const int2* items,
+                              int n_items, int nrep, unsigned* amax, unsigned* counter, const Tuning& tune,
+                              int max_nseg, long long npix_max, long long pairs, hipStream_t st);
 hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st);
 hipError_t tabulate_device(const double* k_ell, int lmax, double h, int n_tab, double* table_host);
 

@@ -104,6 +104,125 @@ def draw_alm(cl: np.ndarray, seed: int) -> np.ndarray:
     return out
 
 
+_SHT_LIB = None
+_HERE = __import__("os").path.dirname(__import__("os").path.abspath(__file__))
+SHT_SO = __import__("os").path.join(_HERE, "_sht_synth.so")
+
+
+def build_sht(verbose: bool = False) -> str:
+    """Compile the ring synthesis helper (plain C, OpenMP) next to this file."""
+    import subprocess
+    src = __import__("os").path.join(_HERE, "sht_synth.c")
+    cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-o", SHT_SO + ".tmp", src, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    __import__("os").replace(SHT_SO + ".tmp", SHT_SO)
+    return SHT_SO
+
+
+def _sht():
+    global _SHT_LIB
+    if _SHT_LIB is None:
+        import ctypes
+        import os
+        if not os.path.exists(SHT_SO):
+            build_sht()
+        lib = ctypes.CDLL(SHT_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.synth_ring_pairs.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, dp, dp]
+        lib.synth_ring_pairs.restype = None
+        _SHT_LIB = lib
+    return _SHT_LIB
+
+
+def _ring_layout(nside: int):
+    """Where the pixels of the ring-ordered equal-area grid sit (needed to place a field on them):
+    per ring z, sin(theta), azimuth of its first pixel, pixel count, first pixel index."""
+    N = int(nside)
+    rings = []
+    z = np.empty(4 * N - 1)
+    st = np.empty(4 * N - 1)
+    start = 0
+    for i in range(1, 4 * N):
+        k = min(i, 4 * N - i)                    # rings counted from the nearer pole
+        if k < N:                                # polar cap: 4k pixels, half-step offset
+            n = 4 * k
+            om = k * k / (3.0 * N * N)           # 1 - |z|
+            zabs = 1.0 - om
+            s = math.sqrt(om * (2.0 - om))
+            phi0 = math.pi / (4.0 * k)
+        else:                                    # belt: 4N pixels, offset alternating by ring
+            n = 4 * N
+            zabs = abs(2.0 * N - i) * 2.0 / (3.0 * N)
+            s = math.sqrt((1.0 - zabs) * (1.0 + zabs))
+            phi0 = math.pi * ((i - N + 1) % 2) / (4.0 * N)
+        z[i - 1] = zabs if i <= 2 * N else -zabs
+        st[i - 1] = s
+        rings.append((n, start, phi0))
+        start += n
+    return z, st, rings
+
+
+def synthesize(nside: int, alm: np.ndarray, lmax: int) -> np.ndarray:
+    """Real map sum_lm a_lm Y_lm on the ring grid from m-major packed a_lm (m >= 0)."""
+    import ctypes
+    N = int(nside)
+    z, st, rings = _ring_layout(N)
+    nr = 4 * N - 1
+    npix = 12 * N * N
+    out = np.empty(npix)
+    re = np.ascontiguousarray(alm.real)
+    im = np.ascontiguousarray(alm.imag)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib = _sht()
+    north = list(range(0, 2 * N))              # rings 1..2N (equator last)
+    m = np.arange(lmax + 1)
+    cm = np.where(m == 0, 1.0, 2.0)
+    block = 256
+    for b0 in range(0, len(north), block):
+        idx = north[b0:b0 + block]
+        zn = np.ascontiguousarray(z[idx])
+        sn = np.ascontiguousarray(st[idx])
+        fn = np.zeros((len(idx), lmax + 1, 2))
+        fs = np.zeros((len(idx), lmax + 1, 2))
+        lib.synth_ring_pairs(lmax, re.ctypes.data_as(dp), im.ctypes.data_as(dp), len(idx),
+                             zn.ctypes.data_as(dp), sn.ctypes.data_as(dp),
+                             fn.ctypes.data_as(dp), fs.ctypes.data_as(dp))
+        for t, r in enumerate(idx):
+            todo = [(r, fn[t])]
+            if nr - 1 - r != r:                  # the equator ring is its own mirror
+                todo.append((nr - 1 - r, fs[t]))
+            for rr, F in todo:
+                n, s0, phi0 = rings[rr]
+                c = (F[:, 0] + 1j * F[:, 1]) * cm * np.exp(1j * m * phi0)
+                G = np.bincount(m % n, weights=c.real, minlength=n) + \
+                    1j * np.bincount(m % n, weights=c.imag, minlength=n)
+                out[s0:s0 + n] = np.real(np.fft.ifft(G)) * n
+    return out
+
+
+def grf_map(nside: int, cl: np.ndarray, seed: int) -> np.ndarray:
+    """Gaussian random field with power spectrum cl on the ring grid (FP64)."""
+    lmax = len(cl) - 1
+    return synthesize(nside, draw_alm(cl, seed), lmax)
+
+
+def workload_maps(w, nmaps: int = 1) -> np.ndarray:
+    """The maps of a named workload, [nmaps, Npix], in the workload's map dtype."""
+    dt = np.float64 if w.dtype == "f64" else np.float32
+    if w.map_kind == "white":
+        return white_noise(w.nside, nmaps, seed=w.seed, dtype=dt)
+    maps = []
+    for k in range(nmaps):
+        f = grf_map(w.nside, red_spectrum(w.map_lmax), w.seed + 1000 * k)
+        if w.map_kind == "red+noise":
+            g = rng(w.seed + 1000 * k + 1)
+            f = f + w.noise_frac * float(np.std(f)) * g.standard_normal(f.size)
+        maps.append(f)
+    return np.stack(maps).astype(dt)
+
+
 @dataclass
 class Workload:
     """One named workload: a map recipe and a radial kernel given by k_l."""

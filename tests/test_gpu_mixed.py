@@ -61,6 +61,19 @@ def test_mixed_small_and_degenerate_grids(cuda_device):
         _check(y, ref.reshape(1, -1))
 
 
+def test_mixed_large_table_fallback(cuda_device):
+    """A table too large for the LDS coefficient form sends cap-touching pairs to the FP64
+    per-pair kernel; the result still meets the tolerance."""
+    nside, sigma = 32, 1.5 * DEG
+    tc = 5 * sigma
+    T = ok.tabulate(synth.gaussian_beam_sigma(512, sigma), tc, 6000)
+    x = synth.white_noise(nside, 1, seed=12, dtype=np.float32)
+    with cr.Plan(nside, T, tc, "mixed") as plan:
+        y = _run(plan, x)
+    ref = oc.convolve_sampled(nside, T, tc, x.astype(np.float64), np.arange(x.shape[1]))
+    _check(y, ref.reshape(1, -1))
+
+
 def test_mixed_residual_kernel_512(cuda_device):
     """Oscillating residual kernel (beam minus tapered low-l part), Nside 512, sampled pixels."""
     w = synth.workload("resid512")

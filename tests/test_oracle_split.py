@@ -1,0 +1,111 @@
+"""Pins of the oracle's split models (Estimating Errors section, Eqs. 1-8; Table 1).
+
+* Cost model: Eqs. 7-8 with the paper's Table 1 cuts and wall = max(t_gpu, t_cpu) reproduce the
+  quoted speedup plateau (12-15x for FWHM 7-10', "160 seconds to approximately 12 seconds").
+* Least-squares split: closed forms at the extremes (l_cut = lmax is exact; no real-space nodes
+  leaves the truncated harmonic kernel), the Legendre operator is exact on band-limited profiles
+  (Gauss-Legendre quadrature), the normal equations hold on the kept singular subspace, and Eq. 6
+  is normalised so that dropping the whole kernel is a 100% error (alpha = 1).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import kernel, split
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "table1_optimum_cuts.txt")
+
+
+def table1():
+    rows = [ln.split() for ln in open(GOLD) if ln.strip() and not ln.startswith("#")]
+    return [(int(a), int(b), int(c)) for a, b, c in rows]
+
+
+def test_cost_model_reproduces_speedups():
+    full = split.cost_cpu_paper(4096)
+    assert full == pytest.approx(160.0)
+    speed = {}
+    for fwhm, lc, tc in table1():
+        wall = split.wall_time(split.cost_gpu_paper(tc), split.cost_cpu_paper(lc))
+        speed[fwhm] = full / wall
+    for fwhm, want in [(7, 12.51), (8, 13.94), (9, 14.84), (10, 14.84)]:
+        assert speed[fwhm] == pytest.approx(want, rel=1e-3)
+    assert all(12.0 <= speed[f] <= 15.0 for f in (7, 8, 9, 10))   # "plateauing in the range 12-15"
+    assert 160.0 / speed[7] == pytest.approx(12.0, rel=0.1)      # "160 seconds to approximately 12"
+
+
+def _beam(lmax, fwhm_arcmin):
+    s = fwhm_arcmin / 60 * math.pi / 180 / math.sqrt(8 * math.log(2))
+    ell = np.arange(lmax + 1)
+    return np.exp(-0.5 * ell * (ell + 1) * s * s)
+
+
+def test_full_harmonic_part_is_exact():
+    lmax = 128
+    K = _beam(lmax, 120.0)
+    C = np.ones(lmax + 1)
+    _, _, _, kt = split.lsq_split(K, C, lmax, 0.05)
+    assert split.rms_error(K, kt, C) <= 1e-12 * np.max(np.abs(K))
+
+
+def test_no_real_space_nodes_truncates():
+    lmax = 128
+    K = _beam(lmax, 300.0)
+    C = np.ones(lmax + 1)
+    ell_cut = 40
+    tiny = 1e-4                                  # no Gauss-Legendre node this close to the pole
+    assert len(split.real_space_nodes(lmax, tiny)[0]) == 0
+    _, _, _, kt = split.lsq_split(K, C, ell_cut, tiny)
+    ell = np.arange(lmax + 1)
+    expect = math.sqrt(np.sum(((2 * ell + 1) * K ** 2)[ell_cut + 1:]) / (4 * math.pi))
+    assert split.rms_error(K, kt, C) == pytest.approx(expect, rel=1e-12)
+
+
+def test_legendre_operator_exact_on_band_limited():
+    lmax = 60
+    g = np.random.default_rng(1)
+    f_ell = g.standard_normal(lmax + 1)
+    z, w = split.real_space_nodes(lmax, math.pi)           # the whole rule
+    assert len(z) == lmax + 1
+    P = split.legendre_operator(lmax, z, w)
+    samples = kernel.legendre_series_u(f_ell, 1.0 - z)
+    assert np.allclose(P @ samples, f_ell, atol=1e-10)
+
+
+def test_normal_equations_on_kept_subspace():
+    lmax = 200
+    K = _beam(lmax, 60.0)
+    C = 1.0 / np.maximum(np.arange(lmax + 1) * (np.arange(lmax + 1) + 1.0), 1.0)
+    ell_cut, tc = 60, 0.3
+    _, _, _, kt = split.lsq_split(K, C, ell_cut, tc)
+    A, z, w = split.design_matrix(lmax, ell_cut, tc)
+    Wd = (2 * np.arange(lmax + 1) + 1.0) * C
+    M = A.T @ (Wd[:, None] * A)
+    U, s, Vt = np.linalg.svd(M)
+    keep = s >= 1e-6 * s[0]
+    grad = A.T @ (Wd * (kt - K))
+    assert np.max(np.abs(U[:, keep].T @ grad)) <= 1e-8 * np.max(np.abs(A.T @ (Wd * K)))
+    # the harmonic part reproduces K exactly below l_cut only up to what the real-space part adds
+    assert split.rms_error(K, kt, C) < split.rms_error(K, np.where(np.arange(lmax + 1) <= ell_cut, K, 0), C)
+
+
+def test_fractional_error_normalisation():
+    lmax = 50
+    K = _beam(lmax, 200.0)
+    C = np.ones(lmax + 1)
+    assert split.fractional_error(K, np.zeros_like(K), C, alpha=1.0) == pytest.approx(1.0)
+    assert split.fractional_error(K, np.zeros_like(K), C, alpha=5.0) == pytest.approx(5.0)
+
+
+def test_split_search_prefers_balanced_cheap_pair():
+    lmax = 256
+    K = _beam(lmax, 40.0)
+    C = np.ones(lmax + 1)
+    grid = [0.03, 0.06, 0.09]
+    best = split.split_search(K, C, 1e-4, grid, t_gpu=lambda tc: 10.0 * tc, t_cpu=lambda lc: (lc / lmax) ** 2)
+    assert best is not None
+    tc, lc, wall, err = best
+    assert err <= 1e-4 and tc in grid and 0 <= lc <= lmax
+    assert wall == pytest.approx(max(10.0 * tc, (lc / lmax) ** 2))
