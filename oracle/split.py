@@ -74,6 +74,31 @@ def lsq_split(K_ell: np.ndarray, C_in: np.ndarray, ell_cut: int, theta_cut: floa
     return x[: ell_cut + 1], x[ell_cut + 1:], z, K_tilde
 
 
+def lsq_split_reduced(K_ell: np.ndarray, C_in: np.ndarray, ell_cut: int, theta_cut: float,
+                      sv_cut: float = 1e-6):
+    """Eq. 3 with the identity block eliminated. Rows l <= l_cut of A are [e_l | P_l]: K^_l is free
+    there, so those residuals vanish at the optimum and x minimises the remaining rows alone,
+        sum_{l > l_cut} (2l + 1) C_l (K_l - (P x)_l)^2,
+    solved through the eigen-decomposition of its normal matrix P_r^T W_r P_r, dropping eigenvalues
+    below sv_cut times the largest (the cutoff is applied to this matrix, not to the full one of
+    Eq. 3). Then K^_l = K_l - (P x)_l for l <= l_cut. Returns (K_hat_ell, x, z_nodes, K_tilde)."""
+    lmax = len(K_ell) - 1
+    z, w = real_space_nodes(lmax, theta_cut)
+    P = legendre_operator(lmax, z, w)
+    Wd = (2.0 * np.arange(lmax + 1) + 1.0) * C_in
+    x = np.zeros(len(z))
+    if len(z) > 0 and ell_cut < lmax:
+        Pr, Wr, Kr = P[ell_cut + 1:], Wd[ell_cut + 1:], K_ell[ell_cut + 1:]
+        M = Pr.T @ (Wr[:, None] * Pr)
+        rhs = Pr.T @ (Wr * Kr)
+        lam, V = np.linalg.eigh(M)
+        keep = (lam >= sv_cut * lam.max()) & (lam > 0)
+        x = V[:, keep] @ ((V[:, keep].T @ rhs) / lam[keep])
+    k_real = P @ x
+    K_tilde = np.where(np.arange(lmax + 1) <= ell_cut, K_ell, k_real)
+    return K_ell[: ell_cut + 1] - k_real[: ell_cut + 1], x, z, K_tilde
+
+
 def rms_error(K_ell, K_tilde, C_in) -> float:
     """sigma_rms of Eq. 2."""
     ell = np.arange(len(K_ell))
@@ -102,14 +127,36 @@ def wall_time(t_gpu: float, t_cpu: float) -> float:
     return max(t_gpu, t_cpu)
 
 
+def pairs_estimate(nside: int, theta_cut: float) -> float:
+    """Pixel pairs of one map within theta_cut, estimated: every one of the Npix pixels sees the
+    fraction (1 - cos theta_cut) / 2 of the sphere, i.e. of the Npix pixels."""
+    npix = 12.0 * nside * nside
+    return npix * npix * (1.0 - math.cos(theta_cut)) / 2.0
+
+
+def cost_fit(pairs, t_real, work_sht, t_sht):
+    """Measured-constant cost model in the form of Eqs. 7-8: t_real = a + b pairs (least squares;
+    a = 0 from a single point), t_sht = c ell_cut^2 lmax (least squares through the origin)."""
+    pairs, t_real = np.asarray(pairs, float), np.asarray(t_real, float)
+    work_sht, t_sht = np.asarray(work_sht, float), np.asarray(t_sht, float)
+    if len(pairs) == 1:
+        a, b = 0.0, t_real[0] / pairs[0]
+    else:
+        b, a = np.polyfit(pairs, t_real, 1)
+    c = float(np.dot(work_sht, t_sht) / np.dot(work_sht, work_sht))
+    return float(a), float(b), c
+
+
 def split_search(K_ell, C_in, bound: float, theta_grid, t_gpu, t_cpu, alpha: float = 5.0,
-                 sv_cut: float = 1e-6):
+                 sv_cut: float = 1e-6, solver=None):
     """Scan theta_cut; binary-search the smallest feasible l_cut for each; keep the cheapest.
+    solver is the least-squares split to use (default: the full solve of Eq. 3).
     Returns (theta_cut, ell_cut, wall, error) or None if no pair meets the bound."""
     lmax = len(K_ell) - 1
+    solve = lsq_split if solver is None else solver
 
     def err(lc, tc):
-        _, _, _, kt = lsq_split(K_ell, C_in, lc, tc, sv_cut)
+        _, _, _, kt = solve(K_ell, C_in, lc, tc, sv_cut)
         return fractional_error(K_ell, kt, C_in, alpha)
 
     best = None

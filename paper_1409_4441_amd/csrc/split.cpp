@@ -1,0 +1,540 @@
+// Kernel-split model of libconvreal: Gauss-Legendre real-space samples, the Legendre operator,
+// the reduced least-squares split (Eqs. 3-5), its errors (Eqs. 2 and 6), the cost model and the
+// split search. Host-side FP64.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <utility>
+#include <vector>
+
+#include "../../include/convsplit.h"
+#include "internal.h"
+
+using convreal::set_error;
+
+namespace {
+
+// Symmetric eigen-decomposition by cyclic Jacobi rotations: A (n x n, row-major, destroyed) ->
+// eigenvalues lam[n], eigenvectors as columns of V (row-major n x n). Jacobi keeps small
+// eigenvalues to high relative accuracy, which the cutoff test relies on.
+void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V) {
+  V.assign(static_cast<size_t>(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) V[static_cast<size_t>(i) * n + i] = 1.0;
+  auto a = [&](int i, int j) -> double& { return A[static_cast<size_t>(i) * n + j]; };
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int i = 0; i < n; ++i) {
+      diag += a(i, i) * a(i, i);
+      for (int j = i + 1; j < n; ++j) off += a(i, j) * a(i, j);
+    }
+    if (off <= 1e-32 * diag || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a(p, q);
+        if (std::fabs(apq) <= 1e-300) continue;
+        // rotation angle that zeroes a(p, q): tan(2 phi) = 2 a_pq / (a_qq - a_pp), smaller root
+        const double th = (a(q, q) - a(p, p)) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0);
+        const double s = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a(k, p), akq = a(k, q);
+          a(k, p) = c * akp - s * akq;
+          a(k, q) = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a(p, k), aqk = a(q, k);
+          a(p, k) = c * apk - s * aqk;
+          a(q, k) = s * apk + c * aqk;
+        }
+        a(p, q) = 0.0;
+        a(q, p) = 0.0;
+        for (int k = 0; k < n; ++k) {
+          double& vkp = V[static_cast<size_t>(k) * n + p];
+          double& vkq = V[static_cast<size_t>(k) * n + q];
+          const double x = vkp, y = vkq;
+          vkp = c * x - s * y;
+          vkq = s * x + c * y;
+        }
+      }
+    }
+  }
+  lam.resize(n);
+  for (int i = 0; i < n; ++i) lam[i] = a(i, i);
+}
+
+// Nodes z_k and weights w_k of the n-point Gauss-Legendre rule with z_k > zmin, in decreasing z:
+// Newton's method on P_n from the usual asymptotic first guesses.
+void gauss_legendre_above(int n, double zmin, std::vector<double>& z, std::vector<double>& w) {
+  z.clear();
+  w.clear();
+  for (int k = 1; k <= n; ++k) {
+    double x = std::cos(M_PI * (k - 0.25) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int l = 1; l < n; ++l) {
+        const double p2 = ((2.0 * l + 1.0) * x * p1 - l * p0) / (l + 1.0);
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_n(x), p0 = P_{n-1}(x); P_n'(x) = n (x P_n - P_{n-1}) / (x^2 - 1)
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) <= 1e-16 * std::max(1.0, std::fabs(x))) {
+        // derivative at the converged node for the weight
+        p0 = 1.0;
+        p1 = x;
+        for (int l = 1; l < n; ++l) {
+          const double p2 = ((2.0 * l + 1.0) * x * p1 - l * p0) / (l + 1.0);
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (x * p1 - p0) / (x * x - 1.0);
+        break;
+      }
+    }
+    if (!(x > zmin)) break;
+    z.push_back(x);
+    w.push_back(2.0 / ((1.0 - x * x) * dp * dp));
+  }
+}
+
+struct Eig {
+  std::vector<double> lam;  // n
+  std::vector<double> V;    // n x n, columns are eigenvectors
+};
+
+}  // namespace
+
+struct conv_split_ctx {
+  int lmax = 0;
+  double theta_max = 0.0;
+  double sv_cut = 1e-6;
+  std::vector<double> W;   // (2l + 1) C_l
+  std::vector<double> z, w;
+  int nmax = 0;
+  std::vector<double> P;   // (lmax + 1) x nmax row-major: 2 pi w_k P_l(z_k)
+  std::mutex mu;
+  // (z_cut, ell_cut) -> eigen-decomposition of the normal matrix; shared so that a worker keeps its
+  // entry alive when another one clears the cache
+  std::map<std::pair<int, int>, std::shared_ptr<const Eig>> cache;
+};
+
+namespace {
+
+int count_nodes(const conv_split_ctx* c, double theta_cut) {
+  const double zc = std::cos(theta_cut);
+  int n = 0;
+  while (n < c->nmax && c->z[n] > zc) ++n;
+  return n;
+}
+
+// normal matrix of the reduced problem, sum_{l > ell_cut} W_l p_l p_l^T over the first n samples,
+// and its eigen-decomposition; it does not depend on the kernel, so it is cached per (n, ell_cut)
+std::shared_ptr<const Eig> normal_eigen(conv_split_ctx* c, int n, int ell_cut) {
+  {
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->cache.find({n, ell_cut});
+    if (it != c->cache.end()) return it->second;
+  }
+  std::vector<double> M(static_cast<size_t>(n) * n, 0.0);
+  for (int l = ell_cut + 1; l <= c->lmax; ++l) {
+    const double* p = c->P.data() + static_cast<size_t>(l) * c->nmax;
+    const double wl = c->W[l];
+    for (int i = 0; i < n; ++i) {
+      const double wi = wl * p[i];
+      double* row = M.data() + static_cast<size_t>(i) * n;
+      for (int j = i; j < n; ++j) row[j] += wi * p[j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) M[static_cast<size_t>(i) * n + j] = M[static_cast<size_t>(j) * n + i];
+  auto e = std::make_shared<Eig>();
+  jacobi_eigen(n, M, e->lam, e->V);
+  std::lock_guard<std::mutex> g(c->mu);
+  if (c->cache.size() > 8192) c->cache.clear();
+  auto res = c->cache.emplace(std::make_pair(n, ell_cut), e);
+  return res.first->second;
+}
+
+// solve the reduced problem; x has n entries (n = 0: nothing to solve)
+void solve_reduced(conv_split_ctx* c, const double* K, int ell_cut, int n, std::vector<double>& x) {
+  x.assign(n, 0.0);
+  if (n == 0 || ell_cut >= c->lmax) return;
+  std::vector<double> rhs(n, 0.0);
+  for (int l = ell_cut + 1; l <= c->lmax; ++l) {
+    const double* p = c->P.data() + static_cast<size_t>(l) * c->nmax;
+    const double f = c->W[l] * K[l];
+    for (int k = 0; k < n; ++k) rhs[k] += p[k] * f;
+  }
+  const std::shared_ptr<const Eig> ep = normal_eigen(c, n, ell_cut);
+  const Eig& e = *ep;
+  double lmax_ev = 0.0;
+  for (double v : e.lam) lmax_ev = std::max(lmax_ev, v);
+  for (int i = 0; i < n; ++i) {
+    if (!(e.lam[i] >= c->sv_cut * lmax_ev) || !(e.lam[i] > 0.0)) continue;
+    double proj = 0.0;
+    for (int k = 0; k < n; ++k) proj += e.V[static_cast<size_t>(k) * n + i] * rhs[k];
+    proj /= e.lam[i];
+    for (int k = 0; k < n; ++k) x[k] += e.V[static_cast<size_t>(k) * n + i] * proj;
+  }
+}
+
+// Eq. 2 sigma_rms^2 * 4 pi and the Eq. 6 normalisation * 4 pi for the split with samples x
+void split_sums(const conv_split_ctx* c, const double* K, int ell_cut, int n, const std::vector<double>& x,
+                double* err_sum, double* norm_sum) {
+  double es = 0.0, ns = 0.0;
+  for (int l = 0; l <= c->lmax; ++l) {
+    ns += (2.0 * l + 1.0) * K[l] * K[l];
+    if (l <= ell_cut) continue;
+    const double* p = c->P.data() + static_cast<size_t>(l) * c->nmax;
+    double kr = 0.0;
+    for (int k = 0; k < n; ++k) kr += p[k] * x[k];
+    const double r = K[l] - kr;
+    es += c->W[l] * r * r;
+  }
+  *err_sum = es;
+  *norm_sum = ns;
+}
+
+int check_ctx(const conv_split_ctx* c, const char* who) {
+  if (!c) {
+    set_error(std::string(who) + ": NULL context");
+    return CONV_REAL_EINVAL;
+  }
+  return CONV_REAL_OK;
+}
+
+int check_split(const conv_split_ctx* c, const double* k_ell, int ell_cut, double theta_cut, const char* who) {
+  if (int e = check_ctx(c, who)) return e;
+  if (!k_ell) {
+    set_error(std::string(who) + ": NULL k_ell");
+    return CONV_REAL_EINVAL;
+  }
+  if (ell_cut < 0 || ell_cut > c->lmax) {
+    set_error(std::string(who) + ": ell_cut must be in [0, lmax]");
+    return CONV_REAL_EINVAL;
+  }
+  if (!(theta_cut > 0.0) || !(theta_cut <= c->theta_max * (1.0 + 1e-12))) {
+    set_error(std::string(who) + ": theta_cut must be in (0, theta_max]");
+    return CONV_REAL_EINVAL;
+  }
+  return CONV_REAL_OK;
+}
+
+double sigma_of(conv_split_ctx* c, const double* K, int ell_cut, double theta_cut, double alpha) {
+  const int n = count_nodes(c, theta_cut);
+  std::vector<double> x;
+  solve_reduced(c, K, ell_cut, n, x);
+  double es, ns;
+  split_sums(c, K, ell_cut, n, x, &es, &ns);
+  return ns > 0.0 ? alpha * std::sqrt(es / ns) : 0.0;
+}
+
+// the scan for one kernel; returns true if some pair meets the bound
+bool search_one(conv_split_ctx* c, const double* K, int nside, double bound, double alpha, const double* grid,
+                int n_theta, int step, const conv_cost_model* m, double* th_out, int* lc_out, double* wall_out,
+                double* sig_out) {
+  bool found = false;
+  double best_wall = 0.0, best_th = 0.0, best_sig = 0.0;
+  int best_lc = 0;
+  const int lmax = c->lmax;
+  const int nsteps = lmax / step;  // candidates s * k for k = 0..nsteps, then lmax itself
+  auto cand = [&](int k) { return k > nsteps ? lmax : std::min(lmax, k * step); };
+  for (int g = 0; g < n_theta; ++g) {
+    const double th = grid[g];
+    // smallest feasible candidate index: the error falls as ell_cut grows; lmax is always exact
+    int hi = nsteps + 1;               // lmax: error 0
+    double sig_hi = 0.0;
+    if (!(sigma_of(c, K, lmax, th, alpha) <= bound)) continue;
+    int lo = -1;                       // index known infeasible (virtual)
+    const double s0 = sigma_of(c, K, cand(0), th, alpha);
+    if (s0 <= bound) {
+      hi = 0;
+      sig_hi = s0;
+    } else {
+      lo = 0;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        const double s = sigma_of(c, K, cand(mid), th, alpha);
+        if (s <= bound) {
+          hi = mid;
+          sig_hi = s;
+        } else {
+          lo = mid;
+        }
+      }
+      if (hi == nsteps + 1) sig_hi = 0.0;
+    }
+    const int lc = cand(hi);
+    double w = 0.0;
+    conv_cost_eval(m, nside, lmax, th, lc, nullptr, nullptr, &w);
+    if (!found || w < best_wall) {
+      found = true;
+      best_wall = w;
+      best_th = th;
+      best_lc = lc;
+      best_sig = sig_hi;
+    }
+  }
+  if (found) {
+    if (th_out) *th_out = best_th;
+    if (lc_out) *lc_out = best_lc;
+    if (wall_out) *wall_out = best_wall;
+    if (sig_out) *sig_out = best_sig;
+  }
+  return found;
+}
+
+int check_search(const conv_split_ctx* c, int nside, double alpha, const double* grid, int n_theta, int step,
+                 const conv_cost_model* m, const char* who) {
+  if (int e = check_ctx(c, who)) return e;
+  if (!grid || n_theta <= 0 || !m) {
+    set_error(std::string(who) + ": NULL grid or model, or empty grid");
+    return CONV_REAL_EINVAL;
+  }
+  if (nside < 1 || nside > CONV_REAL_MAX_NSIDE || step < 1 || !(alpha > 0.0)) {
+    set_error(std::string(who) + ": bad nside, ell_step or alpha");
+    return CONV_REAL_EINVAL;
+  }
+  for (int g = 0; g < n_theta; ++g) {
+    if (!(grid[g] > 0.0) || !(grid[g] <= c->theta_max * (1.0 + 1e-12))) {
+      set_error(std::string(who) + ": theta_grid values must be in (0, theta_max]");
+      return CONV_REAL_EINVAL;
+    }
+  }
+  return CONV_REAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int conv_split_create(conv_split_ctx** ctx, int lmax, const double* c_in, double theta_max, double sv_cut) {
+  if (!ctx) {
+    set_error("conv_split_create: NULL ctx");
+    return CONV_REAL_EINVAL;
+  }
+  if (lmax < 1 || lmax > CONV_REAL_MAX_LMAX || !(theta_max > 0.0) || !(theta_max <= M_PI) || !(sv_cut > 0.0) ||
+      !(sv_cut < 1.0)) {
+    set_error("conv_split_create: need 1 <= lmax <= CONV_REAL_MAX_LMAX, theta_max in (0, pi], sv_cut in (0, 1)");
+    return CONV_REAL_EINVAL;
+  }
+  conv_split_ctx* c = new (std::nothrow) conv_split_ctx;
+  if (!c) {
+    set_error("conv_split_create: out of memory");
+    return CONV_REAL_ENOMEM;
+  }
+  c->lmax = lmax;
+  c->theta_max = theta_max;
+  c->sv_cut = sv_cut;
+  c->W.resize(lmax + 1);
+  for (int l = 0; l <= lmax; ++l) {
+    const double cl = c_in ? c_in[l] : 1.0;
+    if (!(cl >= 0.0) || !std::isfinite(cl)) {
+      delete c;
+      set_error("conv_split_create: c_in must be finite and >= 0");
+      return CONV_REAL_EINVAL;
+    }
+    c->W[l] = (2.0 * l + 1.0) * cl;
+  }
+  gauss_legendre_above(lmax + 1, std::cos(theta_max), c->z, c->w);
+  c->nmax = static_cast<int>(c->z.size());
+  c->P.assign(static_cast<size_t>(lmax + 1) * std::max(c->nmax, 1), 0.0);
+  for (int k = 0; k < c->nmax; ++k) {
+    const double x = c->z[k], f = 2.0 * M_PI * c->w[k];
+    double p0 = 1.0, p1 = x;
+    c->P[k] = f;
+    if (lmax >= 1) c->P[static_cast<size_t>(c->nmax) + k] = f * x;
+    for (int l = 1; l < lmax; ++l) {
+      const double p2 = ((2.0 * l + 1.0) * x * p1 - l * p0) / (l + 1.0);
+      p0 = p1;
+      p1 = p2;
+      c->P[static_cast<size_t>(l + 1) * c->nmax + k] = f * p2;
+    }
+  }
+  *ctx = c;
+  return CONV_REAL_OK;
+}
+
+int conv_split_destroy(conv_split_ctx* ctx) {
+  delete ctx;
+  return CONV_REAL_OK;
+}
+
+int conv_split_nodes(const conv_split_ctx* ctx, double theta_cut, int* z_cut) {
+  if (int e = check_ctx(ctx, "conv_split_nodes")) return e;
+  if (!z_cut || !(theta_cut > 0.0) || !(theta_cut <= ctx->theta_max * (1.0 + 1e-12))) {
+    set_error("conv_split_nodes: NULL z_cut or theta_cut outside (0, theta_max]");
+    return CONV_REAL_EINVAL;
+  }
+  *z_cut = count_nodes(ctx, theta_cut);
+  return CONV_REAL_OK;
+}
+
+int conv_split_lsq(conv_split_ctx* ctx, const double* k_ell, int ell_cut, double theta_cut, double* k_hat,
+                   double* k_theta, double* k_real, double* k_tilde) {
+  if (int e = check_split(ctx, k_ell, ell_cut, theta_cut, "conv_split_lsq")) return e;
+  const int n = count_nodes(ctx, theta_cut);
+  std::vector<double> x;
+  solve_reduced(ctx, k_ell, ell_cut, n, x);
+  const int lmax = ctx->lmax;
+  std::vector<double> kr(lmax + 1, 0.0);
+  for (int l = 0; l <= lmax; ++l) {
+    const double* p = ctx->P.data() + static_cast<size_t>(l) * ctx->nmax;
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s += p[k] * x[k];
+    kr[l] = s;
+  }
+  if (k_hat)
+    for (int l = 0; l <= ell_cut; ++l) k_hat[l] = k_ell[l] - kr[l];
+  if (k_theta)
+    for (int k = 0; k < n; ++k) k_theta[k] = x[k];
+  if (k_real)
+    for (int l = 0; l <= lmax; ++l) k_real[l] = kr[l];
+  if (k_tilde)
+    for (int l = 0; l <= lmax; ++l) k_tilde[l] = l <= ell_cut ? k_ell[l] : kr[l];
+  return CONV_REAL_OK;
+}
+
+int conv_split_error(conv_split_ctx* ctx, const double* k_ell, int ell_cut, double theta_cut, double alpha,
+                     double* sigma_rms, double* sigma) {
+  if (int e = check_split(ctx, k_ell, ell_cut, theta_cut, "conv_split_error")) return e;
+  const int n = count_nodes(ctx, theta_cut);
+  std::vector<double> x;
+  solve_reduced(ctx, k_ell, ell_cut, n, x);
+  double es, ns;
+  split_sums(ctx, k_ell, ell_cut, n, x, &es, &ns);
+  if (sigma_rms) *sigma_rms = std::sqrt(es / (4.0 * M_PI));
+  if (sigma) *sigma = ns > 0.0 ? alpha * std::sqrt(es / ns) : 0.0;
+  return CONV_REAL_OK;
+}
+
+double conv_cost_pairs(int nside, double theta_cut) {
+  const double npix = 12.0 * static_cast<double>(nside) * static_cast<double>(nside);
+  const double th = std::min(std::max(theta_cut, 0.0), M_PI);
+  // 1 - cos(theta) = 2 sin^2(theta / 2), without cancellation at small theta
+  const double s = std::sin(0.5 * th);
+  return npix * npix * s * s;
+}
+
+int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const double* work_sht,
+                  const double* t_sht, int n_sht, conv_cost_model* m) {
+  if (!pairs || !t_real || !work_sht || !t_sht || !m || n_real < 1 || n_sht < 1) {
+    set_error("conv_cost_fit: NULL argument or empty measurement set");
+    return CONV_REAL_EINVAL;
+  }
+  double a = 0.0, b = 0.0;
+  if (n_real == 1) {
+    if (!(pairs[0] > 0.0)) {
+      set_error("conv_cost_fit: pairs must be > 0");
+      return CONV_REAL_EINVAL;
+    }
+    b = t_real[0] / pairs[0];
+  } else {
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    for (int k = 0; k < n_real; ++k) {
+      sx += pairs[k];
+      sy += t_real[k];
+      sxx += pairs[k] * pairs[k];
+      sxy += pairs[k] * t_real[k];
+    }
+    const double nn = static_cast<double>(n_real);
+    const double den = nn * sxx - sx * sx;
+    if (!(std::fabs(den) > 0.0)) {
+      set_error("conv_cost_fit: the pair counts must not all be equal");
+      return CONV_REAL_EINVAL;
+    }
+    b = (nn * sxy - sx * sy) / den;
+    a = (sy - b * sx) / nn;
+  }
+  double sw = 0, swt = 0;
+  for (int k = 0; k < n_sht; ++k) {
+    sw += work_sht[k] * work_sht[k];
+    swt += work_sht[k] * t_sht[k];
+  }
+  if (!(sw > 0.0)) {
+    set_error("conv_cost_fit: harmonic work must be > 0");
+    return CONV_REAL_EINVAL;
+  }
+  m->a = a;
+  m->b = b;
+  m->c = swt / sw;
+  return CONV_REAL_OK;
+}
+
+int conv_cost_eval(const conv_cost_model* m, int nside, int lmax, double theta_cut, int ell_cut, double* t_real,
+                   double* t_sht, double* wall) {
+  if (!m || nside < 1 || lmax < 0 || ell_cut < 0 || !(theta_cut >= 0.0)) {
+    set_error("conv_cost_eval: bad argument");
+    return CONV_REAL_EINVAL;
+  }
+  const double tr = m->a + m->b * conv_cost_pairs(nside, theta_cut);
+  const double ts = m->c * static_cast<double>(ell_cut) * static_cast<double>(ell_cut) * static_cast<double>(lmax);
+  if (t_real) *t_real = tr;
+  if (t_sht) *t_sht = ts;
+  if (wall) *wall = std::max(tr, ts);
+  return CONV_REAL_OK;
+}
+
+int conv_split_search(conv_split_ctx* ctx, const double* k_ell, int nside, double bound, double alpha,
+                      const double* theta_grid, int n_theta, int ell_step, const conv_cost_model* m,
+                      double* theta_cut, int* ell_cut, double* wall, double* sigma) {
+  if (int e = check_search(ctx, nside, alpha, theta_grid, n_theta, ell_step, m, "conv_split_search")) return e;
+  if (!k_ell || !(bound > 0.0)) {
+    set_error("conv_split_search: NULL k_ell or bound <= 0");
+    return CONV_REAL_EINVAL;
+  }
+  return search_one(ctx, k_ell, nside, bound, alpha, theta_grid, n_theta, ell_step, m, theta_cut, ell_cut, wall,
+                    sigma)
+             ? CONV_REAL_OK
+             : CONV_SPLIT_INFEASIBLE;
+}
+
+int conv_split_search_many(conv_split_ctx* ctx, const double* k_ells, int n, int nside, const double* bounds,
+                           double alpha, const double* theta_grid, int n_theta, int ell_step,
+                           const conv_cost_model* m, int nthreads, double* theta_cut, int* ell_cut, double* wall,
+                           double* sigma) {
+  if (int e = check_search(ctx, nside, alpha, theta_grid, n_theta, ell_step, m, "conv_split_search_many")) return e;
+  if (!k_ells || !bounds || n < 0 || !theta_cut || !ell_cut || !wall || !sigma) {
+    set_error("conv_split_search_many: NULL argument or n < 0");
+    return CONV_REAL_EINVAL;
+  }
+  for (int k = 0; k < n; ++k) {
+    if (!(bounds[k] > 0.0)) {
+      set_error("conv_split_search_many: bounds must be > 0");
+      return CONV_REAL_EINVAL;
+    }
+  }
+  int nt = nthreads > 0 ? nthreads : static_cast<int>(std::thread::hardware_concurrency());
+  nt = std::max(1, std::min(nt, std::max(n, 1)));
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n) break;
+      const double* K = k_ells + static_cast<size_t>(k) * (ctx->lmax + 1);
+      if (!search_one(ctx, K, nside, bounds[k], alpha, theta_grid, n_theta, ell_step, m, &theta_cut[k], &ell_cut[k],
+                      &wall[k], &sigma[k])) {
+        theta_cut[k] = -1.0;
+        ell_cut[k] = -1;
+        wall[k] = 0.0;
+        sigma[k] = 0.0;
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+  return CONV_REAL_OK;
+}
+
+}  // extern "C"

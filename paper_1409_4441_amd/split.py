@@ -1,0 +1,191 @@
+"""Kernel-split model: ctypes binding of include/convsplit.h (argument marshalling only).
+
+    from paper_1409_4441_amd import split
+    ctx = split.Context(lmax, theta_max)                  # Gauss-Legendre samples, Legendre operator
+    k_hat, k_theta, k_real, k_tilde = ctx.lsq(k_ell, ell_cut, theta_cut)   # Eqs. 3-5
+    sigma_rms, sigma = ctx.error(k_ell, ell_cut, theta_cut, alpha=5.0)      # Eqs. 2 and 6
+    model = split.CostModel.fit(pairs, t_real, work_sht, t_sht)
+    best = ctx.search(k_ell, nside, bound, theta_grid, model)             # the split scan
+
+Everything runs in libconvreal's host code (FP64); no GPU is needed.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import ConvRealError, _check, lib
+
+INFEASIBLE = 1
+
+# Every entry point that include/convsplit.h declares.
+EXPORTS = ("conv_split_create", "conv_split_destroy", "conv_split_nodes", "conv_split_lsq", "conv_split_error",
+           "conv_cost_pairs", "conv_cost_fit", "conv_cost_eval", "conv_split_search", "conv_split_search_many")
+
+_c_int, _c_double, _c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+_dptr_t = ctypes.POINTER(ctypes.c_double)
+_iptr_t = ctypes.POINTER(ctypes.c_int)
+
+
+class _Cost(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double)]
+
+
+def _bind():
+    lib.conv_split_create.argtypes = [ctypes.POINTER(_c_void_p), _c_int, _dptr_t, _c_double, _c_double]
+    lib.conv_split_destroy.argtypes = [_c_void_p]
+    lib.conv_split_nodes.argtypes = [_c_void_p, _c_double, _iptr_t]
+    lib.conv_split_lsq.argtypes = [_c_void_p, _dptr_t, _c_int, _c_double, _dptr_t, _dptr_t, _dptr_t, _dptr_t]
+    lib.conv_split_error.argtypes = [_c_void_p, _dptr_t, _c_int, _c_double, _c_double, _dptr_t, _dptr_t]
+    lib.conv_cost_pairs.argtypes = [_c_int, _c_double]
+    lib.conv_cost_pairs.restype = _c_double
+    lib.conv_cost_fit.argtypes = [_dptr_t, _dptr_t, _c_int, _dptr_t, _dptr_t, _c_int, ctypes.POINTER(_Cost)]
+    lib.conv_cost_eval.argtypes = [ctypes.POINTER(_Cost), _c_int, _c_int, _c_double, _c_int, _dptr_t, _dptr_t,
+                                   _dptr_t]
+    lib.conv_split_search.argtypes = [_c_void_p, _dptr_t, _c_int, _c_double, _c_double, _dptr_t, _c_int, _c_int,
+                                      ctypes.POINTER(_Cost), _dptr_t, _iptr_t, _dptr_t, _dptr_t]
+    lib.conv_split_search_many.argtypes = [_c_void_p, _dptr_t, _c_int, _c_int, _dptr_t, _c_double, _dptr_t, _c_int,
+                                           _c_int, ctypes.POINTER(_Cost), _c_int, _dptr_t, _iptr_t, _dptr_t,
+                                           _dptr_t]
+    for f in ("conv_split_create", "conv_split_destroy", "conv_split_nodes", "conv_split_lsq", "conv_split_error",
+              "conv_cost_fit", "conv_cost_eval", "conv_split_search", "conv_split_search_many"):
+        getattr(lib, f).restype = _c_int
+
+
+_bind()
+
+
+def _d(a):
+    return a.ctypes.data_as(_dptr_t)
+
+
+def _f64(a, n=None, name="array"):
+    out = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and out.shape != (n,):
+        raise ConvRealError(-1, name, f"expected {n} values, got shape {out.shape}")
+    return out
+
+
+class CostModel:
+    """t_real = a + b pairs, t_sht = c ell_cut^2 lmax, wall = max of the two."""
+
+    def __init__(self, a: float, b: float, c: float):
+        self._s = _Cost(float(a), float(b), float(c))
+
+    @property
+    def a(self):
+        return self._s.a
+
+    @property
+    def b(self):
+        return self._s.b
+
+    @property
+    def c(self):
+        return self._s.c
+
+    def as_dict(self):
+        return {"a": self.a, "b": self.b, "c": self.c}
+
+    @classmethod
+    def fit(cls, pairs, t_real, work_sht, t_sht) -> "CostModel":
+        p, tr = _f64(pairs), _f64(t_real)
+        w, ts = _f64(work_sht), _f64(t_sht)
+        m = _Cost()
+        _check(lib.conv_cost_fit(_d(p), _d(tr), len(p), _d(w), _d(ts), len(w), ctypes.byref(m)), "conv_cost_fit")
+        return cls(m.a, m.b, m.c)
+
+    def eval(self, nside: int, lmax: int, theta_cut: float, ell_cut: int):
+        """(t_real, t_sht, wall) in seconds."""
+        tr, ts, wl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib.conv_cost_eval(ctypes.byref(self._s), int(nside), int(lmax), float(theta_cut), int(ell_cut),
+                                  ctypes.byref(tr), ctypes.byref(ts), ctypes.byref(wl)), "conv_cost_eval")
+        return tr.value, ts.value, wl.value
+
+
+def pairs_estimate(nside: int, theta_cut: float) -> float:
+    """Npix^2 (1 - cos theta_cut) / 2."""
+    return float(lib.conv_cost_pairs(int(nside), float(theta_cut)))
+
+
+class Context:
+    """Split model for one lmax and input weighting C_in (None: flat), theta_cut <= theta_max."""
+
+    def __init__(self, lmax: int, theta_max: float, c_in=None, sv_cut: float = 1e-6):
+        self.lmax = int(lmax)
+        self.theta_max = float(theta_max)
+        c = None if c_in is None else _f64(c_in, self.lmax + 1, "c_in")
+        h = _c_void_p()
+        _check(lib.conv_split_create(ctypes.byref(h), self.lmax, None if c is None else _d(c), self.theta_max,
+                                     float(sv_cut)), "conv_split_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.conv_split_destroy(self._h)
+            self._h = _c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def nodes(self, theta_cut: float) -> int:
+        n = ctypes.c_int()
+        _check(lib.conv_split_nodes(self._h, float(theta_cut), ctypes.byref(n)), "conv_split_nodes")
+        return n.value
+
+    def lsq(self, k_ell, ell_cut: int, theta_cut: float):
+        """(k_hat[ell_cut+1], k_theta[z_cut], k_real[lmax+1], k_tilde[lmax+1])."""
+        k = _f64(k_ell, self.lmax + 1, "k_ell")
+        n = self.nodes(theta_cut)
+        kh = np.empty(int(ell_cut) + 1 if 0 <= int(ell_cut) <= self.lmax else 1)
+        kt = np.empty(max(n, 1))
+        kr = np.empty(self.lmax + 1)
+        ktl = np.empty(self.lmax + 1)
+        _check(lib.conv_split_lsq(self._h, _d(k), int(ell_cut), float(theta_cut), _d(kh), _d(kt), _d(kr), _d(ktl)),
+               "conv_split_lsq")
+        return kh, kt[:n], kr, ktl
+
+    def error(self, k_ell, ell_cut: int, theta_cut: float, alpha: float = 5.0):
+        """(sigma_rms of Eq. 2, sigma of Eq. 6)."""
+        k = _f64(k_ell, self.lmax + 1, "k_ell")
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib.conv_split_error(self._h, _d(k), int(ell_cut), float(theta_cut), float(alpha), ctypes.byref(a),
+                                    ctypes.byref(b)), "conv_split_error")
+        return a.value, b.value
+
+    def search(self, k_ell, nside: int, bound: float, theta_grid, model: CostModel, alpha: float = 5.0,
+               ell_step: int = 1):
+        """Cheapest feasible (theta_cut, ell_cut, wall, sigma), or None."""
+        k = _f64(k_ell, self.lmax + 1, "k_ell")
+        g = _f64(theta_grid)
+        th, lc, wl, sg = ctypes.c_double(), ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        code = lib.conv_split_search(self._h, _d(k), int(nside), float(bound), float(alpha), _d(g), len(g),
+                                     int(ell_step), ctypes.byref(model._s), ctypes.byref(th), ctypes.byref(lc),
+                                     ctypes.byref(wl), ctypes.byref(sg))
+        if code == INFEASIBLE:
+            return None
+        _check(code, "conv_split_search")
+        return th.value, lc.value, wl.value, sg.value
+
+    def search_many(self, k_ells, nside: int, bounds, theta_grid, model: CostModel, alpha: float = 5.0,
+                    ell_step: int = 1, nthreads: int = 0):
+        """Arrays (theta_cut, ell_cut, wall, sigma) per kernel; theta_cut < 0 marks infeasible."""
+        K = np.ascontiguousarray(k_ells, dtype=np.float64)
+        if K.ndim != 2 or K.shape[1] != self.lmax + 1:
+            raise ConvRealError(-1, "search_many", f"k_ells must be [n, {self.lmax + 1}]")
+        n = K.shape[0]
+        b = _f64(bounds, n, "bounds")
+        g = _f64(theta_grid)
+        th, wl, sg = np.empty(n), np.empty(n), np.empty(n)
+        lc = np.empty(n, dtype=np.int32)
+        _check(lib.conv_split_search_many(self._h, _d(K), n, int(nside), _d(b), float(alpha), _d(g), len(g),
+                                          int(ell_step), ctypes.byref(model._s), int(nthreads), _d(th),
+                                          lc.ctypes.data_as(_iptr_t), _d(wl), _d(sg)), "conv_split_search_many")
+        return th, lc, wl, sg

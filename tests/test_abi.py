@@ -1,6 +1,7 @@
 """The C-ABI library loads, exports every declared entry point, and rejects bad
 arguments on the host before any device call (runs without a GPU)."""
 import ctypes
+import glob
 import math
 import os
 import re
@@ -10,21 +11,28 @@ import pytest
 
 import paper_1409_4441_amd as cr
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "convreal.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
 
 
-def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(conv_real_\w+)\s*\(", text)))
+def declared_functions(header=None):
+    names = set()
+    headers = [header] if header else sorted(glob.glob(os.path.join(INCLUDE, "*.h")))
+    for h in headers:
+        text = open(os.path.join(INCLUDE, h) if header else h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(conv_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported():
+    from paper_1409_4441_amd import split
     names = declared_functions()
-    assert len(names) >= 7
+    assert len(names) >= 20
     for n in names:
         assert hasattr(cr.lib, n), n
-    assert sorted(cr.EXPORTS) == names
+    assert sorted(cr.EXPORTS) == declared_functions("convreal.h")
+    assert sorted(split.EXPORTS) == declared_functions("convsplit.h")
+    assert sorted(set(cr.EXPORTS) | set(split.EXPORTS)) == names
 
 
 def test_strerror():

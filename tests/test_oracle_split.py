@@ -109,3 +109,73 @@ def test_split_search_prefers_balanced_cheap_pair():
     tc, lc, wall, err = best
     assert err <= 1e-4 and tc in grid and 0 <= lc <= lmax
     assert wall == pytest.approx(max(10.0 * tc, (lc / lmax) ** 2))
+
+
+def _eig_ratio(M):
+    lam = np.linalg.eigvalsh(M)
+    return lam.min() / lam.max()
+
+
+def test_reduced_solve_equals_full_solve_when_nothing_is_cut():
+    # the reduced problem is the Schur complement of the identity block of Eq. 3, so both solves
+    # give the same split whenever the eigenvalue cutoff removes nothing from either matrix
+    lmax = 96
+    K = _beam(lmax, 150.0)
+    C = np.ones(lmax + 1)
+    for ell_cut, tc in [(20, 0.12), (12, 0.2), (30, 0.1), (4, 0.15)]:
+        A, z, w = split.design_matrix(lmax, ell_cut, tc)
+        Wd = (2 * np.arange(lmax + 1) + 1.0) * C
+        M = A.T @ (Wd[:, None] * A)
+        Pr = A[ell_cut + 1:, ell_cut + 1:]
+        Mr = Pr.T @ (Wd[ell_cut + 1:, None] * Pr)
+        assert _eig_ratio(M) > 1e-5 and _eig_ratio(Mr) > 1e-5, (ell_cut, tc)
+        kh_full, x_full, _, kt_full = split.lsq_split(K, C, ell_cut, tc)
+        kh, x_red, _, kt_red = split.lsq_split_reduced(K, C, ell_cut, tc)
+        assert np.allclose(x_red, x_full, rtol=1e-9, atol=1e-12 * np.max(np.abs(x_full)))
+        assert np.allclose(kt_red, kt_full, rtol=1e-9, atol=1e-12)
+        assert np.allclose(kh, kh_full, rtol=1e-9, atol=1e-12)
+
+
+def test_reduced_solve_recovers_a_pure_real_space_kernel():
+    # K_l = (P x0)_l for samples x0 inside the cut: the split reproduces K exactly with x = x0
+    lmax = 128
+    tc = 0.15
+    z, w = split.real_space_nodes(lmax, tc)
+    P = split.legendre_operator(lmax, z, w)
+    x0 = np.random.default_rng(3).standard_normal(len(z))
+    K = P @ x0
+    C = np.ones(lmax + 1)
+    for ell_cut in (0, 15, 30):          # normal matrix well conditioned (no eigenvalue cut)
+        kh, x, _, kt = split.lsq_split_reduced(K, C, ell_cut, tc)
+        assert np.allclose(x, x0, rtol=1e-8, atol=1e-10)
+        assert split.rms_error(K, kt, C) <= 1e-9 * np.max(np.abs(K))
+        assert np.allclose(kh, K[: ell_cut + 1] - (P @ x)[: ell_cut + 1], atol=1e-12)
+
+
+def test_reduced_solve_rows_below_cut_are_exact():
+    lmax = 80
+    K = _beam(lmax, 240.0)
+    C = np.ones(lmax + 1)
+    kh, x, z, kt = split.lsq_split_reduced(K, C, 25, 0.2)
+    assert np.array_equal(kt[:26], K[:26])
+    P = split.legendre_operator(lmax, *split.real_space_nodes(lmax, 0.2))
+    assert np.allclose(kh + (P @ x)[:26], K[:26], atol=1e-14)
+    assert np.allclose(kt[26:], (P @ x)[26:], atol=0)
+
+
+def test_cost_fit_recovers_linear_model():
+    pairs = np.array([1e9, 5e9, 2e10, 4.8e10])
+    t_real = 2e-4 + 3e-14 * pairs
+    work = np.array([1e6, 1e8, 1e10]) * 4096
+    t_sht = 2.5e-12 * work
+    a, b, c = split.cost_fit(pairs, t_real, work, t_sht)
+    assert a == pytest.approx(2e-4, rel=1e-9) and b == pytest.approx(3e-14, rel=1e-9)
+    assert c == pytest.approx(2.5e-12, rel=1e-12)
+    assert split.cost_fit([4e9], [1e-3], work, t_sht)[:2] == (0.0, pytest.approx(2.5e-13))
+
+
+def test_pairs_estimate_tracks_the_exact_count():
+    from oracle import convolve
+    for nside, tc in [(16, 0.2), (32, 0.12)]:
+        exact = convolve.pair_count_total(nside, tc)
+        assert split.pairs_estimate(nside, tc) == pytest.approx(exact, rel=0.05)

@@ -1,0 +1,144 @@
+"""The library's split model (include/convsplit.h) against the oracle: Gauss-Legendre samples,
+least-squares split (reduced form of Eqs. 3-5), Eqs. 2 and 6, the cost model and the split scan.
+Host code only: these run without a GPU."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import split as osplit
+
+cr = pytest.importorskip("paper_1409_4441_amd")
+from paper_1409_4441_amd import split  # noqa: E402
+
+ARCMIN = math.pi / (180 * 60)
+
+
+def _beam(lmax, fwhm_arcmin):
+    s = fwhm_arcmin * ARCMIN / math.sqrt(8 * math.log(2))
+    ell = np.arange(lmax + 1)
+    return np.exp(-0.5 * ell * (ell + 1) * s * s)
+
+
+CASES = [  # (lmax, fwhm arcmin, ell_cut, theta_cut)
+    (96, 150.0, 20, 0.12),
+    (128, 120.0, 40, 0.15),      # eigenvalue cutoff active
+    (256, 60.0, 90, 0.06),
+    (512, 30.0, 200, 0.04),
+    (512, 30.0, 511, 0.04),
+    (300, 45.0, 0, 0.08),
+]
+
+
+@pytest.mark.parametrize("lmax,fwhm,ell_cut,tc", CASES)
+def test_lsq_matches_oracle(lmax, fwhm, ell_cut, tc):
+    K = _beam(lmax, fwhm)
+    C = np.ones(lmax + 1)
+    with split.Context(lmax, 0.2) as ctx:
+        kh, kt, kr, ktl = ctx.lsq(K, ell_cut, tc)
+    okh, ox, oz, oktl = osplit.lsq_split_reduced(K, C, ell_cut, tc)
+    assert len(kt) == len(oz)
+    P = osplit.legendre_operator(lmax, *osplit.real_space_nodes(lmax, tc))
+    # The oracle's quadrature weights (NumPy's leggauss) carry relative errors up to ~1e-9 at these
+    # sizes (measured against 40-digit Newton nodes), and a nearly singular reduced problem turns
+    # them into large, mutually cancelling samples; tolerances scale with the summed terms.
+    terms = np.max(np.abs(P) @ np.abs(ox)) if len(ox) else 0.0
+    tol = 1e-11 * np.max(np.abs(K)) + 2e-9 * terms
+    assert np.allclose(ktl, oktl, rtol=1e-9, atol=tol)
+    assert np.allclose(kh, okh, rtol=1e-9, atol=tol)
+    assert np.allclose(kr, P @ ox, rtol=1e-9, atol=tol)
+    # samples in decreasing z on the library side, increasing in the oracle
+    assert np.allclose(kt, ox[::-1], rtol=1e-7, atol=1e-7 * max(1.0, np.max(np.abs(ox), initial=0.0)))
+
+
+@pytest.mark.parametrize("lmax,fwhm,ell_cut,tc", CASES)
+def test_errors_match_oracle(lmax, fwhm, ell_cut, tc):
+    K = _beam(lmax, fwhm)
+    g = np.random.default_rng(lmax)
+    C = np.exp(g.uniform(-1, 1, lmax + 1))
+    with split.Context(lmax, 0.2, c_in=C) as ctx:
+        srms, sig = ctx.error(K, ell_cut, tc, alpha=5.0)
+    _, _, _, oktl = osplit.lsq_split_reduced(K, C, ell_cut, tc)
+    assert srms == pytest.approx(osplit.rms_error(K, oktl, C), rel=1e-8, abs=1e-14)
+    assert sig == pytest.approx(osplit.fractional_error(K, oktl, C, 5.0), rel=1e-8, abs=1e-14)
+
+
+def test_node_counts_match_the_rule():
+    with split.Context(1024, 0.5) as ctx:
+        for tc in (0.01, 0.05, 0.2, 0.5):
+            assert ctx.nodes(tc) == len(osplit.real_space_nodes(1024, tc)[0])
+
+
+def test_cost_model_matches_oracle():
+    pairs = np.array([2e9, 9e9, 4.8e10])
+    t_real = np.array([0.9e-3, 1.7e-3, 4.1e-3])
+    work = np.array([512.0 ** 2 * 1024, 1024.0 ** 2 * 2048, 1500.0 ** 2 * 4096])
+    t_sht = np.array([0.02, 0.2, 1.1])
+    m = split.CostModel.fit(pairs, t_real, work, t_sht)
+    a, b, c = osplit.cost_fit(pairs, t_real, work, t_sht)
+    assert (m.a, m.b, m.c) == (pytest.approx(a, rel=1e-9, abs=1e-15), pytest.approx(b, rel=1e-9),
+                               pytest.approx(c, rel=1e-12))
+    for nside, tc in [(2048, 30 * ARCMIN), (256, 2.0 * math.pi / 180), (64, math.pi)]:
+        assert split.pairs_estimate(nside, tc) == pytest.approx(osplit.pairs_estimate(nside, tc), rel=1e-12)
+    tr, ts, wall = m.eval(2048, 4096, 30 * ARCMIN, 1500)
+    assert tr == pytest.approx(a + b * osplit.pairs_estimate(2048, 30 * ARCMIN), rel=1e-12)
+    assert ts == pytest.approx(c * 1500 ** 2 * 4096, rel=1e-12)
+    assert wall == max(tr, ts)
+
+
+def test_search_matches_oracle_scan():
+    lmax, nside = 128, 64
+    K = _beam(lmax, 100.0)
+    C = np.ones(lmax + 1)
+    m = split.CostModel(1e-4, 1e-12, 1e-9)
+    grid = [0.03, 0.05, 0.08, 0.12]
+    bound = 1e-3
+    with split.Context(lmax, max(grid)) as ctx:
+        got = ctx.search(K, nside, bound, grid, m)
+    want = osplit.split_search(
+        K, C, bound, grid,
+        t_gpu=lambda tc: m.a + m.b * osplit.pairs_estimate(nside, tc),
+        t_cpu=lambda lc: m.c * lc * lc * lmax, solver=osplit.lsq_split_reduced)
+    assert got is not None and want is not None
+    assert got[0] == want[0] and got[1] == want[1]
+    assert got[2] == pytest.approx(want[2], rel=1e-12)
+    assert got[3] == pytest.approx(want[3], rel=1e-8)
+
+
+def test_search_step_and_many():
+    lmax, nside = 200, 128
+    m = split.CostModel(1e-4, 5e-13, 2e-10)
+    grid = np.array([0.02, 0.04, 0.06, 0.09])
+    kernels = np.stack([_beam(lmax, f) for f in (60.0, 80.0, 100.0)])
+    bounds = np.array([1e-3, 1e-4, 1e-2])
+    with split.Context(lmax, grid.max()) as ctx:
+        single = [ctx.search(k, nside, b, grid, m, ell_step=8) for k, b in zip(kernels, bounds)]
+        th, lc, wl, sg = ctx.search_many(kernels, nside, bounds, grid, m, ell_step=8, nthreads=3)
+    for k, s in enumerate(single):
+        assert s is not None
+        assert (th[k], lc[k]) == (s[0], s[1]) and wl[k] == s[2] and sg[k] == s[3]
+        assert lc[k] % 8 == 0 or lc[k] == lmax
+        assert sg[k] <= bounds[k]
+
+
+def test_search_infeasible_and_bad_arguments():
+    lmax = 64
+    K = _beam(lmax, 200.0)
+    m = split.CostModel(0.0, 1e-12, 1e-9)
+    with split.Context(lmax, 0.3) as ctx:
+        with pytest.raises(cr.ConvRealError):
+            ctx.lsq(K, lmax + 1, 0.1)
+        with pytest.raises(cr.ConvRealError):
+            ctx.error(K, 10, 0.31)
+        with pytest.raises(cr.ConvRealError):
+            ctx.search(K, 32, 1e-3, [0.0], m)
+        # ell_cut = lmax is always exact, so a bound is always met; with no real-space sample inside
+        # the cut nothing can replace the dropped coefficients, so that is the only feasible split
+        assert ctx.nodes(1e-3) == 0
+        assert ctx.search(K, 32, 1e-12, [1e-3], m)[1] == lmax
+        best = ctx.search(K, 32, 1e-12, [0.1], m)
+        assert best is not None and best[3] <= 1e-12
+    with pytest.raises(cr.ConvRealError):
+        split.Context(0, 0.1)
+    with pytest.raises(cr.ConvRealError):
+        split.Context(64, 4.0)
