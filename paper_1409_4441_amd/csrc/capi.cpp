@@ -382,6 +382,30 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
     }
     for (int r = 0; r < g.nrings; ++r)
       ring_add[r] = (p->belt_enabled && r >= blo && r <= bhi && roff[r + 1] > roff[r]) ? 1 : 0;
+    // one record per cap-touching ring pair, in the order of the rest list
+    std::vector<double> pA(p->npairs_ring), pB(p->npairs_ring);
+    if ((e = hipMemcpy(pA.data(), p->d_pA, sizeof(double) * pA.size(), hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipMemcpy(pB.data(), p->d_pB, sizeof(double) * pB.size(), hipMemcpyDeviceToHost)) != hipSuccess)
+      return e;
+    std::vector<convreal::CapPair> cpair(ridx.size());
+    for (int r = 0; r < g.nrings; ++r) {
+      for (long long kk = roff[r]; kk < roff[r + 1]; ++kk) {
+        const long long k = ridx[kk];
+        const int j = pj[k];
+        convreal::CapPair& c = cpair[kk];
+        c.A = pA[k];
+        c.B = pB[k];
+        c.hw = hw[k];
+        c.scale = M_PI / (2.0 * static_cast<double>(g.n[r]) * static_cast<double>(g.n[j]));
+        c.xoff = g.start[j];
+        c.xoff_m = g.start[g.nrings - 1 - j];
+        c.nj = g.n[j];
+        c.cj = g.c[j];
+        c.whole = 2.0 * hw[k] >= static_cast<double>(g.n[j]) ? 1 : 0;
+        c.pad = 0;
+      }
+    }
+    if (!cpair.empty() && (e = dev_upload(p, &p->d_cpair, cpair)) != hipSuccess) return e;
     p->n_citems = static_cast<int>(citem_ring.size());
     p->cap_nseg = nseg;
     p->cost_cap.clear();
@@ -440,11 +464,7 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
   d.citem_ring = p->d_citem_ring;
   d.citem_a0 = p->d_citem_a0;
   d.rest_off = p->d_rest_off;
-  d.rest_idx = p->d_rest_idx;
-  d.pj = p->d_pj;
-  d.pA = p->d_pA;
-  d.pB = p->d_pB;
-  d.phw = p->d_phw;
+  d.cpair = p->d_cpair;
   d.inv_h = p->inv_h;
   d.dcut2 = p->dcut2;
   d.inv_sw = static_cast<float>(1.0 / p->belt_sw);

@@ -42,6 +42,22 @@ void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std
 
 constexpr int kMaxSlots = 64;  // maps per persistent mixed-path launch
 
+// One cap-touching ring pair (output ring i, input ring j) as the mixed path's cap tiles read it:
+// one 64-byte record, fetched with a single scalar load per pair and tile.
+struct CapPair {
+  double A;          // (z_i - z_j)^2 + (s_i - s_j)^2
+  double B;          // 4 s_i s_j
+  double hw;         // window half-width in pixels of ring j
+  double scale;      // half azimuth difference per unit of the integer numerator: pi / (2 n_i n_j)
+  long long xoff;    // first pixel of ring j
+  long long xoff_m;  // first pixel of the north/south mirror of ring j
+  int nj;            // pixels of ring j
+  int cj;            // azimuth offset numerator of ring j
+  int whole;         // 1 if the window is the whole ring (2 hw >= n_j)
+  int pad;
+};
+static_assert(sizeof(CapPair) == 64, "CapPair is one 64-byte record");
+
 // Everything the mixed path's device routines read about one plan (lives in device memory).
 struct MixedDesc {
   // geometry
@@ -70,12 +86,8 @@ struct MixedDesc {
   int n_citems;
   const int* citem_ring;
   const int* citem_a0;
-  const long long* rest_off;
-  const long long* rest_idx;
-  const int* pj;
-  const double* pA;
-  const double* pB;
-  const double* phw;
+  const long long* rest_off;  // per ring: first record in cpair
+  const CapPair* cpair;       // cap-touching ring pairs, grouped by output ring
   double inv_h;
   double dcut2;
   float inv_sw;
@@ -178,6 +190,7 @@ struct conv_real_plan {
   int* d_citem_ring = nullptr; // per work item: output ring (north half)
   int* d_citem_a0 = nullptr;   // per work item: first pixel of a 16-pixel tile
   int n_citems = 0;
+  convreal::CapPair* d_cpair = nullptr;  // per cap-touching ring pair, in d_rest_idx order
   int* d_ring_add = nullptr;   // per ring: 1 if it gets a belt and a cap-pair contribution
   int cap_nseg = 0;            // coefficient segments (n_tab - 2) if cap_mode
   convreal::MixedDesc* d_desc = nullptr;  // device copy of the plan's descriptor

@@ -51,6 +51,26 @@ constexpr int kFold = 4;   // ring pairs per FP32 -> FP64 fold
 constexpr int kNKMax = 4;  // largest K-chunk count of a belt weight block
 
 // ---------------------------------------------------------------- shared helpers
+// Load of a value that is the same in every lane and read-only for the kernel's lifetime (plan
+// tables written at set-up): through the constant address space, so that it becomes a scalar load
+// into SGPRs and the compiler treats the result as wave-uniform.
+template <typename T>
+__device__ __forceinline__ T ldu(const T& ref) {
+  return *(const __attribute__((address_space(4))) T*)(&ref);
+}
+
+// the same for a record, word by word (the words merge into one wide scalar load)
+template <typename T>
+__device__ __forceinline__ T ldu_record(const T& ref) {
+  static_assert(sizeof(T) % 4 == 0, "records are whole 32-bit words");
+  T out;
+  const __attribute__((address_space(4))) unsigned* src = (const __attribute__((address_space(4))) unsigned*)(&ref);
+  unsigned* dst = reinterpret_cast<unsigned*>(&out);
+#pragma unroll
+  for (int k = 0; k < static_cast<int>(sizeof(T) / 4); ++k) dst[k] = src[k];
+  return out;
+}
+
 // power of two s with max|x| * s in [2^12, 2^13)
 __device__ __forceinline__ float map_scale(unsigned bits) {
   const float mx = __uint_as_float(bits);
@@ -182,20 +202,25 @@ __device__ void belt_item(const convreal::MixedDesc* __restrict__ d, int idx, co
                           float* __restrict__ ym, float sx, _Float16* __restrict__ S) {
   using BL = BeltLayout<SEG>;
   constexpr int NB = SEG / (16 * kWaves);  // 16-pixel blocks per wave
-  const int nsegs = (d->ring_n + SEG - 1) / SEG;
+  const int ring_n = ldu(d->ring_n);
+  const int nsegs = (ring_n + SEG - 1) / SEG;
   const int band = idx / nsegs;
   const int seg = idx % nsegs;
   const int a0 = seg * SEG;
-  const int jf = d->band_jf[band];
-  const int nj = d->band_nj[band];
-  const int woff = d->band_woff[band];
+  const int jf = ldu(d->band_jf[band]);
+  const int nj = ldu(d->band_nj[band]);
+  const int woff = ldu(d->band_woff[band]);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int n = lane & 15;
   const int g = lane >> 4;
   const int cpy = n & 7;
   const int lane_off = cpy * BL::CS + 16 * (NB * wave) + (n - cpy) + 8 * g;
-  const half8* wt = reinterpret_cast<const half8*>(d->wt);
+  const half8* wt = reinterpret_cast<const half8*>(ldu(d->wt));
+  const long long* rstart = ldu(d->rstart);
+  const int* blk_mlo = ldu(d->blk_mlo);
+  const int* blk_nk = ldu(d->blk_nk);
+  const int* blk_koff = ldu(d->blk_koff);
 
   floatx4 acc[NB];
   double accd[NB][4];
@@ -206,15 +231,15 @@ __device__ void belt_item(const convreal::MixedDesc* __restrict__ d, int idx, co
     for (int r = 0; r < 4; ++r) accd[b][r] = 0.0;
   }
 
-  stage_ring<SEG>(S, xm + d->rstart[jf], a0 + d->blk_mlo[woff], SEG + 32 * d->blk_nk[woff], d->ring_n, sx);
+  stage_ring<SEG>(S, xm + ldu(rstart[jf]), a0 + ldu(blk_mlo[woff]), SEG + 32 * ldu(blk_nk[woff]), ring_n, sx);
   __syncthreads();
   for (int jj = 0; jj < nj; ++jj) {
     const int buf = jj & 1;
     if (jj + 1 < nj)
-      stage_ring<SEG>(S + (buf ^ 1) * BL::BUF, xm + d->rstart[jf + jj + 1], a0 + d->blk_mlo[woff + jj + 1],
-                      SEG + 32 * d->blk_nk[woff + jj + 1], d->ring_n, sx);
-    const int nk = d->blk_nk[woff + jj];
-    const half8* wblk = wt + static_cast<long long>(d->blk_koff[woff + jj]) * 128;
+      stage_ring<SEG>(S + (buf ^ 1) * BL::BUF, xm + ldu(rstart[jf + jj + 1]), a0 + ldu(blk_mlo[woff + jj + 1]),
+                      SEG + 32 * ldu(blk_nk[woff + jj + 1]), ring_n, sx);
+    const int nk = ldu(blk_nk[woff + jj]);
+    const half8* wblk = wt + static_cast<long long>(ldu(blk_koff[woff + jj])) * 128;
     const _Float16* Sb = S + buf * BL::BUF + lane_off;
     for (int q = 0; q < nk; ++q) {
       const half8 whi = wblk[q * 128 + lane];
@@ -243,77 +268,107 @@ __device__ void belt_item(const convreal::MixedDesc* __restrict__ d, int idx, co
     __syncthreads();
   }
 
-  const double inv = static_cast<double>(d->inv_sw) / static_cast<double>(sx);
+  const double inv = static_cast<double>(ldu(d->inv_sw)) / static_cast<double>(sx);
+  const int belt_lo = ldu(d->belt_lo), belt_hi = ldu(d->belt_hi);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int px = a0 + 16 * (NB * wave + b) + n;
-    if (px >= d->ring_n) continue;
+    if (px >= ring_n) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int ring = d->belt_lo + 16 * band + 4 * g + r;
-      if (ring <= d->belt_hi) put(ym + d->rstart[ring] + px, accd[b][r] * inv, d->ring_add[ring] != 0);
+      const int ring = belt_lo + 16 * band + 4 * g + r;
+      if (ring <= belt_hi) put(ym + rstart[ring] + px, accd[b][r] * inv, ldu(d->ring_add)[ring] != 0);
     }
   }
 }
 
 // ---------------------------------------------------------------- cap item
-__device__ __forceinline__ double sin2_of(double alpha) {
-  // sin^2(alpha) = t P(t), t = alpha^2; P fitted on t in [0, 2.6] (|alpha| <= 1.61), relative
-  // error below 1e-11 there.
-  const double t = alpha * alpha;
-  double p = -1.366547170656072e-09;
-  p = fma(p, t, 9.31392155360743e-08);
-  p = fma(p, t, -4.273732374386684e-06);
-  p = fma(p, t, 0.00014109120522641625);
-  p = fma(p, t, -0.0031746016082493094);
-  p = fma(p, t, 0.04444444389087041);
-  p = fma(p, t, -0.3333333332512937);
-  p = fma(p, t, 0.9999999999970449);
-  return t * p;
+// sin^2(al) / al^2 as a polynomial in t = al^2 (al = half the azimuth difference). Each ring pair
+// scales the coefficients by B_ij, so that d^2 = A_ij + t * poly(t).
+//   short form, |al| <= 0.2 (t <= 0.04): relative error below 3e-12
+//   long form, |al| <= 1.61 (t <= 2.6): relative error below 1e-11
+// Either error moves d by far less than the 1e-7-pixel slack of the pair windows.
+constexpr double kShortAlpha = 0.2;
+constexpr double kSinShort[4] = {0.9999999999971675, -0.33333333107313623, 0.04444416233415409,
+                                 -0.0031633255222186167};
+constexpr double kSinLong[8] = {0.9999999999970449,     -0.3333333332512937,     0.04444444389087041,
+                                -0.0031746016082493094, 0.00014109120522641625,  -4.273732374386684e-06,
+                                9.31392155360743e-08,   -1.366547170656072e-09};
+
+// Omega s_w Ktilde(d) from q = (d / h)^2, the squared chord in units of the table spacing (0 beyond
+// the cut q > qcut). t = d / h comes from a single-precision reciprocal square root refined by one
+// Newton step in FP64 (relative error ~1e-14); segment floor(t), local coordinate frac(t). Lanes
+// beyond the cut clamp the segment so that they stay inside the coefficient table; inside the cut
+// t <= (n_tab - 3)(1 + 1e-9), so the clamp never moves a kept pair.
+__device__ __forceinline__ float weight_of(double q, double qcut, int seg_max, const float4* __restrict__ s_coef) {
+  const float y0 = __builtin_amdgcn_rsqf(fmaxf(static_cast<float>(q), 1e-30f));
+  const double y = static_cast<double>(y0);
+  const double t0 = q * y;
+  const double r = fma(-t0, t0, q);
+  const double t = fma(r, 0.5 * y, t0);
+  const int sg = min(static_cast<int>(t), seg_max);
+  const float f = static_cast<float>(__builtin_amdgcn_fract(t));
+  const float4 c = s_coef[sg];
+  const float w = fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
+  return q <= qcut ? w : 0.0f;
 }
 
-// sqrt for d^2 > 0 from the hardware reciprocal square root and one Newton step; 0 for d^2 = 0
-__device__ __forceinline__ double chord_of(double d2) {
-  double y = __builtin_amdgcn_rsq(d2);
-  y = y * fma(-0.5 * d2, y * y, 1.5);
-  return d2 > 0.0 ? d2 * y : 0.0;
+// v mod n for |v| < 2^24, n > 0 (reciprocal-based quotient, corrected by one step either way)
+__device__ __forceinline__ int mod_any(int v, int n, float rcp_n) {
+  const int q = static_cast<int>(floorf(static_cast<float>(v) * rcp_n));
+  int m = v - q * n;
+  m = m < 0 ? m + n : m;
+  return m >= n ? m - n : m;
 }
 
-// first and last input pixel of ring j in the window of output pixel a of ring i
-__device__ __forceinline__ void row_window(int a, int ni, int ci, int nj, int cj, double hw, bool whole,
-                                           long long* lo, long long* hi) {
-  const double bc =
-      static_cast<double>(static_cast<long long>(2 * a + ci) * nj - static_cast<long long>(cj) * ni) / (2.0 * ni);
-  if (whole) {
-    *lo = static_cast<long long>(floor(bc)) - nj / 2;
-    *hi = *lo + nj - 1;
-  } else {
-    *lo = static_cast<long long>(ceil(bc - hw - 1e-7));
-    *hi = static_cast<long long>(floor(bc + hw + 1e-7));
+__device__ __forceinline__ void split8(const float (&v)[8], half8& hi, half8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const _Float16 h = static_cast<_Float16>(v[e]);
+    hi[e] = h;
+    lo[e] = static_cast<_Float16>(v[e] - static_cast<float>(h));
   }
 }
 
-__device__ __forceinline__ long long wrap_num(long long v, long long M) {
-  const long long m2 = 2 * M;
-  while (v > M) v -= m2;
-  while (v <= -M) v += m2;
-  return v;
-}
-
-__device__ __forceinline__ int mod_pos(long long v, int n) {
-  long long r = v % n;
-  if (r < 0) r += n;
-  return static_cast<int>(r);
+// B operand of one K-chunk: image col of inputs b = bA .. bA + 7, i.e. pixels pofs + dir * b (mod nj)
+// of the lane's ring, scaled by sx. Lanes read 8 consecutive pixels (reversed for reflected images);
+// the wave takes the no-wrap branch when no lane crosses the ring's start.
+__device__ __forceinline__ void load_inputs(const float* __restrict__ xj, int pofs, int dir, int bA, int nj,
+                                            float rcp_n, float sx, half8& xhi, half8& xlo) {
+  const int p0 = mod_any(pofs + dir * bA, nj, rcp_n);
+  const int s = dir > 0 ? p0 : p0 - 7;   // lowest pixel index read by this lane
+  float v[8];
+  if (__all(s >= 0 && s + 7 < nj)) {
+    const float* xp = xj + s;
+    float L[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) L[e] = xp[e];
+    // forward lanes keep the order, reflected lanes reverse it (a bitwise select per element)
+    const unsigned fwd = dir > 0 ? 0xffffffffu : 0u;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      v[e] = __uint_as_float((fwd & __float_as_uint(L[e])) | (~fwd & __float_as_uint(L[7 - e]))) * sx;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int idx = p0 + dir * e;
+      idx = idx < 0 ? idx + nj : idx;
+      idx = idx >= nj ? idx - nj : idx;
+      v[e] = xj[idx] * sx;
+    }
+  }
+  split8(v, xhi, xlo);
 }
 
 // one wave: tile t (16 output pixels of the fundamental domain of one north-half ring)
-__device__ void cap_tile(const convreal::MixedDesc* __restrict__ d, int t, const float* __restrict__ xm,
-                         float* __restrict__ ym, float sx, const float4* __restrict__ s_coef) {
-  const int r = d->citem_ring[t];
-  const int a0 = d->citem_a0[t];
-  const int ni = d->rn[r];
-  const int ci = d->rc[r];
-  const int mr = d->nrings - 1 - r;
+__device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__ d, int t,
+                                         const float* __restrict__ xm, float* __restrict__ ym, float sx,
+                                         const float4* __restrict__ s_coef) {
+  const int r = ldu(ldu(d->citem_ring)[t]);
+  const int a0 = ldu(ldu(d->citem_a0)[t]);
+  const int ni = ldu(ldu(d->rn)[r]);
+  const int ci = ldu(ldu(d->rc)[r]);
+  const int mr = ldu(d->nrings) - 1 - r;
   const int lane = threadIdx.x & 63;
   const int row = lane & 15;       // A operand: output pixel a0 + row
   const int kgrp = lane >> 4;      // A and B operands: k-group of 8
@@ -321,75 +376,130 @@ __device__ void cap_tile(const convreal::MixedDesc* __restrict__ d, int t, const
   const int ch = col >> 3;         // hemisphere
   const int cf = (col >> 2) & 1;   // reflection
   const int cq = col & 3;          // quarter turn
-  const int arow = a0 + row;
+  const int dir = cf ? -1 : 1;
+  const int u_row = 2 * (a0 + row) + ci;    // azimuth numerator of the lane's output pixel
+  const int u_first = 2 * a0 + ci;
+  const int u_last = 2 * (a0 + 15) + ci;
+  // squared chords are formed directly in units of the table spacing: q = d^2 / h^2
+  const double inv_h = ldu(d->inv_h);
+  const double ih2 = inv_h * inv_h;
+  const double qcut = ldu(d->dcut2) * ih2;
+  const int seg_max = ldu(d->nseg) - 1;
 
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   double accd[4] = {0.0, 0.0, 0.0, 0.0};
-  const long long k0 = d->rest_off[r];
-  const long long k1 = d->rest_off[r + 1];
+  const long long* rest_off = ldu(d->rest_off);
+  const convreal::CapPair* cpair = ldu(d->cpair);
+  const long long k0 = ldu(rest_off[r]);
+  const long long k1 = ldu(rest_off[r + 1]);
   int nfold = 0;
   for (long long kk = k0; kk < k1; ++kk) {
-    const long long k = d->rest_idx[kk];
-    const int j = d->pj[k];
-    const int nj = d->rn[j];
-    const int cj = d->rc[j];
-    const double hw = d->phw[k];
-    const double A = d->pA[k];
-    const double B = d->pB[k];
-    const bool whole = 2.0 * hw >= static_cast<double>(nj);
-    long long b0, bend, lo_r, hi_r, tmp;
-    row_window(a0, ni, ci, nj, cj, hw, whole, &b0, &tmp);
-    row_window(a0 + 15, ni, ci, nj, cj, hw, whole, &tmp, &bend);
-    row_window(arow, ni, ci, nj, cj, hw, whole, &lo_r, &hi_r);
-    const int K = static_cast<int>(bend - b0 + 1);
+    const convreal::CapPair P = ldu_record(cpair[kk]);
+    const int nj = P.nj;
+    const int cj = P.cj;
+    // union of the 16 rows' windows [b0, bend] (the rows' centres increase with a)
+    const double bc0 = static_cast<double>(u_first * nj - cj * ni) / (2.0 * ni);
+    const double bc1 = static_cast<double>(u_last * nj - cj * ni) / (2.0 * ni);
+    int b0, bend;
+    if (P.whole) {
+      b0 = static_cast<int>(floor(bc0)) - nj / 2;
+      bend = static_cast<int>(floor(bc1)) - nj / 2 + nj - 1;
+    } else {
+      b0 = static_cast<int>(ceil(bc0 - P.hw - 1e-7));
+      bend = static_cast<int>(floor(bc1 + P.hw + 1e-7));
+    }
+    const int K = bend - b0 + 1;
     if (K <= 0) continue;
     const int nk = (K + 31) >> 5;
-    const long long M = static_cast<long long>(ni) * nj;
-    const double alpha_scale = M_PI / (2.0 * static_cast<double>(M));
-    const int jh = ch ? (d->nrings - 1 - j) : j;
-    const float* xj = xm + d->rstart[jh];
-    const int qoff = cq * (nj >> 2);
-    for (int q = 0; q < nk; ++q) {
-      // A operand: weights of row arow for inputs b = b0 + 32q + 8 kgrp + e; the FP64 test
-      // d^2 <= d_cut^2 decides the pairs in the window's slack exactly as the per-pair path does
-      const long long bA = b0 + 32 * q + 8 * kgrp;
-      long long num = wrap_num(static_cast<long long>(2 * arow + ci) * nj - (2 * bA + cj) * static_cast<long long>(ni), M);
-      half8 whi, wlo;
+    const int blast = b0 + 32 * nk - 1;
+    const float* xj = xm + (ch ? P.xoff_m : P.xoff);
+    const int pofs = cf ? (nj - cj + cq * (nj >> 2)) : cq * (nj >> 2);
+    const float rcp_n = 1.0f / static_cast<float>(nj);
+    // largest |numerator| over the tile's rows and padded inputs: the numerator grows with a and
+    // falls with b, so the extremes sit at (last row, b0) and (first row, blast)
+    const double lim = kShortAlpha / P.scale;
+    const bool shortform = static_cast<double>(u_last * nj - (2 * b0 + cj) * ni) <= lim &&
+                           -static_cast<double>(u_first * nj - (2 * blast + cj) * ni) <= lim;
+    if (shortform) {
+      // |al| <= 0.2 on every (row, input) of the tile: no wrap of the numerator, and every padded
+      // input lies outside the cut (d^2 > d_cut^2 decides), so no per-row window test is needed
+      const double Bh = P.B * ih2;
+      const double Ah = P.A * ih2;
+      const double c0 = Bh * kSinShort[0], c1 = Bh * kSinShort[1], c2 = Bh * kSinShort[2], c3 = Bh * kSinShort[3];
+      const double delta = 2.0 * static_cast<double>(ni) * P.scale;   // al step per input pixel
+      for (int q = 0; q < nk; ++q) {
+        const int bA = b0 + 32 * q + 8 * kgrp;
+        half8 xhi, xlo;
+        load_inputs(xj, pofs, dir, bA, nj, rcp_n, sx, xhi, xlo);
+        double al = static_cast<double>(u_row * nj - (2 * bA + cj) * ni) * P.scale;
+        float w[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const long long b = bA + e;
-        float w = 0.0f;
-        const double d2 = fma(B, sin2_of(static_cast<double>(num) * alpha_scale), A);
-        if (b >= lo_r && b <= hi_r && d2 <= d->dcut2) {
-          const double tt = chord_of(d2) * d->inv_h;
-          int sg = static_cast<int>(tt);
-          sg = min(sg, d->nseg - 1);
-          const float f = static_cast<float>(tt - static_cast<double>(sg));
-          const float4 c = s_coef[sg];
-          w = fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
+        for (int e = 0; e < 8; ++e) {
+          const double tq = al * al;
+          const double bp = fma(fma(fma(c3, tq, c2), tq, c1), tq, c0);
+          w[e] = weight_of(fma(tq, bp, Ah), qcut, seg_max, s_coef);
+          al -= delta;
         }
-        const _Float16 h = static_cast<_Float16>(w);
-        whi[e] = h;
-        wlo[e] = static_cast<_Float16>(w - static_cast<float>(h));
-        num = wrap_num(num - 2 * static_cast<long long>(ni), M);
+        half8 whi, wlo;
+        split8(w, whi, wlo);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
       }
-      // B operand: image col of the same inputs
-      int p = cf ? mod_pos(static_cast<long long>(nj) - bA - cj + qoff, nj) : mod_pos(bA + qoff, nj);
-      half8 xhi, xlo;
+    } else {
+      // general form (rings near a pole): numerator reduced to [-M, M], the long polynomial, and
+      // the lane's own window [lo_r, hi_r], which also keeps a pixel from entering twice when the
+      // union is wider than the ring
+      const double Bh = P.B * ih2;
+      const double Ah = P.A * ih2;
+      double cl[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float xs = xj[p] * sx;
-        const _Float16 h = static_cast<_Float16>(xs);
-        xhi[e] = h;
-        xlo[e] = static_cast<_Float16>(xs - static_cast<float>(h));
-        if (cf)
-          p = (p == 0) ? nj - 1 : p - 1;
-        else
-          p = (p + 1 == nj) ? 0 : p + 1;
+      for (int u = 0; u < 8; ++u) cl[u] = Bh * kSinLong[u];
+      const double Md = static_cast<double>(ni) * static_cast<double>(nj);
+      const double twoM = 2.0 * Md;
+      const double inv_twoM = 1.0 / twoM;
+      const double two_ni = 2.0 * static_cast<double>(ni);
+      const double bcr = static_cast<double>(u_row * nj - cj * ni) / (2.0 * ni);
+      int lo_r, hi_r;
+      if (P.whole) {
+        lo_r = static_cast<int>(floor(bcr)) - nj / 2;
+        hi_r = lo_r + nj - 1;
+      } else {
+        lo_r = static_cast<int>(ceil(bcr - P.hw - 1e-7));
+        hi_r = static_cast<int>(floor(bcr + P.hw + 1e-7));
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
+      for (int q = 0; q < nk; ++q) {
+        const int bA = b0 + 32 * q + 8 * kgrp;
+        half8 xhi, xlo;
+        {
+          float v[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] = xj[mod_any(pofs + dir * (bA + e), nj, rcp_n)] * sx;
+          split8(v, xhi, xlo);
+        }
+        double nd = static_cast<double>(u_row * nj - (2 * bA + cj) * ni);
+        nd = fma(-rint(nd * inv_twoM), twoM, nd);
+        float w[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          double ne = nd - static_cast<double>(e) * two_ni;
+          ne = ne < -Md ? ne + twoM : ne;
+          ne = ne < -Md ? ne + twoM : ne;
+          const double al = ne * P.scale;
+          const double tq = al * al;
+          double bp = cl[7];
+#pragma unroll
+          for (int u = 6; u >= 0; --u) bp = fma(bp, tq, cl[u]);
+          const float wv = weight_of(fma(tq, bp, Ah), qcut, seg_max, s_coef);
+          const int b = bA + e;
+          w[e] = (b >= lo_r && b <= hi_r) ? wv : 0.0f;
+        }
+        half8 whi, wlo;
+        split8(w, whi, wlo);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
+      }
     }
     if (++nfold == kFold) {
       nfold = 0;
@@ -407,19 +517,19 @@ __device__ void cap_tile(const convreal::MixedDesc* __restrict__ d, int t, const
   const int F = ((ni >> 2) - ci) / 2 + 1;
   if (ch && mr == r) return;
   const int rr = ch ? mr : r;
-  const double inv = static_cast<double>(d->inv_sw) / static_cast<double>(sx);
-  float* yr = ym + d->rstart[rr];
-  const bool add = d->ring_add[rr] != 0;
+  const double inv = static_cast<double>(ldu(d->inv_sw)) / static_cast<double>(sx);
+  float* yr = ym + ldu(ldu(d->rstart)[rr]);
+  const bool add = ldu(ldu(d->ring_add)[rr]) != 0;
   const int quarter = ni >> 2;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int ao = a0 + 4 * kgrp + u;
     if (ao >= F) continue;
     if (cf && ((2 * ao + ci) % quarter) == 0) continue;
-    int P = cf ? (ni - ao - ci + cq * quarter) : (ao + cq * quarter);
-    P %= ni;
-    if (P < 0) P += ni;
-    put(yr + P, accd[u] * inv, add);
+    int Pp = cf ? (ni - ao - ci + cq * quarter) : (ao + cq * quarter);
+    Pp %= ni;
+    if (Pp < 0) Pp += ni;
+    put(yr + Pp, accd[u] * inv, add);
   }
 }
 
@@ -438,31 +548,39 @@ __global__ __launch_bounds__(kBlock, 2) void mixed_persistent_kernel(convreal::S
   _Float16* stage = reinterpret_cast<_Float16*>(lds);
   float4* s_coef = reinterpret_cast<float4*>(lds + coef_offset_bytes);
   if (threadIdx.x == 0) s_coef_owner = nullptr;
-  const long long total = static_cast<long long>(n_items) * nrep;
+  const int total = n_items * nrep;   // the host keeps this below 2^31
   for (;;) {
     if (threadIdx.x == 0) s_item = static_cast<int>(atomicAdd(counter, 1u));
     __syncthreads();
-    const long long gi = s_item;
-    const convreal::MixedDesc* owner = s_coef_owner;
+    // values read from LDS are the same in every lane; readfirstlane tells the compiler so, which
+    // keeps the item's descriptor and its pointers in scalar registers and their loads scalar
+    const int gi = __builtin_amdgcn_readfirstlane(s_item);
+    const unsigned long long ow = reinterpret_cast<unsigned long long>(s_coef_owner);
+    const unsigned long long ow_u =
+        static_cast<unsigned long long>(static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(ow)))) |
+        (static_cast<unsigned long long>(static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(ow >> 32))))
+         << 32);
+    const convreal::MixedDesc* owner = reinterpret_cast<const convreal::MixedDesc*>(ow_u);
     __syncthreads();
     if (gi >= total) break;
-    const int2 it = items[gi % n_items];
+    const int2 it = ldu_record(items[gi % n_items]);
     const int slot = it.x + static_cast<int>(gi / n_items);
     const int kind = it.y >> 30;
     const int idx = it.y & 0x3fffffff;
     const convreal::MixedDesc* d = S.desc[slot];
-    const float sx = map_scale(amax[slot]);
+    const float sx = map_scale(ldu(amax[slot]));
     if (kind == 0) {
       belt_item<SEG>(d, idx, S.x[slot], S.y[slot], sx, stage);
     } else {
       if (owner != d) {
-        const float4* coef = reinterpret_cast<const float4*>(d->coef);
-        for (int k = threadIdx.x; k < d->nseg; k += kBlock) s_coef[k] = coef[k];
+        const float4* coef = reinterpret_cast<const float4*>(ldu(d->coef));
+        const int nseg = ldu(d->nseg);
+        for (int k = threadIdx.x; k < nseg; k += kBlock) s_coef[k] = coef[k];
         __syncthreads();
         if (threadIdx.x == 0) s_coef_owner = d;
       }
-      const int t = idx * kWaves + (threadIdx.x >> 6);
-      if (t < d->n_citems) cap_tile(d, t, S.x[slot], S.y[slot], sx, s_coef);
+      const int t = idx * kWaves + __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+      if (t < ldu(d->n_citems)) cap_tile(d, t, S.x[slot], S.y[slot], sx, s_coef);
     }
     __syncthreads();
   }
@@ -523,6 +641,7 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     long long total = static_cast<long long>(n_items) * nrep;
+    if (total >= (1LL << 31)) return hipErrorInvalidValue;   // item counter is 32-bit
     long long grid = static_cast<long long>(ncu) * (tune.wg_per_cu > 0 ? tune.wg_per_cu : 2);
     if (grid > total) grid = total;
     if (tune.seg == 512)
