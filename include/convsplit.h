@@ -99,10 +99,10 @@ int conv_split_search(conv_split_ctx* ctx, const double* k_ell, int nside, doubl
                       double* theta_cut, int* ell_cut, double* wall, double* sigma);
 
 /* The search for n kernels at once on worker threads (nthreads <= 0: hardware threads):
- * k_ells is n x (lmax + 1) row-major, bounds[n]; outputs are n-arrays, theta_cut[k] < 0 marks an
- * infeasible kernel. */
+ * k_ells is n x (lmax + 1) row-major, bounds[n], theta_grids n x n_theta row-major (one scan grid
+ * per kernel); outputs are n-arrays, theta_cut[k] < 0 marks an infeasible kernel. */
 int conv_split_search_many(conv_split_ctx* ctx, const double* k_ells, int n, int nside, const double* bounds,
-                           double alpha, const double* theta_grid, int n_theta, int ell_step,
+                           double alpha, const double* theta_grids, int n_theta, int ell_step,
                            const conv_cost_model* m, int nthreads, double* theta_cut, int* ell_cut, double* wall,
                            double* sigma);
 

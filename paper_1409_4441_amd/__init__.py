@@ -101,6 +101,26 @@ def _load():
 lib = _load()
 
 
+_RUNTIME_READY = False
+
+
+def device_runtime():
+    """Initialise PyTorch's device runtime before the library's first device call. PyTorch ships its
+    own HIP runtime next to the system one the library links; the two coexist in one process (they
+    share the device's address space, so tensors pass straight to the library), but only when
+    PyTorch's starts first: started second, it finds no device."""
+    global _RUNTIME_READY
+    if _RUNTIME_READY:
+        return
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
+    _RUNTIME_READY = True
+
+
 def _check(code: int, where: str):
     if code != OK:
         msg = lib.conv_real_last_error().decode() or lib.conv_real_strerror(code).decode()
@@ -113,6 +133,7 @@ def _dptr(a: np.ndarray):
 
 def tabulate(k_ell, theta_cut: float, n_tab: int) -> np.ndarray:
     """K(d_k) = sum_l (2l+1)/(4 pi) k_l P_l(cos theta_k) on the plan's chord nodes (device FP64)."""
+    device_runtime()
     k = np.ascontiguousarray(k_ell, dtype=np.float64)
     out = np.empty(int(n_tab), dtype=np.float64)
     _check(lib.conv_real_tabulate(_dptr(k), len(k) - 1, float(theta_cut), int(n_tab), _dptr(out)),
@@ -133,6 +154,7 @@ class Plan:
     def __init__(self, nside: int, table, theta_cut: float, precision: str = "f64"):
         if precision not in _PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
+        device_runtime()
         t = np.ascontiguousarray(table, dtype=np.float64)
         handle = ctypes.c_void_p()
         _check(lib.conv_real_init(ctypes.byref(handle), int(nside), _dptr(t), len(t),

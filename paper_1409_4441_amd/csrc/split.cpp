@@ -106,6 +106,8 @@ void gauss_legendre_above(int n, double zmin, std::vector<double>& z, std::vecto
   }
 }
 
+constexpr size_t kCacheBytes = size_t(512) << 20;  // eigen-decompositions kept per context
+
 struct Eig {
   std::vector<double> lam;  // n
   std::vector<double> V;    // n x n, columns are eigenvectors
@@ -125,6 +127,7 @@ struct conv_split_ctx {
   // (z_cut, ell_cut) -> eigen-decomposition of the normal matrix; shared so that a worker keeps its
   // entry alive when another one clears the cache
   std::map<std::pair<int, int>, std::shared_ptr<const Eig>> cache;
+  size_t cache_bytes = 0;
 };
 
 namespace {
@@ -159,8 +162,13 @@ std::shared_ptr<const Eig> normal_eigen(conv_split_ctx* c, int n, int ell_cut) {
   auto e = std::make_shared<Eig>();
   jacobi_eigen(n, M, e->lam, e->V);
   std::lock_guard<std::mutex> g(c->mu);
-  if (c->cache.size() > 8192) c->cache.clear();
+  const size_t bytes = sizeof(double) * (static_cast<size_t>(n) * n + n);
+  if (c->cache_bytes + bytes > kCacheBytes) {
+    c->cache.clear();
+    c->cache_bytes = 0;
+  }
   auto res = c->cache.emplace(std::make_pair(n, ell_cut), e);
+  if (res.second) c->cache_bytes += bytes;
   return res.first->second;
 }
 
@@ -499,15 +507,17 @@ int conv_split_search(conv_split_ctx* ctx, const double* k_ell, int nside, doubl
 }
 
 int conv_split_search_many(conv_split_ctx* ctx, const double* k_ells, int n, int nside, const double* bounds,
-                           double alpha, const double* theta_grid, int n_theta, int ell_step,
+                           double alpha, const double* theta_grids, int n_theta, int ell_step,
                            const conv_cost_model* m, int nthreads, double* theta_cut, int* ell_cut, double* wall,
                            double* sigma) {
-  if (int e = check_search(ctx, nside, alpha, theta_grid, n_theta, ell_step, m, "conv_split_search_many")) return e;
   if (!k_ells || !bounds || n < 0 || !theta_cut || !ell_cut || !wall || !sigma) {
     set_error("conv_split_search_many: NULL argument or n < 0");
     return CONV_REAL_EINVAL;
   }
   for (int k = 0; k < n; ++k) {
+    if (int e = check_search(ctx, nside, alpha, theta_grids + static_cast<size_t>(k) * n_theta, n_theta, ell_step, m,
+                             "conv_split_search_many"))
+      return e;
     if (!(bounds[k] > 0.0)) {
       set_error("conv_split_search_many: bounds must be > 0");
       return CONV_REAL_EINVAL;
@@ -521,8 +531,8 @@ int conv_split_search_many(conv_split_ctx* ctx, const double* k_ells, int n, int
       const int k = next.fetch_add(1);
       if (k >= n) break;
       const double* K = k_ells + static_cast<size_t>(k) * (ctx->lmax + 1);
-      if (!search_one(ctx, K, nside, bounds[k], alpha, theta_grid, n_theta, ell_step, m, &theta_cut[k], &ell_cut[k],
-                      &wall[k], &sigma[k])) {
+      if (!search_one(ctx, K, nside, bounds[k], alpha, theta_grids + static_cast<size_t>(k) * n_theta, n_theta,
+                      ell_step, m, &theta_cut[k], &ell_cut[k], &wall[k], &sigma[k])) {
         theta_cut[k] = -1.0;
         ell_cut[k] = -1;
         wall[k] = 0.0;

@@ -176,16 +176,20 @@ class Context:
 
     def search_many(self, k_ells, nside: int, bounds, theta_grid, model: CostModel, alpha: float = 5.0,
                     ell_step: int = 1, nthreads: int = 0):
-        """Arrays (theta_cut, ell_cut, wall, sigma) per kernel; theta_cut < 0 marks infeasible."""
+        """Arrays (theta_cut, ell_cut, wall, sigma) per kernel; theta_cut < 0 marks infeasible.
+        theta_grid is one grid for all kernels or one row per kernel."""
         K = np.ascontiguousarray(k_ells, dtype=np.float64)
         if K.ndim != 2 or K.shape[1] != self.lmax + 1:
             raise ConvRealError(-1, "search_many", f"k_ells must be [n, {self.lmax + 1}]")
         n = K.shape[0]
         b = _f64(bounds, n, "bounds")
-        g = _f64(theta_grid)
+        g = np.asarray(theta_grid, dtype=np.float64)
+        g = np.ascontiguousarray(np.broadcast_to(g, (n, g.shape[-1])) if g.ndim == 1 else g)
+        if g.shape[0] != n:
+            raise ConvRealError(-1, "search_many", "theta_grid must be [n_theta] or [n, n_theta]")
         th, wl, sg = np.empty(n), np.empty(n), np.empty(n)
         lc = np.empty(n, dtype=np.int32)
-        _check(lib.conv_split_search_many(self._h, _d(K), n, int(nside), _d(b), float(alpha), _d(g), len(g),
+        _check(lib.conv_split_search_many(self._h, _d(K), n, int(nside), _d(b), float(alpha), _d(g), g.shape[1],
                                           int(ell_step), ctypes.byref(model._s), int(nthreads), _d(th),
                                           lc.ctypes.data_as(_iptr_t), _d(wl), _d(sg)), "conv_split_search_many")
         return th, lc, wl, sg

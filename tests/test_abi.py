@@ -25,14 +25,15 @@ def declared_functions(header=None):
 
 
 def test_every_declared_symbol_is_exported():
-    from paper_1409_4441_amd import split
+    from paper_1409_4441_amd import learn, split
     names = declared_functions()
-    assert len(names) >= 20
+    assert len(names) >= 30
     for n in names:
         assert hasattr(cr.lib, n), n
     assert sorted(cr.EXPORTS) == declared_functions("convreal.h")
     assert sorted(split.EXPORTS) == declared_functions("convsplit.h")
-    assert sorted(set(cr.EXPORTS) | set(split.EXPORTS)) == names
+    assert sorted(learn.EXPORTS) == declared_functions("convlearn.h")
+    assert sorted(set(cr.EXPORTS) | set(split.EXPORTS) | set(learn.EXPORTS)) == names
 
 
 def test_strerror():
