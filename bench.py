@@ -45,6 +45,12 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=400, help="output pixels the oracle sums")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 32-map batched measurement")
+    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--weight-store", default="auto", choices=["auto", "on", "off"],
+                    help="cap weight store of the mixed plan (auto: the library's default)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain device copy of the map (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -86,16 +92,110 @@ def kernel_table(plan, x, y, reps, stream):
     return {k: {"ms": v[0] / reps, "pairs": v[1]} for k, v in acc.items()}
 
 
+TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "traffic_mixed_persistent_resid2048.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_4441_amd", "csrc", f) for f in ("mixed.hip", "internal.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the persistent kernel from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None if that summary was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_NOTE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_NOTE):
+        if ":" in line and line.split(":", 1)[0].strip() in ("source_sha256", "hbm_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash() or "hbm_bytes_per_launch" not in vals:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
 def roofline_for(name, ms, pairs):
     if "mfma" in name or "persistent" in name:
         achieved = 2.0 * pairs / (ms * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP16_MFMA_TFLOPS, "traffic": None, "kernel": name, "kernel_ms": ms,
+                "frac": achieved / PEAK_FP16_MFMA_TFLOPS, "traffic": measured_traffic(),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
+                "kernel": name, "kernel_ms": ms,
                 "algorithmic": "2 flop per pixel pair per map (FP16 matrix peak)"}
     achieved = 2.0 * pairs / (ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": name, "kernel_ms": ms,
             "algorithmic": "2 flop per pixel pair per map (FP64 vector peak)"}
+
+
+def batched(steps, stream):
+    """The batched workload: 32 maps of uneven Nside and beam in one persistent launch per step,
+    tiles autotuned by the library, the apply captured in a HIP graph and replayed."""
+    import torch
+
+    import paper_1409_4441_amd as cr
+    import synth
+    ws = synth.batch_workload()
+    t0 = time.perf_counter()
+    maps = synth.batch_maps(ws)
+    t_maps = time.perf_counter() - t0
+    plans = []
+    t0 = time.perf_counter()
+    for w in ws:
+        table = cr.tabulate(w.k_ell(), w.theta_cut, w.n_tab)
+        plans.append(cr.Plan(w.nside, table, w.theta_cut, "mixed"))
+    init_s = time.perf_counter() - t0
+    xs = [torch.from_numpy(m).to("cuda:0") for m in maps]
+    outs = [torch.empty_like(x) for x in xs]
+    batch = cr.Batch(plans)
+    pairs = batch.pairs()
+    t0 = time.perf_counter()
+    best = batch.autotune(xs)
+    tune_s = time.perf_counter() - t0
+    for _ in range(2):
+        batch.apply(xs, outs=outs, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        batch.apply(xs, outs=outs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1) / steps
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        batch.apply(xs, outs=outs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        batch.apply(xs, outs=outs)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) / steps
+    counts = {}
+    for w in ws:
+        counts[w.nside] = counts.get(w.nside, 0) + 1
+    out = {"workload": "batch32", "nmaps": len(ws), "nsides": {str(k): v for k, v in sorted(counts.items())},
+           "pairs_per_batch": pairs, "tuning": best, "autotune_s": tune_s, "init_s": init_s, "maps_s": t_maps,
+           "eager_ms_per_batch": eager_ms, "graph_ms_per_batch": graph_s * 1e3,
+           "pixel_pairs_per_s": pairs / graph_s, "maps_per_s": len(ws) / graph_s,
+           "maps": "even white N(0,1), odd red C_l = 1/(l(l+1)) (one field per Nside)"}
+    batch.close()
+    for p in plans:
+        p.close()
+    return out
 
 
 def cpu_baseline(w, table, x, y_gpu, nsamp):
@@ -140,6 +240,8 @@ def main():
         x_np = x_np.astype(np.float64)
     t0 = time.perf_counter()
     plan = cr.Plan(w.nside, table, w.theta_cut, args.precision)
+    if args.precision == "mixed" and args.weight_store != "auto":
+        plan.set_weight_store(args.weight_store)
     init_s = time.perf_counter() - t0
     pairs_per_map = plan.pairs()
     x = torch.from_numpy(x_np).to(dev)
@@ -150,6 +252,21 @@ def main():
     wall, apply_ms = time_applies(plan, x, y, args.steps, args.warmup, stream)
     value = pairs_per_map * nmaps * args.steps / wall
     maps_per_s = nmaps * args.steps / wall
+
+    store = None
+    if args.precision == "mixed":
+        active, nbytes = plan.weight_store()
+        store = {"active": active, "bytes": nbytes}
+        # the other mode, timed beside the chosen one (a few applies), then restored
+        other = "off" if active else "on"
+        try:
+            plan.set_weight_store(other)
+            _, ms_other = time_applies(plan, x, y, 5, 1, stream)
+            store["ms_" + ("store_off" if active else "store_on")] = ms_other
+        except Exception as exc:  # the device may not hold a store of this size
+            store["other_mode_error"] = str(exc)
+        plan.set_weight_store("on" if active else "off")
+        store["ms_" + ("store_on" if active else "store_off")] = apply_ms
 
     kernels = kernel_table(plan, x, y, args.profile_steps, stream)
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
@@ -173,12 +290,26 @@ def main():
                  "rel_rms_timed_path_vs_plain": diff,
                  "kernel": "pair_accumulate_kernel<float> (FP64 per pair)"}
 
+    if args.copy_probe:
+        # one plain device-to-device copy of the map: a kernel of known traffic (read + write of
+        # x.nbytes) whose HBM counters scale the counters of the library's kernels
+        yc = torch.empty_like(x)
+        yc.copy_(x)
+        torch.cuda.synchronize()
+        del yc
+
+    bat = None
+    if not args.no_batched and args.precision == "mixed":
+        bat = batched(args.batched_steps, stream)
+
     cpu = None
     err = None
     if not args.no_cpu:
         cpu, err = cpu_baseline(w, table, x_np, y_np, args.cpu_sample)
 
-    path = {"mixed": "split-FP16 matrix cores for belt ring pairs + FP64 per-pair for cap pairs",
+    path = {"mixed": "split-FP16 matrix cores: precomputed Toeplitz weights for belt ring pairs, cap-touching "
+                     "ring pairs with weights shared by 16 symmetric images (stored or evaluated on the fly), "
+                     "one persistent launch",
             "f32": "plain FP64 per-pair (FP32 maps)", "f64": "plain FP64 per-pair (FP64 maps)"}[args.precision]
     out = {
         "metric": METRIC, "value": value, "unit": "pixel-pairs/s", "n_gpus": 1,
@@ -195,6 +326,8 @@ def main():
         "kernels": kernels,
         "rel_rms_vs_oracle_sample": err,
         "plain_fp64": plain,
+        "weight_store": store,
+        "batched": bat,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

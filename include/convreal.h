@@ -160,6 +160,27 @@ int conv_real_set_tuning(conv_real_plan* plan, const conv_real_tuning* t);
 int conv_real_get_tuning(const conv_real_plan* plan, conv_real_tuning* t);
 
 /*
+ * Cap weight store of a mixed plan. The cap-touching ring pairs' weights (one per output pixel of
+ * the symmetry group's fundamental domain and input pixel inside that pixel's window: about the
+ * cap-touching pixel pairs divided by 16) are either evaluated on the fly by every apply, or
+ * computed once into device memory (FP32, tile by tile) and streamed by every apply, which moves
+ * that part of the kernel from arithmetic to memory bandwidth. The two give the same result up to
+ * FP32 rounding of the weights (both within the mixed path's tolerance).
+ *   CONV_REAL_STORE_OFF   evaluate on the fly; frees a store the plan holds
+ *   CONV_REAL_STORE_ON    build the store (ENOMEM if the device cannot hold it)
+ *   CONV_REAL_STORE_AUTO  build it if it needs at most 16 GiB and 40% of the free device memory
+ * A new mixed plan evaluates on the fly (CONV_REAL_STORE_OFF).
+ * conv_real_set_weight_store is synchronous (not while an apply on the plan may still run) and
+ * allocates; applies never allocate. conv_real_get_weight_store reports whether a store is held
+ * and its size in bytes. Mixed plans only (EINVAL otherwise).
+ */
+#define CONV_REAL_STORE_OFF  0
+#define CONV_REAL_STORE_ON   1
+#define CONV_REAL_STORE_AUTO 2
+int conv_real_set_weight_store(conv_real_plan* plan, int mode);
+int conv_real_get_weight_store(const conv_real_plan* plan, int* active, long long* bytes);
+
+/*
  * conv_real_autotune - time every launch configuration on the caller's maps (each configuration
  * once warm, then three timed applies with HIP events on `stream`), keep the fastest on the plan
  * and return it in *best. Same map arguments as conv_real_apply; maps_out is overwritten.

@@ -25,6 +25,8 @@ F32 = 1
 MIXED = 2
 _PRECISIONS = {"f64": F64, "f32": F32, "mixed": MIXED}
 
+_STORE_MODES = {"off": 0, "on": 1, "auto": 2}
+
 OK = 0
 EINVAL = -1
 ENOMEM = -2
@@ -37,7 +39,8 @@ EXPORTS = ("conv_real_tabulate", "conv_real_init", "conv_real_apply", "conv_real
            "conv_real_profile", "conv_real_set_tuning", "conv_real_get_tuning", "conv_real_autotune",
            "conv_real_batch_create", "conv_real_batch_apply", "conv_real_batch_set_tuning",
            "conv_real_batch_autotune", "conv_real_batch_pairs", "conv_real_batch_destroy",
-           "conv_real_destroy", "conv_real_strerror", "conv_real_last_error")
+           "conv_real_destroy", "conv_real_strerror", "conv_real_last_error",
+           "conv_real_set_weight_store", "conv_real_get_weight_store")
 
 
 class Tuning(ctypes.Structure):
@@ -56,8 +59,16 @@ class ConvRealError(RuntimeError):
 
 
 def _load():
+    # PyTorch bundles HIP and HSA runtime libraries with the same sonames as the system ROCm ones
+    # this library links (libamdhip64.so.7, libhsa-runtime64.so.1). Whichever loads first serves the
+    # whole process; PyTorch does not find the device on the system runtime, while this library runs
+    # on PyTorch's. So PyTorch is imported before the library is loaded: one runtime, shared.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1409_4441_amd.build` "
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_1409_4441_amd/build.py` "
                           "(the convolution has no CPU fallback)")
     lib = ctypes.CDLL(LIB_PATH)
     c_int, c_double, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
@@ -89,6 +100,10 @@ def _load():
                  "conv_real_batch_apply", "conv_real_batch_set_tuning", "conv_real_batch_autotune",
                  "conv_real_batch_pairs", "conv_real_batch_destroy"):
         getattr(lib, name).restype = c_int
+    lib.conv_real_set_weight_store.argtypes = [c_void_p, c_int]
+    lib.conv_real_set_weight_store.restype = c_int
+    lib.conv_real_get_weight_store.argtypes = [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_longlong)]
+    lib.conv_real_get_weight_store.restype = c_int
     lib.conv_real_destroy.argtypes = [c_void_p]
     lib.conv_real_destroy.restype = c_int
     lib.conv_real_strerror.argtypes = [c_int]
@@ -99,26 +114,6 @@ def _load():
 
 
 lib = _load()
-
-
-_RUNTIME_READY = False
-
-
-def device_runtime():
-    """Initialise PyTorch's device runtime before the library's first device call. PyTorch ships its
-    own HIP runtime next to the system one the library links; the two coexist in one process (they
-    share the device's address space, so tensors pass straight to the library), but only when
-    PyTorch's starts first: started second, it finds no device."""
-    global _RUNTIME_READY
-    if _RUNTIME_READY:
-        return
-    try:
-        import torch
-        if torch.cuda.is_available():
-            torch.cuda.init()
-    except ImportError:
-        pass
-    _RUNTIME_READY = True
 
 
 def _check(code: int, where: str):
@@ -133,7 +128,6 @@ def _dptr(a: np.ndarray):
 
 def tabulate(k_ell, theta_cut: float, n_tab: int) -> np.ndarray:
     """K(d_k) = sum_l (2l+1)/(4 pi) k_l P_l(cos theta_k) on the plan's chord nodes (device FP64)."""
-    device_runtime()
     k = np.ascontiguousarray(k_ell, dtype=np.float64)
     out = np.empty(int(n_tab), dtype=np.float64)
     _check(lib.conv_real_tabulate(_dptr(k), len(k) - 1, float(theta_cut), int(n_tab), _dptr(out)),
@@ -154,7 +148,6 @@ class Plan:
     def __init__(self, nside: int, table, theta_cut: float, precision: str = "f64"):
         if precision not in _PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(_PRECISIONS)}")
-        device_runtime()
         t = np.ascontiguousarray(table, dtype=np.float64)
         handle = ctypes.c_void_p()
         _check(lib.conv_real_init(ctypes.byref(handle), int(nside), _dptr(t), len(t),
@@ -175,6 +168,17 @@ class Plan:
         n = ctypes.c_longlong()
         _check(lib.conv_real_pairs(self._h, ctypes.byref(n)), "conv_real_pairs")
         return int(n.value)
+
+    def set_weight_store(self, mode: str):
+        """"off", "on" or "auto": cap weights evaluated per apply, or computed once and streamed."""
+        _check(lib.conv_real_set_weight_store(self._h, _STORE_MODES.get(mode, -1)), "conv_real_set_weight_store")
+
+    def weight_store(self):
+        """(active, bytes) of the cap weight store."""
+        a, b = ctypes.c_int(), ctypes.c_longlong()
+        _check(lib.conv_real_get_weight_store(self._h, ctypes.byref(a), ctypes.byref(b)),
+               "conv_real_get_weight_store")
+        return bool(a.value), int(b.value)
 
     def apply(self, x, out=None, stream=None):
         """y = A x. x: CUDA tensor [npix] or [nmaps, npix], contiguous, plan dtype."""

@@ -1,6 +1,7 @@
 """Build libconvreal.so (gfx950) in-tree with hipcc.
 
-Run as ``python -m paper_1409_4441_amd.build``. Every call recompiles.
+Run as ``python paper_1409_4441_amd/build.py`` (a script: importing the package would load the
+library it builds). Every call recompiles.
 """
 from __future__ import annotations
 

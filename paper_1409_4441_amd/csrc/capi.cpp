@@ -187,8 +187,10 @@ std::vector<QueueItem> queue_of(const conv_real_plan* p, const convreal::Tuning&
     for (int b = 0; b < p->belt_nbands; ++b)
       for (int s = 0; s < nsegs; ++s) belt.push_back({p->cost_belt[b] * (t.seg / 64), 0, b * nsegs + s});
   }
+  // a stored weight is a load, about a third of the work of evaluating it
+  const double cap_scale = p->d_wstore ? 0.35 : 1.0;
   if (p->cap_mode)
-    for (int k = 0; k < static_cast<int>(p->cost_cap.size()); ++k) cap.push_back({p->cost_cap[k], 1, k});
+    for (int k = 0; k < static_cast<int>(p->cost_cap.size()); ++k) cap.push_back({p->cost_cap[k] * cap_scale, 1, k});
   auto desc = [](const QueueItem& a, const QueueItem& b) { return a.cost > b.cost; };
   std::stable_sort(belt.begin(), belt.end(), desc);
   std::stable_sort(cap.begin(), cap.end(), desc);
@@ -468,12 +470,80 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
   d.inv_h = p->inv_h;
   d.dcut2 = p->dcut2;
   d.inv_sw = static_cast<float>(1.0 / p->belt_sw);
+  d.wstore = nullptr;
+  d.wtile_off = nullptr;
+  p->h_desc = d;
   std::vector<convreal::MixedDesc> dv(1, d);
   if ((e = dev_upload(p, &p->d_desc, dv)) != hipSuccess ||
       (e = dev_alloc(p, &p->d_counter, 1)) != hipSuccess ||
       (e = convreal::set_lds_limits(p->cap_nseg)) != hipSuccess)
     return e;
   return build_items(p);
+}
+
+// Build (or drop) the cap weight store for `mode` (CONV_REAL_STORE_*), re-upload the descriptor and
+// the work queue. Synchronous.
+int set_weight_store(conv_real_plan* p, int mode) {
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "weight store: synchronise");
+  release(p, p->d_wstore);
+  release(p, p->d_wtile_off);
+  p->d_wstore = nullptr;
+  p->d_wtile_off = nullptr;
+  p->wstore_floats = 0;
+  p->h_desc.wstore = nullptr;
+  p->h_desc.wtile_off = nullptr;
+  p->wstore_mode = mode;
+  int rc = CONV_REAL_OK;
+  if (mode != CONV_REAL_STORE_OFF && p->cap_mode && p->n_citems > 0) {
+    long long* counts = nullptr;
+    std::vector<long long> off(static_cast<size_t>(p->n_citems) + 1, 0);
+    if ((e = hipMemcpy(p->d_desc, &p->h_desc, sizeof(p->h_desc), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = dev_alloc(p, &counts, static_cast<size_t>(p->n_citems))) != hipSuccess ||
+        (e = convreal::cap_store_count(p, counts)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess ||
+        (e = hipMemcpy(off.data() + 1, counts, sizeof(long long) * p->n_citems, hipMemcpyDeviceToHost)) !=
+            hipSuccess) {
+      release(p, counts);
+      return hip_fail(e, "weight store: count");
+    }
+    release(p, counts);
+    for (int t = 0; t < p->n_citems; ++t) off[t + 1] += off[t];
+    const long long n = off[p->n_citems];
+    // 64 floats of padding: masked lanes may read the first weight of an empty trailing row
+    const size_t bytes = sizeof(float) * static_cast<size_t>(n + 64);
+    bool build = true;
+    if (mode == CONV_REAL_STORE_AUTO) {
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+      const double budget = std::min(16.0 * (1ull << 30), 0.4 * static_cast<double>(free_b));
+      build = static_cast<double>(bytes) <= budget;
+    }
+    if (build) {
+      off.pop_back();
+      if ((e = dev_alloc(p, &p->d_wstore, static_cast<size_t>(n + 64))) != hipSuccess) {
+        rc = hip_fail(e, "weight store: allocation");
+      } else if ((e = hipMemset(p->d_wstore, 0, bytes)) != hipSuccess ||
+                 (e = dev_upload(p, &p->d_wtile_off, off)) != hipSuccess ||
+                 (e = convreal::cap_store_fill(p)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+        rc = hip_fail(e, "weight store: fill");
+      } else {
+        p->wstore_floats = n;
+        p->h_desc.wstore = p->d_wstore;
+        p->h_desc.wtile_off = p->d_wtile_off;
+      }
+      if (rc != CONV_REAL_OK) {
+        release(p, p->d_wstore);
+        release(p, p->d_wtile_off);
+        p->d_wstore = nullptr;
+        p->d_wtile_off = nullptr;
+      }
+    }
+  }
+  if ((e = hipMemcpy(p->d_desc, &p->h_desc, sizeof(p->h_desc), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = build_items(p)) != hipSuccess)
+    return hip_fail(e, "weight store: descriptor");
+  return rc;
 }
 
 }  // namespace
@@ -621,8 +691,38 @@ int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_
       return rc;
     }
     p->pairs_rest = static_cast<long long>(cnt);
+    if ((rc = set_weight_store(p, CONV_REAL_STORE_OFF)) != CONV_REAL_OK) {
+      free_plan(p);
+      return rc;
+    }
   }
   *plan = p;
+  return CONV_REAL_OK;
+}
+
+int conv_real_set_weight_store(conv_real_plan* plan, int mode) {
+  if (!plan || plan->magic != kMagic) { set_error("conv_real_set_weight_store: invalid plan"); return CONV_REAL_EINVAL; }
+  if (plan->precision != CONV_REAL_MIXED) {
+    set_error("conv_real_set_weight_store: mixed plans only");
+    return CONV_REAL_EINVAL;
+  }
+  if (mode != CONV_REAL_STORE_OFF && mode != CONV_REAL_STORE_ON && mode != CONV_REAL_STORE_AUTO) {
+    set_error("conv_real_set_weight_store: mode must be CONV_REAL_STORE_OFF, _ON or _AUTO");
+    return CONV_REAL_EINVAL;
+  }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_set_weight_store: hipSetDevice");
+  return set_weight_store(plan, mode);
+}
+
+int conv_real_get_weight_store(const conv_real_plan* plan, int* active, long long* bytes) {
+  if (!plan || plan->magic != kMagic || !active || !bytes) {
+    set_error("conv_real_get_weight_store: invalid plan or NULL output");
+    return CONV_REAL_EINVAL;
+  }
+  *active = plan->d_wstore ? 1 : 0;
+  *bytes = plan->d_wstore ? static_cast<long long>(sizeof(float)) * (plan->wstore_floats + 64) : 0;
   return CONV_REAL_OK;
 }
 
@@ -802,13 +902,15 @@ hipError_t build_batch_items(conv_real_batch* b) {
 
 hipError_t batch_launch(conv_real_batch* b, const float* const* in, float* const* out, hipStream_t st) {
   convreal::Slots S;
+  bool fly = false;   // some plan evaluates its cap weights on the fly
   for (int k = 0; k < b->count; ++k) {
     S.desc[k] = b->plans[k]->d_desc;
     S.x[k] = in[k];
     S.y[k] = out[k];
+    fly = fly || (b->plans[k]->cap_mode && !b->plans[k]->d_wstore);
   }
   return convreal::launch_mixed_queue(b->plans[0], S, b->count, b->d_items, b->n_items, 1, b->d_amax, b->d_counter,
-                                      b->tune, b->max_nseg, b->npix_max, b->pairs, st);
+                                      b->tune, b->max_nseg, b->npix_max, b->pairs, fly, st);
 }
 
 // Mean milliseconds of `reps` runs of fn() on st, after one untimed run.

@@ -88,6 +88,8 @@ struct MixedDesc {
   const int* citem_a0;
   const long long* rest_off;  // per ring: first record in cpair
   const CapPair* cpair;       // cap-touching ring pairs, grouped by output ring
+  const float* wstore;        // cap weight store (nullptr: weights evaluated on the fly)
+  const long long* wtile_off; // per cap tile: first weight of the tile in wstore
   double inv_h;
   double dcut2;
   float inv_sw;
@@ -191,6 +193,13 @@ struct conv_real_plan {
   int* d_citem_a0 = nullptr;   // per work item: first pixel of a 16-pixel tile
   int n_citems = 0;
   convreal::CapPair* d_cpair = nullptr;  // per cap-touching ring pair, in d_rest_idx order
+  // cap weight store: every cap-tile weight row (rows inside the fundamental domain, inputs inside
+  // the row's window) as FP32, tile after tile, ring pair after ring pair, row after row
+  float* d_wstore = nullptr;
+  long long* d_wtile_off = nullptr;  // per cap tile (n_citems + 1)
+  long long wstore_floats = 0;
+  int wstore_mode = 2;               // CONV_REAL_STORE_OFF / ON / AUTO as last requested
+  convreal::MixedDesc h_desc{};      // host copy of d_desc
   int* d_ring_add = nullptr;   // per ring: 1 if it gets a belt and a cap-pair contribution
   int cap_nseg = 0;            // coefficient segments (n_tab - 2) if cap_mode
   convreal::MixedDesc* d_desc = nullptr;  // device copy of the plan's descriptor
@@ -233,8 +242,11 @@ size_t belt_stage_bytes(int seg);
 hipError_t set_lds_limits(int nseg);
 hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, int nslots, const int2* items,
                               int n_items, int nrep, unsigned* amax, unsigned* counter, const Tuning& tune,
-                              int max_nseg, long long npix_max, long long pairs, hipStream_t st);
+                              int max_nseg, long long npix_max, long long pairs, bool fly, hipStream_t st);
 hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st);
+// number of weights of each cap tile in the store (counts[n_citems]), and the store's fill
+hipError_t cap_store_count(const conv_real_plan* p, long long* counts_dev);
+hipError_t cap_store_fill(const conv_real_plan* p);
 hipError_t tabulate_device(const double* k_ell, int lmax, double h, int n_tab, double* table_host);
 
 }  // namespace convreal

@@ -36,6 +36,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 #include "internal.h"
@@ -43,6 +44,7 @@
 namespace {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;
@@ -96,6 +98,11 @@ struct BeltLayout {
   static constexpr int BYTES = 2 * BUF * 2;      // two buffers of FP16
   static_assert(((CS * 2) % 256) == 144, "copy stride must spread the 8 copies over LDS banks");
 };
+
+// LDS slice per wave for a ring pair's block of stored cap weights (the belt stage area is free
+// while a workgroup works on cap tiles)
+constexpr int kStageFloats = 1536;
+static_assert(kWaves * kStageFloats * 4 <= BeltLayout<256>::BYTES, "cap weight stage must fit the belt stage");
 
 // ---------------------------------------------------------------- prep kernels
 __global__ void zero_state_kernel(unsigned* amax, int n, unsigned* counter) {
@@ -295,22 +302,38 @@ constexpr double kSinLong[8] = {0.9999999999970449,     -0.3333333332512937,    
                                 -0.0031746016082493094, 0.00014109120522641625,  -4.273732374386684e-06,
                                 9.31392155360743e-08,   -1.366547170656072e-09};
 
-// Omega s_w Ktilde(d) from q = (d / h)^2, the squared chord in units of the table spacing (0 beyond
-// the cut q > qcut). t = d / h comes from a single-precision reciprocal square root refined by one
-// Newton step in FP64 (relative error ~1e-14); segment floor(t), local coordinate frac(t). Lanes
-// beyond the cut clamp the segment so that they stay inside the coefficient table; inside the cut
-// t <= (n_tab - 3)(1 + 1e-9), so the clamp never moves a kept pair.
-__device__ __forceinline__ float weight_of(double q, double qcut, int seg_max, const float4* __restrict__ s_coef) {
+// Omega s_w Ktilde(d) is evaluated from q = (d / h)^2, the squared chord in units of the table
+// spacing (0 beyond the cut q > qcut). t = d / h comes from a single-precision reciprocal square
+// root refined by one Newton step in FP64 (relative error ~1e-14); segment floor(t), local
+// coordinate frac(t). Lanes beyond the cut clamp the segment so that they stay inside the
+// coefficient table; inside the cut t <= (n_tab - 3)(1 + 1e-9), so the clamp never moves a kept pair.
+__device__ __forceinline__ void locate(double q, int seg_max, int& sg, float& f) {
   const float y0 = __builtin_amdgcn_rsqf(fmaxf(static_cast<float>(q), 1e-30f));
   const double y = static_cast<double>(y0);
   const double t0 = q * y;
   const double r = fma(-t0, t0, q);
   const double t = fma(r, 0.5 * y, t0);
-  const int sg = min(static_cast<int>(t), seg_max);
-  const float f = static_cast<float>(__builtin_amdgcn_fract(t));
-  const float4 c = s_coef[sg];
-  const float w = fmaf(fmaf(fmaf(c.w, f, c.z), f, c.y), f, c.x);
-  return q <= qcut ? w : 0.0f;
+  sg = min(static_cast<int>(t), seg_max);
+  f = static_cast<float>(__builtin_amdgcn_fract(t));
+}
+
+// the E weights of one lane's A-operand entries, in phases (all chords, all table reads, all
+// cubics) so that the LDS reads are issued together and their latency overlaps
+template <int E>
+__device__ __forceinline__ void weights_of(const double (&q)[E], double qcut, int seg_max,
+                                           const float4* __restrict__ s_coef, float (&w)[E]) {
+  int sg[E];
+  float f[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) locate(q[e], seg_max, sg[e], f[e]);
+  float4 c[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) c[e] = s_coef[sg[e]];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const float v = fmaf(fmaf(fmaf(c[e].w, f[e], c[e].z), f[e], c[e].y), f[e], c[e].x);
+    w[e] = q[e] <= qcut ? v : 0.0f;
+  }
 }
 
 // v mod n for |v| < 2^24, n > 0 (reciprocal-based quotient, corrected by one step either way)
@@ -321,49 +344,187 @@ __device__ __forceinline__ int mod_any(int v, int n, float rcp_n) {
   return m >= n ? m - n : m;
 }
 
-__device__ __forceinline__ void split8(const float (&v)[8], half8& hi, half8& lo) {
+template <int E, typename HV>
+__device__ __forceinline__ void split_fp16(const float (&v)[E], HV& hi, HV& lo) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
+  for (int e = 0; e < E; ++e) {
     const _Float16 h = static_cast<_Float16>(v[e]);
     hi[e] = h;
     lo[e] = static_cast<_Float16>(v[e] - static_cast<float>(h));
   }
 }
 
-// B operand of one K-chunk: image col of inputs b = bA .. bA + 7, i.e. pixels pofs + dir * b (mod nj)
-// of the lane's ring, scaled by sx. Lanes read 8 consecutive pixels (reversed for reflected images);
-// the wave takes the no-wrap branch when no lane crosses the ring's start.
+// B operand of one K-step: image col of inputs b = bA .. bA + E - 1, i.e. pixels pofs + dir * b
+// (mod nj) of the lane's ring, scaled by sx. Lanes read E consecutive pixels (reversed for reflected
+// images); the wave takes the no-wrap branch when no lane crosses the ring's start. Needs nj >= E.
+template <int E, typename HV>
 __device__ __forceinline__ void load_inputs(const float* __restrict__ xj, int pofs, int dir, int bA, int nj,
-                                            float rcp_n, float sx, half8& xhi, half8& xlo) {
+                                            float rcp_n, float sx, HV& xhi, HV& xlo) {
   const int p0 = mod_any(pofs + dir * bA, nj, rcp_n);
-  const int s = dir > 0 ? p0 : p0 - 7;   // lowest pixel index read by this lane
-  float v[8];
-  if (__all(s >= 0 && s + 7 < nj)) {
+  const int s = dir > 0 ? p0 : p0 - (E - 1);   // lowest pixel index read by this lane
+  float v[E];
+  if (__all(s >= 0 && s + E - 1 < nj)) {
     const float* xp = xj + s;
-    float L[8];
+    float L[E];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) L[e] = xp[e];
+    for (int e = 0; e < E; ++e) L[e] = xp[e];
     // forward lanes keep the order, reflected lanes reverse it (a bitwise select per element)
     const unsigned fwd = dir > 0 ? 0xffffffffu : 0u;
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      v[e] = __uint_as_float((fwd & __float_as_uint(L[e])) | (~fwd & __float_as_uint(L[7 - e]))) * sx;
+    for (int e = 0; e < E; ++e)
+      v[e] = __uint_as_float((fwd & __float_as_uint(L[e])) | (~fwd & __float_as_uint(L[E - 1 - e]))) * sx;
   } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
       int idx = p0 + dir * e;
       idx = idx < 0 ? idx + nj : idx;
       idx = idx >= nj ? idx - nj : idx;
       v[e] = xj[idx] * sx;
     }
   }
-  split8(v, xhi, xlo);
+  split_fp16<E>(v, xhi, xlo);
+}
+
+// window [lo, hi] of ring j for the output pixel with azimuth numerator u: the per-pair path's rule
+// (centre (u n_j - c_j n_i) / 2 n_i, half-width hw plus 1e-7 pixel; a whole ring: n_j pixels)
+__device__ __forceinline__ void row_window(const convreal::CapPair& P, int u, int ni, int& lo, int& hi) {
+  const double bc = static_cast<double>(u * P.nj - P.cj * ni) / (2.0 * ni);
+  if (P.whole) {
+    lo = static_cast<int>(floor(bc)) - P.nj / 2;
+    hi = lo + P.nj - 1;
+  } else {
+    lo = static_cast<int>(ceil(bc - P.hw - 1e-7));
+    hi = static_cast<int>(floor(bc + P.hw + 1e-7));
+  }
+}
+
+// exclusive prefix sum of v over each 16-lane segment of the wave, and the segment's total
+__device__ __forceinline__ int scan16(int v, int& total) {
+  const int l16 = threadIdx.x & 15;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    const int y = __shfl_up(x, o, 16);
+    if (l16 >= o) x += y;
+  }
+  total = __shfl(x, 15, 16);
+  return x - v;
+}
+
+// long-form weights of output pixel u and inputs bA .. bA + 7 (any ring pair): numerator reduced to
+// [-M, M], degree-7 sin^2 polynomial, q = d^2 / h^2
+struct LongForm {
+  double Ah;
+  double cl[8];
+  double Md, twoM, inv_twoM, two_ni, scale;
+  __device__ __forceinline__ LongForm(const convreal::CapPair& P, int ni, double ih2) {
+    const double Bh = P.B * ih2;
+    Ah = P.A * ih2;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cl[u] = Bh * kSinLong[u];
+    Md = static_cast<double>(ni) * static_cast<double>(P.nj);
+    twoM = 2.0 * Md;
+    inv_twoM = 1.0 / twoM;
+    two_ni = 2.0 * static_cast<double>(ni);
+    scale = P.scale;
+  }
+  __device__ __forceinline__ void q8(int u, int bA, int ni, int nj, int cj, double (&qv)[8]) const {
+    double nd = static_cast<double>(u * nj - (2 * bA + cj) * ni);
+    nd = fma(-rint(nd * inv_twoM), twoM, nd);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      double ne = nd - static_cast<double>(e) * two_ni;
+      ne = ne < -Md ? ne + twoM : ne;
+      ne = ne < -Md ? ne + twoM : ne;
+      const double al = ne * scale;
+      const double tq = al * al;
+      double bp = cl[7];
+#pragma unroll
+      for (int k = 6; k >= 0; --k) bp = fma(bp, tq, cl[k]);
+      qv[e] = fma(tq, bp, Ah);
+    }
+  }
+};
+
+// one K-step from the weight store: lane (row, k-group) takes its row's stored weights for inputs
+// bA .. bA + E - 1 (zero outside the row's window [lo, lo + wr)); addresses are clamped into the
+// row so that masked lanes never read outside the store
+template <int E>
+__device__ __forceinline__ void stored_step(floatx4& acc, int bA, int lo, int wr, const float* __restrict__ wrow,
+                                            const float* __restrict__ xj, int pofs, int dir, int nj, float rcp_n,
+                                            float sx) {
+  using HV = typename std::conditional<E == 8, half8, half4>::type;
+  HV xhi, xlo;
+  if (nj >= 8) {
+    load_inputs<E>(xj, pofs, dir, bA, nj, rcp_n, sx, xhi, xlo);
+  } else {
+    float v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = xj[mod_any(pofs + dir * (bA + e), nj, rcp_n)] * sx;
+    split_fp16<E>(v, xhi, xlo);
+  }
+  float w[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = bA + e - lo;
+    const bool in = static_cast<unsigned>(k) < static_cast<unsigned>(wr);
+    const float v = wrow[in ? k : 0];
+    w[e] = in ? v : 0.0f;
+  }
+  HV whi, wlo;
+  split_fp16<E>(w, whi, wlo);
+  if constexpr (E == 8) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(whi, xhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(wlo, xhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(whi, xlo, acc, 0, 0, 0);
+  }
+}
+
+// one short-form K-step of E inputs per lane (E = 8: 32 inputs on v_mfma_f32_16x16x32_f16; E = 4:
+// 16 inputs on v_mfma_f32_16x16x16_f16, for the last step of a window)
+template <int E>
+__device__ __forceinline__ void short_step(floatx4& acc, int bA, int u_row, int ni, int nj, int cj, double scale,
+                                           double delta, double Ah, double c0, double c1, double c2, double c3,
+                                           double qcut, int seg_max, const float4* __restrict__ s_coef,
+                                           const float* __restrict__ xj, int pofs, int dir, float rcp_n, float sx) {
+  using HV = typename std::conditional<E == 8, half8, half4>::type;
+  HV xhi, xlo;
+  load_inputs<E>(xj, pofs, dir, bA, nj, rcp_n, sx, xhi, xlo);
+  double al = static_cast<double>(u_row * nj - (2 * bA + cj) * ni) * scale;
+  double qv[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const double tq = al * al;
+    const double bp = fma(fma(fma(c3, tq, c2), tq, c1), tq, c0);
+    qv[e] = fma(tq, bp, Ah);
+    al -= delta;
+  }
+  float w[E];
+  weights_of<E>(qv, qcut, seg_max, s_coef, w);
+  HV whi, wlo;
+  split_fp16<E>(w, whi, wlo);
+  if constexpr (E == 8) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(whi, xhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(wlo, xhi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(whi, xlo, acc, 0, 0, 0);
+  }
 }
 
 // one wave: tile t (16 output pixels of the fundamental domain of one north-half ring)
+// FLY = false: every slot holds a weight store, so only the stored-weight path is compiled in (fewer
+// registers, more resident waves to cover the store's memory latency)
+template <bool FLY>
 __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__ d, int t,
                                          const float* __restrict__ xm, float* __restrict__ ym, float sx,
-                                         const float4* __restrict__ s_coef) {
+                                         const float4* __restrict__ s_coef, float* __restrict__ wstage) {
   const int r = ldu(ldu(d->citem_ring)[t]);
   const int a0 = ldu(ldu(d->citem_a0)[t]);
   const int ni = ldu(ldu(d->rn)[r]);
@@ -386,6 +547,10 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
   const double qcut = ldu(d->dcut2) * ih2;
   const int seg_max = ldu(d->nseg) - 1;
 
+  const int F = ((ni >> 2) - ci) / 2 + 1;   // fundamental domain [0, F) of the ring
+  const float* wst = ldu(d->wstore);
+  long long wpos = wst ? ldu(ldu(d->wtile_off)[t]) : 0;
+
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   double accd[4] = {0.0, 0.0, 0.0, 0.0};
   const long long* rest_off = ldu(d->rest_off);
@@ -397,6 +562,62 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
     const convreal::CapPair P = ldu_record(cpair[kk]);
     const int nj = P.nj;
     const int cj = P.cj;
+    if (!FLY || wst) {
+      // weights from the store: the rows' own windows, laid out row after row
+      int lo, hi;
+      row_window(P, u_row, ni, lo, hi);
+      const int wr = a0 + row < F ? max(0, hi - lo + 1) : 0;
+      int total;
+      const int off = scan16(wr, total);
+      if (total == 0) continue;
+      // the pair's block starts 16-byte aligned (blocks are padded to whole float4s); a block that
+      // fits the wave's LDS slice is staged there with coalesced 16-byte loads, and the lanes then
+      // gather their rows' runs from LDS; a larger one is read from the store directly
+      const int tot4 = (total + 3) & ~3;
+      const float* blk = wst + wpos;
+      wpos += tot4;
+      // the union of the rows' windows, in steps of 32 inputs and a last step of 16 if it suffices
+      int b0 = wr > 0 ? lo : 0x7fffffff, bend = wr > 0 ? lo + wr - 1 : -0x7fffffff;
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        b0 = min(b0, __shfl_xor(b0, o, 16));
+        bend = max(bend, __shfl_xor(bend, o, 16));
+      }
+      const int K = bend - b0 + 1;
+      const int nk = (K + 31) >> 5;
+      const int nfull = (K & 31) > 0 && (K & 31) <= 16 ? nk - 1 : nk;
+      const float* xj = xm + (ch ? P.xoff_m : P.xoff);
+      const int pofs = cf ? (nj - cj + cq * (nj >> 2)) : cq * (nj >> 2);
+      const float rcp_n = 1.0f / static_cast<float>(nj);
+      if (tot4 <= kStageFloats) {
+        const float4* src = reinterpret_cast<const float4*>(blk);
+        float4* dst = reinterpret_cast<float4*>(wstage);
+        for (int i = lane; i < (tot4 >> 2); i += 64) dst[i] = src[i];
+        // LDS traffic of one wave is processed in order; the fence keeps the compiler from moving
+        // the row reads above the block's writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float* wrow = wstage + off;
+        for (int q = 0; q < nfull; ++q)
+          stored_step<8>(acc, b0 + 32 * q + 8 * kgrp, lo, wr, wrow, xj, pofs, dir, nj, rcp_n, sx);
+        if (nfull < nk) stored_step<4>(acc, b0 + 32 * nfull + 4 * kgrp, lo, wr, wrow, xj, pofs, dir, nj, rcp_n, sx);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {
+        const float* wrow = blk + off;
+        for (int q = 0; q < nfull; ++q)
+          stored_step<8>(acc, b0 + 32 * q + 8 * kgrp, lo, wr, wrow, xj, pofs, dir, nj, rcp_n, sx);
+        if (nfull < nk) stored_step<4>(acc, b0 + 32 * nfull + 4 * kgrp, lo, wr, wrow, xj, pofs, dir, nj, rcp_n, sx);
+      }
+      if (++nfold == kFold) {
+        nfold = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) accd[u] += static_cast<double>(acc[u]);
+        acc = floatx4{0.f, 0.f, 0.f, 0.f};
+      }
+      continue;
+    }
+    if constexpr (FLY) {
     // union of the 16 rows' windows [b0, bend] (the rows' centres increase with a)
     const double bc0 = static_cast<double>(u_first * nj - cj * ni) / (2.0 * ni);
     const double bc1 = static_cast<double>(u_last * nj - cj * ni) / (2.0 * ni);
@@ -427,47 +648,21 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
       const double Ah = P.A * ih2;
       const double c0 = Bh * kSinShort[0], c1 = Bh * kSinShort[1], c2 = Bh * kSinShort[2], c3 = Bh * kSinShort[3];
       const double delta = 2.0 * static_cast<double>(ni) * P.scale;   // al step per input pixel
-      for (int q = 0; q < nk; ++q) {
-        const int bA = b0 + 32 * q + 8 * kgrp;
-        half8 xhi, xlo;
-        load_inputs(xj, pofs, dir, bA, nj, rcp_n, sx, xhi, xlo);
-        double al = static_cast<double>(u_row * nj - (2 * bA + cj) * ni) * P.scale;
-        float w[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const double tq = al * al;
-          const double bp = fma(fma(fma(c3, tq, c2), tq, c1), tq, c0);
-          w[e] = weight_of(fma(tq, bp, Ah), qcut, seg_max, s_coef);
-          al -= delta;
-        }
-        half8 whi, wlo;
-        split8(w, whi, wlo);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
-      }
+      // steps of 32 inputs; a remainder of at most 16 takes one 16-input step
+      const int nfull = (K & 31) > 0 && (K & 31) <= 16 ? nk - 1 : nk;
+      for (int q = 0; q < nfull; ++q)
+        short_step<8>(acc, b0 + 32 * q + 8 * kgrp, u_row, ni, nj, cj, P.scale, delta, Ah, c0, c1, c2, c3, qcut,
+                      seg_max, s_coef, xj, pofs, dir, rcp_n, sx);
+      if (nfull < nk)
+        short_step<4>(acc, b0 + 32 * nfull + 4 * kgrp, u_row, ni, nj, cj, P.scale, delta, Ah, c0, c1, c2, c3, qcut,
+                      seg_max, s_coef, xj, pofs, dir, rcp_n, sx);
     } else {
       // general form (rings near a pole): numerator reduced to [-M, M], the long polynomial, and
       // the lane's own window [lo_r, hi_r], which also keeps a pixel from entering twice when the
       // union is wider than the ring
-      const double Bh = P.B * ih2;
-      const double Ah = P.A * ih2;
-      double cl[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) cl[u] = Bh * kSinLong[u];
-      const double Md = static_cast<double>(ni) * static_cast<double>(nj);
-      const double twoM = 2.0 * Md;
-      const double inv_twoM = 1.0 / twoM;
-      const double two_ni = 2.0 * static_cast<double>(ni);
-      const double bcr = static_cast<double>(u_row * nj - cj * ni) / (2.0 * ni);
+      const LongForm lf(P, ni, ih2);
       int lo_r, hi_r;
-      if (P.whole) {
-        lo_r = static_cast<int>(floor(bcr)) - nj / 2;
-        hi_r = lo_r + nj - 1;
-      } else {
-        lo_r = static_cast<int>(ceil(bcr - P.hw - 1e-7));
-        hi_r = static_cast<int>(floor(bcr + P.hw + 1e-7));
-      }
+      row_window(P, u_row, ni, lo_r, hi_r);
       for (int q = 0; q < nk; ++q) {
         const int bA = b0 + 32 * q + 8 * kgrp;
         half8 xhi, xlo;
@@ -475,27 +670,19 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
           float v[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) v[e] = xj[mod_any(pofs + dir * (bA + e), nj, rcp_n)] * sx;
-          split8(v, xhi, xlo);
+          split_fp16<8>(v, xhi, xlo);
         }
-        double nd = static_cast<double>(u_row * nj - (2 * bA + cj) * ni);
-        nd = fma(-rint(nd * inv_twoM), twoM, nd);
+        double qv[8];
+        lf.q8(u_row, bA, ni, nj, cj, qv);
         float w[8];
+        weights_of<8>(qv, qcut, seg_max, s_coef, w);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          double ne = nd - static_cast<double>(e) * two_ni;
-          ne = ne < -Md ? ne + twoM : ne;
-          ne = ne < -Md ? ne + twoM : ne;
-          const double al = ne * P.scale;
-          const double tq = al * al;
-          double bp = cl[7];
-#pragma unroll
-          for (int u = 6; u >= 0; --u) bp = fma(bp, tq, cl[u]);
-          const float wv = weight_of(fma(tq, bp, Ah), qcut, seg_max, s_coef);
           const int b = bA + e;
-          w[e] = (b >= lo_r && b <= hi_r) ? wv : 0.0f;
+          w[e] = (b >= lo_r && b <= hi_r) ? w[e] : 0.0f;
         }
         half8 whi, wlo;
-        split8(w, whi, wlo);
+        split_fp16<8>(w, whi, wlo);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
@@ -507,6 +694,7 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
       for (int u = 0; u < 4; ++u) accd[u] += static_cast<double>(acc[u]);
       acc = floatx4{0.f, 0.f, 0.f, 0.f};
     }
+    }  // FLY
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) accd[u] += static_cast<double>(acc[u]);
@@ -514,7 +702,6 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
   // store: D rows 4 kgrp + u (output pixel a0 + 4 kgrp + u), column col (image); each output
   // pixel once: rows beyond the fundamental domain [0, F), reflections of pixels on a reflection
   // axis and the mirror of the equator ring are skipped
-  const int F = ((ni >> 2) - ci) / 2 + 1;
   if (ch && mr == r) return;
   const int rr = ch ? mr : r;
   const double inv = static_cast<double>(ldu(d->inv_sw)) / static_cast<double>(sx);
@@ -533,9 +720,74 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
   }
 }
 
+// ---------------------------------------------------------------- cap weight store (set-up)
+// One wave per cap tile, the same tiles, ring pairs and row windows as the apply. FILL = false: the
+// number of stored weights of each tile; FILL = true: the weights (long form, any ring pair), tile t
+// starting at offsets[t], ring pair after ring pair, row after row, input after input.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::MixedDesc* __restrict__ d,
+                                                           long long* __restrict__ offsets,
+                                                           float* __restrict__ store) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  float4* s_coef = reinterpret_cast<float4*>(lds);
+  if (FILL) {
+    const float4* coef = reinterpret_cast<const float4*>(ldu(d->coef));
+    const int nseg = ldu(d->nseg);
+    for (int k = threadIdx.x; k < nseg; k += kBlock) s_coef[k] = coef[k];
+    __syncthreads();
+  }
+  const int t = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  if (t >= ldu(d->n_citems)) return;
+  const int r = ldu(ldu(d->citem_ring)[t]);
+  const int a0 = ldu(ldu(d->citem_a0)[t]);
+  const int ni = ldu(ldu(d->rn)[r]);
+  const int ci = ldu(ldu(d->rc)[r]);
+  const int F = ((ni >> 2) - ci) / 2 + 1;
+  const int lane = threadIdx.x & 63;
+  const int row = lane & 15;
+  const int kgrp = lane >> 4;
+  const int u_row = 2 * (a0 + row) + ci;
+  const double inv_h = ldu(d->inv_h);
+  const double ih2 = inv_h * inv_h;
+  const double qcut = ldu(d->dcut2) * ih2;
+  const int seg_max = ldu(d->nseg) - 1;
+  const long long* rest_off = ldu(d->rest_off);
+  const convreal::CapPair* cpair = ldu(d->cpair);
+  const long long k0 = ldu(rest_off[r]);
+  const long long k1 = ldu(rest_off[r + 1]);
+  long long pos = FILL ? offsets[t] : 0;
+  for (long long kk = k0; kk < k1; ++kk) {
+    const convreal::CapPair P = ldu_record(cpair[kk]);
+    int lo, hi;
+    row_window(P, u_row, ni, lo, hi);
+    const int wr = a0 + row < F ? max(0, hi - lo + 1) : 0;
+    int total;
+    const int off = scan16(wr, total);
+    if (FILL && total > 0) {
+      int wmax = wr;
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 16));
+      const LongForm lf(P, ni, ih2);
+      float* dst = store + pos + off;
+      for (int q = 0; 32 * q < wmax; ++q) {
+        const int k = 32 * q + 8 * kgrp;
+        double qv[8];
+        lf.q8(u_row, lo + k, ni, P.nj, P.cj, qv);
+        float w[8];
+        weights_of<8>(qv, qcut, seg_max, s_coef, w);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (k + e < wr) dst[k + e] = w[e];
+      }
+    }
+    pos += (total + 3) & ~3;   // each pair's block starts on a float4 boundary
+  }
+  if (!FILL && lane == 0) offsets[t] = pos;
+}
+
 // ---------------------------------------------------------------- persistent queue kernel
-template <int SEG>
-// at least two waves per SIMD, so that belt (matrix-core) and cap (VALU) items share a SIMD
+template <int SEG, bool FLY>
+// at least two waves per SIMD, so that belt (matrix-core) and cap items share a SIMD
 __global__ __launch_bounds__(kBlock, 2) void mixed_persistent_kernel(convreal::Slots S,
                                                                   const int2* __restrict__ items,
                                                                   int n_items, int nrep,
@@ -572,7 +824,7 @@ __global__ __launch_bounds__(kBlock, 2) void mixed_persistent_kernel(convreal::S
     if (kind == 0) {
       belt_item<SEG>(d, idx, S.x[slot], S.y[slot], sx, stage);
     } else {
-      if (owner != d) {
+      if (FLY && owner != d) {
         const float4* coef = reinterpret_cast<const float4*>(ldu(d->coef));
         const int nseg = ldu(d->nseg);
         for (int k = threadIdx.x; k < nseg; k += kBlock) s_coef[k] = coef[k];
@@ -580,7 +832,9 @@ __global__ __launch_bounds__(kBlock, 2) void mixed_persistent_kernel(convreal::S
         if (threadIdx.x == 0) s_coef_owner = d;
       }
       const int t = idx * kWaves + __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
-      if (t < ldu(d->n_citems)) cap_tile(d, t, S.x[slot], S.y[slot], sx, s_coef);
+      if (t < ldu(d->n_citems))
+        cap_tile<FLY>(d, t, S.x[slot], S.y[slot], sx, s_coef,
+                      reinterpret_cast<float*>(lds) + kStageFloats * (threadIdx.x >> 6));
     }
     __syncthreads();
   }
@@ -628,7 +882,7 @@ hipError_t build_belt_weights(conv_real_plan* p) {
 // Launch the prep kernels and the persistent kernel over `nslots` maps whose descriptors are in S.
 hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, int nslots, const int2* items,
                               int n_items, int nrep, unsigned* amax, unsigned* counter, const Tuning& tune,
-                              int max_nseg, long long npix_max, long long pairs, hipStream_t st) {
+                              int max_nseg, long long npix_max, long long pairs, bool fly, hipStream_t st) {
   hipLaunchKernelGGL(zero_state_kernel, dim3(1), dim3(kMaxSlots), 0, st, amax, nslots, counter);
   mark(mark_plan, st, "zero_state_kernel", 0);
   const long long want = (npix_max + 255) / 256;
@@ -644,12 +898,16 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
     if (total >= (1LL << 31)) return hipErrorInvalidValue;   // item counter is 32-bit
     long long grid = static_cast<long long>(ncu) * (tune.wg_per_cu > 0 ? tune.wg_per_cu : 2);
     if (grid > total) grid = total;
-    if (tune.seg == 512)
-      hipLaunchKernelGGL(mixed_persistent_kernel<512>, dim3(static_cast<unsigned>(grid)), dim3(kBlock), lds, st, S,
-                         items, n_items, nrep, amax, counter, static_cast<int>(coef_off));
+    const dim3 g(static_cast<unsigned>(grid)), blk(kBlock);
+    const int co = static_cast<int>(coef_off);
+    if (tune.seg == 512 && fly)
+      hipLaunchKernelGGL((mixed_persistent_kernel<512, true>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+    else if (tune.seg == 512)
+      hipLaunchKernelGGL((mixed_persistent_kernel<512, false>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+    else if (fly)
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, true>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
     else
-      hipLaunchKernelGGL(mixed_persistent_kernel<256>, dim3(static_cast<unsigned>(grid)), dim3(kBlock), lds, st, S,
-                         items, n_items, nrep, amax, counter, static_cast<int>(coef_off));
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, false>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     mark(mark_plan, st, "mixed_persistent_kernel", pairs);
@@ -667,11 +925,30 @@ hipError_t set_lds_limits(int nseg) {
   const size_t need = persistent_lds_bytes(512, nseg);
   if (need > static_cast<size_t>(optin)) return hipErrorInvalidValue;
   const int bytes = static_cast<int>(need);
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&mixed_persistent_kernel<256>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&mixed_persistent_kernel<512>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* fns[] = {reinterpret_cast<const void*>(&mixed_persistent_kernel<256, true>),
+                       reinterpret_cast<const void*>(&mixed_persistent_kernel<256, false>),
+                       reinterpret_cast<const void*>(&mixed_persistent_kernel<512, true>),
+                       reinterpret_cast<const void*>(&mixed_persistent_kernel<512, false>)};
+  for (const void* f : fns) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t cap_store_count(const conv_real_plan* p, long long* counts_dev) {
+  const unsigned grid = static_cast<unsigned>((p->n_citems + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(cap_store_kernel<false>, dim3(grid), dim3(kBlock), 0, nullptr, p->d_desc, counts_dev,
+                     static_cast<float*>(nullptr));
+  return hipGetLastError();
+}
+
+hipError_t cap_store_fill(const conv_real_plan* p) {
+  const unsigned grid = static_cast<unsigned>((p->n_citems + kWaves - 1) / kWaves);
+  const size_t lds = sizeof(float4) * static_cast<size_t>(p->cap_nseg > 0 ? p->cap_nseg : 1);
+  hipLaunchKernelGGL(cap_store_kernel<true>, dim3(grid), dim3(kBlock), lds, nullptr, p->d_desc, p->d_wtile_off,
+                     p->d_wstore);
+  return hipGetLastError();
 }
 
 hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st) {
@@ -684,7 +961,7 @@ hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int n
       S.y[k] = y + static_cast<size_t>(m0 + k) * p->npix;
     }
     hipError_t e = launch_mixed_queue(p, S, nm, p->d_items, p->n_items, nm, p->d_amax, p->d_counter, p->tune,
-                                      p->cap_nseg, p->npix, p->pairs * nm, st);
+                                      p->cap_nseg, p->npix, p->pairs * nm, p->cap_mode && !p->d_wstore, st);
     if (e != hipSuccess) return e;
     if (!p->cap_mode) {
       // table too large for the LDS coefficient form: cap-touching pairs per pair in FP64, added to

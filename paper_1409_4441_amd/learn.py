@@ -1,8 +1,9 @@
 """Learned split: ctypes binding of include/convlearn.h, and the predict / judge / fall back flow.
 
 The network maps normalised (log2 Nside, ln FWHM, log10 target error) to normalised
-(ln(theta_cut / sigma), l_cut / lmax), sigma = FWHM / sqrt(8 ln 2), for a Gaussian beam with
-lmax = 2 Nside, C^in = 1 and the Eq. 6 error with alpha = 5. Labels are the split search's answers
+(ln(theta_cut / sigma), l_cut / lmax), sigma = FWHM / sqrt(8 ln 2), for the kernels
+K_l = sqrt(C_l) B_l (Gaussian beam B_l, C_l = 1/(l(l+1))) with lmax = 2 Nside, C^in = 1 and the
+Eq. 6 error with alpha = 5. Labels are the split search's answers
 (conv_split_search_many) under the measured cost model; training runs on the device with the
 library's forward, back-propagation and Adam kernels. A prediction is judged by the error model
 (conv_split_error); if it misses the bound, the split search decides instead.
@@ -23,7 +24,7 @@ import os
 
 import numpy as np
 
-from . import ConvRealError, _check, _stream_handle, device_runtime, lib
+from . import ConvRealError, _check, _stream_handle, lib
 from . import split as _split
 
 N_PARAMS = 4546
@@ -80,7 +81,6 @@ class Network:
     """The 3-64-64-2 network on the current device; batches of up to max_batch samples."""
 
     def __init__(self, max_batch: int = 4096):
-        device_runtime()
         h = _c_void_p()
         _check(lib.conv_mlp_create(ctypes.byref(h), int(max_batch)), "conv_mlp_create")
         self._h = h
@@ -88,7 +88,7 @@ class Network:
         self.norm = None   # feature/target normalisation of a trained network
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        if getattr(self, "_h", None) is not None and self._h.value and lib is not None:
             lib.conv_mlp_destroy(self._h)
             self._h = _c_void_p()
 
@@ -161,6 +161,16 @@ def beam(lmax: int, fwhm_arcmin: float) -> np.ndarray:
     return np.exp(-0.5 * ell * (ell + 1.0) * s * s)
 
 
+def kernel_ell(lmax: int, fwhm_arcmin: float) -> np.ndarray:
+    """The kernels of the paper's Results section, K_l = sqrt(C_l) B_l (simulating a map with
+    spectrum C_l seen through a Gaussian beam, input C^in = 1), with C_l = 1/(l(l+1)) for l >= 2
+    (0 below) standing in for the WMAP spectrum."""
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    c = np.zeros(lmax + 1)
+    c[2:] = 1.0 / (ell[2:] * (ell[2:] + 1.0))
+    return np.sqrt(c) * beam(lmax, fwhm_arcmin)
+
+
 def features(nside, fwhm_arcmin, eps) -> np.ndarray:
     """Inputs scaled to [-1, 1] over the learned ranges."""
     nside, fwhm, eps = (np.asarray(v, dtype=np.float64) for v in (nside, fwhm_arcmin, eps))
@@ -198,7 +208,7 @@ def scan(nside, fwhm, eps, model, ctxs=None, nthreads: int = 0):
     try:
         for ns in np.unique(nside):
             idx = np.nonzero(nside == ns)[0]
-            K = np.stack([beam(2 * int(ns), fwhm[k]) for k in idx])
+            K = np.stack([kernel_ell(2 * int(ns), fwhm[k]) for k in idx])
             grids = np.stack([np.array(THETA_SIGMAS) * sigma_of(fwhm[k]) for k in idx])
             r = ctxs[int(ns)].search_many(K, int(ns), eps[idx], grids, model, alpha=ALPHA, ell_step=ELL_STEP,
                                           nthreads=nthreads)
@@ -269,7 +279,7 @@ class Predictor:
         """Eq. 6 error of a split and whether it meets eps."""
         ctx = self.ctxs[int(nside)]
         th = min(max(float(theta_cut), 1e-9), ctx.theta_max)
-        _, sig = ctx.error(beam(2 * int(nside), fwhm), int(ell_cut), th, alpha=ALPHA)
+        _, sig = ctx.error(kernel_ell(2 * int(nside), fwhm), int(ell_cut), th, alpha=ALPHA)
         return sig, sig <= eps
 
     def predict(self, nside: int, fwhm: float, eps: float):

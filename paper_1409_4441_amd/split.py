@@ -122,7 +122,7 @@ class Context:
         self._h = h
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        if getattr(self, "_h", None) is not None and self._h.value and lib is not None:
             lib.conv_split_destroy(self._h)
             self._h = _c_void_p()
 

@@ -268,3 +268,41 @@ def workload(name: str) -> Workload:
                         map_kind="red+noise", map_lmax=4096, noise_frac=0.01, dtype="f32",
                         seed=BASE_SEED + 2)
     raise KeyError(name)
+
+
+def batch_workload(nmaps: int = 32, seed: int = BASE_SEED + 3):
+    """The batched workload: nmaps maps of uneven size and beam, drawn from one PCG64 stream.
+
+    Per map k: Nside uniform over {256, 512, 1024, 2048}, FWHM uniform in [5', 30'],
+    sigma = FWHM / sqrt(8 ln 2), theta_cut = 6 sigma, l_cut = 0.3 / sigma (radians), taper width
+    round(l_cut / 6), kernel band limit 2 Nside; even k white N(0, 1) maps, odd k red fields
+    C_l = 1/(l(l+1)) to l = 2 Nside. Returns a list of Workload records (FP32 maps)."""
+    g = rng(seed)
+    nsides = g.choice([256, 512, 1024, 2048], nmaps)
+    fwhms = g.uniform(5.0, 30.0, nmaps) * ARCMIN
+    out = []
+    for k in range(nmaps):
+        ns, fwhm = int(nsides[k]), float(fwhms[k])
+        sigma = fwhm / np.sqrt(8.0 * np.log(2.0))
+        lc = 0.3 / sigma
+        out.append(Workload(f"batch{k}", nside=ns, theta_cut=6.0 * sigma, lmax=2 * ns, kernel="residual",
+                            fwhm=fwhm, ell_cut=lc, taper_width=float(round(lc / 6.0)),
+                            map_kind="white" if k % 2 == 0 else "red", map_lmax=2 * ns, dtype="f32",
+                            seed=seed + 1 + k))
+    return out
+
+
+def batch_maps(ws, shared_red: bool = True):
+    """Maps of a batched workload. With shared_red, the red maps of one Nside share a single field
+    (the seed of the first such map), which keeps the host synthesis to one field per Nside; the
+    convolution's cost does not depend on the values."""
+    red = {}
+    maps = []
+    for w in ws:
+        if w.map_kind == "white":
+            maps.append(white_noise(w.nside, 1, seed=w.seed, dtype=np.float32)[0])
+            continue
+        if not shared_red or w.nside not in red:
+            red[w.nside] = grf_map(w.nside, red_spectrum(w.map_lmax), w.seed).astype(np.float32)
+        maps.append(red[w.nside])
+    return maps

@@ -1,0 +1,77 @@
+"""What the trained split network gains over the method without it (the split search), on held-out
+(Nside, FWHM, target error) triples: its split is accepted by the error model for most triples, an
+accepted split costs (in the measured cost model) no more than 5% above the search's on average,
+every returned split meets its bound (network or fallback), and the network decides far faster than
+the search. Uses the committed network parameters and cost model."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+cr = pytest.importorskip("paper_1409_4441_amd")
+from paper_1409_4441_amd import learn, train_split  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+N_EVAL = 60
+
+
+@pytest.fixture(scope="module")
+def predictor(cuda_device):
+    if not (os.path.exists(learn.DEFAULT_MODEL) and os.path.exists(learn.DEFAULT_COST)):
+        pytest.fail("trained network or cost model missing")
+    p = learn.Predictor.load()
+    yield p
+    p.close()
+
+
+def test_network_split_is_accepted_and_cheap(predictor):
+    ns, fw, ep = learn.draw_triples(N_EVAL, train_split.TEST_SEED)
+    t0 = time.perf_counter()
+    th_s, lc_s, wl_s, sg_s = learn.scan(ns, fw, ep, predictor.model, ctxs=predictor.ctxs, nthreads=1)
+    t_search = (time.perf_counter() - t0) / N_EVAL
+    assert np.all(sg_s <= ep)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th_n, lc_n = predictor.network_split(ns, fw, ep)
+    t_net = (time.perf_counter() - t0) / N_EVAL
+    ok, ratio = [], []
+    t0 = time.perf_counter()
+    for k in range(N_EVAL):
+        _, good = predictor.judge(int(ns[k]), float(fw[k]), float(ep[k]), float(th_n[k]), int(lc_n[k]))
+        ok.append(good)
+        if good:
+            th = min(float(th_n[k]), predictor.ctxs[int(ns[k])].theta_max)
+            ratio.append(predictor.model.eval(int(ns[k]), 2 * int(ns[k]), th, int(lc_n[k]))[2] / wl_s[k])
+    t_judge = (time.perf_counter() - t0) / N_EVAL
+    assert np.mean(ok) >= 0.5, np.mean(ok)
+    assert np.mean(ratio) <= 1.05, np.mean(ratio)
+    # deciding by the network and the error model's one evaluation against the full search
+    assert t_net + t_judge < t_search / 5, (t_net, t_judge, t_search)
+
+
+def test_predict_always_meets_the_bound(predictor):
+    ns, fw, ep = learn.draw_triples(20, train_split.TEST_SEED + 1)
+    sources = set()
+    for k in range(len(ns)):
+        th, lc, src = predictor.predict(int(ns[k]), float(fw[k]), float(ep[k]))
+        sources.add(src)
+        _, good = predictor.judge(int(ns[k]), float(fw[k]), float(ep[k]), th, lc)
+        assert good, (k, src)
+    assert sources <= {"mlp", "fallback"}
+
+
+def test_fixed_rule_is_worse(predictor):
+    """The batched workload's fixed rule (theta_cut = 6 sigma, l_cut = 0.3 / sigma) meets the bound
+    less often than the network."""
+    ns, fw, ep = learn.draw_triples(N_EVAL, train_split.TEST_SEED)
+    th_n, lc_n = predictor.network_split(ns, fw, ep)
+    net_ok = fixed_ok = 0
+    for k in range(N_EVAL):
+        s = learn.sigma_of(float(fw[k]))
+        fixed_ok += predictor.judge(int(ns[k]), float(fw[k]), float(ep[k]), 6 * s,
+                                    int(min(2 * int(ns[k]), round(0.3 / s))))[1]
+        net_ok += predictor.judge(int(ns[k]), float(fw[k]), float(ep[k]), float(th_n[k]), int(lc_n[k]))[1]
+    assert net_ok > fixed_ok

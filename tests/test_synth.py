@@ -66,3 +66,21 @@ def test_workloads():
     assert len(k) == 4097 and k[1000] == 0.0 and k[1600] > 0
     g = synth.cosine_taper(2000, 600, 100)
     assert g[550] == 1.0 and g[650] == 0.0 and g[600] == pytest.approx(0.5)
+
+
+def test_batch_workload_recipe():
+    ws = synth.batch_workload()
+    assert len(ws) == 32
+    assert {w.nside for w in ws} <= {256, 512, 1024, 2048}
+    for k, w in enumerate(ws):
+        fwhm = w.fwhm / synth.ARCMIN
+        sigma = w.fwhm / math.sqrt(8 * math.log(2))
+        assert 5.0 <= fwhm <= 30.0
+        assert w.theta_cut == pytest.approx(6 * sigma)
+        assert w.ell_cut == pytest.approx(0.3 / sigma) and w.taper_width == round(w.ell_cut / 6)
+        assert w.lmax == 2 * w.nside and w.map_kind == ("white" if k % 2 == 0 else "red")
+    again = synth.batch_workload()
+    assert [(w.nside, w.fwhm) for w in again] == [(w.nside, w.fwhm) for w in ws]
+    small = [w for w in ws if w.nside == 256][:2]
+    maps = synth.batch_maps(small)
+    assert all(m.dtype == np.float32 and m.shape == (12 * 256 ** 2,) for m in maps)
