@@ -102,6 +102,7 @@ struct BeltLayout {
 // LDS slice per wave for a ring pair's block of stored cap weights (the belt stage area is free
 // while a workgroup works on cap tiles)
 constexpr int kStageFloats = 1536;
+static_assert(kStageFloats % 256 == 0, "whole float4 rows of 64 lanes");
 static_assert(kWaves * kStageFloats * 4 <= BeltLayout<256>::BYTES, "cap weight stage must fit the belt stage");
 
 // ---------------------------------------------------------------- prep kernels
@@ -183,32 +184,71 @@ __global__ __launch_bounds__(256) void belt_weights_kernel(WeightArgs a) {
 }
 
 // ---------------------------------------------------------------- belt item
+// Belt staging, software-pipelined one input ring ahead: while the matrix cores work on ring j,
+// every thread holds ring j+1's share of the input window (PX pixels) and of the weight fragments
+// (2 half8) in registers; after the products they go to the other LDS buffer.
 template <int SEG>
-__device__ __forceinline__ void stage_ring(_Float16* __restrict__ S, const float* __restrict__ xj,
-                                           int start_px, int len, int ring_n, float sx) {
-  using BL = BeltLayout<SEG>;
-  for (int u = threadIdx.x; u < len; u += kBlock) {
-    int p = start_px + u;
-    while (p < 0) p += ring_n;
-    while (p >= ring_n) p -= ring_n;
-    const float xs = xj[p] * sx;
-    const _Float16 hh = static_cast<_Float16>(xs);
-    const _Float16 ll = static_cast<_Float16>(xs - static_cast<float>(hh));
+struct BeltPrefetch {
+  static constexpr int PX = (SEG + 32 * kNKMax + kBlock - 1) / kBlock;
+  float x[PX];
+  half8 w[2];
+  int len;     // window pixels
+  int nwv;     // weight half8 of the ring (128 per K-chunk)
+
+  __device__ __forceinline__ void load(const float* __restrict__ xj, int start_px, int len_, int ring_n,
+                                       const half8* __restrict__ wsrc, int nwv_) {
+    len = len_;
+    nwv = nwv_;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      if (u >= c) {
-        S[c * BL::CS + u - c] = hh;
-        S[c * BL::CS + BL::L + u - c] = ll;
+    for (int i = 0; i < PX; ++i) {
+      const int u = threadIdx.x + i * kBlock;
+      if (u < len) {
+        int p = start_px + u;   // start_px > -ring_n and the window is shorter than the ring
+        p = p < 0 ? p + ring_n : p;
+        p = p >= ring_n ? p - ring_n : p;
+        x[i] = xj[p];
       }
     }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int v = threadIdx.x + i * kBlock;
+      if (v < nwv) w[i] = wsrc[v];
+    }
   }
-}
+
+  // 8 copies of the window shifted by one pixel, split into FP16 pairs; weights as they are
+  __device__ __forceinline__ void store(_Float16* __restrict__ S, half8* __restrict__ W, float sx) const {
+    using BL = BeltLayout<SEG>;
+#pragma unroll
+    for (int i = 0; i < PX; ++i) {
+      const int u = threadIdx.x + i * kBlock;
+      if (u < len) {
+        const float xs = x[i] * sx;
+        const _Float16 hh = static_cast<_Float16>(xs);
+        const _Float16 ll = static_cast<_Float16>(xs - static_cast<float>(hh));
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          if (u >= c) {
+            S[c * BL::CS + u - c] = hh;
+            S[c * BL::CS + BL::L + u - c] = ll;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int v = threadIdx.x + i * kBlock;
+      if (v < nwv) W[v] = w[i];
+    }
+  }
+};
 
 template <int SEG>
 __device__ void belt_item(const convreal::MixedDesc* __restrict__ d, int idx, const float* __restrict__ xm,
                           float* __restrict__ ym, float sx, _Float16* __restrict__ S) {
   using BL = BeltLayout<SEG>;
   constexpr int NB = SEG / (16 * kWaves);  // 16-pixel blocks per wave
+  half8* Wbuf = reinterpret_cast<half8*>(S + 2 * BL::BUF);   // 2 x kNKMax x 128 weight fragments
   const int ring_n = ldu(d->ring_n);
   const int nsegs = (ring_n + SEG - 1) / SEG;
   const int band = idx / nsegs;
@@ -238,15 +278,23 @@ __device__ void belt_item(const convreal::MixedDesc* __restrict__ d, int idx, co
     for (int r = 0; r < 4; ++r) accd[b][r] = 0.0;
   }
 
-  stage_ring<SEG>(S, xm + ldu(rstart[jf]), a0 + ldu(blk_mlo[woff]), SEG + 32 * ldu(blk_nk[woff]), ring_n, sx);
+  BeltPrefetch<SEG> pf;
+  {
+    const int nk0 = ldu(blk_nk[woff]);
+    pf.load(xm + ldu(rstart[jf]), a0 + ldu(blk_mlo[woff]), SEG + 32 * nk0, ring_n,
+            wt + static_cast<long long>(ldu(blk_koff[woff])) * 128, nk0 * 128);
+    pf.store(S, Wbuf, sx);
+  }
   __syncthreads();
   for (int jj = 0; jj < nj; ++jj) {
     const int buf = jj & 1;
-    if (jj + 1 < nj)
-      stage_ring<SEG>(S + (buf ^ 1) * BL::BUF, xm + ldu(rstart[jf + jj + 1]), a0 + ldu(blk_mlo[woff + jj + 1]),
-                      SEG + 32 * ldu(blk_nk[woff + jj + 1]), ring_n, sx);
+    if (jj + 1 < nj) {
+      const int nk1 = ldu(blk_nk[woff + jj + 1]);
+      pf.load(xm + ldu(rstart[jf + jj + 1]), a0 + ldu(blk_mlo[woff + jj + 1]), SEG + 32 * nk1, ring_n,
+              wt + static_cast<long long>(ldu(blk_koff[woff + jj + 1])) * 128, nk1 * 128);
+    }
     const int nk = ldu(blk_nk[woff + jj]);
-    const half8* wblk = wt + static_cast<long long>(ldu(blk_koff[woff + jj])) * 128;
+    const half8* wblk = Wbuf + buf * (kNKMax * 128);
     const _Float16* Sb = S + buf * BL::BUF + lane_off;
     for (int q = 0; q < nk; ++q) {
       const half8 whi = wblk[q * 128 + lane];
@@ -272,6 +320,8 @@ __device__ void belt_item(const convreal::MixedDesc* __restrict__ d, int idx, co
         acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
     }
+    // the other buffers were last read in ring jj - 1, before the previous barrier
+    if (jj + 1 < nj) pf.store(S + (buf ^ 1) * BL::BUF, Wbuf + (buf ^ 1) * (kNKMax * 128), sx);
     __syncthreads();
   }
 
@@ -590,9 +640,19 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
       const int pofs = cf ? (nj - cj + cq * (nj >> 2)) : cq * (nj >> 2);
       const float rcp_n = 1.0f / static_cast<float>(nj);
       if (tot4 <= kStageFloats) {
+        // all of the lane's loads are issued before the first LDS write, so one memory latency
+        // covers the whole block
         const float4* src = reinterpret_cast<const float4*>(blk);
         float4* dst = reinterpret_cast<float4*>(wstage);
-        for (int i = lane; i < (tot4 >> 2); i += 64) dst[i] = src[i];
+        const int n4 = tot4 >> 2;
+        constexpr int kPer = kStageFloats / 4 / 64;
+        float4 v[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+          if (lane + 64 * k < n4) v[k] = src[lane + 64 * k];
+#pragma unroll
+        for (int k = 0; k < kPer; ++k)
+          if (lane + 64 * k < n4) dst[lane + 64 * k] = v[k];
         // LDS traffic of one wave is processed in order; the fence keeps the compiler from moving
         // the row reads above the block's writes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -844,8 +904,11 @@ __global__ __launch_bounds__(kBlock, 2) void mixed_persistent_kernel(convreal::S
 
 namespace convreal {
 
+// belt stage: two window buffers (8 shifted copies, hi and lo planes) and two weight-fragment buffers
 size_t belt_stage_bytes(int seg) {
-  return seg == 512 ? static_cast<size_t>(BeltLayout<512>::BYTES) : static_cast<size_t>(BeltLayout<256>::BYTES);
+  const size_t wbytes = 2 * kNKMax * 128 * sizeof(half8);
+  return (seg == 512 ? static_cast<size_t>(BeltLayout<512>::BYTES) : static_cast<size_t>(BeltLayout<256>::BYTES)) +
+         wbytes;
 }
 
 // Dynamic LDS of the persistent kernel: the belt stage, then the coefficient table.
@@ -891,7 +954,8 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
   mark(mark_plan, st, "prep_kernel", 0);
   if (n_items > 0 && nrep > 0) {
     const size_t coef_off = (belt_stage_bytes(tune.seg) + 15) / 16 * 16;
-    const size_t lds = persistent_lds_bytes(tune.seg, max_nseg);
+    // the coefficient table is only read when some slot evaluates cap weights on the fly
+    const size_t lds = persistent_lds_bytes(tune.seg, fly ? max_nseg : 0);
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     long long total = static_cast<long long>(n_items) * nrep;
