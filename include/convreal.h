@@ -141,8 +141,8 @@ int conv_real_profile(conv_real_plan* plan, const void* maps_in, void* maps_out,
 /*
  * Launch configuration of the mixed path (CONV_REAL_MIXED). All of a mixed apply's pair sums run
  * in one persistent kernel that drains a work queue of belt items (a band of 16 output rings x
- * `seg` output pixels, matrix-core bound) and cap items (64 output pixels with their 16 symmetric
- * images each, bound by on-the-fly weight evaluation).
+ * `seg` output pixels, bound by LDS traffic) and cap items (64 output pixels with their 16 symmetric
+ * images each, bound by on-the-fly weight evaluation or by the weight store's stream).
  *   seg        belt output pixels per work item: 256 or 512
  *   wg_per_cu  resident workgroups per compute unit (persistent grid = CUs x wg_per_cu): 1..4
  *   order      0: items by decreasing estimated cost; 1: belt and cap items alternating
@@ -163,13 +163,17 @@ int conv_real_get_tuning(const conv_real_plan* plan, conv_real_tuning* t);
  * Cap weight store of a mixed plan. The cap-touching ring pairs' weights (one per output pixel of
  * the symmetry group's fundamental domain and input pixel inside that pixel's window: about the
  * cap-touching pixel pairs divided by 16) are either evaluated on the fly by every apply, or
- * computed once into device memory (FP32, tile by tile) and streamed by every apply, which moves
- * that part of the kernel from arithmetic to memory bandwidth. The two give the same result up to
- * FP32 rounding of the weights (both within the mixed path's tolerance).
+ * computed once into device memory and streamed by every apply, which moves that part of the kernel
+ * from arithmetic to memory bandwidth. The store keeps each weight as the FP16 pair the matrix cores
+ * take, in 16-byte groups of 4 inputs that meet the output pixel's window (about 4.5 bytes per
+ * weight). Both evaluate the same interpolated kernel; their results differ only by the rounding
+ * of the weights' two evaluation forms, far within the mixed path's tolerance.
  *   CONV_REAL_STORE_OFF   evaluate on the fly; frees a store the plan holds
  *   CONV_REAL_STORE_ON    build the store (ENOMEM if the device cannot hold it)
  *   CONV_REAL_STORE_AUTO  build it if it needs at most 16 GiB and 40% of the free device memory
- * A new mixed plan evaluates on the fly (CONV_REAL_STORE_OFF).
+ * A new mixed plan takes CONV_REAL_STORE_AUTO. Unless the plan's launch configuration was set by
+ * conv_real_set_tuning or conv_real_autotune, changing the store also picks its default seg: 512
+ * with a store, 256 without.
  * conv_real_set_weight_store is synchronous (not while an apply on the plan may still run) and
  * allocates; applies never allocate. conv_real_get_weight_store reports whether a store is held
  * and its size in bytes. Mixed plans only (EINVAL otherwise).

@@ -490,7 +490,7 @@ int set_weight_store(conv_real_plan* p, int mode) {
   release(p, p->d_wtile_off);
   p->d_wstore = nullptr;
   p->d_wtile_off = nullptr;
-  p->wstore_floats = 0;
+  p->wstore_groups = 0;
   p->h_desc.wstore = nullptr;
   p->h_desc.wtile_off = nullptr;
   p->wstore_mode = mode;
@@ -510,8 +510,8 @@ int set_weight_store(conv_real_plan* p, int mode) {
     release(p, counts);
     for (int t = 0; t < p->n_citems; ++t) off[t + 1] += off[t];
     const long long n = off[p->n_citems];
-    // 64 floats of padding: masked lanes may read the first weight of an empty trailing row
-    const size_t bytes = sizeof(float) * static_cast<size_t>(n + 64);
+    // 16-byte groups (each tile's block starts with its zero groups), every one written by the fill
+    const size_t bytes = sizeof(uint4) * static_cast<size_t>(n);
     bool build = true;
     if (mode == CONV_REAL_STORE_AUTO) {
       size_t free_b = 0, total_b = 0;
@@ -521,14 +521,17 @@ int set_weight_store(conv_real_plan* p, int mode) {
     }
     if (build) {
       off.pop_back();
-      if ((e = dev_alloc(p, &p->d_wstore, static_cast<size_t>(n + 64))) != hipSuccess) {
-        rc = hip_fail(e, "weight store: allocation");
-      } else if ((e = hipMemset(p->d_wstore, 0, bytes)) != hipSuccess ||
-                 (e = dev_upload(p, &p->d_wtile_off, off)) != hipSuccess ||
+      if ((e = dev_alloc(p, &p->d_wstore, static_cast<size_t>(n))) != hipSuccess) {
+        // the automatic mode falls back to evaluating on the fly
+        if (mode == CONV_REAL_STORE_AUTO)
+          (void)hipGetLastError();
+        else
+          rc = hip_fail(e, "weight store: allocation");
+      } else if ((e = dev_upload(p, &p->d_wtile_off, off)) != hipSuccess ||
                  (e = convreal::cap_store_fill(p)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
         rc = hip_fail(e, "weight store: fill");
       } else {
-        p->wstore_floats = n;
+        p->wstore_groups = n;
         p->h_desc.wstore = p->d_wstore;
         p->h_desc.wtile_off = p->d_wtile_off;
       }
@@ -540,6 +543,10 @@ int set_weight_store(conv_real_plan* p, int mode) {
       }
     }
   }
+  // Unless the caller chose the launch configuration: with a store the kernel needs no coefficient
+  // table in LDS, so two workgroups with 512-pixel belt items fit a compute unit, and they are
+  // faster than 256-pixel items; without one the table leaves room for 256-pixel items only.
+  if (!p->tune_user) p->tune.seg = p->d_wstore ? 512 : 256;
   if ((e = hipMemcpy(p->d_desc, &p->h_desc, sizeof(p->h_desc), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = build_items(p)) != hipSuccess)
     return hip_fail(e, "weight store: descriptor");
@@ -691,7 +698,7 @@ int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_
       return rc;
     }
     p->pairs_rest = static_cast<long long>(cnt);
-    if ((rc = set_weight_store(p, CONV_REAL_STORE_OFF)) != CONV_REAL_OK) {
+    if ((rc = set_weight_store(p, CONV_REAL_STORE_AUTO)) != CONV_REAL_OK) {
       free_plan(p);
       return rc;
     }
@@ -722,7 +729,7 @@ int conv_real_get_weight_store(const conv_real_plan* plan, int* active, long lon
     return CONV_REAL_EINVAL;
   }
   *active = plan->d_wstore ? 1 : 0;
-  *bytes = plan->d_wstore ? static_cast<long long>(sizeof(float)) * (plan->wstore_floats + 64) : 0;
+  *bytes = plan->d_wstore ? static_cast<long long>(sizeof(uint4)) * plan->wstore_groups : 0;
   return CONV_REAL_OK;
 }
 
@@ -949,6 +956,7 @@ int conv_real_set_tuning(conv_real_plan* plan, const conv_real_tuning* t) {
   if (e != hipSuccess) return hip_fail(e, "conv_real_set_tuning: hipSetDevice");
   if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "conv_real_set_tuning: sync");
   plan->tune = to_internal(t);
+  plan->tune_user = 1;
   if ((e = build_items(plan)) != hipSuccess) return hip_fail(e, "conv_real_set_tuning: work queue");
   return CONV_REAL_OK;
 }

@@ -88,8 +88,8 @@ struct MixedDesc {
   const int* citem_a0;
   const long long* rest_off;  // per ring: first record in cpair
   const CapPair* cpair;       // cap-touching ring pairs, grouped by output ring
-  const float* wstore;        // cap weight store (nullptr: weights evaluated on the fly)
-  const long long* wtile_off; // per cap tile: first weight of the tile in wstore
+  const void* wstore;         // cap weight store, 16-byte groups (nullptr: weights evaluated on the fly)
+  const long long* wtile_off; // per cap tile: first group of the tile in wstore
   double inv_h;
   double dcut2;
   float inv_sw;
@@ -193,17 +193,18 @@ struct conv_real_plan {
   int* d_citem_a0 = nullptr;   // per work item: first pixel of a 16-pixel tile
   int n_citems = 0;
   convreal::CapPair* d_cpair = nullptr;  // per cap-touching ring pair, in d_rest_idx order
-  // cap weight store: every cap-tile weight row (rows inside the fundamental domain, inputs inside
-  // the row's window) as FP32, tile after tile, ring pair after ring pair, row after row
-  float* d_wstore = nullptr;
-  long long* d_wtile_off = nullptr;  // per cap tile (n_citems + 1)
-  long long wstore_floats = 0;
+  // cap weight store: per cap tile, ring pair and row inside the fundamental domain, the row's
+  // weights in 16-byte groups of 4 inputs (FP16 hi x 4, FP16 lo x 4) that meet the row's window
+  uint4* d_wstore = nullptr;
+  long long* d_wtile_off = nullptr;  // per cap tile: first group
+  long long wstore_groups = 0;
   int wstore_mode = 2;               // CONV_REAL_STORE_OFF / ON / AUTO as last requested
   convreal::MixedDesc h_desc{};      // host copy of d_desc
   int* d_ring_add = nullptr;   // per ring: 1 if it gets a belt and a cap-pair contribution
   int cap_nseg = 0;            // coefficient segments (n_tab - 2) if cap_mode
   convreal::MixedDesc* d_desc = nullptr;  // device copy of the plan's descriptor
   convreal::Tuning tune;
+  int tune_user = 0;           // 1 once the caller set the launch configuration (or autotuned it)
   int2* d_items = nullptr;     // work queue of one map (slot 0)
   int n_items = 0;
   unsigned* d_counter = nullptr;

@@ -18,10 +18,12 @@
 // every weight invariant when both pixels move together, so one weight row of output pixel a
 // serves its 16 images: y[img_g(a)] = sum_b w(a, b) x[img_g(b)]. A wave takes 16 output pixels of
 // the group's fundamental domain and, per neighbour ring, computes D[16 pixels][16 images] +=
-// W[16][K] X[K][16]. W is evaluated on the fly: integer azimuth numerator -> alpha = dphi/2,
+// W[16][K] X[K][16]. W is either evaluated on the fly: integer azimuth numerator -> alpha = dphi/2,
 // sin^2 alpha by a polynomial, d^2 = A + B sin^2 alpha, all in FP64 (the oscillating kernel is
 // sensitive to d at the 1e-8 level near the cut), then the 4-point interpolant in cubic form from
-// an LDS table of per-segment FP32 coefficients. Images that coincide are stored once.
+// an LDS table of per-segment FP32 coefficients; or it is streamed from a weight store built once
+// per plan (the same weights, already split, in groups of 4 inputs that meet a row's window), with
+// the loads of several steps in flight. Images that coincide are stored once.
 //
 // Precision of both: weights and map values are split into FP16 pairs, w s_w = w_hi + w_lo,
 // x s_x = x_hi + x_lo (powers of two), and each block is w_hi x_hi + w_lo x_hi + w_hi x_lo
@@ -30,7 +32,8 @@
 //
 // Scheduling: one workgroup of 4 waves repeatedly takes the next item of a cost-sorted queue: a
 // belt item (one band x one segment of output pixels, MFMA-bound) or a cap item (4 tiles, one per
-// wave, VALU-bound by weight evaluation), so that both kinds share every CU. Rows that receive a
+// wave, VALU-bound by weight evaluation or bound by the store's stream), so that both kinds share
+// every CU. Rows that receive a
 // belt and a cap-pair contribution (belt rings near the belt edge) are zeroed beforehand and get
 // exactly two atomic adds, which is order-independent: fl(0 + a + b) = fl(0 + b + a).
 #include <hip/hip_runtime.h>
@@ -98,12 +101,6 @@ struct BeltLayout {
   static constexpr int BYTES = 2 * BUF * 2;      // two buffers of FP16
   static_assert(((CS * 2) % 256) == 144, "copy stride must spread the 8 copies over LDS banks");
 };
-
-// LDS slice per wave for a ring pair's block of stored cap weights (the belt stage area is free
-// while a workgroup works on cap tiles)
-constexpr int kStageFloats = 1536;
-static_assert(kStageFloats % 256 == 0, "whole float4 rows of 64 lanes");
-static_assert(kWaves * kStageFloats * 4 <= BeltLayout<256>::BYTES, "cap weight stage must fit the belt stage");
 
 // ---------------------------------------------------------------- prep kernels
 __global__ void zero_state_kernel(unsigned* amax, int n, unsigned* counter) {
@@ -436,9 +433,12 @@ __device__ __forceinline__ void load_inputs(const float* __restrict__ xj, int po
 }
 
 // window [lo, hi] of ring j for the output pixel with azimuth numerator u: the per-pair path's rule
-// (centre (u n_j - c_j n_i) / 2 n_i, half-width hw plus 1e-7 pixel; a whole ring: n_j pixels)
-__device__ __forceinline__ void row_window(const convreal::CapPair& P, int u, int ni, int& lo, int& hi) {
-  const double bc = static_cast<double>(u * P.nj - P.cj * ni) / (2.0 * ni);
+// (centre (u n_j - c_j n_i) / 2 n_i, half-width hw plus 1e-7 pixel; a whole ring: n_j pixels).
+// inv_2ni = 1 / (2 n_i): the centre is off by an ulp at most, far inside the 1e-7-pixel slack, and
+// every caller (fill, apply, on-the-fly path) forms it the same way.
+__device__ __forceinline__ void row_window(const convreal::CapPair& P, int u, int ni, double inv_2ni, int& lo,
+                                           int& hi) {
+  const double bc = static_cast<double>(u * P.nj - P.cj * ni) * inv_2ni;
   if (P.whole) {
     lo = static_cast<int>(floor(bc)) - P.nj / 2;
     hi = lo + P.nj - 1;
@@ -448,21 +448,36 @@ __device__ __forceinline__ void row_window(const convreal::CapPair& P, int u, in
   }
 }
 
-// exclusive prefix sum of v over each 16-lane segment of the wave, and the segment's total
+// exclusive prefix sum of v over each 16-lane row of the wave (DPP row shifts: lanes without a
+// source in their row read 0); total: the sum over the first row (callers pass values that depend
+// on the lane's row of the tile only, so every 16-lane row agrees)
 __device__ __forceinline__ int scan16(int v, int& total) {
-  const int l16 = threadIdx.x & 15;
   int x = v;
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) {
-    const int y = __shfl_up(x, o, 16);
-    if (l16 >= o) x += y;
-  }
-  total = __shfl(x, 15, 16);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+  total = __builtin_amdgcn_readlane(x, 15);
   return x - v;
 }
 
-// long-form weights of output pixel u and inputs bA .. bA + 7 (any ring pair): numerator reduced to
-// [-M, M], degree-7 sin^2 polynomial, q = d^2 / h^2
+// union [b0, bend] of the windows of ring j over a tile's 16 rows (the centres increase with a, so
+// the first row gives the start and the last row the end)
+__device__ __forceinline__ void tile_union(const convreal::CapPair& P, int u_first, int u_last, int ni,
+                                           double inv_2ni, int& b0, int& bend) {
+  const double bc0 = static_cast<double>(u_first * P.nj - P.cj * ni) * inv_2ni;
+  const double bc1 = static_cast<double>(u_last * P.nj - P.cj * ni) * inv_2ni;
+  if (P.whole) {
+    b0 = static_cast<int>(floor(bc0)) - P.nj / 2;
+    bend = static_cast<int>(floor(bc1)) - P.nj / 2 + P.nj - 1;
+  } else {
+    b0 = static_cast<int>(ceil(bc0 - P.hw - 1e-7));
+    bend = static_cast<int>(floor(bc1 + P.hw + 1e-7));
+  }
+}
+
+// long-form weights of output pixel u and inputs bA .. bA + E - 1 (any ring pair): numerator reduced
+// to [-M, M], degree-7 sin^2 polynomial, q = d^2 / h^2
 struct LongForm {
   double Ah;
   double cl[8];
@@ -478,11 +493,12 @@ struct LongForm {
     two_ni = 2.0 * static_cast<double>(ni);
     scale = P.scale;
   }
-  __device__ __forceinline__ void q8(int u, int bA, int ni, int nj, int cj, double (&qv)[8]) const {
+  template <int E>
+  __device__ __forceinline__ void q(int u, int bA, int ni, int nj, int cj, double (&qv)[E]) const {
     double nd = static_cast<double>(u * nj - (2 * bA + cj) * ni);
     nd = fma(-rint(nd * inv_twoM), twoM, nd);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < E; ++e) {
       double ne = nd - static_cast<double>(e) * two_ni;
       ne = ne < -Md ? ne + twoM : ne;
       ne = ne < -Md ? ne + twoM : ne;
@@ -495,44 +511,6 @@ struct LongForm {
     }
   }
 };
-
-// one K-step from the weight store: lane (row, k-group) takes its row's stored weights for inputs
-// bA .. bA + E - 1 (zero outside the row's window [lo, lo + wr)); addresses are clamped into the
-// row so that masked lanes never read outside the store
-template <int E>
-__device__ __forceinline__ void stored_step(floatx4& acc, int bA, int lo, int wr, const float* __restrict__ wrow,
-                                            const float* __restrict__ xj, int pofs, int dir, int nj, float rcp_n,
-                                            float sx) {
-  using HV = typename std::conditional<E == 8, half8, half4>::type;
-  HV xhi, xlo;
-  if (nj >= 8) {
-    load_inputs<E>(xj, pofs, dir, bA, nj, rcp_n, sx, xhi, xlo);
-  } else {
-    float v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = xj[mod_any(pofs + dir * (bA + e), nj, rcp_n)] * sx;
-    split_fp16<E>(v, xhi, xlo);
-  }
-  float w[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int k = bA + e - lo;
-    const bool in = static_cast<unsigned>(k) < static_cast<unsigned>(wr);
-    const float v = wrow[in ? k : 0];
-    w[e] = in ? v : 0.0f;
-  }
-  HV whi, wlo;
-  split_fp16<E>(w, whi, wlo);
-  if constexpr (E == 8) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
-  } else {
-    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(whi, xhi, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(wlo, xhi, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(whi, xlo, acc, 0, 0, 0);
-  }
-}
 
 // one short-form K-step of E inputs per lane (E = 8: 32 inputs on v_mfma_f32_16x16x32_f16; E = 4:
 // 16 inputs on v_mfma_f32_16x16x16_f16, for the last step of a window)
@@ -568,139 +546,297 @@ __device__ __forceinline__ void short_step(floatx4& acc, int bA, int u_row, int 
   }
 }
 
-// one wave: tile t (16 output pixels of the fundamental domain of one north-half ring)
-// FLY = false: every slot holds a weight store, so only the stored-weight path is compiled in (fewer
-// registers, more resident waves to cover the store's memory latency)
-template <bool FLY>
-__device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__ d, int t,
-                                         const float* __restrict__ xm, float* __restrict__ ym, float sx,
-                                         const float4* __restrict__ s_coef, float* __restrict__ wstage) {
-  const int r = ldu(ldu(d->citem_ring)[t]);
-  const int a0 = ldu(ldu(d->citem_a0)[t]);
-  const int ni = ldu(ldu(d->rn)[r]);
-  const int ci = ldu(ldu(d->rc)[r]);
-  const int mr = ldu(d->nrings) - 1 - r;
-  const int lane = threadIdx.x & 63;
-  const int row = lane & 15;       // A operand: output pixel a0 + row
-  const int kgrp = lane >> 4;      // A and B operands: k-group of 8
-  const int col = lane & 15;       // B operand / D: image index
-  const int ch = col >> 3;         // hemisphere
-  const int cf = (col >> 2) & 1;   // reflection
-  const int cq = col & 3;          // quarter turn
-  const int dir = cf ? -1 : 1;
-  const int u_row = 2 * (a0 + row) + ci;    // azimuth numerator of the lane's output pixel
-  const int u_first = 2 * a0 + ci;
-  const int u_last = 2 * (a0 + 15) + ci;
+// What one lane of a cap tile is: tile t covers output pixels a0 .. a0 + 15 of the fundamental
+// domain [0, F) of north-half ring r. A operand: row = output pixel a0 + row, k-group kgrp; B operand
+// and result: column col = image (hemisphere ch, reflection cf, quarter turn cq).
+struct CapLane {
+  int r, a0, ni, ci, F;
+  int row, kgrp, col, ch, cf, cq, dir;
+  int u_row, u_first, u_last;   // azimuth numerators of the lane's row, the first and the last row
+  double inv_2ni;
+  __device__ __forceinline__ CapLane(const convreal::MixedDesc* __restrict__ d, int t) {
+    r = ldu(ldu(d->citem_ring)[t]);
+    a0 = ldu(ldu(d->citem_a0)[t]);
+    ni = ldu(ldu(d->rn)[r]);
+    ci = ldu(ldu(d->rc)[r]);
+    F = ((ni >> 2) - ci) / 2 + 1;
+    const int lane = threadIdx.x & 63;
+    row = lane & 15;
+    kgrp = lane >> 4;
+    col = lane & 15;
+    ch = col >> 3;
+    cf = (col >> 2) & 1;
+    cq = col & 3;
+    dir = cf ? -1 : 1;
+    u_row = 2 * (a0 + row) + ci;
+    u_first = 2 * a0 + ci;
+    u_last = 2 * (a0 + 15) + ci;
+    inv_2ni = 1.0 / (2.0 * ni);
+  }
+  // first pixel of the lane's image of pixel 0 of ring j, relative to the ring (or its mirror)
+  __device__ __forceinline__ int pofs(int nj, int cj) const {
+    return cf ? (nj - cj + cq * (nj >> 2)) : cq * (nj >> 2);
+  }
+};
+
+// ---------------------------------------------------------------- cap weight store
+// Layout, per cap tile: two zero groups, then per cap-touching ring pair (in list order) and per row
+// of the tile inside the fundamental domain, the row's weights in groups of 4 inputs, group g
+// covering inputs b0 + 4g .. b0 + 4g + 3 of ring j (b0: start of the tile's union window), 16 bytes
+// each: the 4 weights x s_w rounded to FP16 (hi), then the FP16 residues (lo). A row keeps the
+// groups that meet its window [lo, hi], zeros inside them outside the window. Nothing about the
+// layout is stored besides the first group of every tile: the apply recomputes the same windows,
+// and a 16-lane prefix sum of the rows' group counts gives every lane its address. Lanes whose
+// group is not stored read the tile's first zero group, so every load is unconditional and lands in
+// the register that the matrix cores read later; addresses are 32-bit offsets from the tile's
+// block and from the map.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kTileZeroGroups = 2;
+
+// one ring pair of a tile, as the store path's steps read it (lane values)
+// K order of a step: lane kgrp holds inputs 4 kgrp + [0, 4) (half 0) and 16 + 4 kgrp + [0, 4)
+// (half 1) of the step's 32, i.e. weight groups 8q + kgrp and 8q + 4 + kgrp, so that each load
+// instruction reads 64 contiguous bytes per row of weights and per image of inputs.
+struct StorePair {
+  int rbase;     // offset (groups) from the tile's block of group 0 of the lane's row
+  int glo, gn;   // the row's stored groups glo .. glo + gn - 1 (gn = 0: none)
+  unsigned xofs; // map index of the lowest pixel of the lane's step-0 half-0 inputs
+  int nk;        // 32-input steps over the union window (uniform)
+};
+
+// One step's operands as loaded (software-pipelined: the loads of later steps are in flight while
+// the matrix cores work on this one).
+struct StoreStep {
+  u32x4 wa, wb;   // weight groups of the lane's two halves
+  float v[8];     // the lane's inputs, each half in memory order from its lowest pixel
+  bool live;      // a step of the tile (false: the sequence has ended; the loads are not used)
+  bool last;      // last step of its ring pair
+};
+
+// byte offset in the tile's block of group g of the lane's row (the zero group if not stored)
+__device__ __forceinline__ unsigned group_offset(const StorePair& S, int g) {
+  return static_cast<unsigned>(g - S.glo) < static_cast<unsigned>(S.gn) ? static_cast<unsigned>(S.rbase + g) * 16u
+                                                                        : 0u;
+}
+
+__device__ __forceinline__ u32x4 load_group(const unsigned char* __restrict__ tile, unsigned off) {
+  return *reinterpret_cast<const u32x4*>(tile + off);
+}
+
+// w_hi x_hi + w_lo x_hi + w_hi x_lo on the lane's 8 inputs (in input order) and weight groups
+__device__ __forceinline__ void store_mfma(floatx4& acc, const float (&v)[8], const u32x4& wa, const u32x4& wb) {
+  half8 xhi, xlo;
+  split_fp16<8>(v, xhi, xlo);
+  const half8 whi = __builtin_bit_cast(half8, u32x4{wa.x, wa.y, wb.x, wb.y});
+  const half8 wlo = __builtin_bit_cast(half8, u32x4{wa.z, wa.w, wb.z, wb.w});
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ void store_compute(floatx4& acc, const StoreStep& R, int dir, float sx) {
+  // forward lanes keep the memory order, reflected lanes reverse each half (a bitwise select per
+  // element)
+  const unsigned fwd = dir > 0 ? 0xffffffffu : 0u;
+  float v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int r = (e & 4) + 3 - (e & 3);
+    v[e] = __uint_as_float((fwd & __float_as_uint(R.v[e])) | (~fwd & __float_as_uint(R.v[r]))) * sx;
+  }
+  store_mfma(acc, v, R.wa, R.wb);
+}
+
+// FP32 accumulator, folded into FP64 every kFold ring pairs
+struct CapAcc {
+  floatx4 acc;
+  double accd[4];
+  int nfold;
+  __device__ __forceinline__ void pair_done() {
+    if (++nfold == kFold) {
+      nfold = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) accd[u] += static_cast<double>(acc[u]);
+      acc = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+};
+
+// The tile's steps, ring pair after ring pair, as one sequence.
+struct StoreIter {
+  const unsigned char* tile;   // the tile's block
+  convreal::CapPair Pn;        // record kk, loaded one pair ahead of its use
+  long long kk, k1;
+  int pos;                     // next pair's first group, from the tile's block
+  int q;
+  StorePair S;
+
+  // Set up ring pair P and advance pos past its block. Returns the pair's step count, 0 if it has no
+  // stored weight for the tile. A pair whose inputs wrap around ring j for some lane (the first
+  // tiles of a ring, rings of fewer than 8 pixels) is done here at once, without prefetch, and
+  // also returns 0.
+  __device__ __forceinline__ int setup(const convreal::CapPair& P, const CapLane& L, const float* __restrict__ xm,
+                                       float sx, CapAcc& A) {
+    int b0, bend;
+    tile_union(P, L.u_first, L.u_last, L.ni, L.inv_2ni, b0, bend);
+    if (bend < b0) return 0;
+    int lo, hi;
+    row_window(P, L.u_row, L.ni, L.inv_2ni, lo, hi);
+    const bool in = L.a0 + L.row < L.F && hi >= lo;
+    const int glo = (lo - b0) >> 2;
+    const int gn = in ? ((hi - b0) >> 2) - glo + 1 : 0;
+    int total;
+    const int off = scan16(gn, total);
+    S.rbase = pos + off - glo;
+    S.glo = glo;
+    S.gn = gn;
+    pos += total;
+    if (total == 0) return 0;
+    const int nk = (bend - b0 + 32) >> 5;
+    const int nj = P.nj;
+    const long long xoff = L.ch ? P.xoff_m : P.xoff;
+    const int pofs = L.pofs(nj, P.cj);
+    const float rcp_n = __builtin_amdgcn_rcpf(static_cast<float>(nj));
+    // the lane's inputs over all steps lie in b0 + 4 kgrp + [0, span), pixels pofs + dir b (mod nj);
+    // half h of step q starts at b0 + 4 kgrp + 32 q + 16 h
+    const int first = b0 + 4 * L.kgrp, span = 32 * (nk - 1) + 20;
+    const int low = mod_any(L.dir > 0 ? pofs + first : pofs - (first + span - 1), nj, rcp_n);
+    if (__all(low + span <= nj)) {
+      S.xofs = static_cast<unsigned>(xoff + (L.dir > 0 ? low : low + span - 4));
+      return nk;
+    }
+    const float* xj = xm + xoff;
+    for (int q = 0; q < nk; ++q) {
+      const u32x4 wa = load_group(tile, group_offset(S, 8 * q + L.kgrp));
+      const u32x4 wb = load_group(tile, group_offset(S, 8 * q + 4 + L.kgrp));
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int b = first + 32 * q + 16 * (e >> 2) + (e & 3);
+        v[e] = xj[mod_any(pofs + L.dir * b, nj, rcp_n)] * sx;
+      }
+      store_mfma(A.acc, v, wa, wb);
+    }
+    A.pair_done();
+    return 0;
+  }
+
+  // Load the next step into R (R.live = false once the tile has no step left). Every call issues
+  // the same loads, an ended sequence reading the tile's zero group and the map's first pixels, so
+  // that the compiler can count the loads in flight and wait for the oldest only.
+  __device__ __forceinline__ void next(const convreal::CapPair* __restrict__ cpair, const CapLane& L,
+                                       const float* __restrict__ xm, float sx, CapAcc& A, StoreStep& R) {
+    bool ok = true;
+    while (q >= S.nk) {
+      if (kk >= k1) {
+        ok = false;
+        break;
+      }
+      const convreal::CapPair P = Pn;
+      ++kk;
+      if (kk < k1) Pn = ldu_record(cpair[kk]);
+      q = 0;
+      S.nk = setup(P, L, xm, sx, A);
+    }
+    unsigned oa = 0, ob = 0, xa = 0, xc = 0;
+    bool last = false;
+    if (ok) {
+      oa = group_offset(S, 8 * q + L.kgrp);
+      ob = group_offset(S, 8 * q + 4 + L.kgrp);
+      xa = S.xofs + static_cast<unsigned>(L.dir * 32 * q);
+      xc = xa + static_cast<unsigned>(L.dir * 16);
+      ++q;
+      last = q >= S.nk;
+    }
+    R.wa = load_group(tile, oa);
+    R.wb = load_group(tile, ob);
+    // 32-bit byte offsets (maps hold at most 12 * 8192^2 pixels) on the map's base address
+    const float* x0 = reinterpret_cast<const float*>(reinterpret_cast<const unsigned char*>(xm) + xa * 4u);
+    const float* x1 = reinterpret_cast<const float*>(reinterpret_cast<const unsigned char*>(xm) + xc * 4u);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      R.v[e] = x0[e];
+      R.v[4 + e] = x1[e];
+    }
+    R.live = ok;
+    R.last = last;
+  }
+};
+
+constexpr int kStoreSlots = 6;   // steps in flight per wave
+
+// all cap-touching pairs of a tile from the store
+__device__ __forceinline__ void cap_rows_store(const convreal::MixedDesc* __restrict__ d, int t, const CapLane& L,
+                                               const float* __restrict__ xm, float sx, double (&accd)[4]) {
+  StoreIter it;
+  it.tile = reinterpret_cast<const unsigned char*>(ldu(d->wstore)) + 16 * ldu(ldu(d->wtile_off)[t]);
+  it.kk = ldu(ldu(d->rest_off)[L.r]);
+  it.k1 = ldu(ldu(d->rest_off)[L.r + 1]);
+  it.pos = kTileZeroGroups;
+  it.q = 0;
+  it.S.nk = 0;
+  const convreal::CapPair* cpair = ldu(d->cpair);
+  if (it.kk < it.k1) it.Pn = ldu_record(cpair[it.kk]);
+  CapAcc A;
+  A.acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int u = 0; u < 4; ++u) A.accd[u] = 0.0;
+  A.nfold = 0;
+  StoreStep R[kStoreSlots];
+#pragma unroll
+  for (int s = 0; s < kStoreSlots; ++s) it.next(cpair, L, xm, sx, A, R[s]);
+  // Rounds over the slots: slot s holds step n + s; each live slot is used and every slot is
+  // refilled at once, so the oldest slot is live exactly while steps remain.
+  while (R[0].live) {
+#pragma unroll
+    for (int s = 0; s < kStoreSlots; ++s) {
+      if (R[s].live) {
+        store_compute(A.acc, R[s], L.dir, sx);
+        if (R[s].last) A.pair_done();
+      }
+      it.next(cpair, L, xm, sx, A, R[s]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) accd[u] = A.accd[u] + static_cast<double>(A.acc[u]);
+}
+
+// all cap-touching pairs of a tile with weights evaluated on the fly
+__device__ __forceinline__ void cap_rows_fly(const convreal::MixedDesc* __restrict__ d, const CapLane& L,
+                                             const float* __restrict__ xm, float sx,
+                                             const float4* __restrict__ s_coef, double (&accd)[4]) {
   // squared chords are formed directly in units of the table spacing: q = d^2 / h^2
   const double inv_h = ldu(d->inv_h);
   const double ih2 = inv_h * inv_h;
   const double qcut = ldu(d->dcut2) * ih2;
   const int seg_max = ldu(d->nseg) - 1;
-
-  const int F = ((ni >> 2) - ci) / 2 + 1;   // fundamental domain [0, F) of the ring
-  const float* wst = ldu(d->wstore);
-  long long wpos = wst ? ldu(ldu(d->wtile_off)[t]) : 0;
-
+  const int ni = L.ni;
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-  double accd[4] = {0.0, 0.0, 0.0, 0.0};
   const long long* rest_off = ldu(d->rest_off);
   const convreal::CapPair* cpair = ldu(d->cpair);
-  const long long k0 = ldu(rest_off[r]);
-  const long long k1 = ldu(rest_off[r + 1]);
+  const long long k0 = ldu(rest_off[L.r]);
+  const long long k1 = ldu(rest_off[L.r + 1]);
   int nfold = 0;
   for (long long kk = k0; kk < k1; ++kk) {
     const convreal::CapPair P = ldu_record(cpair[kk]);
     const int nj = P.nj;
     const int cj = P.cj;
-    if (!FLY || wst) {
-      // weights from the store: the rows' own windows, laid out row after row
-      int lo, hi;
-      row_window(P, u_row, ni, lo, hi);
-      const int wr = a0 + row < F ? max(0, hi - lo + 1) : 0;
-      int total;
-      const int off = scan16(wr, total);
-      if (total == 0) continue;
-      // the pair's block starts 16-byte aligned (blocks are padded to whole float4s); a block that
-      // fits the wave's LDS slice is staged there with coalesced 16-byte loads, and the lanes then
-      // gather their rows' runs from LDS; a larger one is read from the store directly
-      const int tot4 = (total + 3) & ~3;
-      const float* blk = wst + wpos;
-      wpos += tot4;
-      // the union of the rows' windows, in steps of 32 inputs and a last step of 16 if it suffices
-      int b0 = wr > 0 ? lo : 0x7fffffff, bend = wr > 0 ? lo + wr - 1 : -0x7fffffff;
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) {
-        b0 = min(b0, __shfl_xor(b0, o, 16));
-        bend = max(bend, __shfl_xor(bend, o, 16));
-      }
-      const int K = bend - b0 + 1;
-      const int nk = (K + 31) >> 5;
-      const int nfull = (K & 31) > 0 && (K & 31) <= 16 ? nk - 1 : nk;
-      const float* xj = xm + (ch ? P.xoff_m : P.xoff);
-      const int pofs = cf ? (nj - cj + cq * (nj >> 2)) : cq * (nj >> 2);
-      const float rcp_n = 1.0f / static_cast<float>(nj);
-      if (tot4 <= kStageFloats) {
-        // all of the lane's loads are issued before the first LDS write, so one memory latency
-        // covers the whole block
-        const float4* src = reinterpret_cast<const float4*>(blk);
-        float4* dst = reinterpret_cast<float4*>(wstage);
-        const int n4 = tot4 >> 2;
-        constexpr int kPer = kStageFloats / 4 / 64;
-        float4 v[kPer];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k)
-          if (lane + 64 * k < n4) v[k] = src[lane + 64 * k];
-#pragma unroll
-        for (int k = 0; k < kPer; ++k)
-          if (lane + 64 * k < n4) dst[lane + 64 * k] = v[k];
-        // LDS traffic of one wave is processed in order; the fence keeps the compiler from moving
-        // the row reads above the block's writes
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const float* wrow = wstage + off;
-        for (int q = 0; q < nfull; ++q)
-          stored_step<8>(acc, b0 + 32 * q + 8 * kgrp, lo, wr, wrow, xj, pofs, dir, nj, rcp_n, sx);
-        if (nfull < nk) stored_step<4>(acc, b0 + 32 * nfull + 4 * kgrp, lo, wr, wrow, xj, pofs, dir, nj, rcp_n, sx);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      } else {
-        const float* wrow = blk + off;
-        for (int q = 0; q < nfull; ++q)
-          stored_step<8>(acc, b0 + 32 * q + 8 * kgrp, lo, wr, wrow, xj, pofs, dir, nj, rcp_n, sx);
-        if (nfull < nk) stored_step<4>(acc, b0 + 32 * nfull + 4 * kgrp, lo, wr, wrow, xj, pofs, dir, nj, rcp_n, sx);
-      }
-      if (++nfold == kFold) {
-        nfold = 0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) accd[u] += static_cast<double>(acc[u]);
-        acc = floatx4{0.f, 0.f, 0.f, 0.f};
-      }
-      continue;
-    }
-    if constexpr (FLY) {
-    // union of the 16 rows' windows [b0, bend] (the rows' centres increase with a)
-    const double bc0 = static_cast<double>(u_first * nj - cj * ni) / (2.0 * ni);
-    const double bc1 = static_cast<double>(u_last * nj - cj * ni) / (2.0 * ni);
     int b0, bend;
-    if (P.whole) {
-      b0 = static_cast<int>(floor(bc0)) - nj / 2;
-      bend = static_cast<int>(floor(bc1)) - nj / 2 + nj - 1;
-    } else {
-      b0 = static_cast<int>(ceil(bc0 - P.hw - 1e-7));
-      bend = static_cast<int>(floor(bc1 + P.hw + 1e-7));
-    }
+    tile_union(P, L.u_first, L.u_last, ni, L.inv_2ni, b0, bend);
     const int K = bend - b0 + 1;
     if (K <= 0) continue;
     const int nk = (K + 31) >> 5;
     const int blast = b0 + 32 * nk - 1;
-    const float* xj = xm + (ch ? P.xoff_m : P.xoff);
-    const int pofs = cf ? (nj - cj + cq * (nj >> 2)) : cq * (nj >> 2);
-    const float rcp_n = 1.0f / static_cast<float>(nj);
+    const float* xj = xm + (L.ch ? P.xoff_m : P.xoff);
+    const int pofs = L.pofs(nj, cj);
+    const float rcp_n = __builtin_amdgcn_rcpf(static_cast<float>(nj));
     // largest |numerator| over the tile's rows and padded inputs: the numerator grows with a and
     // falls with b, so the extremes sit at (last row, b0) and (first row, blast)
     const double lim = kShortAlpha / P.scale;
-    const bool shortform = static_cast<double>(u_last * nj - (2 * b0 + cj) * ni) <= lim &&
-                           -static_cast<double>(u_first * nj - (2 * blast + cj) * ni) <= lim;
+    const bool shortform = static_cast<double>(L.u_last * nj - (2 * b0 + cj) * ni) <= lim &&
+                           -static_cast<double>(L.u_first * nj - (2 * blast + cj) * ni) <= lim;
     if (shortform) {
       // |al| <= 0.2 on every (row, input) of the tile: no wrap of the numerator, and every padded
       // input lies outside the cut (d^2 > d_cut^2 decides), so no per-row window test is needed
@@ -711,29 +847,29 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
       // steps of 32 inputs; a remainder of at most 16 takes one 16-input step
       const int nfull = (K & 31) > 0 && (K & 31) <= 16 ? nk - 1 : nk;
       for (int q = 0; q < nfull; ++q)
-        short_step<8>(acc, b0 + 32 * q + 8 * kgrp, u_row, ni, nj, cj, P.scale, delta, Ah, c0, c1, c2, c3, qcut,
-                      seg_max, s_coef, xj, pofs, dir, rcp_n, sx);
+        short_step<8>(acc, b0 + 32 * q + 8 * L.kgrp, L.u_row, ni, nj, cj, P.scale, delta, Ah, c0, c1, c2, c3, qcut,
+                      seg_max, s_coef, xj, pofs, L.dir, rcp_n, sx);
       if (nfull < nk)
-        short_step<4>(acc, b0 + 32 * nfull + 4 * kgrp, u_row, ni, nj, cj, P.scale, delta, Ah, c0, c1, c2, c3, qcut,
-                      seg_max, s_coef, xj, pofs, dir, rcp_n, sx);
+        short_step<4>(acc, b0 + 32 * nfull + 4 * L.kgrp, L.u_row, ni, nj, cj, P.scale, delta, Ah, c0, c1, c2, c3,
+                      qcut, seg_max, s_coef, xj, pofs, L.dir, rcp_n, sx);
     } else {
       // general form (rings near a pole): numerator reduced to [-M, M], the long polynomial, and
       // the lane's own window [lo_r, hi_r], which also keeps a pixel from entering twice when the
       // union is wider than the ring
       const LongForm lf(P, ni, ih2);
       int lo_r, hi_r;
-      row_window(P, u_row, ni, lo_r, hi_r);
+      row_window(P, L.u_row, ni, L.inv_2ni, lo_r, hi_r);
       for (int q = 0; q < nk; ++q) {
-        const int bA = b0 + 32 * q + 8 * kgrp;
+        const int bA = b0 + 32 * q + 8 * L.kgrp;
         half8 xhi, xlo;
         {
           float v[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = xj[mod_any(pofs + dir * (bA + e), nj, rcp_n)] * sx;
+          for (int e = 0; e < 8; ++e) v[e] = xj[mod_any(pofs + L.dir * (bA + e), nj, rcp_n)] * sx;
           split_fp16<8>(v, xhi, xlo);
         }
         double qv[8];
-        lf.q8(u_row, bA, ni, nj, cj, qv);
+        lf.q<8>(L.u_row, bA, ni, nj, cj, qv);
         float w[8];
         weights_of<8>(qv, qcut, seg_max, s_coef, w);
 #pragma unroll
@@ -754,26 +890,41 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
       for (int u = 0; u < 4; ++u) accd[u] += static_cast<double>(acc[u]);
       acc = floatx4{0.f, 0.f, 0.f, 0.f};
     }
-    }  // FLY
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) accd[u] += static_cast<double>(acc[u]);
+}
+
+// one wave: tile t (16 output pixels of the fundamental domain of one north-half ring) and its 16
+// images. FLY = false: every slot holds a weight store, so only the store path is compiled in.
+template <bool FLY>
+__device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__ d, int t,
+                                         const float* __restrict__ xm, float* __restrict__ ym, float sx,
+                                         const float4* __restrict__ s_coef) {
+  const CapLane L(d, t);
+  double accd[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!FLY || ldu(d->wstore) != nullptr)
+    cap_rows_store(d, t, L, xm, sx, accd);
+  else
+    cap_rows_fly(d, L, xm, sx, s_coef, accd);
 
   // store: D rows 4 kgrp + u (output pixel a0 + 4 kgrp + u), column col (image); each output
   // pixel once: rows beyond the fundamental domain [0, F), reflections of pixels on a reflection
   // axis and the mirror of the equator ring are skipped
-  if (ch && mr == r) return;
-  const int rr = ch ? mr : r;
+  const int mr = ldu(d->nrings) - 1 - L.r;
+  if (L.ch && mr == L.r) return;
+  const int rr = L.ch ? mr : L.r;
   const double inv = static_cast<double>(ldu(d->inv_sw)) / static_cast<double>(sx);
   float* yr = ym + ldu(ldu(d->rstart)[rr]);
   const bool add = ldu(ldu(d->ring_add)[rr]) != 0;
+  const int ni = L.ni, ci = L.ci;
   const int quarter = ni >> 2;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int ao = a0 + 4 * kgrp + u;
-    if (ao >= F) continue;
-    if (cf && ((2 * ao + ci) % quarter) == 0) continue;
-    int Pp = cf ? (ni - ao - ci + cq * quarter) : (ao + cq * quarter);
+    const int ao = L.a0 + 4 * L.kgrp + u;
+    if (ao >= L.F) continue;
+    if (L.cf && ((2 * ao + ci) % quarter) == 0) continue;
+    int Pp = L.cf ? (ni - ao - ci + L.cq * quarter) : (ao + L.cq * quarter);
     Pp %= ni;
     if (Pp < 0) Pp += ni;
     put(yr + Pp, accd[u] * inv, add);
@@ -781,13 +932,13 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
 }
 
 // ---------------------------------------------------------------- cap weight store (set-up)
-// One wave per cap tile, the same tiles, ring pairs and row windows as the apply. FILL = false: the
-// number of stored weights of each tile; FILL = true: the weights (long form, any ring pair), tile t
-// starting at offsets[t], ring pair after ring pair, row after row, input after input.
+// One wave per cap tile, the same tiles, ring pairs, union windows and row windows as the apply.
+// FILL = false: the number of 16-byte groups of each tile; FILL = true: the groups (long form, any
+// ring pair), tile t's block (its zero groups first) starting at group offsets[t].
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::MixedDesc* __restrict__ d,
                                                            long long* __restrict__ offsets,
-                                                           float* __restrict__ store) {
+                                                           u32x4* __restrict__ store) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   float4* s_coef = reinterpret_cast<float4*>(lds);
   if (FILL) {
@@ -798,51 +949,48 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
   }
   const int t = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   if (t >= ldu(d->n_citems)) return;
-  const int r = ldu(ldu(d->citem_ring)[t]);
-  const int a0 = ldu(ldu(d->citem_a0)[t]);
-  const int ni = ldu(ldu(d->rn)[r]);
-  const int ci = ldu(ldu(d->rc)[r]);
-  const int F = ((ni >> 2) - ci) / 2 + 1;
-  const int lane = threadIdx.x & 63;
-  const int row = lane & 15;
-  const int kgrp = lane >> 4;
-  const int u_row = 2 * (a0 + row) + ci;
+  const CapLane L(d, t);
   const double inv_h = ldu(d->inv_h);
   const double ih2 = inv_h * inv_h;
   const double qcut = ldu(d->dcut2) * ih2;
   const int seg_max = ldu(d->nseg) - 1;
   const long long* rest_off = ldu(d->rest_off);
   const convreal::CapPair* cpair = ldu(d->cpair);
-  const long long k0 = ldu(rest_off[r]);
-  const long long k1 = ldu(rest_off[r + 1]);
-  long long pos = FILL ? offsets[t] : 0;
+  const long long k0 = ldu(rest_off[L.r]);
+  const long long k1 = ldu(rest_off[L.r + 1]);
+  u32x4* tile = FILL ? store + offsets[t] : nullptr;
+  if (FILL && (threadIdx.x & 63) < kTileZeroGroups) tile[threadIdx.x & 63] = u32x4{0u, 0u, 0u, 0u};
+  int pos = kTileZeroGroups;
   for (long long kk = k0; kk < k1; ++kk) {
     const convreal::CapPair P = ldu_record(cpair[kk]);
+    int b0, bend;
+    tile_union(P, L.u_first, L.u_last, L.ni, L.inv_2ni, b0, bend);
+    if (bend < b0) continue;
     int lo, hi;
-    row_window(P, u_row, ni, lo, hi);
-    const int wr = a0 + row < F ? max(0, hi - lo + 1) : 0;
+    row_window(P, L.u_row, L.ni, L.inv_2ni, lo, hi);
+    const bool in = L.a0 + L.row < L.F && hi >= lo;
+    const int glo = (lo - b0) >> 2, ghi = (hi - b0) >> 2;
     int total;
-    const int off = scan16(wr, total);
-    if (FILL && total > 0) {
-      int wmax = wr;
+    const int off = scan16(in ? ghi - glo + 1 : 0, total);
+    if (FILL && in) {
+      const LongForm lf(P, L.ni, ih2);
+      for (int g = glo + L.kgrp; g <= ghi; g += 4) {
+        const int bA = b0 + 4 * g;
+        double qv[4];
+        lf.q<4>(L.u_row, bA, L.ni, P.nj, P.cj, qv);
+        float w[4];
+        weights_of<4>(qv, qcut, seg_max, s_coef, w);
 #pragma unroll
-      for (int o = 8; o > 0; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 16));
-      const LongForm lf(P, ni, ih2);
-      float* dst = store + pos + off;
-      for (int q = 0; 32 * q < wmax; ++q) {
-        const int k = 32 * q + 8 * kgrp;
-        double qv[8];
-        lf.q8(u_row, lo + k, ni, P.nj, P.cj, qv);
-        float w[8];
-        weights_of<8>(qv, qcut, seg_max, s_coef, w);
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (k + e < wr) dst[k + e] = w[e];
+        for (int e = 0; e < 4; ++e) w[e] = (bA + e >= lo && bA + e <= hi) ? w[e] : 0.0f;
+        half4 wh, wl;
+        split_fp16<4>(w, wh, wl);
+        const u32x2 ph = __builtin_bit_cast(u32x2, wh), pl = __builtin_bit_cast(u32x2, wl);
+        tile[pos + off + (g - glo)] = u32x4{ph.x, ph.y, pl.x, pl.y};
       }
     }
-    pos += (total + 3) & ~3;   // each pair's block starts on a float4 boundary
+    pos += total;
   }
-  if (!FILL && lane == 0) offsets[t] = pos;
+  if (!FILL && (threadIdx.x & 63) == 0) offsets[t] = pos;
 }
 
 // ---------------------------------------------------------------- persistent queue kernel
@@ -893,8 +1041,7 @@ __global__ __launch_bounds__(kBlock, 2) void mixed_persistent_kernel(convreal::S
       }
       const int t = idx * kWaves + __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
       if (t < ldu(d->n_citems))
-        cap_tile<FLY>(d, t, S.x[slot], S.y[slot], sx, s_coef,
-                      reinterpret_cast<float*>(lds) + kStageFloats * (threadIdx.x >> 6));
+        cap_tile<FLY>(d, t, S.x[slot], S.y[slot], sx, s_coef);
     }
     __syncthreads();
   }
@@ -1003,7 +1150,7 @@ hipError_t set_lds_limits(int nseg) {
 hipError_t cap_store_count(const conv_real_plan* p, long long* counts_dev) {
   const unsigned grid = static_cast<unsigned>((p->n_citems + kWaves - 1) / kWaves);
   hipLaunchKernelGGL(cap_store_kernel<false>, dim3(grid), dim3(kBlock), 0, nullptr, p->d_desc, counts_dev,
-                     static_cast<float*>(nullptr));
+                     static_cast<u32x4*>(nullptr));
   return hipGetLastError();
 }
 
@@ -1011,7 +1158,7 @@ hipError_t cap_store_fill(const conv_real_plan* p) {
   const unsigned grid = static_cast<unsigned>((p->n_citems + kWaves - 1) / kWaves);
   const size_t lds = sizeof(float4) * static_cast<size_t>(p->cap_nseg > 0 ? p->cap_nseg : 1);
   hipLaunchKernelGGL(cap_store_kernel<true>, dim3(grid), dim3(kBlock), lds, nullptr, p->d_desc, p->d_wtile_off,
-                     p->d_wstore);
+                     reinterpret_cast<u32x4*>(p->d_wstore));
   return hipGetLastError();
 }
 

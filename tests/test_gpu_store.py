@@ -1,7 +1,9 @@
 """The mixed path's cap weight store (conv_real_set_weight_store): weights evaluated on the fly and
 weights computed once and streamed both meet the oracle at the mixed path's tolerance, on grids
-that exercise the short and long weight forms, whole-ring windows near the poles and the smallest
-rings; switching modes frees and rebuilds the store; results are deterministic in each mode."""
+that exercise the short and long weight forms, whole-ring windows near the poles, the smallest
+rings and inputs that wrap around a ring; switching modes frees and rebuilds the store and resets
+the default launch configuration (never one the caller set); results are deterministic in each
+mode."""
 import math
 
 import numpy as np
@@ -52,14 +54,14 @@ def test_store_modes_match_oracle(cuda_device, nside, sigma_deg, cut_sigma, n_ta
     pix = np.arange(npix) if nside <= 32 else np.random.default_rng(nside).choice(npix, 2500, replace=False)
     ref = oc.convolve_sampled(nside, T, tc, xn.astype(np.float64), pix)
     with cr.Plan(nside, T, tc, "mixed") as plan:
-        assert plan.weight_store() == (False, 0)      # a new plan evaluates on the fly
-        plan.set_weight_store("auto")
         active, nbytes = plan.weight_store()
-        assert active and nbytes > 0                  # small plans fit the automatic budget
+        assert active and nbytes > 0                  # new plans take the automatic mode; small ones fit
+        assert plan.get_tuning()["seg"] == 512        # the library's default with a store
         y_on = _apply(plan, x).clone()
         assert torch.equal(_apply(plan, x), y_on)     # deterministic
         plan.set_weight_store("off")
         assert plan.weight_store() == (False, 0)
+        assert plan.get_tuning()["seg"] == 256
         y_off = _apply(plan, x).clone()
         assert torch.equal(_apply(plan, x), y_off)
         plan.set_weight_store("on")
@@ -90,12 +92,24 @@ def test_store_size_and_bad_mode(cuda_device):
     with cr.Plan(nside, T, tc, "mixed") as plan:
         plan.set_weight_store("on")
         active, nbytes = plan.weight_store()
-        # one FP32 weight per (fundamental-domain pixel, input in its window) of the cap-touching
-        # ring pairs: at most all pixel pairs / 16 (plus the 64-float pad), and a good part of that
+        # 16-byte groups of 4 weights per (fundamental-domain pixel, input group meeting its window)
+        # of the cap-touching ring pairs: about 4 bytes per pixel pair / 16, plus the groups' padding
         assert active
-        assert plan.pairs() / 200 < nbytes <= 4 * (plan.pairs() / 16 + 64) * 1.05
+        assert nbytes % 16 == 0
+        assert plan.pairs() / 200 < nbytes <= 4 * 1.6 * plan.pairs() / 16 + 32
         with pytest.raises(cr.ConvRealError):
             plan.set_weight_store("sometimes")
     with cr.Plan(nside, T, tc, "f32") as plain:
         with pytest.raises(cr.ConvRealError):
             plain.set_weight_store("on")
+
+
+def test_store_keeps_caller_tuning(cuda_device):
+    nside, sigma = 32, 1.5 * DEG
+    tc = 5 * sigma
+    T = ok.tabulate(synth.gaussian_beam_sigma(96, sigma), tc, 1024)
+    with cr.Plan(nside, T, tc, "mixed") as plan:
+        plan.set_tuning(256, 3, 1)
+        plan.set_weight_store("off")
+        plan.set_weight_store("on")
+        assert plan.get_tuning() == {"seg": 256, "wg_per_cu": 3, "order": 1}
