@@ -544,9 +544,12 @@ int set_weight_store(conv_real_plan* p, int mode) {
     }
   }
   // Unless the caller chose the launch configuration: with a store the kernel needs no coefficient
-  // table in LDS, so two workgroups with 512-pixel belt items fit a compute unit, and they are
-  // faster than 256-pixel items; without one the table leaves room for 256-pixel items only.
-  if (!p->tune_user) p->tune.seg = p->d_wstore ? 512 : 256;
+  // table in LDS, so three workgroups with 256-pixel belt items fit a compute unit (and the kernel
+  // is built for three waves per SIMD); without one the table leaves room for two.
+  if (!p->tune_user) {
+    p->tune.seg = 256;
+    p->tune.wg_per_cu = p->d_wstore ? 3 : 2;
+  }
   if ((e = hipMemcpy(p->d_desc, &p->h_desc, sizeof(p->h_desc), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = build_items(p)) != hipSuccess)
     return hip_fail(e, "weight store: descriptor");

@@ -241,7 +241,7 @@ struct BeltPrefetch {
 };
 
 template <int SEG>
-__device__ void belt_item(const convreal::MixedDesc* __restrict__ d, int idx, const float* __restrict__ xm,
+__device__ __forceinline__ void belt_item(const convreal::MixedDesc* __restrict__ d, int idx, const float* __restrict__ xm,
                           float* __restrict__ ym, float sx, _Float16* __restrict__ S) {
   using BL = BeltLayout<SEG>;
   constexpr int NB = SEG / (16 * kWaves);  // 16-pixel blocks per wave
@@ -994,9 +994,11 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
 }
 
 // ---------------------------------------------------------------- persistent queue kernel
-template <int SEG, bool FLY>
-// at least two waves per SIMD, so that belt (matrix-core) and cap items share a SIMD
-__global__ __launch_bounds__(kBlock, 2) void mixed_persistent_kernel(convreal::Slots S,
+// WAVES: resident waves per SIMD the registers are sized for (= workgroups per compute unit); at
+// least two, so that belt and cap items share a SIMD; three where the LDS allows it (256-pixel belt
+// items and no coefficient table), at the price of a few spilled registers
+template <int SEG, bool FLY, int WAVES>
+__global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convreal::Slots S,
                                                                   const int2* __restrict__ items,
                                                                   int n_items, int nrep,
                                                                   const unsigned* __restrict__ amax,
@@ -1112,13 +1114,15 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
     const dim3 g(static_cast<unsigned>(grid)), blk(kBlock);
     const int co = static_cast<int>(coef_off);
     if (tune.seg == 512 && fly)
-      hipLaunchKernelGGL((mixed_persistent_kernel<512, true>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<512, true, 2>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
     else if (tune.seg == 512)
-      hipLaunchKernelGGL((mixed_persistent_kernel<512, false>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<512, false, 2>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
     else if (fly)
-      hipLaunchKernelGGL((mixed_persistent_kernel<256, true>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, true, 2>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+    else if (tune.wg_per_cu >= 3)
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 3>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
     else
-      hipLaunchKernelGGL((mixed_persistent_kernel<256, false>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 2>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     mark(mark_plan, st, "mixed_persistent_kernel", pairs);
@@ -1136,10 +1140,11 @@ hipError_t set_lds_limits(int nseg) {
   const size_t need = persistent_lds_bytes(512, nseg);
   if (need > static_cast<size_t>(optin)) return hipErrorInvalidValue;
   const int bytes = static_cast<int>(need);
-  const void* fns[] = {reinterpret_cast<const void*>(&mixed_persistent_kernel<256, true>),
-                       reinterpret_cast<const void*>(&mixed_persistent_kernel<256, false>),
-                       reinterpret_cast<const void*>(&mixed_persistent_kernel<512, true>),
-                       reinterpret_cast<const void*>(&mixed_persistent_kernel<512, false>)};
+  const void* fns[] = {reinterpret_cast<const void*>(&mixed_persistent_kernel<256, true, 2>),
+                       reinterpret_cast<const void*>(&mixed_persistent_kernel<256, false, 2>),
+                       reinterpret_cast<const void*>(&mixed_persistent_kernel<256, false, 3>),
+                       reinterpret_cast<const void*>(&mixed_persistent_kernel<512, true, 2>),
+                       reinterpret_cast<const void*>(&mixed_persistent_kernel<512, false, 2>)};
   for (const void* f : fns) {
     e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
