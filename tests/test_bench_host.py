@@ -1,0 +1,34 @@
+"""Host-side logic of bench.py (no GPU): the binding roofline follows the larger of the two
+algorithmic floors, and the committed traffic figure is only reported for the sources it was
+measured on."""
+import os
+
+import bench
+
+
+def test_roofline_binds_hbm_at_nside_2048():
+    # one FP32 map in and out at Nside 2048 (402,653,184 bytes) and its 48,266,767,192 pixel pairs
+    r = bench.roofline_for("mixed_persistent_kernel", 3.0, 48266767192, 402653184)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert abs(r["floor_us"] - 50.331648) < 1e-9
+    assert abs(r["achieved"] - 402653184 / 3.0e-3 / 1e9) < 1e-9
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-15
+    other = r["other_roofline"]
+    assert other["bound"] == "mfma" and abs(other["floor_us"] - 2 * 48266767192 / 2.5e15 * 1e6) < 1e-9
+    assert r["traffic"] is None          # only for the profiled configuration
+
+
+def test_roofline_binds_flops_when_pairs_dominate():
+    r = bench.roofline_for("pair_accumulate_kernel", 100.0, 48266767192, 402653184)
+    assert r["bound"] == "alu" and r["peak"] == 78.6
+
+
+def test_traffic_note_matches_sources_or_is_ignored(tmp_path, monkeypatch):
+    note = tmp_path / "note.md"
+    note.write_text("source_sha256: `deadbeef`\nhbm_bytes_per_launch: `123`\n")
+    monkeypatch.setattr(bench, "TRAFFIC_NOTE", str(note))
+    assert bench.measured_traffic() is None
+    note.write_text(f"source_sha256: `{bench.kernel_source_hash()}`\nhbm_bytes_per_launch: `123`\n")
+    assert bench.measured_traffic() == 123.0
+    monkeypatch.setattr(bench, "TRAFFIC_NOTE", os.path.join(str(tmp_path), "missing.md"))
+    assert bench.measured_traffic() is None
