@@ -181,9 +181,9 @@ __global__ __launch_bounds__(256) void belt_weights_kernel(WeightArgs a) {
 }
 
 // ---------------------------------------------------------------- belt item
-// Belt staging, software-pipelined one input ring ahead: while the matrix cores work on ring j,
-// every thread holds ring j+1's share of the input window (PX pixels) and of the weight fragments
-// (2 half8) in registers; after the products they go to the other LDS buffer.
+// Belt staging, software-pipelined AHEAD input rings ahead: while the matrix cores work on ring j,
+// every thread holds its share of the input windows (PX pixels) and of the weight fragments (2 half8)
+// of the next rings in registers; after the products ring j+1 goes to the other LDS buffer.
 template <int SEG>
 struct BeltPrefetch {
   static constexpr int PX = (SEG + 32 * kNKMax + kBlock - 1) / kBlock;
@@ -192,24 +192,25 @@ struct BeltPrefetch {
   int len;     // window pixels
   int nwv;     // weight half8 of the ring (128 per K-chunk)
 
+  // Every thread issues the same PX + 2 loads whatever the window's length (elements past it read
+  // the window's last pixel or the first fragment and are not stored), so that the compiler can
+  // count the loads in flight and wait for the oldest ring only.
   __device__ __forceinline__ void load(const float* __restrict__ xj, int start_px, int len_, int ring_n,
                                        const half8* __restrict__ wsrc, int nwv_) {
     len = len_;
     nwv = nwv_;
 #pragma unroll
     for (int i = 0; i < PX; ++i) {
-      const int u = threadIdx.x + i * kBlock;
-      if (u < len) {
-        int p = start_px + u;   // start_px > -ring_n and the window is shorter than the ring
-        p = p < 0 ? p + ring_n : p;
-        p = p >= ring_n ? p - ring_n : p;
-        x[i] = xj[p];
-      }
+      const int u = min(static_cast<int>(threadIdx.x) + i * kBlock, len - 1);
+      int p = start_px + u;   // start_px > -ring_n and the window is shorter than the ring
+      p = p < 0 ? p + ring_n : p;
+      p = p >= ring_n ? p - ring_n : p;
+      x[i] = xj[p];
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int v = threadIdx.x + i * kBlock;
-      if (v < nwv) w[i] = wsrc[v];
+      const int v = static_cast<int>(threadIdx.x) + i * kBlock;
+      w[i] = wsrc[v < nwv ? v : 0];
     }
   }
 
@@ -240,7 +241,7 @@ struct BeltPrefetch {
   }
 };
 
-template <int SEG>
+template <int SEG, int AHEAD>
 __device__ __forceinline__ void belt_item(const convreal::MixedDesc* __restrict__ d, int idx, const float* __restrict__ xm,
                           float* __restrict__ ym, float sx, _Float16* __restrict__ S) {
   using BL = BeltLayout<SEG>;
@@ -275,51 +276,61 @@ __device__ __forceinline__ void belt_item(const convreal::MixedDesc* __restrict_
     for (int r = 0; r < 4; ++r) accd[b][r] = 0.0;
   }
 
-  BeltPrefetch<SEG> pf;
-  {
-    const int nk0 = ldu(blk_nk[woff]);
-    pf.load(xm + ldu(rstart[jf]), a0 + ldu(blk_mlo[woff]), SEG + 32 * nk0, ring_n,
-            wt + static_cast<long long>(ldu(blk_koff[woff])) * 128, nk0 * 128);
-    pf.store(S, Wbuf, sx);
-  }
+  // Ring r's window and weights travel through register slot r % AHEAD: at iteration jj the
+  // loads of ring jj + AHEAD are issued before the products of ring jj, and ring jj + 1 goes to
+  // LDS after them, so a ring's loads have AHEAD - 1 rings of work to arrive. The loop is
+  // unrolled by AHEAD so that the slots are registers.
+  BeltPrefetch<SEG> pf[AHEAD];
+  auto load_ring = [&](int jj, BeltPrefetch<SEG>& slot) {
+    const int nk1 = ldu(blk_nk[woff + jj]);
+    slot.load(xm + ldu(rstart[jf + jj]), a0 + ldu(blk_mlo[woff + jj]), SEG + 32 * nk1, ring_n,
+              wt + static_cast<long long>(ldu(blk_koff[woff + jj])) * 128, nk1 * 128);
+  };
+  load_ring(0, pf[0]);
+  pf[0].store(S, Wbuf, sx);
+  // rings past the band's last reload that one (not stored): the same loads on every path
+#pragma unroll
+  for (int u = 1; u < AHEAD; ++u) load_ring(min(u, nj - 1), pf[u]);
   __syncthreads();
-  for (int jj = 0; jj < nj; ++jj) {
-    const int buf = jj & 1;
-    if (jj + 1 < nj) {
-      const int nk1 = ldu(blk_nk[woff + jj + 1]);
-      pf.load(xm + ldu(rstart[jf + jj + 1]), a0 + ldu(blk_mlo[woff + jj + 1]), SEG + 32 * nk1, ring_n,
-              wt + static_cast<long long>(ldu(blk_koff[woff + jj + 1])) * 128, nk1 * 128);
-    }
-    const int nk = ldu(blk_nk[woff + jj]);
-    const half8* wblk = Wbuf + buf * (kNKMax * 128);
-    const _Float16* Sb = S + buf * BL::BUF + lane_off;
-    for (int q = 0; q < nk; ++q) {
-      const half8 whi = wblk[q * 128 + lane];
-      const half8 wlo = wblk[q * 128 + 64 + lane];
-      half8 xhi[NB], xlo[NB];
+  for (int jb = 0; jb < nj; jb += AHEAD) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        xhi[b] = *reinterpret_cast<const half8*>(Sb + 16 * b + 32 * q);
-        xlo[b] = *reinterpret_cast<const half8*>(Sb + BL::L + 16 * b + 32 * q);
+    for (int u = 0; u < AHEAD; ++u) {
+      const int jj = jb + u;
+      if (jj >= nj) break;
+      const int buf = jj & 1;
+      load_ring(min(jj + AHEAD, nj - 1), pf[u]);
+      const int nk = ldu(blk_nk[woff + jj]);
+      const half8* wblk = Wbuf + buf * (kNKMax * 128);
+      const _Float16* Sb = S + buf * BL::BUF + lane_off;
+      for (int q = 0; q < nk; ++q) {
+        const half8 whi = wblk[q * 128 + lane];
+        const half8 wlo = wblk[q * 128 + 64 + lane];
+        half8 xhi[NB], xlo[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          xhi[b] = *reinterpret_cast<const half8*>(Sb + 16 * b + 32 * q);
+          xlo[b] = *reinterpret_cast<const half8*>(Sb + BL::L + 16 * b + 32 * q);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi[b], acc[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi[b], acc[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo[b], acc[b], 0, 0, 0);
       }
+      if ((jj % kFold) == kFold - 1 || jj + 1 == nj) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi[b], acc[b], 0, 0, 0);
+        for (int b = 0; b < NB; ++b) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(wlo, xhi[b], acc[b], 0, 0, 0);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo[b], acc[b], 0, 0, 0);
-    }
-    if ((jj % kFold) == kFold - 1 || jj + 1 == nj) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) accd[b][r] += static_cast<double>(acc[b][r]);
-        acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+          for (int r = 0; r < 4; ++r) accd[b][r] += static_cast<double>(acc[b][r]);
+          acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
       }
+      // the other buffers were last read in ring jj - 1, before the previous barrier
+      if (jj + 1 < nj)
+        pf[(u + 1) % AHEAD].store(S + (buf ^ 1) * BL::BUF, Wbuf + (buf ^ 1) * (kNKMax * 128), sx);
+      __syncthreads();
     }
-    // the other buffers were last read in ring jj - 1, before the previous barrier
-    if (jj + 1 < nj) pf.store(S + (buf ^ 1) * BL::BUF, Wbuf + (buf ^ 1) * (kNKMax * 128), sx);
-    __syncthreads();
   }
 
   const double inv = static_cast<double>(ldu(d->inv_sw)) / static_cast<double>(sx);
@@ -1032,7 +1043,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convrea
     const convreal::MixedDesc* d = S.desc[slot];
     const float sx = map_scale(ldu(amax[slot]));
     if (kind == 0) {
-      belt_item<SEG>(d, idx, S.x[slot], S.y[slot], sx, stage);
+      // three rings in flight; one where the registers are sized for three waves per SIMD (there
+      // the other workgroup's waves cover the latency)
+      belt_item<SEG, (WAVES >= 3 ? 1 : 3)>(d, idx, S.x[slot], S.y[slot], sx, stage);
     } else {
       if (FLY && owner != d) {
         const float4* coef = reinterpret_cast<const float4*>(ldu(d->coef));
