@@ -171,7 +171,7 @@ int conv_real_get_tuning(const conv_real_plan* plan, conv_real_tuning* t);
  * of the weights' two evaluation forms, far within the mixed path's tolerance.
  *   CONV_REAL_STORE_OFF   evaluate on the fly; frees a store the plan holds
  *   CONV_REAL_STORE_ON    build the store (ENOMEM if the device cannot hold it)
- *   CONV_REAL_STORE_AUTO  build it if it needs at most 16 GiB and 40% of the free device memory
+ *   CONV_REAL_STORE_AUTO  build it if it needs at most 64 GiB and 40% of the free device memory
  * A new mixed plan takes CONV_REAL_STORE_AUTO. Unless the plan's launch configuration was set by
  * conv_real_set_tuning or conv_real_autotune, changing the store also picks its default: seg 256
  * and 3 workgroups per compute unit with a store (the kernel is then built for three waves per

@@ -228,6 +228,37 @@ hipError_t build_items(conv_real_plan* p) {
   return dev_upload(p, &p->d_items, items);
 }
 
+// The cap tile list for tiles of `rows` output pixels (16 on the fly, 16 kStoreBlocks with a store):
+// tiles, per-item costs (4 tiles per item, one per wave), device copies and the host descriptor.
+hipError_t build_cap_tiles(conv_real_plan* p, int rows) {
+  std::vector<int> ring, a0s;
+  for (int r = 0; r < static_cast<int>(p->cap_F.size()); ++r)
+    for (int a0 = 0; a0 < p->cap_F[r]; a0 += rows) {
+      ring.push_back(r);
+      a0s.push_back(a0);
+    }
+  release(p, p->d_citem_ring);
+  release(p, p->d_citem_a0);
+  p->d_citem_ring = nullptr;
+  p->d_citem_a0 = nullptr;
+  p->n_citems = static_cast<int>(ring.size());
+  p->cap_rows = rows;
+  p->cost_cap.clear();
+  for (int t = 0; t < p->n_citems; t += 4) {
+    double c = 0.0;
+    for (int u = t; u < std::min(t + 4, p->n_citems); ++u) c = std::max(c, p->cap_ring_cost[ring[u]]);
+    p->cost_cap.push_back(c * (rows / 16));
+  }
+  hipError_t e = hipSuccess;
+  if (!ring.empty() && ((e = dev_upload(p, &p->d_citem_ring, ring)) != hipSuccess ||
+                        (e = dev_upload(p, &p->d_citem_a0, a0s)) != hipSuccess))
+    return e;
+  p->h_desc.n_citems = p->n_citems;
+  p->h_desc.citem_ring = p->d_citem_ring;
+  p->h_desc.citem_a0 = p->d_citem_a0;
+  return hipSuccess;
+}
+
 // Mixed path set-up: belt bands, window width, split-FP16 weight blocks, and the list of ring
 // pairs left to the per-pair kernel (every pair touching a polar cap).
 hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std::vector<int>& jlo,
@@ -348,7 +379,6 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
   // Cap-touching pairs on the matrix cores when the coefficient table fits in 64 KB of LDS.
   p->cap_mode = (p->n_tab - 2) * 16 <= 65536 ? 1 : 0;
   std::vector<int> ring_add(g.nrings, 0);
-  std::vector<int> citem_ring, citem_a0;
   if (p->cap_mode) {
     // 4-point Lagrange interpolant of segment k (nodes k-1..k+2, ghost T[-1] = T[1]) in the
     // monomial basis of the local coordinate f, scaled by Omega s_w.
@@ -362,17 +392,15 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
       coef[4 * k + 2] = static_cast<float>(sc * (tm1 / 2.0 - t0 + t1 / 2.0));
       coef[4 * k + 3] = static_cast<float>(sc * (-tm1 / 6.0 + t0 / 2.0 - t1 / 2.0 + t2 / 6.0));
     }
-    // work items: 16-pixel tiles of the symmetry group's fundamental domain [0, F) of every
-    // north-half output ring that has cap-touching pairs (its mirror ring is produced alongside)
-    std::vector<double> ring_cost(g.nrings, 0.0);
+    // cap tiles cover the symmetry group's fundamental domain [0, F) of every north-half output
+    // ring that has cap-touching pairs (its mirror ring is produced alongside)
+    std::vector<double>& ring_cost = p->cap_ring_cost;
+    ring_cost.assign(g.nrings, 0.0);
+    p->cap_F.assign(g.nrings, 0);
     for (int r = 0; r <= (g.nrings - 1) / 2; ++r) {
       if (roff[r + 1] == roff[r]) continue;
-      const int F = (g.n[r] / 4 - g.c[r]) / 2 + 1;
-      for (int a0 = 0; a0 < F; a0 += 16) {
-        citem_ring.push_back(r);
-        citem_a0.push_back(a0);
-      }
-      // estimated cycles of one tile: per neighbour ring, K-chunks x (weights + inputs) work
+      p->cap_F[r] = (g.n[r] / 4 - g.c[r]) / 2 + 1;
+      // estimated cycles of one 16-row tile: per neighbour ring, K-chunks x (weights + inputs) work
       double c = 0.0;
       for (long long kk = roff[r]; kk < roff[r + 1]; ++kk) {
         const long long k = ridx[kk];
@@ -408,18 +436,8 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
       }
     }
     if (!cpair.empty() && (e = dev_upload(p, &p->d_cpair, cpair)) != hipSuccess) return e;
-    p->n_citems = static_cast<int>(citem_ring.size());
     p->cap_nseg = nseg;
-    p->cost_cap.clear();
-    for (int t = 0; t < p->n_citems; t += 4) {
-      double c = 0.0;
-      for (int u = t; u < std::min(t + 4, p->n_citems); ++u) c = std::max(c, ring_cost[citem_ring[u]]);
-      p->cost_cap.push_back(c);
-    }
-    if ((e = dev_upload(p, &p->d_coef, coef)) != hipSuccess ||
-        (e = dev_upload(p, &p->d_citem_ring, citem_ring)) != hipSuccess ||
-        (e = dev_upload(p, &p->d_citem_a0, citem_a0)) != hipSuccess)
-      return e;
+    if ((e = dev_upload(p, &p->d_coef, coef)) != hipSuccess || (e = build_cap_tiles(p, 16)) != hipSuccess) return e;
   }
   if ((e = dev_upload(p, &p->d_ring_add, ring_add)) != hipSuccess) return e;
 
@@ -495,6 +513,11 @@ int set_weight_store(conv_real_plan* p, int mode) {
   p->h_desc.wtile_off = nullptr;
   p->wstore_mode = mode;
   int rc = CONV_REAL_OK;
+  bool built = false;
+  if (mode != CONV_REAL_STORE_OFF && p->cap_mode && !p->cap_F.empty()) {
+    // the store is laid out over tiles of kStoreBlocks x 16 rows
+    if ((e = build_cap_tiles(p, 16 * convreal::kStoreBlocks)) != hipSuccess) return hip_fail(e, "weight store: tiles");
+  }
   if (mode != CONV_REAL_STORE_OFF && p->cap_mode && p->n_citems > 0) {
     long long* counts = nullptr;
     std::vector<long long> off(static_cast<size_t>(p->n_citems) + 1, 0);
@@ -516,7 +539,7 @@ int set_weight_store(conv_real_plan* p, int mode) {
     if (mode == CONV_REAL_STORE_AUTO) {
       size_t free_b = 0, total_b = 0;
       if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
-      const double budget = std::min(16.0 * (1ull << 30), 0.4 * static_cast<double>(free_b));
+      const double budget = std::min(64.0 * (1ull << 30), 0.4 * static_cast<double>(free_b));
       build = static_cast<double>(bytes) <= budget;
     }
     if (build) {
@@ -534,6 +557,7 @@ int set_weight_store(conv_real_plan* p, int mode) {
         p->wstore_groups = n;
         p->h_desc.wstore = p->d_wstore;
         p->h_desc.wtile_off = p->d_wtile_off;
+        built = true;
       }
       if (rc != CONV_REAL_OK) {
         release(p, p->d_wstore);
@@ -543,6 +567,9 @@ int set_weight_store(conv_real_plan* p, int mode) {
       }
     }
   }
+  // without a store the weights are evaluated on the fly, over tiles of 16 rows
+  if (!built && p->cap_mode && p->cap_rows != 16 && (e = build_cap_tiles(p, 16)) != hipSuccess)
+    return hip_fail(e, "weight store: tiles");
   // Unless the caller chose the launch configuration: with a store the kernel needs no coefficient
   // table in LDS, so three workgroups with 256-pixel belt items fit a compute unit (and the kernel
   // is built for three waves per SIMD); without one the table leaves room for two.

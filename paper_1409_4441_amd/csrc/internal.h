@@ -41,6 +41,10 @@ RingGrid make_ring_grid(int nside);
 void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std::vector<int>& jhi);
 
 constexpr int kMaxSlots = 64;  // maps per persistent mixed-path launch
+// 16-row blocks per cap tile when the plan holds a weight store: the blocks of a tile share every
+// step's inputs and every ring pair's set-up, but each block adds its weight registers to every
+// pipeline slot; two blocks exceed the register file at two waves per SIMD and were measured slower
+constexpr int kStoreBlocks = 1;
 
 // One cap-touching ring pair (output ring i, input ring j) as the mixed path's cap tiles read it:
 // one 64-byte record, fetched with a single scalar load per pair and tile.
@@ -189,9 +193,12 @@ struct conv_real_plan {
   // cap-touching ring pairs on the matrix cores (on-the-fly FP32 weights, 16 symmetric images)
   int cap_mode = 0;            // 1: cap_mfma_kernel; 0: FP64 per-pair remainder kernel
   float* d_coef = nullptr;     // (n_tab - 2) x 4: per-segment cubic coefficients x Omega x s_w
-  int* d_citem_ring = nullptr; // per work item: output ring (north half)
-  int* d_citem_a0 = nullptr;   // per work item: first pixel of a 16-pixel tile
+  int* d_citem_ring = nullptr; // per cap tile: output ring (north half)
+  int* d_citem_a0 = nullptr;   // per cap tile: first pixel (tiles of cap_rows pixels)
   int n_citems = 0;
+  int cap_rows = 16;           // 16, or 16 kStoreBlocks while the plan holds a weight store
+  std::vector<int> cap_F;      // per ring: fundamental-domain pixels if it has cap-touching pairs, else 0
+  std::vector<double> cap_ring_cost;   // per ring: estimated cycles of one 16-row tile
   convreal::CapPair* d_cpair = nullptr;  // per cap-touching ring pair, in d_rest_idx order
   // cap weight store: per cap tile, ring pair and row inside the fundamental domain, the row's
   // weights in 16-byte groups of 4 inputs (FP16 hi x 4, FP16 lo x 4) that meet the row's window

@@ -557,15 +557,16 @@ __device__ __forceinline__ void short_step(floatx4& acc, int bA, int u_row, int 
   }
 }
 
-// What one lane of a cap tile is: tile t covers output pixels a0 .. a0 + 15 of the fundamental
-// domain [0, F) of north-half ring r. A operand: row = output pixel a0 + row, k-group kgrp; B operand
-// and result: column col = image (hemisphere ch, reflection cf, quarter turn cq).
+// What one lane of a cap tile is: tile t covers output pixels a0 .. a0 + rows - 1 of the fundamental
+// domain [0, F) of north-half ring r, in blocks of 16. A operand: row = output pixel a0 + 16 blk + row
+// of block blk, k-group kgrp; B operand and result: column col = image (hemisphere ch, reflection cf,
+// quarter turn cq).
 struct CapLane {
   int r, a0, ni, ci, F;
   int row, kgrp, col, ch, cf, cq, dir;
-  int u_row, u_first, u_last;   // azimuth numerators of the lane's row, the first and the last row
+  int u_row, u_first, u_last;   // azimuth numerators of the lane's row in block 0, the tile's first and last row
   double inv_2ni;
-  __device__ __forceinline__ CapLane(const convreal::MixedDesc* __restrict__ d, int t) {
+  __device__ __forceinline__ CapLane(const convreal::MixedDesc* __restrict__ d, int t, int rows) {
     r = ldu(ldu(d->citem_ring)[t]);
     a0 = ldu(ldu(d->citem_a0)[t]);
     ni = ldu(ldu(d->rn)[r]);
@@ -581,7 +582,7 @@ struct CapLane {
     dir = cf ? -1 : 1;
     u_row = 2 * (a0 + row) + ci;
     u_first = 2 * a0 + ci;
-    u_last = 2 * (a0 + 15) + ci;
+    u_last = 2 * (a0 + rows - 1) + ci;
     inv_2ni = 1.0 / (2.0 * ni);
   }
   // first pixel of the lane's image of pixel 0 of ring j, relative to the ring (or its mirror)
@@ -591,55 +592,62 @@ struct CapLane {
 };
 
 // ---------------------------------------------------------------- cap weight store
-// Layout, per cap tile: two zero groups, then per cap-touching ring pair (in list order) and per row
-// of the tile inside the fundamental domain, the row's weights in groups of 4 inputs, group g
-// covering inputs b0 + 4g .. b0 + 4g + 3 of ring j (b0: start of the tile's union window), 16 bytes
-// each: the 4 weights x s_w rounded to FP16 (hi), then the FP16 residues (lo). A row keeps the
-// groups that meet its window [lo, hi], zeros inside them outside the window. Nothing about the
-// layout is stored besides the first group of every tile: the apply recomputes the same windows,
-// and a 16-lane prefix sum of the rows' group counts gives every lane its address. Lanes whose
-// group is not stored read the tile's first zero group, so every load is unconditional and lands in
-// the register that the matrix cores read later; addresses are 32-bit offsets from the tile's
-// block and from the map.
+// Store tiles are kStoreBlocks blocks of 16 rows (one wave each). Layout, per store tile: two zero
+// groups, then per cap-touching ring pair (in list order), per block and per row of the block inside
+// the fundamental domain, the row's weights in groups of 4 inputs, group g covering inputs b0 + 4g ..
+// b0 + 4g + 3 of ring j (b0: start of the tile's union window), 16 bytes each: the 4 weights x s_w
+// rounded to FP16 (hi), then the FP16 residues (lo). A row keeps the groups that meet its window
+// [lo, hi], zeros inside them outside the window. Nothing about the layout is stored besides the
+// first group of every tile: the apply recomputes the same windows, and 16-lane prefix sums of the
+// rows' group counts give every lane its addresses. Lanes whose group is not stored read the tile's
+// first zero group, so every load is unconditional and lands in the register that the matrix cores
+// read later; addresses are 32-bit offsets from the tile's block and from the map. The blocks of a
+// tile share each step's inputs: loaded, reversed, scaled and split once.
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kTileZeroGroups = 2;
+constexpr int kStoreBlocks = convreal::kStoreBlocks;
+constexpr int kStoreRows = 16 * kStoreBlocks;
 
-// one ring pair of a tile, as the store path's steps read it (lane values)
 // K order of a step: lane kgrp holds inputs 4 kgrp + [0, 4) (half 0) and 16 + 4 kgrp + [0, 4)
 // (half 1) of the step's 32, i.e. weight groups 8q + kgrp and 8q + 4 + kgrp, so that each load
 // instruction reads 64 contiguous bytes per row of weights and per image of inputs.
 struct StorePair {
-  int rbase;     // offset (groups) from the tile's block of group 0 of the lane's row
-  int glo, gn;   // the row's stored groups glo .. glo + gn - 1 (gn = 0: none)
-  unsigned xofs; // map index of the lowest pixel of the lane's step-0 half-0 inputs
-  int nk;        // 32-input steps over the union window (uniform)
+  int rbase[kStoreBlocks];   // offset (groups) from the tile's block of group 0 of the lane's row
+  int glo[kStoreBlocks];     // the row's stored groups glo .. glo + gn - 1 (gn = 0: none)
+  int gn[kStoreBlocks];
+  int slo[kStoreBlocks];     // the steps in which the block has stored groups (uniform)
+  int shi[kStoreBlocks];
+  unsigned xofs;             // map index of the lowest pixel of the lane's step-0 half-0 inputs
+  int nk;                    // 32-input steps over the union window (uniform)
 };
 
 // One step's operands as loaded (software-pipelined: the loads of later steps are in flight while
 // the matrix cores work on this one).
 struct StoreStep {
-  u32x4 wa, wb;   // weight groups of the lane's two halves
+  u32x4 wa[kStoreBlocks], wb[kStoreBlocks];   // weight groups of each block's row, both halves
   float v[8];     // the lane's inputs, each half in memory order from its lowest pixel
+  int blocks;     // bit b: block b has stored groups in this step (uniform)
   bool live;      // a step of the tile (false: the sequence has ended; the loads are not used)
   bool last;      // last step of its ring pair
 };
 
-// byte offset in the tile's block of group g of the lane's row (the zero group if not stored)
-__device__ __forceinline__ unsigned group_offset(const StorePair& S, int g) {
-  return static_cast<unsigned>(g - S.glo) < static_cast<unsigned>(S.gn) ? static_cast<unsigned>(S.rbase + g) * 16u
-                                                                        : 0u;
+// byte offset in the tile's block of group g of the lane's row of block b (the zero group if not
+// stored)
+__device__ __forceinline__ unsigned group_offset(const StorePair& S, int b, int g) {
+  return static_cast<unsigned>(g - S.glo[b]) < static_cast<unsigned>(S.gn[b])
+             ? static_cast<unsigned>(S.rbase[b] + g) * 16u
+             : 0u;
 }
 
 __device__ __forceinline__ u32x4 load_group(const unsigned char* __restrict__ tile, unsigned off) {
   return *reinterpret_cast<const u32x4*>(tile + off);
 }
 
-// w_hi x_hi + w_lo x_hi + w_hi x_lo on the lane's 8 inputs (in input order) and weight groups
-__device__ __forceinline__ void store_mfma(floatx4& acc, const float (&v)[8], const u32x4& wa, const u32x4& wb) {
-  half8 xhi, xlo;
-  split_fp16<8>(v, xhi, xlo);
+// w_hi x_hi + w_lo x_hi + w_hi x_lo of one block on the step's split inputs
+__device__ __forceinline__ void block_mfma(floatx4& acc, const half8& xhi, const half8& xlo, const u32x4& wa,
+                                           const u32x4& wb) {
   const half8 whi = __builtin_bit_cast(half8, u32x4{wa.x, wa.y, wb.x, wb.y});
   const half8 wlo = __builtin_bit_cast(half8, u32x4{wa.z, wa.w, wb.z, wb.w});
   acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xhi, acc, 0, 0, 0);
@@ -647,7 +655,25 @@ __device__ __forceinline__ void store_mfma(floatx4& acc, const float (&v)[8], co
   acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(whi, xlo, acc, 0, 0, 0);
 }
 
-__device__ __forceinline__ void store_compute(floatx4& acc, const StoreStep& R, int dir, float sx) {
+// FP32 accumulators of the blocks, folded into FP64 every kFold ring pairs
+struct CapAcc {
+  floatx4 acc[kStoreBlocks];
+  double accd[kStoreBlocks][4];
+  int nfold;
+  __device__ __forceinline__ void pair_done() {
+    if (++nfold == kFold) {
+      nfold = 0;
+#pragma unroll
+      for (int b = 0; b < kStoreBlocks; ++b) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) accd[b][u] += static_cast<double>(acc[b][u]);
+        acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ void store_compute(CapAcc& A, const StoreStep& R, int dir, float sx) {
   // forward lanes keep the memory order, reflected lanes reverse each half (a bitwise select per
   // element)
   const unsigned fwd = dir > 0 ? 0xffffffffu : 0u;
@@ -657,23 +683,12 @@ __device__ __forceinline__ void store_compute(floatx4& acc, const StoreStep& R, 
     const int r = (e & 4) + 3 - (e & 3);
     v[e] = __uint_as_float((fwd & __float_as_uint(R.v[e])) | (~fwd & __float_as_uint(R.v[r]))) * sx;
   }
-  store_mfma(acc, v, R.wa, R.wb);
-}
-
-// FP32 accumulator, folded into FP64 every kFold ring pairs
-struct CapAcc {
-  floatx4 acc;
-  double accd[4];
-  int nfold;
-  __device__ __forceinline__ void pair_done() {
-    if (++nfold == kFold) {
-      nfold = 0;
+  half8 xhi, xlo;
+  split_fp16<8>(v, xhi, xlo);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) accd[u] += static_cast<double>(acc[u]);
-      acc = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-  }
-};
+  for (int b = 0; b < kStoreBlocks; ++b)
+    if (R.blocks & (1 << b)) block_mfma(A.acc[b], xhi, xlo, R.wa[b], R.wb[b]);
+}
 
 // The tile's steps, ring pair after ring pair, as one sequence.
 struct StoreIter {
@@ -693,19 +708,27 @@ struct StoreIter {
     int b0, bend;
     tile_union(P, L.u_first, L.u_last, L.ni, L.inv_2ni, b0, bend);
     if (bend < b0) return 0;
-    int lo, hi;
-    row_window(P, L.u_row, L.ni, L.inv_2ni, lo, hi);
-    const bool in = L.a0 + L.row < L.F && hi >= lo;
-    const int glo = (lo - b0) >> 2;
-    const int gn = in ? ((hi - b0) >> 2) - glo + 1 : 0;
-    int total;
-    const int off = scan16(gn, total);
-    S.rbase = pos + off - glo;
-    S.glo = glo;
-    S.gn = gn;
-    pos += total;
-    if (total == 0) return 0;
     const int nk = (bend - b0 + 32) >> 5;
+    const int pos0 = pos;
+#pragma unroll
+    for (int b = 0; b < kStoreBlocks; ++b) {
+      int lo, hi;
+      row_window(P, L.u_row + 32 * b, L.ni, L.inv_2ni, lo, hi);
+      const bool in = L.a0 + 16 * b + L.row < L.F && hi >= lo;
+      const int glo = (lo - b0) >> 2;
+      const int gn = in ? ((hi - b0) >> 2) - glo + 1 : 0;
+      int total;
+      const int off = scan16(gn, total);
+      S.rbase[b] = pos + off - glo;
+      S.glo[b] = glo;
+      S.gn[b] = gn;
+      // the block's windows run from its first row's start to its last row's end
+      const int lo0 = __builtin_amdgcn_readlane(lo, 0), hi15 = __builtin_amdgcn_readlane(hi, 15);
+      S.slo[b] = total > 0 ? max(0, ((lo0 - b0) >> 2) >> 3) : 1;
+      S.shi[b] = total > 0 ? min(nk - 1, ((hi15 - b0) >> 2) >> 3) : 0;
+      pos += total;
+    }
+    if (pos == pos0) return 0;
     const int nj = P.nj;
     const long long xoff = L.ch ? P.xoff_m : P.xoff;
     const int pofs = L.pofs(nj, P.cj);
@@ -720,15 +743,21 @@ struct StoreIter {
     }
     const float* xj = xm + xoff;
     for (int q = 0; q < nk; ++q) {
-      const u32x4 wa = load_group(tile, group_offset(S, 8 * q + L.kgrp));
-      const u32x4 wb = load_group(tile, group_offset(S, 8 * q + 4 + L.kgrp));
       float v[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int b = first + 32 * q + 16 * (e >> 2) + (e & 3);
-        v[e] = xj[mod_any(pofs + L.dir * b, nj, rcp_n)] * sx;
+        const int bb = first + 32 * q + 16 * (e >> 2) + (e & 3);
+        v[e] = xj[mod_any(pofs + L.dir * bb, nj, rcp_n)] * sx;
       }
-      store_mfma(A.acc, v, wa, wb);
+      half8 xhi, xlo;
+      split_fp16<8>(v, xhi, xlo);
+#pragma unroll
+      for (int b = 0; b < kStoreBlocks; ++b) {
+        if (q < S.slo[b] || q > S.shi[b]) continue;
+        const u32x4 wa = load_group(tile, group_offset(S, b, 8 * q + L.kgrp));
+        const u32x4 wb = load_group(tile, group_offset(S, b, 8 * q + 4 + L.kgrp));
+        block_mfma(A.acc[b], xhi, xlo, wa, wb);
+      }
     }
     A.pair_done();
     return 0;
@@ -751,18 +780,28 @@ struct StoreIter {
       q = 0;
       S.nk = setup(P, L, xm, sx, A);
     }
-    unsigned oa = 0, ob = 0, xa = 0, xc = 0;
+    unsigned oa[kStoreBlocks], ob[kStoreBlocks], xa = 0, xc = 0;
+    int blocks = 0;
     bool last = false;
+#pragma unroll
+    for (int b = 0; b < kStoreBlocks; ++b) oa[b] = ob[b] = 0;
     if (ok) {
-      oa = group_offset(S, 8 * q + L.kgrp);
-      ob = group_offset(S, 8 * q + 4 + L.kgrp);
+#pragma unroll
+      for (int b = 0; b < kStoreBlocks; ++b) {
+        oa[b] = group_offset(S, b, 8 * q + L.kgrp);
+        ob[b] = group_offset(S, b, 8 * q + 4 + L.kgrp);
+        if (q >= S.slo[b] && q <= S.shi[b]) blocks |= 1 << b;
+      }
       xa = S.xofs + static_cast<unsigned>(L.dir * 32 * q);
       xc = xa + static_cast<unsigned>(L.dir * 16);
       ++q;
       last = q >= S.nk;
     }
-    R.wa = load_group(tile, oa);
-    R.wb = load_group(tile, ob);
+#pragma unroll
+    for (int b = 0; b < kStoreBlocks; ++b) {
+      R.wa[b] = load_group(tile, oa[b]);
+      R.wb[b] = load_group(tile, ob[b]);
+    }
     // 32-bit byte offsets (maps hold at most 12 * 8192^2 pixels) on the map's base address
     const float* x0 = reinterpret_cast<const float*>(reinterpret_cast<const unsigned char*>(xm) + xa * 4u);
     const float* x1 = reinterpret_cast<const float*>(reinterpret_cast<const unsigned char*>(xm) + xc * 4u);
@@ -771,16 +810,18 @@ struct StoreIter {
       R.v[e] = x0[e];
       R.v[4 + e] = x1[e];
     }
+    R.blocks = blocks;
     R.live = ok;
     R.last = last;
   }
 };
 
-constexpr int kStoreSlots = 6;   // steps in flight per wave
+constexpr int kStoreSlots = 4;   // steps in flight per wave
 
-// all cap-touching pairs of a tile from the store
+// all cap-touching pairs of a store tile, all blocks
 __device__ __forceinline__ void cap_rows_store(const convreal::MixedDesc* __restrict__ d, int t, const CapLane& L,
-                                               const float* __restrict__ xm, float sx, double (&accd)[4]) {
+                                               const float* __restrict__ xm, float sx,
+                                               double (&accd)[kStoreBlocks][4]) {
   StoreIter it;
   it.tile = reinterpret_cast<const unsigned char*>(ldu(d->wstore)) + 16 * ldu(ldu(d->wtile_off)[t]);
   it.kk = ldu(ldu(d->rest_off)[L.r]);
@@ -791,9 +832,12 @@ __device__ __forceinline__ void cap_rows_store(const convreal::MixedDesc* __rest
   const convreal::CapPair* cpair = ldu(d->cpair);
   if (it.kk < it.k1) it.Pn = ldu_record(cpair[it.kk]);
   CapAcc A;
-  A.acc = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int u = 0; u < 4; ++u) A.accd[u] = 0.0;
+  for (int b = 0; b < kStoreBlocks; ++b) {
+    A.acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) A.accd[b][u] = 0.0;
+  }
   A.nfold = 0;
   StoreStep R[kStoreSlots];
 #pragma unroll
@@ -804,14 +848,16 @@ __device__ __forceinline__ void cap_rows_store(const convreal::MixedDesc* __rest
 #pragma unroll
     for (int s = 0; s < kStoreSlots; ++s) {
       if (R[s].live) {
-        store_compute(A.acc, R[s], L.dir, sx);
+        store_compute(A, R[s], L.dir, sx);
         if (R[s].last) A.pair_done();
       }
       it.next(cpair, L, xm, sx, A, R[s]);
     }
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) accd[u] = A.accd[u] + static_cast<double>(A.acc[u]);
+  for (int b = 0; b < kStoreBlocks; ++b)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) accd[b][u] = A.accd[b][u] + static_cast<double>(A.acc[b][u]);
 }
 
 // all cap-touching pairs of a tile with weights evaluated on the fly
@@ -906,22 +952,11 @@ __device__ __forceinline__ void cap_rows_fly(const convreal::MixedDesc* __restri
   for (int u = 0; u < 4; ++u) accd[u] += static_cast<double>(acc[u]);
 }
 
-// one wave: tile t (16 output pixels of the fundamental domain of one north-half ring) and its 16
-// images. FLY = false: every slot holds a weight store, so only the store path is compiled in.
-template <bool FLY>
-__device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__ d, int t,
-                                         const float* __restrict__ xm, float* __restrict__ ym, float sx,
-                                         const float4* __restrict__ s_coef) {
-  const CapLane L(d, t);
-  double accd[4] = {0.0, 0.0, 0.0, 0.0};
-  if (!FLY || ldu(d->wstore) != nullptr)
-    cap_rows_store(d, t, L, xm, sx, accd);
-  else
-    cap_rows_fly(d, L, xm, sx, s_coef, accd);
-
-  // store: D rows 4 kgrp + u (output pixel a0 + 4 kgrp + u), column col (image); each output
-  // pixel once: rows beyond the fundamental domain [0, F), reflections of pixels on a reflection
-  // axis and the mirror of the equator ring are skipped
+// store D rows 4 kgrp + u (output pixel a0 + 4 kgrp + u), column col (image) of one 16-row block
+// starting at a0; each output pixel once: rows beyond the fundamental domain [0, F), reflections of
+// pixels on a reflection axis and the mirror of the equator ring are skipped
+__device__ __forceinline__ void cap_put(const convreal::MixedDesc* __restrict__ d, const CapLane& L, int a0,
+                                        const double (&accd)[4], float* __restrict__ ym, float sx) {
   const int mr = ldu(d->nrings) - 1 - L.r;
   if (L.ch && mr == L.r) return;
   const int rr = L.ch ? mr : L.r;
@@ -932,7 +967,7 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
   const int quarter = ni >> 2;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int ao = L.a0 + 4 * L.kgrp + u;
+    const int ao = a0 + 4 * L.kgrp + u;
     if (ao >= L.F) continue;
     if (L.cf && ((2 * ao + ci) % quarter) == 0) continue;
     int Pp = L.cf ? (ni - ao - ci + L.cq * quarter) : (ao + L.cq * quarter);
@@ -942,8 +977,29 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
   }
 }
 
+// one wave: cap tile t of the plan's tile list and its 16 images. A plan with a weight store lists
+// store tiles of kStoreRows rows; one without lists tiles of 16 rows, evaluated on the fly.
+// FLY = false: every slot holds a weight store, so only the store path is compiled in.
+template <bool FLY>
+__device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__ d, int t,
+                                         const float* __restrict__ xm, float* __restrict__ ym, float sx,
+                                         const float4* __restrict__ s_coef) {
+  if (!FLY || ldu(d->wstore) != nullptr) {
+    const CapLane L(d, t, kStoreRows);
+    double accd[kStoreBlocks][4];
+    cap_rows_store(d, t, L, xm, sx, accd);
+#pragma unroll
+    for (int b = 0; b < kStoreBlocks; ++b) cap_put(d, L, L.a0 + 16 * b, accd[b], ym, sx);
+  } else if constexpr (FLY) {
+    const CapLane L(d, t, 16);
+    double accd[4] = {0.0, 0.0, 0.0, 0.0};
+    cap_rows_fly(d, L, xm, sx, s_coef, accd);
+    cap_put(d, L, L.a0, accd, ym, sx);
+  }
+}
+
 // ---------------------------------------------------------------- cap weight store (set-up)
-// One wave per cap tile, the same tiles, ring pairs, union windows and row windows as the apply.
+// One wave per store tile, the same tiles, ring pairs, union windows and row windows as the apply.
 // FILL = false: the number of 16-byte groups of each tile; FILL = true: the groups (long form, any
 // ring pair), tile t's block (its zero groups first) starting at group offsets[t].
 template <bool FILL>
@@ -960,7 +1016,7 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
   }
   const int t = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   if (t >= ldu(d->n_citems)) return;
-  const CapLane L(d, t);
+  const CapLane L(d, t, kStoreRows);
   const double inv_h = ldu(d->inv_h);
   const double ih2 = inv_h * inv_h;
   const double qcut = ldu(d->dcut2) * ih2;
@@ -977,29 +1033,32 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
     int b0, bend;
     tile_union(P, L.u_first, L.u_last, L.ni, L.inv_2ni, b0, bend);
     if (bend < b0) continue;
-    int lo, hi;
-    row_window(P, L.u_row, L.ni, L.inv_2ni, lo, hi);
-    const bool in = L.a0 + L.row < L.F && hi >= lo;
-    const int glo = (lo - b0) >> 2, ghi = (hi - b0) >> 2;
-    int total;
-    const int off = scan16(in ? ghi - glo + 1 : 0, total);
-    if (FILL && in) {
-      const LongForm lf(P, L.ni, ih2);
-      for (int g = glo + L.kgrp; g <= ghi; g += 4) {
-        const int bA = b0 + 4 * g;
-        double qv[4];
-        lf.q<4>(L.u_row, bA, L.ni, P.nj, P.cj, qv);
-        float w[4];
-        weights_of<4>(qv, qcut, seg_max, s_coef, w);
+    for (int b = 0; b < kStoreBlocks; ++b) {
+      const int u_row = L.u_row + 32 * b;
+      int lo, hi;
+      row_window(P, u_row, L.ni, L.inv_2ni, lo, hi);
+      const bool in = L.a0 + 16 * b + L.row < L.F && hi >= lo;
+      const int glo = (lo - b0) >> 2, ghi = (hi - b0) >> 2;
+      int total;
+      const int off = scan16(in ? ghi - glo + 1 : 0, total);
+      if (FILL && in) {
+        const LongForm lf(P, L.ni, ih2);
+        for (int g = glo + L.kgrp; g <= ghi; g += 4) {
+          const int bA = b0 + 4 * g;
+          double qv[4];
+          lf.q<4>(u_row, bA, L.ni, P.nj, P.cj, qv);
+          float w[4];
+          weights_of<4>(qv, qcut, seg_max, s_coef, w);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) w[e] = (bA + e >= lo && bA + e <= hi) ? w[e] : 0.0f;
-        half4 wh, wl;
-        split_fp16<4>(w, wh, wl);
-        const u32x2 ph = __builtin_bit_cast(u32x2, wh), pl = __builtin_bit_cast(u32x2, wl);
-        tile[pos + off + (g - glo)] = u32x4{ph.x, ph.y, pl.x, pl.y};
+          for (int e = 0; e < 4; ++e) w[e] = (bA + e >= lo && bA + e <= hi) ? w[e] : 0.0f;
+          half4 wh, wl;
+          split_fp16<4>(w, wh, wl);
+          const u32x2 ph = __builtin_bit_cast(u32x2, wh), pl = __builtin_bit_cast(u32x2, wl);
+          tile[pos + off + (g - glo)] = u32x4{ph.x, ph.y, pl.x, pl.y};
+        }
       }
+      pos += total;
     }
-    pos += total;
   }
   if (!FILL && (threadIdx.x & 63) == 0) offsets[t] = pos;
 }
@@ -1043,9 +1102,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convrea
     const convreal::MixedDesc* d = S.desc[slot];
     const float sx = map_scale(ldu(amax[slot]));
     if (kind == 0) {
-      // three rings in flight; one where the registers are sized for three waves per SIMD (there
-      // the other workgroup's waves cover the latency)
-      belt_item<SEG, (WAVES >= 3 ? 1 : 3)>(d, idx, S.x[slot], S.y[slot], sx, stage);
+      // three rings in flight, two where the registers are sized for three waves per SIMD
+      belt_item<SEG, (WAVES >= 3 ? 2 : 3)>(d, idx, S.x[slot], S.y[slot], sx, stage);
     } else {
       if (FLY && owner != d) {
         const float4* coef = reinterpret_cast<const float4*>(ldu(d->coef));
