@@ -110,7 +110,8 @@ __global__ void zero_state_kernel(unsigned* amax, int n, unsigned* counter) {
 }
 
 // per slot: |x| maximum (atomicMax on the bit pattern: non-negative floats order like their bits),
-// and zero of the rows that will receive two atomic adds
+// and zero of the rows that will receive two atomic adds. 16-byte loads where the map is 16-byte
+// aligned (N_pix = 12 N^2 is a multiple of 4), a plain loop otherwise.
 __global__ __launch_bounds__(256) void prep_kernel(convreal::Slots S, unsigned* __restrict__ amax) {
   const int slot = blockIdx.y;
   const convreal::MixedDesc* d = S.desc[slot];
@@ -118,15 +119,32 @@ __global__ __launch_bounds__(256) void prep_kernel(convreal::Slots S, unsigned* 
   const float* x = S.x[slot];
   float* y = S.y[slot];
   const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+  const long long t0 = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   float v = 0.0f;
-  for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < npix; i += stride)
-    v = fmaxf(v, fabsf(x[i]));
+  if ((reinterpret_cast<unsigned long long>(x) & 15) == 0) {
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const long long n4 = npix >> 2;
+    for (long long i = t0; i < n4; i += stride) {
+      const float4 q = x4[i];
+      v = fmaxf(v, fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fmaxf(fabsf(q.z), fabsf(q.w))));
+    }
+    for (long long i = (n4 << 2) + t0; i < npix; i += stride) v = fmaxf(v, fabsf(x[i]));
+  } else {
+    for (long long i = t0; i < npix; i += stride) v = fmaxf(v, fabsf(x[i]));
+  }
+  // one atomic per workgroup: atomics on one address serialise
+  __shared__ float wmax[256 / 64];
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  if ((threadIdx.x & 63) == 0) atomicMax(amax + slot, __float_as_uint(v));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = wmax[0];
+    for (int k = 1; k < 256 / 64; ++k) m = fmaxf(m, wmax[k]);
+    atomicMax(amax + slot, __float_as_uint(m));
+  }
   for (int z = 0; z < 2; ++z) {
     const long long z0 = d->zero_lo[z], z1 = d->zero_hi[z];
-    for (long long i = z0 + static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < z1; i += stride)
-      y[i] = 0.0f;
+    for (long long i = z0 + t0; i < z1; i += stride) y[i] = 0.0f;
   }
 }
 
@@ -1168,8 +1186,9 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
                               int max_nseg, long long npix_max, long long pairs, bool fly, hipStream_t st) {
   hipLaunchKernelGGL(zero_state_kernel, dim3(1), dim3(kMaxSlots), 0, st, amax, nslots, counter);
   mark(mark_plan, st, "zero_state_kernel", 0);
-  const long long want = (npix_max + 255) / 256;
-  const unsigned gx = static_cast<unsigned>(want < 1024 ? want : 1024);
+  // at least 8 float4 per thread, at most 1024 workgroups (and atomics) per map
+  const long long want = (npix_max / 4 + 2047) / 2048;
+  const unsigned gx = static_cast<unsigned>(want < 1 ? 1 : (want < 1024 ? want : 1024));
   hipLaunchKernelGGL(prep_kernel, dim3(gx, nslots), dim3(256), 0, st, S, amax);
   mark(mark_plan, st, "prep_kernel", 0);
   if (n_items > 0 && nrep > 0) {
