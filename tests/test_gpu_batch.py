@@ -72,11 +72,16 @@ def test_autotune_and_cache(cuda_device, tmp_path):
     plan.close()
 
 
-def test_batch_matches_single_and_oracle(cuda_device):
+@pytest.mark.parametrize("stores", ["all", "mixed"])
+def test_batch_matches_single_and_oracle(cuda_device, stores):
+    """A batch equals its plans' single applies bitwise and meets the oracle; "mixed": some plans
+    stream cap weights from their store and others evaluate them, in the same launch."""
     specs = [(16, 12.0, None), (32, 6.0, None), (64, 4.0, 120), (32, 9.0, 40), (8, 20.0, None)]
     plans, xs, Ts = [], [], []
     for k, (ns, fwhm, lc) in enumerate(specs):
         p, T, tc = _plan(ns, fwhm, ell_cut=lc)
+        if stores == "mixed" and k % 2 == 1:
+            p.set_weight_store("off")
         plans.append(p)
         Ts.append((T, tc))
         xs.append(_maps(ns, 10 + k)[0])

@@ -1,9 +1,11 @@
 """GPU parity of the mixed-precision path (CONV_REAL_MIXED) against the CPU oracle.
 
 Belt ring pairs run as split-FP16 products on the matrix cores (FP32 sums per ring pair,
-FP64 across ring pairs); the remaining ring pairs per pixel pair in FP64. Tolerance: the
-relative rms error per map against the FP64 oracle is at most 1e-6 (the target stated for
-this path); the largest single-pixel error is bounded at 1e-5 of the map's largest output.
+FP64 across ring pairs); cap-touching ring pairs likewise, with weights streamed from the
+plan's weight store (the default where it fits) or evaluated on the fly; the tests that vary
+the grid run in both modes. Tolerance: the relative rms error per map against the FP64 oracle
+is at most 1e-6 (the target stated for this path); the largest single-pixel error is bounded at
+1e-5 of the map's largest output.
 """
 import math
 
@@ -36,13 +38,18 @@ def _check(y, ref):
         assert np.max(np.abs(y[m] - ref[m])) <= 1e-5 * np.max(np.abs(ref[m]))
 
 
+STORE_MODES = ["on", "off"]
+
+
+@pytest.mark.parametrize("store", STORE_MODES)
 @pytest.mark.parametrize("nside,sigma_deg,cut_sigma", [(16, 4.0, 4.0), (32, 1.5, 5.0), (64, 1.0, 5.0)])
-def test_mixed_full_map(cuda_device, nside, sigma_deg, cut_sigma):
+def test_mixed_full_map(cuda_device, nside, sigma_deg, cut_sigma, store):
     sigma = sigma_deg * DEG
     tc = cut_sigma * sigma
     T = ok.tabulate(synth.gaussian_beam_sigma(512, sigma), tc, 2048)
     x = synth.white_noise(nside, 2, seed=nside, dtype=np.float32)
     with cr.Plan(nside, T, tc, "mixed") as plan:
+        plan.set_weight_store(store)
         y = _run(plan, x)
     npix = x.shape[1]
     pix = np.arange(npix) if nside <= 32 else np.random.default_rng(1).choice(npix, 3000, replace=False)
@@ -50,12 +57,15 @@ def test_mixed_full_map(cuda_device, nside, sigma_deg, cut_sigma):
     _check(y[:, pix], ref)
 
 
-def test_mixed_small_and_degenerate_grids(cuda_device):
-    """Grids too small for the belt contraction fall back to per-pair sums for every ring pair."""
+@pytest.mark.parametrize("store", STORE_MODES)
+def test_mixed_small_and_degenerate_grids(cuda_device, store):
+    """Grids too small for the belt contraction: every ring pair goes through the cap path (rings of
+    4 pixels, whole-ring windows, a cut of pi)."""
     for nside, tc in [(1, 1.0), (2, 0.7), (4, 0.5), (8, math.pi)]:
         T = ok.tabulate(synth.gaussian_beam_sigma(64, tc / 3), tc, 64)
         x = synth.white_noise(nside, 1, seed=3, dtype=np.float32)
         with cr.Plan(nside, T, tc, "mixed") as plan:
+            plan.set_weight_store(store)
             y = _run(plan, x)
         ref = oc.convolve_sampled(nside, T, tc, x.astype(np.float64), np.arange(x.shape[1]))
         _check(y, ref.reshape(1, -1))
@@ -74,14 +84,21 @@ def test_mixed_large_table_fallback(cuda_device):
     _check(y, ref.reshape(1, -1))
 
 
-def test_mixed_residual_kernel_512(cuda_device):
-    """Oscillating residual kernel (beam minus tapered low-l part), Nside 512, sampled pixels."""
+@pytest.mark.parametrize("store", STORE_MODES)
+def test_mixed_residual_kernel_512(cuda_device, store):
+    """Oscillating residual kernel (beam minus tapered low-l part), Nside 512, sampled pixels, among
+    them the first and last pixels of the polar rings and of the rings at the cap/belt edges."""
     w = synth.workload("resid512")
     T = ok.tabulate(w.k_ell(), w.theta_cut, w.n_tab)
     x = synth.white_noise(w.nside, 1, seed=w.seed, dtype=np.float32)
     with cr.Plan(w.nside, T, w.theta_cut, "mixed") as plan:
+        plan.set_weight_store(store)
         y = _run(plan, x)
-    pix = np.random.default_rng(5).choice(x.shape[1], 1500, replace=False)
+    npix, N = x.shape[1], w.nside
+    edge = [2 * N * (N - 1) - 1, 2 * N * (N - 1), 2 * N * (N + 1) - 1, 2 * N * (N + 1),
+            npix - 2 * N * (N - 1) - 1, npix - 2 * N * (N - 1)]
+    pix = np.unique(np.concatenate([np.random.default_rng(5).choice(npix, 1500, replace=False),
+                                    np.arange(12), npix - 1 - np.arange(12), edge]))
     ref = oc.convolve_sampled(w.nside, T, w.theta_cut, x.astype(np.float64), pix)
     assert oc.rel_rms(y[0, pix], ref) <= TOL
 
