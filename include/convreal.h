@@ -146,7 +146,10 @@ int conv_real_profile(conv_real_plan* plan, const void* maps_in, void* maps_out,
  *   seg        belt output pixels per work item: 256 or 512
  *   wg_per_cu  workgroups per compute unit (persistent grid = CUs x wg_per_cu): 1..4; at most 2
  *              are resident at once, 3 where seg is 256 and the plan holds a cap weight store
- *   order      0: items by decreasing estimated cost; 1: belt and cap items alternating
+ *   order      0: items by decreasing estimated cost; 1: belt and cap items alternating; 2: one
+ *              queue per XCD holding neighbouring belt bands and cap rings (whose input rings overlap,
+ *              so they share that XCD's L2), alternating as in 1, with workgroups taking from
+ *              other XCDs' queues once their own is empty
  */
 typedef struct conv_real_tuning {
   int seg;
@@ -173,9 +176,9 @@ int conv_real_get_tuning(const conv_real_plan* plan, conv_real_tuning* t);
  *   CONV_REAL_STORE_ON    build the store (ENOMEM if the device cannot hold it)
  *   CONV_REAL_STORE_AUTO  build it if it needs at most 64 GiB and 40% of the free device memory
  * A new mixed plan takes CONV_REAL_STORE_AUTO. Unless the plan's launch configuration was set by
- * conv_real_set_tuning or conv_real_autotune, changing the store also picks its default: seg 256
- * and 3 workgroups per compute unit with a store (the kernel is then built for three waves per
- * SIMD), seg 256 and 2 without.
+ * conv_real_set_tuning or conv_real_autotune, changing the store also picks its default: seg 256,
+ * 3 workgroups per compute unit and order 1 with a store (the kernel is then built for three waves
+ * per SIMD), seg 256, 2 workgroups and order 0 without.
  * conv_real_set_weight_store is synchronous (not while an apply on the plan may still run) and
  * allocates; applies never allocate. conv_real_get_weight_store reports whether a store is held
  * and its size in bytes. Mixed plans only (EINVAL otherwise).

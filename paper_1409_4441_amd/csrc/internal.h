@@ -41,6 +41,7 @@ RingGrid make_ring_grid(int nside);
 void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std::vector<int>& jhi);
 
 constexpr int kMaxSlots = 64;  // maps per persistent mixed-path launch
+constexpr int kMaxChunks = 8;  // work-queue chunks (one per XCD)
 // 16-row blocks per cap tile when the plan holds a weight store: the blocks of a tile share every
 // step's inputs and every ring pair's set-up, but each block adds its weight registers to every
 // pipeline slot; two blocks exceed the register file at two waves per SIMD and were measured slower
@@ -110,7 +111,8 @@ struct Slots {
 struct Tuning {
   int seg = 256;       // belt output pixels per work item: 256 or 512
   int wg_per_cu = 2;   // resident workgroups per compute unit
-  int order = 0;       // 0: all items by decreasing cost; 1: belt and cap items alternating
+  int order = 0;       // 0: all items by decreasing cost; 1: belt and cap items alternating;
+                       // 2: one chunk per XCD of neighbouring rings, each by decreasing cost
 };
 
 // Events recorded between kernels by conv_real_profile.
@@ -212,9 +214,11 @@ struct conv_real_plan {
   convreal::MixedDesc* d_desc = nullptr;  // device copy of the plan's descriptor
   convreal::Tuning tune;
   int tune_user = 0;           // 1 once the caller set the launch configuration (or autotuned it)
-  int2* d_items = nullptr;     // work queue of one map (slot 0)
+  int2* d_items = nullptr;     // work queue of one map (slot 0), chunk after chunk
   int n_items = 0;
-  unsigned* d_counter = nullptr;
+  int* d_qchunk_off = nullptr; // n_qchunks + 1 offsets into d_items
+  int n_qchunks = 1;
+  unsigned* d_counter = nullptr;   // kMaxChunks counters
   std::vector<double> cost_belt;   // per belt band: estimated cycles per 16-pixel column block
   std::vector<double> cost_cap;    // per cap work item (4 tiles): estimated cycles
 
@@ -249,8 +253,9 @@ hipError_t build_belt_weights(conv_real_plan* p);
 size_t belt_stage_bytes(int seg);
 hipError_t set_lds_limits(int nseg);
 hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, int nslots, const int2* items,
-                              int n_items, int nrep, unsigned* amax, unsigned* counter, const Tuning& tune,
-                              int max_nseg, long long npix_max, long long pairs, bool fly, hipStream_t st);
+                              int n_items, int nrep, const int* chunk_off, int n_chunks, unsigned* amax,
+                              unsigned* counter, const Tuning& tune, int max_nseg, long long npix_max,
+                              long long pairs, bool fly, hipStream_t st);
 hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st);
 // number of weights of each cap tile in the store (counts[n_citems]), and the store's fill
 hipError_t cap_store_count(const conv_real_plan* p, long long* counts_dev);

@@ -103,10 +103,10 @@ struct BeltLayout {
 };
 
 // ---------------------------------------------------------------- prep kernels
-__global__ void zero_state_kernel(unsigned* amax, int n, unsigned* counter) {
+__global__ void zero_state_kernel(unsigned* amax, int n, unsigned* counter, int ncounters) {
   const int t = threadIdx.x;
   if (t < n) amax[t] = 0u;
-  if (t == 0) *counter = 0u;
+  if (t < ncounters) counter[t] = 0u;
 }
 
 // per slot: |x| maximum (atomicMax on the bit pattern: non-negative floats order like their bits),
@@ -1085,10 +1085,16 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
 // WAVES: resident waves per SIMD the registers are sized for (= workgroups per compute unit); at
 // least two, so that belt and cap items share a SIMD; three where the LDS allows it (256-pixel belt
 // items and no coefficient table), at the price of a few spilled registers
+// The queue is split into n_chunks chunks of items (chunk c: items chunk_off[c] .. chunk_off[c+1]
+// - 1, each for nrep maps), one counter each. A workgroup takes items from chunk blockIdx.x % n_chunks
+// first (workgroups are spread over the XCDs in turn, so with one chunk per XCD the items of a chunk
+// share one L2) and then from the others, until every chunk is empty.
 template <int SEG, bool FLY, int WAVES>
 __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convreal::Slots S,
                                                                   const int2* __restrict__ items,
                                                                   int n_items, int nrep,
+                                                                  const int* __restrict__ chunk_off,
+                                                                  int n_chunks,
                                                                   const unsigned* __restrict__ amax,
                                                                   unsigned* __restrict__ counter,
                                                                   int coef_offset_bytes) {
@@ -1098,9 +1104,23 @@ __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convrea
   _Float16* stage = reinterpret_cast<_Float16*>(lds);
   float4* s_coef = reinterpret_cast<float4*>(lds + coef_offset_bytes);
   if (threadIdx.x == 0) s_coef_owner = nullptr;
-  const int total = n_items * nrep;   // the host keeps this below 2^31
+  const int home = static_cast<int>(blockIdx.x % static_cast<unsigned>(n_chunks));
+  unsigned empty = 0u;   // chunks this workgroup found empty (thread 0)
   for (;;) {
-    if (threadIdx.x == 0) s_item = static_cast<int>(atomicAdd(counter, 1u));
+    if (threadIdx.x == 0) {
+      int got = -1;   // map repetition x n_items + item (the host keeps n_items x nrep below 2^31)
+      for (int k = 0; k < n_chunks && got < 0; ++k) {
+        const int c = home + k < n_chunks ? home + k : home + k - n_chunks;
+        if (empty & (1u << c)) continue;
+        const int c0 = chunk_off[c], len = chunk_off[c + 1] - c0;
+        const unsigned v = len > 0 ? atomicAdd(counter + c, 1u) : 0u;
+        if (len > 0 && v < static_cast<unsigned>(len) * static_cast<unsigned>(nrep))
+          got = static_cast<int>(v / len) * n_items + c0 + static_cast<int>(v % len);
+        else
+          empty |= 1u << c;
+      }
+      s_item = got;
+    }
     __syncthreads();
     // values read from LDS are the same in every lane; readfirstlane tells the compiler so, which
     // keeps the item's descriptor and its pointers in scalar registers and their loads scalar
@@ -1112,7 +1132,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convrea
          << 32);
     const convreal::MixedDesc* owner = reinterpret_cast<const convreal::MixedDesc*>(ow_u);
     __syncthreads();
-    if (gi >= total) break;
+    if (gi < 0) break;
     const int2 it = ldu_record(items[gi % n_items]);
     const int slot = it.x + static_cast<int>(gi / n_items);
     const int kind = it.y >> 30;
@@ -1182,9 +1202,11 @@ hipError_t build_belt_weights(conv_real_plan* p) {
 
 // Launch the prep kernels and the persistent kernel over `nslots` maps whose descriptors are in S.
 hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, int nslots, const int2* items,
-                              int n_items, int nrep, unsigned* amax, unsigned* counter, const Tuning& tune,
-                              int max_nseg, long long npix_max, long long pairs, bool fly, hipStream_t st) {
-  hipLaunchKernelGGL(zero_state_kernel, dim3(1), dim3(kMaxSlots), 0, st, amax, nslots, counter);
+                              int n_items, int nrep, const int* chunk_off, int n_chunks, unsigned* amax,
+                              unsigned* counter, const Tuning& tune, int max_nseg, long long npix_max,
+                              long long pairs, bool fly, hipStream_t st) {
+  if (n_chunks < 1 || n_chunks > kMaxChunks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zero_state_kernel, dim3(1), dim3(kMaxSlots), 0, st, amax, nslots, counter, n_chunks);
   mark(mark_plan, st, "zero_state_kernel", 0);
   // at least 8 float4 per thread, at most 1024 workgroups (and atomics) per map
   const long long want = (npix_max / 4 + 2047) / 2048;
@@ -1204,15 +1226,15 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
     const dim3 g(static_cast<unsigned>(grid)), blk(kBlock);
     const int co = static_cast<int>(coef_off);
     if (tune.seg == 512 && fly)
-      hipLaunchKernelGGL((mixed_persistent_kernel<512, true, 2>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<512, true, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
     else if (tune.seg == 512)
-      hipLaunchKernelGGL((mixed_persistent_kernel<512, false, 2>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<512, false, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
     else if (fly)
-      hipLaunchKernelGGL((mixed_persistent_kernel<256, true, 2>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, true, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
     else if (tune.wg_per_cu >= 3)
-      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 3>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 3>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
     else
-      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 2>), g, blk, lds, st, S, items, n_items, nrep, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     mark(mark_plan, st, "mixed_persistent_kernel", pairs);
@@ -1266,8 +1288,9 @@ hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int n
       S.x[k] = x + static_cast<size_t>(m0 + k) * p->npix;
       S.y[k] = y + static_cast<size_t>(m0 + k) * p->npix;
     }
-    hipError_t e = launch_mixed_queue(p, S, nm, p->d_items, p->n_items, nm, p->d_amax, p->d_counter, p->tune,
-                                      p->cap_nseg, p->npix, p->pairs * nm, p->cap_mode && !p->d_wstore, st);
+    hipError_t e = launch_mixed_queue(p, S, nm, p->d_items, p->n_items, nm, p->d_qchunk_off, p->n_qchunks, p->d_amax,
+                                      p->d_counter, p->tune, p->cap_nseg, p->npix, p->pairs * nm,
+                                      p->cap_mode && !p->d_wstore, st);
     if (e != hipSuccess) return e;
     if (!p->cap_mode) {
       // table too large for the LDS coefficient form: cap-touching pairs per pair in FP64, added to
