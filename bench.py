@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -214,6 +215,17 @@ def batched(steps, stream):
     return out
 
 
+def paper_context(theta_cut, pairs_per_map, maps_per_s):
+    """The paper's cost model for its GPU real-space convolution (Eq. 7, fitted on a GeForce GTX 480
+    in single precision, Nside 2048, l_max 4096): t = 0.0232 s per arcminute of theta_cut + 2.428 s.
+    Context for the figures measured here, not a target (it is a model of another design on other
+    hardware)."""
+    t = 0.0232 * math.degrees(theta_cut) * 60.0 + 2.428
+    return {"source": "Eq. 7 cost model, GeForce GTX 480, single precision, Nside 2048",
+            "seconds_per_map": t, "maps_per_s": 1.0 / t, "pixel_pairs_per_s_implied": pairs_per_map / t,
+            "ratio_maps_per_s_here": maps_per_s * t}
+
+
 def cpu_baseline(w, table, x, y_gpu, nsamp):
     """The oracle, as it stands, on nsamp sampled output pixels of the same map; single thread."""
     from threadpoolctl import threadpool_limits
@@ -348,6 +360,7 @@ def main():
         "weight_store": store,
         "batched": bat,
         "roofline": roofline, "cpu_baseline": cpu,
+        "paper_context": paper_context(w.theta_cut, pairs_per_map, maps_per_s) if w.nside == 2048 else None,
     }
     print(json.dumps(out), flush=True)
     plan.close()

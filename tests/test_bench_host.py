@@ -32,3 +32,12 @@ def test_traffic_note_matches_sources_or_is_ignored(tmp_path, monkeypatch):
     assert bench.measured_traffic() == 123.0
     monkeypatch.setattr(bench, "TRAFFIC_NOTE", os.path.join(str(tmp_path), "missing.md"))
     assert bench.measured_traffic() is None
+
+
+def test_paper_context_is_eq7():
+    # Eq. 7 at theta_cut = 30 arcmin: 0.0232 s x 30 + 2.428 s = 3.124 s per Nside 2048 map
+    import math
+    c = bench.paper_context(30.0 / 60.0 * math.pi / 180.0, 48266767192, 400.0)
+    assert abs(c["seconds_per_map"] - 3.124) < 1e-12
+    assert abs(c["maps_per_s"] - 1.0 / 3.124) < 1e-12
+    assert abs(c["ratio_maps_per_s_here"] - 400.0 * 3.124) < 1e-9
