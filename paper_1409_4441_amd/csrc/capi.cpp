@@ -583,8 +583,8 @@ int set_weight_store(conv_real_plan* p, int mode) {
     release(p, counts);
     for (int t = 0; t < p->n_citems; ++t) off[t + 1] += off[t];
     const long long n = off[p->n_citems];
-    // 16-byte groups (each tile's block starts with its zero groups), every one written by the fill
-    const size_t bytes = sizeof(uint4) * static_cast<size_t>(n);
+    // 16-byte groups, every one written by the fill (at least one, so that the store is never empty)
+    const size_t bytes = sizeof(uint4) * static_cast<size_t>(std::max(n, 1LL));
     bool build = true;
     if (mode == CONV_REAL_STORE_AUTO) {
       size_t free_b = 0, total_b = 0;
@@ -594,7 +594,7 @@ int set_weight_store(conv_real_plan* p, int mode) {
     }
     if (build) {
       off.pop_back();
-      if ((e = dev_alloc(p, &p->d_wstore, static_cast<size_t>(n))) != hipSuccess) {
+      if ((e = dev_alloc(p, &p->d_wstore, static_cast<size_t>(std::max(n, 1LL)))) != hipSuccess) {
         // the automatic mode falls back to evaluating on the fly
         if (mode == CONV_REAL_STORE_AUTO)
           (void)hipGetLastError();
@@ -731,9 +731,23 @@ int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_
     }
   p->ntiles = static_cast<int>(tile_ring.size());
   std::vector<double> tab(table, table + n_tab);
+  // per-segment coefficients of the interpolating cubic in f = t - k (nodes k-1..k+2, ghost node
+  // T[-1] = T[1]) for the per-pair kernel, when they fit in 64 KB of LDS
+  std::vector<double> coef64;
+  if (n_tab - 2 <= convreal::kCoefMaxSegs) {
+    coef64.resize(4 * static_cast<size_t>(n_tab - 2));
+    for (int k = 0; k + 2 < n_tab; ++k) {
+      const double tm1 = tab[k == 0 ? 1 : k - 1], t0 = tab[k], t1 = tab[k + 1], t2 = tab[k + 2];
+      coef64[4 * k + 0] = t0;
+      coef64[4 * k + 1] = -tm1 / 3.0 - t0 / 2.0 + t1 - t2 / 6.0;
+      coef64[4 * k + 2] = tm1 / 2.0 - t0 + t1 / 2.0;
+      coef64[4 * k + 3] = -tm1 / 6.0 + t0 / 2.0 - t1 / 2.0 + t2 / 6.0;
+    }
+  }
 
   hipError_t e = hipSuccess;
   if ((e = dev_upload(p, &p->d_table, tab)) != hipSuccess ||
+      (!coef64.empty() && (e = dev_upload(p, &p->d_coef64, coef64)) != hipSuccess) ||
       (e = dev_upload(p, &p->d_rn, g.n)) != hipSuccess ||
       (e = dev_upload(p, &p->d_rc, g.c)) != hipSuccess ||
       (e = dev_upload(p, &p->d_rstart, g.start)) != hipSuccess ||

@@ -5,6 +5,27 @@
 
 namespace convreal {
 
+// Buffer resources: word 3 for untyped 32-bit accesses, the range given to every resource, and the
+// offset that a lane with nothing to load gives (past the range: the hardware returns zeros without
+// a memory access). Such loads are issued by every lane on every path, so that the compiler can
+// count the loads in flight, while only the data in use moves through the caches. Offsets are 32-bit
+// byte offsets from the resource's base.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kBufferRange = 0x7fffffff;
+constexpr unsigned kNoLoad = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_resource(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, kBufferRange, kBufferWord3);
+}
+
+// Load of a value that is the same in every lane and read-only for the kernel's lifetime (plan
+// tables written at set-up): through the constant address space, so that it becomes a scalar load
+// into SGPRs and the compiler treats the result as wave-uniform.
+template <typename T>
+__device__ __forceinline__ T ldu(const T& ref) {
+  return *(const __attribute__((address_space(4))) T*)(&ref);
+}
+
 // Blocks are dealt round-robin to the 8 XCDs of the MI355X; give each XCD a contiguous run of
 // work items so that items sharing neighbour rings share an L2. Bijective on [0, n).
 __device__ __forceinline__ int xcd_remap(int b, int n) {

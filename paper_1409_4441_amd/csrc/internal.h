@@ -46,6 +46,9 @@ constexpr int kMaxChunks = 8;  // work-queue chunks (one per XCD)
 // step's inputs and every ring pair's set-up, but each block adds its weight registers to every
 // pipeline slot; two blocks exceed the register file at two waves per SIMD and were measured slower
 constexpr int kStoreBlocks = 1;
+// the per-pair kernel stages the table as cubic coefficients (4 doubles per segment, 64 KB of LDS)
+// up to this many segments, as nodes beyond
+constexpr int kCoefMaxSegs = 2048;
 
 // One cap-touching ring pair (output ring i, input ring j) as the mixed path's cap tiles read it:
 // one 64-byte record, fetched with a single scalar load per pair and tile.
@@ -147,6 +150,7 @@ struct conv_real_plan {
 
   // device arrays (plain path)
   double* d_table = nullptr;   // n_tab
+  double* d_coef64 = nullptr;  // (n_tab - 2) x 4: cubic coefficients per segment (null: n_tab > 2050)
   int* d_rn = nullptr;         // per ring
   int* d_rc = nullptr;
   long long* d_rstart = nullptr;

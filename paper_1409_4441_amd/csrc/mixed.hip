@@ -56,15 +56,11 @@ constexpr int kFold = 4;   // ring pairs per FP32 -> FP64 fold
 constexpr int kNKMax = 4;  // largest K-chunk count of a belt weight block
 
 // ---------------------------------------------------------------- shared helpers
-// Load of a value that is the same in every lane and read-only for the kernel's lifetime (plan
-// tables written at set-up): through the constant address space, so that it becomes a scalar load
-// into SGPRs and the compiler treats the result as wave-uniform.
-template <typename T>
-__device__ __forceinline__ T ldu(const T& ref) {
-  return *(const __attribute__((address_space(4))) T*)(&ref);
-}
+using convreal::buffer_resource;
+using convreal::kNoLoad;
+using convreal::ldu;
 
-// the same for a record, word by word (the words merge into one wide scalar load)
+// ldu for a record, word by word (the words merge into one wide scalar load)
 template <typename T>
 __device__ __forceinline__ T ldu_record(const T& ref) {
   static_assert(sizeof(T) % 4 == 0, "records are whole 32-bit words");
@@ -210,9 +206,9 @@ struct BeltPrefetch {
   int len;     // window pixels
   int nwv;     // weight half8 of the ring (128 per K-chunk)
 
-  // Every thread issues the same PX + 2 loads whatever the window's length (elements past it read
-  // the window's last pixel or the first fragment and are not stored), so that the compiler can
-  // count the loads in flight and wait for the oldest ring only.
+  // Every thread issues the same PX + 2 buffer loads whatever the window's length (elements past it
+  // load nothing and are not stored), so that the compiler can count the loads in flight and wait
+  // for the oldest ring only.
   __device__ __forceinline__ void load(const float* __restrict__ xj, int start_px, int len_, int ring_n,
                                        const half8* __restrict__ wsrc, int nwv_) {
     len = len_;
@@ -610,21 +606,22 @@ struct CapLane {
 };
 
 // ---------------------------------------------------------------- cap weight store
-// Store tiles are kStoreBlocks blocks of 16 rows (one wave each). Layout, per store tile: two zero
-// groups, then per cap-touching ring pair (in list order), per block and per row of the block inside
-// the fundamental domain, the row's weights in groups of 4 inputs, group g covering inputs b0 + 4g ..
-// b0 + 4g + 3 of ring j (b0: start of the tile's union window), 16 bytes each: the 4 weights x s_w
-// rounded to FP16 (hi), then the FP16 residues (lo). A row keeps the groups that meet its window
-// [lo, hi], zeros inside them outside the window. Nothing about the layout is stored besides the
-// first group of every tile: the apply recomputes the same windows, and 16-lane prefix sums of the
-// rows' group counts give every lane its addresses. Lanes whose group is not stored read the tile's
-// first zero group, so every load is unconditional and lands in the register that the matrix cores
-// read later; addresses are 32-bit offsets from the tile's block and from the map. The blocks of a
-// tile share each step's inputs: loaded, reversed, scaled and split once.
+// Store tiles are kStoreBlocks blocks of 16 rows (one wave each). Layout, per store tile: per
+// cap-touching ring pair (in list order), per block and per row of the block inside the fundamental
+// domain, the row's weights in groups of 4 inputs, group g covering inputs b0 + 4g .. b0 + 4g + 3 of
+// ring j (b0: start of the tile's union window), 16 bytes each: the 4 weights x s_w rounded to FP16
+// (hi), then the FP16 residues (lo). A row keeps the groups that meet its window [lo, hi], zeros
+// inside them outside the window. Nothing about the layout is stored besides the first group of
+// every tile: the apply recomputes the same windows, and 16-lane prefix sums of the rows' group
+// counts give every lane its addresses. Weights are read through a buffer resource over the tile's
+// block: a lane whose group is not stored gives an offset past the resource's range, which the
+// hardware answers with zeros without a memory access, so every load instruction is issued
+// unconditionally (and lands in the register that the matrix cores read later) while only stored
+// groups move through the caches; addresses are 32-bit offsets from the tile's block and from the
+// map. The blocks of a tile share each step's inputs: loaded, reversed, scaled and split once.
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kTileZeroGroups = 2;
 constexpr int kStoreBlocks = convreal::kStoreBlocks;
 constexpr int kStoreRows = 16 * kStoreBlocks;
 
@@ -651,16 +648,15 @@ struct StoreStep {
   bool last;      // last step of its ring pair
 };
 
-// byte offset in the tile's block of group g of the lane's row of block b (the zero group if not
-// stored)
+// byte offset in the tile's block of group g of the lane's row of block b (kNoLoad if not stored)
 __device__ __forceinline__ unsigned group_offset(const StorePair& S, int b, int g) {
   return static_cast<unsigned>(g - S.glo[b]) < static_cast<unsigned>(S.gn[b])
              ? static_cast<unsigned>(S.rbase[b] + g) * 16u
-             : 0u;
+             : kNoLoad;
 }
 
-__device__ __forceinline__ u32x4 load_group(const unsigned char* __restrict__ tile, unsigned off) {
-  return *reinterpret_cast<const u32x4*>(tile + off);
+__device__ __forceinline__ u32x4 load_group(__amdgpu_buffer_rsrc_t tile, unsigned off) {
+  return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(tile, off, 0, 0));
 }
 
 // w_hi x_hi + w_lo x_hi + w_hi x_lo of one block on the step's split inputs
@@ -710,7 +706,7 @@ __device__ __forceinline__ void store_compute(CapAcc& A, const StoreStep& R, int
 
 // The tile's steps, ring pair after ring pair, as one sequence.
 struct StoreIter {
-  const unsigned char* tile;   // the tile's block
+  __amdgpu_buffer_rsrc_t tile;   // over the tile's block
   convreal::CapPair Pn;        // record kk, loaded one pair ahead of its use
   long long kk, k1;
   int pos;                     // next pair's first group, from the tile's block
@@ -782,8 +778,8 @@ struct StoreIter {
   }
 
   // Load the next step into R (R.live = false once the tile has no step left). Every call issues
-  // the same loads, an ended sequence reading the tile's zero group and the map's first pixels, so
-  // that the compiler can count the loads in flight and wait for the oldest only.
+  // the same loads, an ended sequence reading no weight (zeros) and the map's first pixels, so that
+  // the compiler can count the loads in flight and wait for the oldest only.
   __device__ __forceinline__ void next(const convreal::CapPair* __restrict__ cpair, const CapLane& L,
                                        const float* __restrict__ xm, float sx, CapAcc& A, StoreStep& R) {
     bool ok = true;
@@ -802,7 +798,7 @@ struct StoreIter {
     int blocks = 0;
     bool last = false;
 #pragma unroll
-    for (int b = 0; b < kStoreBlocks; ++b) oa[b] = ob[b] = 0;
+    for (int b = 0; b < kStoreBlocks; ++b) oa[b] = ob[b] = kNoLoad;
     if (ok) {
 #pragma unroll
       for (int b = 0; b < kStoreBlocks; ++b) {
@@ -841,10 +837,10 @@ __device__ __forceinline__ void cap_rows_store(const convreal::MixedDesc* __rest
                                                const float* __restrict__ xm, float sx,
                                                double (&accd)[kStoreBlocks][4]) {
   StoreIter it;
-  it.tile = reinterpret_cast<const unsigned char*>(ldu(d->wstore)) + 16 * ldu(ldu(d->wtile_off)[t]);
+  it.tile = buffer_resource(reinterpret_cast<const unsigned char*>(ldu(d->wstore)) + 16 * ldu(ldu(d->wtile_off)[t]));
   it.kk = ldu(ldu(d->rest_off)[L.r]);
   it.k1 = ldu(ldu(d->rest_off)[L.r + 1]);
-  it.pos = kTileZeroGroups;
+  it.pos = 0;
   it.q = 0;
   it.S.nk = 0;
   const convreal::CapPair* cpair = ldu(d->cpair);
@@ -1019,7 +1015,7 @@ __device__ __forceinline__ void cap_tile(const convreal::MixedDesc* __restrict__
 // ---------------------------------------------------------------- cap weight store (set-up)
 // One wave per store tile, the same tiles, ring pairs, union windows and row windows as the apply.
 // FILL = false: the number of 16-byte groups of each tile; FILL = true: the groups (long form, any
-// ring pair), tile t's block (its zero groups first) starting at group offsets[t].
+// ring pair), tile t's block starting at group offsets[t].
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::MixedDesc* __restrict__ d,
                                                            long long* __restrict__ offsets,
@@ -1044,8 +1040,7 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
   const long long k0 = ldu(rest_off[L.r]);
   const long long k1 = ldu(rest_off[L.r + 1]);
   u32x4* tile = FILL ? store + offsets[t] : nullptr;
-  if (FILL && (threadIdx.x & 63) < kTileZeroGroups) tile[threadIdx.x & 63] = u32x4{0u, 0u, 0u, 0u};
-  int pos = kTileZeroGroups;
+  int pos = 0;
   for (long long kk = k0; kk < k1; ++kk) {
     const convreal::CapPair P = ldu_record(cpair[kk]);
     int b0, bend;

@@ -2,14 +2,24 @@
 //
 //   y_p = Omega * sum_{q : d_pq <= d_cut} Ktilde(d_pq) x_q
 //
-// One thread per output pixel a of ring i; a workgroup owns a tile of up to 256 consecutive pixels
-// of one ring, and the kernel table sits in LDS. For each listed neighbour ring j (from the
-// ring_window pass) the thread walks the candidate pixels b of its azimuthal window. The
-// half-angle alpha = (phi_a - phi_b) / 2 = (pi / 2) * num / (n_i n_j) has the exact integer
-// numerator num = (2a + c_i) n_j - (2b + c_j) n_i; sin(alpha) is seeded from that numerator and
-// advanced by the rotation alpha -> alpha - pi / n_j from one pixel to the next (re-seeded every
-// 64 steps). The chord is d^2 = A_ij + B_ij sin^2(alpha); pairs with d^2 <= d_cut^2 are
-// interpolated from the table and accumulated in FP64.
+// One thread per output pixel a of ring i; 256 threads own a tile of up to 256 consecutive pixels
+// of one ring. For each listed neighbour ring j (from the ring_window pass) the thread walks the
+// candidate pixels b of its azimuthal window. The half-angle alpha = (phi_a - phi_b) / 2 =
+// (pi / 2) * num / (n_i n_j) has the exact integer numerator num = (2a + c_i) n_j - (2b + c_j) n_i;
+// sin(alpha) is seeded from that numerator and advanced by the rotation alpha -> alpha - pi / n_j
+// from one pixel to the next (re-seeded every 64 steps). The chord is d^2 = A_ij + B_ij sin^2(alpha);
+// pairs with d^2 <= d_cut^2 are interpolated from the table and accumulated in FP64.
+//
+// The accumulate kernel is persistent: a workgroup of kGroups x 256 threads stages the kernel table
+// in LDS once and its groups of 256 threads take tiles in turn. The table is staged as the
+// per-segment coefficients of the interpolating cubic (4 doubles per segment, evaluated in Horner
+// form) when they fit in 64 KB, else as the nodes themselves (4-point Lagrange weights per pair).
+// t = d / h comes from the hardware reciprocal square root of (d / h)^2 refined by two Newton
+// steps. The ring-pair tables are read with scalar loads (one tile = one ring, so every lane of a
+// wave reads the same entries), and the azimuth numerator is reduced in exact FP64 arithmetic rather
+// than by 64-bit integer division. Inputs are read straight from the map (neighbouring lanes read
+// neighbouring pixels of ring j, through the L1): the loop is bound by its FP64 arithmetic, about 32
+// vector instructions per pair, and staging the windows in LDS would add work without removing any.
 //
 // The same loop serves two callers:
 //   * the plain path (CONV_REAL_F64 / F32): every ring pair of every output ring, stored;
@@ -23,9 +33,11 @@
 namespace {
 
 constexpr int kTile = 256;
+constexpr int kGroups = 3;   // tiles in flight per workgroup of the accumulate kernel (two fit a CU)
 
 struct PairArgs {
   const double* table;
+  const double* coef;     // per segment c0..c3 of the cubic in f = t - k (nullptr: node form)
   const int* rn;
   const int* rc;
   const long long* rstart;
@@ -50,93 +62,191 @@ struct PairArgs {
   long long npix;
 };
 
-template <bool kCount, int kMaxMaps, typename T>
-__device__ __forceinline__ void pair_loop(const PairArgs& a, const double* __restrict__ s_tab, int r,
-                                          int ai, const T* __restrict__ x, int nm, double* acc,
-                                          unsigned long long* cnt) {
-  const int ni = a.rn[r];
-  const long long twoa_ci = 2LL * ai + a.rc[r];
-  const long long k0 = a.off[r];
-  const long long k1 = a.off[r + 1];
+// The candidate pixels b of neighbour ring j (ring pair k) for output pixel a of ring i: the window
+// [blo, blo + nb) in ring j's pixel indices (unwrapped, blo in (-n_j, n_j)), and the pair's chord
+// constants. Every table value is the same for all lanes of a tile (one ring i, one list of ring
+// pairs) and comes through scalar loads.
+struct RingWalk {
+  int blo;
+  int nb;
+  int nj;
+  int cj;
+  long long sj;   // first pixel of ring j in the map
+  double A, B;    // d^2 = A + B sin^2(alpha)
+  double cd, sd;  // cos and sin of pi / n_j (one step of alpha)
+};
+
+__device__ __forceinline__ bool ring_walk(const PairArgs& a, long long k, int ni, int twoa_ci, RingWalk& w) {
+  using convreal::ldu;
+  const int j = ldu(ldu(a.pj)[k]);
+  w.nj = ldu(ldu(a.rn)[j]);
+  w.cj = ldu(ldu(a.rc)[j]);
+  const double hw = ldu(ldu(a.phw)[k]);
+  // window centre in pixels of ring j: b_c = ((2a + c_i) n_j / n_i - c_j) / 2, in [-1/2, n_j)
+  const double bc2 = static_cast<double>(twoa_ci) * w.nj - static_cast<double>(w.cj) * ni;   // exact
+  const double bc = bc2 / (2.0 * ni);
+  int nb;
+  if (2.0 * hw >= static_cast<double>(w.nj)) {
+    w.blo = static_cast<int>(floor(bc)) - w.nj / 2;
+    nb = w.nj;
+  } else {
+    w.blo = static_cast<int>(ceil(bc - hw - 1e-7));
+    nb = static_cast<int>(floor(bc + hw + 1e-7)) - w.blo + 1;
+    if (nb > w.nj) nb = w.nj;
+  }
+  if (nb <= 0) return false;
+  w.nb = nb;
+  w.A = ldu(ldu(a.pA)[k]);
+  w.B = ldu(ldu(a.pB)[k]);
+  w.sj = ldu(ldu(a.rstart)[j]);
+  w.cd = ldu(ldu(a.rcd)[j]);
+  w.sd = ldu(ldu(a.rsd)[j]);
+  return true;
+}
+
+// sin and cos of alpha = (pi / 2) num / (n_i n_j) at window step t, from the exact numerator
+// num = (2a + c_i) n_j - (2b + c_j) n_i, reduced modulo 2 n_i n_j (a shift of alpha by a multiple of
+// pi, which leaves sin^2 alpha and the rotation unchanged). Every integer here is below 2^53, so the
+// products, the difference and the fused reduction are exact in FP64.
+__device__ __forceinline__ void seed_alpha(const RingWalk& w, int twoa_ci, int ni, int t, double& sa, double& ca) {
+  const double num = static_cast<double>(twoa_ci) * w.nj - static_cast<double>(2 * (w.blo + t) + w.cj) * ni;
+  const double m2 = 2.0 * static_cast<double>(ni) * static_cast<double>(w.nj);
+  const double r = fma(-rint(num / m2), m2, num);
+  sincospi(r / m2, &sa, &ca);
+}
+
+// first window pixel as an index into ring j
+__device__ __forceinline__ int first_index(const RingWalk& w) { return w.blo < 0 ? w.blo + w.nj : w.blo; }
+
+// number of pairs with d^2 <= d_cut^2 of output pixel ai of ring r (alpha advanced by rotation,
+// re-seeded every 64 steps)
+__device__ __forceinline__ unsigned long long count_pixel(const PairArgs& a, int r, int ai) {
+  using convreal::ldu;
+  const int ni = ldu(ldu(a.rn)[r]);
+  const int twoa_ci = 2 * ai + ldu(ldu(a.rc)[r]);
+  const long long k0 = ldu(ldu(a.off)[r]), k1 = ldu(ldu(a.off)[r + 1]);
+  const long long* idx = ldu(a.idx);
+  unsigned long long cnt = 0;
   for (long long kk = k0; kk < k1; ++kk) {
-    const long long k = a.idx ? a.idx[kk] : kk;
-    const int j = a.pj[k];
-    const int nj = a.rn[j];
-    const long long cj = a.rc[j];
-    const long long sj = a.rstart[j];
-    const double A = a.pA[k];
-    const double B = a.pB[k];
-    const double hw = a.phw[k];
-    // window centre in pixels of ring j: b_c = ((2a + c_i) n_j / n_i - c_j) / 2
-    const long long bc2 = twoa_ci * nj - cj * ni;
-    const double bc = static_cast<double>(bc2) / (2.0 * ni);
-    long long blo, nb;
-    if (2.0 * hw >= static_cast<double>(nj)) {
-      blo = static_cast<long long>(floor(bc)) - nj / 2;
-      nb = nj;
-    } else {
-      blo = static_cast<long long>(ceil(bc - hw - 1e-7));
-      const long long bhi = static_cast<long long>(floor(bc + hw + 1e-7));
-      nb = bhi - blo + 1;
-      if (nb > nj) nb = nj;
-    }
-    if (nb <= 0) continue;
-    const long long M = static_cast<long long>(ni) * nj;
-    const double cd = a.rcd[j];
-    const double sd = a.rsd[j];
-    int bm = static_cast<int>(((blo % nj) + nj) % nj);
+    RingWalk w;
+    if (!ring_walk(a, idx ? ldu(idx[kk]) : kk, ni, twoa_ci, w)) continue;
     double sa = 0.0, ca = 1.0;
-    for (long long t = 0; t < nb; ++t) {
-      if ((t & 63) == 0) {
-        long long num = twoa_ci * nj - (2 * (blo + t) + cj) * ni;
-        const long long m2 = 2 * M;
-        num %= m2;
-        if (num > M) num -= m2;
-        else if (num <= -M) num += m2;
-        sincos(static_cast<double>(num) * (M_PI / 2.0) / static_cast<double>(M), &sa, &ca);
-      }
-      const double d2 = fma(B, sa * sa, A);
-      if (d2 <= a.dcut2) {
-        if constexpr (kCount) {
-          *cnt += 1;
-        } else {
-          const double kt = convreal::interp_f64(s_tab, a.n_tab, sqrt(d2), a.inv_h);
-          const T* xp = x + sj + bm;
-#pragma unroll
-          for (int m = 0; m < kMaxMaps; ++m)
-            if (m < nm) acc[m] = fma(kt, static_cast<double>(xp[m * a.npix]), acc[m]);
-        }
-      }
-      const double sa2 = sa * cd - ca * sd;
-      ca = ca * cd + sa * sd;
+    for (int t = 0; t < w.nb; ++t) {
+      if ((t & 63) == 0) seed_alpha(w, twoa_ci, ni, t, sa, ca);
+      if (fma(w.B, sa * sa, w.A) <= a.dcut2) ++cnt;
+      const double sa2 = sa * w.cd - ca * w.sd;
+      ca = ca * w.cd + sa * w.sd;
       sa = sa2;
-      if (++bm == nj) bm = 0;
+    }
+  }
+  return cnt;
+}
+
+// t = sqrt(q) for q > 0: hardware reciprocal square root refined by two Newton steps on t^2 = q
+__device__ __forceinline__ double sqrt_refined(double q) {
+  const double y = __builtin_amdgcn_rsq(q);
+  const double hy = 0.5 * y;
+  double t = q * y;
+  t = fma(fma(-t, t, q), hy, t);
+  return fma(fma(-t, t, q), hy, t);
+}
+
+// (d / h)^2 plus the smallest normal, so that the pixel itself (d = 0) gets t ~ 1e-154 (segment 0,
+// the value at d = 0) and every other pair its own value: q is at least ~1e-30 there, far above the
+// addend
+__device__ __forceinline__ double scaled_q(double d2, double ih2) { return fma(d2, ih2, 2.2250738585072014e-308); }
+
+// Ktilde at t = d / h, t in [0, n_tab - 3] (clamped there otherwise)
+template <bool kCoef>
+__device__ __forceinline__ double table_value(const double* __restrict__ s_tab, int n_tab, double t) {
+  // f = t - k: t never exceeds n_tab - 3 (+ rounding) for a pair inside the cut; the clamp only keeps
+  // other lanes' reads inside the table
+  const int k = min(static_cast<int>(t), n_tab - 3);
+  const double f = __builtin_amdgcn_fract(t);
+  if constexpr (kCoef) {
+    const double4 c = reinterpret_cast<const double4*>(s_tab)[k];
+    return fma(fma(fma(c.w, f, c.z), f, c.y), f, c.x);
+  } else {
+    const double tm1 = s_tab[k == 0 ? 1 : k - 1];
+    const double t0 = s_tab[k];
+    const double t1 = s_tab[k + 1];
+    const double t2 = s_tab[k + 2];
+    const double fm1 = f - 1.0;
+    const double fm2 = f - 2.0;
+    const double fp1 = f + 1.0;
+    const double ff1 = f * fm1;
+    const double g = fp1 * fm2;
+    const double wm1 = -(ff1 * fm2) * (1.0 / 6.0);
+    const double w2 = (fp1 * ff1) * (1.0 / 6.0);
+    const double w0 = (g * fm1) * 0.5;
+    const double w1 = -(g * f) * 0.5;
+    return wm1 * tm1 + w0 * t0 + w1 * t1 + w2 * t2;
+  }
+}
+
+// sum over the listed neighbour rings of output pixel ai of ring r: acc[m] += Ktilde(d) x_m(q), in
+// window order (alpha as in count_pixel)
+template <bool kCoef, int kMaxMaps, typename T>
+__device__ __forceinline__ void accumulate_pixel(const PairArgs& a, const double* __restrict__ s_tab, int r, int ai,
+                                                 const T* __restrict__ x, int nm, double* acc) {
+  using convreal::ldu;
+  const int ni = ldu(ldu(a.rn)[r]);
+  const int twoa_ci = 2 * ai + ldu(ldu(a.rc)[r]);
+  const long long k0 = ldu(ldu(a.off)[r]), k1 = ldu(ldu(a.off)[r + 1]);
+  const long long* idx = ldu(a.idx);
+  const double ih2 = a.inv_h * a.inv_h;
+  for (long long kk = k0; kk < k1; ++kk) {
+    RingWalk w;
+    if (!ring_walk(a, idx ? ldu(idx[kk]) : kk, ni, twoa_ci, w)) continue;
+    const T* xj = x + w.sj;
+    int bm = first_index(w);
+    double sa = 0.0, ca = 1.0;
+    for (int t = 0; t < w.nb; ++t) {
+      if ((t & 63) == 0) seed_alpha(w, twoa_ci, ni, t, sa, ca);
+      const double d2 = fma(w.B, sa * sa, w.A);
+      if (d2 <= a.dcut2) {
+        const double kt = table_value<kCoef>(s_tab, a.n_tab, sqrt_refined(scaled_q(d2, ih2)));
+#pragma unroll
+        for (int m = 0; m < kMaxMaps; ++m)
+          if (m < nm) acc[m] = fma(kt, static_cast<double>(xj[m * a.npix + bm]), acc[m]);
+      }
+      const double sa2 = sa * w.cd - ca * w.sd;
+      ca = ca * w.cd + sa * w.sd;
+      sa = sa2;
+      if (++bm == w.nj) bm = 0;
     }
   }
 }
 
-template <int kMaxMaps, typename T>
-__global__ __launch_bounds__(kTile) void pair_accumulate_kernel(PairArgs a, const T* __restrict__ x,
-                                                                T* __restrict__ y, int nm) {
+template <bool kCoef, int kMaxMaps, typename T>
+__global__ __launch_bounds__(kTile * kGroups) void pair_accumulate_kernel(PairArgs a, const T* __restrict__ x,
+                                                                          T* __restrict__ y, int nm) {
   extern __shared__ double s_tab[];
-  const int tile = convreal::xcd_remap(blockIdx.x, a.ntiles);
-  for (int k = threadIdx.x; k < a.n_tab; k += blockDim.x) s_tab[k] = a.table[k];
+  const int nwords = kCoef ? 4 * (a.n_tab - 2) : a.n_tab;
+  const double* src = kCoef ? a.coef : a.table;
+  for (int k = threadIdx.x; k < nwords; k += blockDim.x) s_tab[k] = src[k];
   __syncthreads();
-  const int r = a.tile_ring[tile];
-  const int ai = a.tile_a0[tile] + threadIdx.x;
-  if (ai >= a.rn[r]) return;
-  double acc[kMaxMaps];
+  using convreal::ldu;
+  // the group (and so its tile, ring and ring-pair list) is the same in every lane of a wave
+  const int grp = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kTile);
+  const int lane = static_cast<int>(threadIdx.x) % kTile;
+  for (int tile = blockIdx.x * kGroups + grp; tile < a.ntiles; tile += gridDim.x * kGroups) {
+    const int r = ldu(ldu(a.tile_ring)[tile]);
+    const int ai = ldu(ldu(a.tile_a0)[tile]) + lane;
+    if (ai >= ldu(ldu(a.rn)[r])) continue;
+    double acc[kMaxMaps];
 #pragma unroll
-  for (int m = 0; m < kMaxMaps; ++m) acc[m] = 0.0;
-  pair_loop<false, kMaxMaps, T>(a, s_tab, r, ai, x, nm, acc, nullptr);
-  const long long out = a.rstart[r] + ai;
-  const bool add = a.accumulate_belt && r >= a.belt_lo && r <= a.belt_hi;
+    for (int m = 0; m < kMaxMaps; ++m) acc[m] = 0.0;
+    accumulate_pixel<kCoef, kMaxMaps, T>(a, s_tab, r, ai, x, nm, acc);
+    const long long out = a.rstart[r] + ai;
+    const bool add = a.accumulate_belt && r >= a.belt_lo && r <= a.belt_hi;
 #pragma unroll
-  for (int m = 0; m < kMaxMaps; ++m) {
-    if (m < nm) {
-      T* yp = y + m * a.npix + out;
-      const double v = a.omega * acc[m];
-      *yp = add ? static_cast<T>(static_cast<double>(*yp) + v) : static_cast<T>(v);
+    for (int m = 0; m < kMaxMaps; ++m) {
+      if (m < nm) {
+        T* yp = y + m * a.npix + out;
+        const double v = a.omega * acc[m];
+        *yp = add ? static_cast<T>(static_cast<double>(*yp) + v) : static_cast<T>(v);
+      }
     }
   }
 }
@@ -144,11 +254,12 @@ __global__ __launch_bounds__(kTile) void pair_accumulate_kernel(PairArgs a, cons
 __global__ __launch_bounds__(kTile) void pair_count_kernel(PairArgs a,
                                                            unsigned long long* __restrict__ total) {
   __shared__ unsigned long long s_red[kTile];
+  using convreal::ldu;
   const int tile = convreal::xcd_remap(blockIdx.x, a.ntiles);
-  const int r = a.tile_ring[tile];
-  const int ai = a.tile_a0[tile] + threadIdx.x;
+  const int r = ldu(ldu(a.tile_ring)[tile]);
+  const int ai = ldu(ldu(a.tile_a0)[tile]) + static_cast<int>(threadIdx.x);
   unsigned long long cnt = 0;
-  if (ai < a.rn[r]) pair_loop<true, 1, float>(a, nullptr, r, ai, nullptr, 0, nullptr, &cnt);
+  if (ai < ldu(ldu(a.rn)[r])) cnt = count_pixel(a, r, ai);
   s_red[threadIdx.x] = cnt;
   __syncthreads();
   for (int w = kTile / 2; w > 0; w >>= 1) {
@@ -161,6 +272,7 @@ __global__ __launch_bounds__(kTile) void pair_count_kernel(PairArgs a,
 PairArgs make_args(const conv_real_plan* p, bool remainder) {
   PairArgs a;
   a.table = p->d_table;
+  a.coef = p->d_coef64;
   a.rn = p->d_rn;
   a.rc = p->d_rc;
   a.rstart = p->d_rstart;
@@ -195,20 +307,43 @@ PairArgs make_args(const conv_real_plan* p, bool remainder) {
   return a;
 }
 
+// One launch of the accumulate kernel over up to kMaxMaps maps: as many workgroups as can be
+// resident at once (each stages the table once), at most one per kGroups tiles.
+template <bool kCoef, int kMaxMaps, typename T>
+hipError_t launch_accumulate(const PairArgs& a, const T* x, T* y, int nm, size_t lds, hipStream_t st) {
+  const auto kern = pair_accumulate_kernel<kCoef, kMaxMaps, T>;
+  int dev = 0, ncu = 256, per = 1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kTile * kGroups, lds)) != hipSuccess) return e;
+  if (per < 1) per = 1;
+  const long long want = (static_cast<long long>(a.ntiles) + kGroups - 1) / kGroups;
+  const long long grid = want < static_cast<long long>(ncu) * per ? want : static_cast<long long>(ncu) * per;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(kTile * kGroups), lds, st, a, x, y, nm);
+  return hipGetLastError();
+}
+
 template <typename T>
-hipError_t launch_loop(const conv_real_plan* p, const PairArgs& a, const T* x, T* y, int nmaps,
-                       size_t lds, hipStream_t st, const char* name, long long pairs_per_map) {
+hipError_t launch_loop(const conv_real_plan* p, const PairArgs& a, const T* x, T* y, int nmaps, hipStream_t st,
+                       const char* name, long long pairs_per_map) {
   constexpr int kChunk = 4;
   if (a.ntiles == 0) return hipSuccess;
+  // the coefficient form when the plan holds it (n_tab - 2 <= kCoefMaxSegs), else the nodes
+  const bool coef = a.coef != nullptr;
+  const size_t lds = coef ? sizeof(double) * 4 * static_cast<size_t>(a.n_tab - 2)
+                          : sizeof(double) * static_cast<size_t>(a.n_tab);
   for (int m0 = 0; m0 < nmaps; m0 += kChunk) {
     const int nm = nmaps - m0 < kChunk ? nmaps - m0 : kChunk;
     const T* xi = x + static_cast<size_t>(m0) * p->npix;
     T* yo = y + static_cast<size_t>(m0) * p->npix;
-    if (nm == 1)
-      hipLaunchKernelGGL((pair_accumulate_kernel<1, T>), dim3(a.ntiles), dim3(kTile), lds, st, a, xi, yo, nm);
+    hipError_t e;
+    if (coef)
+      e = nm == 1 ? launch_accumulate<true, 1, T>(a, xi, yo, nm, lds, st)
+                  : launch_accumulate<true, kChunk, T>(a, xi, yo, nm, lds, st);
     else
-      hipLaunchKernelGGL((pair_accumulate_kernel<kChunk, T>), dim3(a.ntiles), dim3(kTile), lds, st, a, xi, yo, nm);
-    hipError_t e = hipGetLastError();
+      e = nm == 1 ? launch_accumulate<false, 1, T>(a, xi, yo, nm, lds, st)
+                  : launch_accumulate<false, kChunk, T>(a, xi, yo, nm, lds, st);
     if (e != hipSuccess) return e;
     convreal::mark(p, st, name, pairs_per_map * nm);
   }
@@ -229,20 +364,17 @@ hipError_t launch_pair_count(const conv_real_plan* p, bool remainder, hipStream_
 hipError_t launch_pair_accumulate(const conv_real_plan* p, const void* x, void* y, int nmaps,
                                   hipStream_t st) {
   const PairArgs a = make_args(p, false);
-  const size_t lds = sizeof(double) * static_cast<size_t>(p->n_tab);
   if (p->precision == CONV_REAL_F64)
-    return launch_loop(p, a, static_cast<const double*>(x), static_cast<double*>(y), nmaps, lds, st,
+    return launch_loop(p, a, static_cast<const double*>(x), static_cast<double*>(y), nmaps, st,
                        "pair_accumulate_kernel<double>", p->pairs);
-  return launch_loop(p, a, static_cast<const float*>(x), static_cast<float*>(y), nmaps, lds, st,
+  return launch_loop(p, a, static_cast<const float*>(x), static_cast<float*>(y), nmaps, st,
                      "pair_accumulate_kernel<float>", p->pairs);
 }
 
 hipError_t launch_remainder(const conv_real_plan* p, const float* x, float* y, int nmaps,
                             hipStream_t st) {
   const PairArgs a = make_args(p, true);
-  const size_t lds = sizeof(double) * static_cast<size_t>(p->n_tab);
-  return launch_loop(p, a, x, y, nmaps, lds, st, "pair_accumulate_kernel<float> (cap pairs)",
-                     p->pairs_rest);
+  return launch_loop(p, a, x, y, nmaps, st, "pair_accumulate_kernel<float> (cap pairs)", p->pairs_rest);
 }
 
 }  // namespace convreal
