@@ -94,7 +94,7 @@ def kernel_table(plan, x, y, reps, stream):
 
 
 TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "traffic_mixed_persistent_resid2048.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_4441_amd", "csrc", f) for f in ("mixed.hip", "internal.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_4441_amd", "csrc", f) for f in ("mixed.hip", "internal.h", "common.h")]
 
 
 def kernel_source_hash() -> str:
