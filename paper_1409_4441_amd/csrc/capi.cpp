@@ -250,6 +250,15 @@ std::vector<int> order_queue(const std::vector<E>& belt_in, const std::vector<E>
   return std::vector<int>{0, static_cast<int>(out.size())};
 }
 
+// The kernel maps every counter value of chunk c to an item of chunk_off[c] .. chunk_off[c+1] - 1
+// and reads that item and its map slot, so the offsets must cover exactly the uploaded items.
+bool queue_ok(const std::vector<int>& off, size_t n_items) {
+  if (off.size() < 2 || off.size() - 1 > static_cast<size_t>(convreal::kMaxChunks) || off.front() != 0) return false;
+  for (size_t c = 1; c < off.size(); ++c)
+    if (off[c] < off[c - 1]) return false;
+  return static_cast<size_t>(off.back()) == n_items;
+}
+
 void release(conv_real_plan* p, void* ptr) {
   if (!ptr) return;
   for (auto it = p->owned.begin(); it != p->owned.end(); ++it)
@@ -267,6 +276,7 @@ hipError_t build_items(conv_real_plan* p) {
                                            [](const QueueItem& e) { return e.kind; }, q);
   std::vector<int2> items(q.size());
   for (size_t k = 0; k < q.size(); ++k) items[k] = make_int2(0, (q[k].kind << 30) | q[k].idx);
+  if (!queue_ok(off, items.size())) return hipErrorInvalidValue;
   release(p, p->d_items);
   release(p, p->d_qchunk_off);
   p->d_items = nullptr;
@@ -987,6 +997,7 @@ hipError_t build_batch_items(conv_real_batch* b) {
   std::vector<int2> items(ordered.size());
   for (size_t k = 0; k < ordered.size(); ++k)
     items[k] = make_int2(ordered[k].second, (ordered[k].first.kind << 30) | ordered[k].first.idx);
+  if (!queue_ok(off, items.size())) return hipErrorInvalidValue;
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_qchunk_off) (void)hipFree(b->d_qchunk_off);
   b->d_items = nullptr;
