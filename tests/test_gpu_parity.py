@@ -83,6 +83,23 @@ def test_f64_small_grids_all_cuts(cuda_device, nside, tc_deg):
     assert oc.rel_rms(y, ref) <= 1e-12
 
 
+@pytest.mark.parametrize("n_tab", [2050, 2051, 6000])
+def test_f64_table_forms(cuda_device, n_tab):
+    """The per-pair kernel stages the table as per-segment cubic coefficients up to 2048 segments
+    (n_tab = 2050 fills 64 KB of LDS exactly) and as nodes with per-pair Lagrange weights beyond;
+    both meet the oracle, on three maps at once (the four-map launch with one map slot unused)."""
+    nside, sigma = 16, 4.0 * DEG
+    tc = 4 * sigma
+    T = _gauss_table(sigma, tc, n_tab=n_tab, lmax=128)
+    x = synth.white_noise(nside, 3, seed=n_tab)
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        y = _run(plan, x)
+    ref = oc.convolve_sampled(nside, T, tc, x, np.arange(x.shape[1]))
+    for m in range(3):
+        assert oc.rel_rms(y[m], ref[m]) <= 1e-12, (n_tab, m)
+        assert np.max(np.abs(y[m] - ref[m])) <= 1e-12 * np.max(np.abs(ref[m]))
+
+
 def test_per_pixel_counts(cuda_device):
     """With K = 1, y_p / Omega is the number of neighbours of p (exact in FP64)."""
     nside, tc = 16, 0.3
