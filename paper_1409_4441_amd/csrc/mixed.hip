@@ -1081,15 +1081,18 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
 // least two, so that belt and cap items share a SIMD; three where the LDS allows it (256-pixel belt
 // items and no coefficient table), at the price of a few spilled registers
 // The queue is split into n_chunks chunks of items (chunk c: items chunk_off[c] .. chunk_off[c+1]
-// - 1, each for nrep maps), one counter each. A workgroup takes items from chunk blockIdx.x % n_chunks
-// first (workgroups are spread over the XCDs in turn, so with one chunk per XCD the items of a chunk
-// share one L2) and then from the others, until every chunk is empty.
+// - 1, each for nrep maps), one counter each. A workgroup takes items from its home chunk
+// (blockIdx.x / home_div) % n_chunks first and then from the others, until every chunk is empty.
+// home_div = 1 with one chunk per XCD: workgroups are spread over the XCDs in turn, so the items of
+// a chunk share one L2. home_div = number of CUs with a belt chunk and two cap chunks: the first
+// workgroups fill one slot on every CU, so each CU starts with one workgroup on belt items (matrix
+// cores, LDS) beside two on cap items (the vector memory path).
 template <int SEG, bool FLY, int WAVES>
 __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convreal::Slots S,
                                                                   const int2* __restrict__ items,
                                                                   int n_items, int nrep,
                                                                   const int* __restrict__ chunk_off,
-                                                                  int n_chunks,
+                                                                  int n_chunks, int home_div,
                                                                   const unsigned* __restrict__ amax,
                                                                   unsigned* __restrict__ counter,
                                                                   int coef_offset_bytes) {
@@ -1099,7 +1102,7 @@ __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convrea
   _Float16* stage = reinterpret_cast<_Float16*>(lds);
   float4* s_coef = reinterpret_cast<float4*>(lds + coef_offset_bytes);
   if (threadIdx.x == 0) s_coef_owner = nullptr;
-  const int home = static_cast<int>(blockIdx.x % static_cast<unsigned>(n_chunks));
+  const int home = static_cast<int>((blockIdx.x / static_cast<unsigned>(home_div)) % static_cast<unsigned>(n_chunks));
   unsigned empty = 0u;   // chunks this workgroup found empty (thread 0)
   for (;;) {
     if (threadIdx.x == 0) {
@@ -1219,17 +1222,20 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
     long long grid = static_cast<long long>(ncu) * (tune.wg_per_cu > 0 ? tune.wg_per_cu : 2);
     if (grid > total) grid = total;
     const dim3 g(static_cast<unsigned>(grid)), blk(kBlock);
+    // the role order hands out home chunks by workgroup slot on a CU (the first ncu workgroups fill
+    // one slot on every CU), the others by workgroup (workgroups go round the XCDs in turn)
+    const int home_div = tune.order == 3 ? ncu : 1;
     const int co = static_cast<int>(coef_off);
     if (tune.seg == 512 && fly)
-      hipLaunchKernelGGL((mixed_persistent_kernel<512, true, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<512, true, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);
     else if (tune.seg == 512)
-      hipLaunchKernelGGL((mixed_persistent_kernel<512, false, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<512, false, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);
     else if (fly)
-      hipLaunchKernelGGL((mixed_persistent_kernel<256, true, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, true, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);
     else if (tune.wg_per_cu >= 3)
-      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 3>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 3>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);
     else
-      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, amax, counter, co);
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, false, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     mark(mark_plan, st, "mixed_persistent_kernel", pairs);

@@ -56,7 +56,7 @@ def test_store_modes_match_oracle(cuda_device, nside, sigma_deg, cut_sigma, n_ta
     with cr.Plan(nside, T, tc, "mixed") as plan:
         active, nbytes = plan.weight_store()
         assert active and nbytes > 0                  # new plans take the automatic mode; small ones fit
-        assert plan.get_tuning() == {"seg": 256, "wg_per_cu": 3, "order": 1}   # the default with a store
+        assert plan.get_tuning() == {"seg": 256, "wg_per_cu": 3, "order": 3}   # the default with a store
         y_on = _apply(plan, x).clone()
         assert torch.equal(_apply(plan, x), y_on)     # deterministic
         plan.set_weight_store("off")
