@@ -98,11 +98,17 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1409_4441_amd", "csrc", f) for f in 
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 over the persistent kernel's sources with comments removed and whitespace runs folded
+    to one space, so that only a change of the code itself voids the committed traffic figure."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -206,9 +206,9 @@ struct BeltPrefetch {
   int len;     // window pixels
   int nwv;     // weight half8 of the ring (128 per K-chunk)
 
-  // Every thread issues the same PX + 2 buffer loads whatever the window's length (elements past it
-  // load nothing and are not stored), so that the compiler can count the loads in flight and wait
-  // for the oldest ring only.
+  // Every thread issues the same PX + 2 loads whatever the window's length (elements past it read
+  // the window's last pixel or the first fragment and are not stored), so that the compiler can
+  // count the loads in flight and wait for the oldest ring only.
   __device__ __forceinline__ void load(const float* __restrict__ xj, int start_px, int len_, int ring_n,
                                        const half8* __restrict__ wsrc, int nwv_) {
     len = len_;

@@ -34,6 +34,17 @@ def test_traffic_note_matches_sources_or_is_ignored(tmp_path, monkeypatch):
     assert bench.measured_traffic() is None
 
 
+def test_source_hash_follows_code_not_comments(tmp_path, monkeypatch):
+    src = tmp_path / "k.hip"
+    monkeypatch.setattr(bench, "KERNEL_SOURCES", [str(src)])
+    src.write_text("int f(int a) {  // doubles\n  return 2 * a; /* twice */ }\n")
+    h0 = bench.kernel_source_hash()
+    src.write_text("// a header comment\nint f(int a) {\n  /* the value, twice\n   over */\n  return 2 * a;  }\n")
+    assert bench.kernel_source_hash() == h0
+    src.write_text("int f(int a) { return 3 * a; }\n")
+    assert bench.kernel_source_hash() != h0
+
+
 def test_paper_context_is_eq7():
     # Eq. 7 at theta_cut = 30 arcmin: 0.0232 s x 30 + 2.428 s = 3.124 s per Nside 2048 map
     import math
