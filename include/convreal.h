@@ -194,6 +194,27 @@ int conv_real_set_weight_store(conv_real_plan* plan, int mode);
 int conv_real_get_weight_store(const conv_real_plan* plan, int* active, long long* bytes);
 
 /*
+ * Method of an FP64 plan (CONV_REAL_F64). The paper's real-space convolver costs time linear in
+ * theta_cut (Eq. 7; Results section), which a per-pair sum (quadratic) cannot match at the wide cuts
+ * its optimal splits choose (Table 1). For two rings of the equatorial belt (4 Nside pixels each)
+ * the pair sum is a circular convolution along the ring, so it can run in Fourier space:
+ *   CONV_REAL_METHOD_DIRECT    every pixel pair summed directly (the default)
+ *   CONV_REAL_METHOD_RING_FFT  belt ring pairs as a product per frequency of the input ring's
+ *                              spectrum and the pair's kernel spectrum (computed once here, FP64,
+ *                              (n/2 + 1) x 16 bytes per belt ring pair, n = 4 Nside), one inverse
+ *                              FFT per output ring; ring pairs touching a polar cap summed per
+ *                              pair. Same pairs and kernel values as DIRECT; results differ by FP64
+ *                              rounding only. Requires a power-of-two nside <= 2048 (EINVAL
+ *                              otherwise) and a device that can hold the spectra (ENOMEM).
+ * Synchronous and allocating (not while an apply on the plan may run); conv_real_apply then uses the
+ * method, one map at a time for the belt part. FP64 plans only (EINVAL otherwise).
+ */
+#define CONV_REAL_METHOD_DIRECT   0
+#define CONV_REAL_METHOD_RING_FFT 1
+int conv_real_set_method(conv_real_plan* plan, int method);
+int conv_real_get_method(const conv_real_plan* plan, int* method);
+
+/*
  * conv_real_autotune - time every launch configuration on the caller's maps (each configuration
  * once warm, then three timed applies with HIP events on `stream`), keep the fastest on the plan
  * and return it in *best. Same map arguments as conv_real_apply; maps_out is overwritten.

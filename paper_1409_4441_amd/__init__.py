@@ -26,6 +26,7 @@ MIXED = 2
 _PRECISIONS = {"f64": F64, "f32": F32, "mixed": MIXED}
 
 _STORE_MODES = {"off": 0, "on": 1, "auto": 2}
+_METHODS = {"direct": 0, "ring_fft": 1}
 
 OK = 0
 EINVAL = -1
@@ -40,7 +41,8 @@ EXPORTS = ("conv_real_tabulate", "conv_real_init", "conv_real_apply", "conv_real
            "conv_real_batch_create", "conv_real_batch_apply", "conv_real_batch_set_tuning",
            "conv_real_batch_autotune", "conv_real_batch_pairs", "conv_real_batch_destroy",
            "conv_real_destroy", "conv_real_strerror", "conv_real_last_error",
-           "conv_real_set_weight_store", "conv_real_get_weight_store")
+           "conv_real_set_weight_store", "conv_real_get_weight_store", "conv_real_set_method",
+           "conv_real_get_method")
 
 
 class Tuning(ctypes.Structure):
@@ -104,6 +106,10 @@ def _load():
     lib.conv_real_set_weight_store.restype = c_int
     lib.conv_real_get_weight_store.argtypes = [c_void_p, ctypes.POINTER(c_int), ctypes.POINTER(ctypes.c_longlong)]
     lib.conv_real_get_weight_store.restype = c_int
+    lib.conv_real_set_method.argtypes = [c_void_p, c_int]
+    lib.conv_real_set_method.restype = c_int
+    lib.conv_real_get_method.argtypes = [c_void_p, ctypes.POINTER(c_int)]
+    lib.conv_real_get_method.restype = c_int
     lib.conv_real_destroy.argtypes = [c_void_p]
     lib.conv_real_destroy.restype = c_int
     lib.conv_real_strerror.argtypes = [c_int]
@@ -179,6 +185,15 @@ class Plan:
         _check(lib.conv_real_get_weight_store(self._h, ctypes.byref(a), ctypes.byref(b)),
                "conv_real_get_weight_store")
         return bool(a.value), int(b.value)
+
+    def set_method(self, method: str):
+        """"direct" or "ring_fft" (FP64 plans): pair sums, or belt ring pairs through ring FFTs."""
+        _check(lib.conv_real_set_method(self._h, _METHODS.get(method, -1)), "conv_real_set_method")
+
+    def method(self) -> str:
+        m = ctypes.c_int()
+        _check(lib.conv_real_get_method(self._h, ctypes.byref(m)), "conv_real_get_method")
+        return {v: k for k, v in _METHODS.items()}[m.value]
 
     def apply(self, x, out=None, stream=None):
         """y = A x. x: CUDA tensor [npix] or [nmaps, npix], contiguous, plan dtype."""

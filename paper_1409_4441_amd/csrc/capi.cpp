@@ -853,6 +853,143 @@ int conv_real_get_weight_store(const conv_real_plan* plan, int* active, long lon
   return CONV_REAL_OK;
 }
 
+namespace {
+
+void release_ring_fft(conv_real_plan* p) {
+  for (void* ptr : {static_cast<void*>(p->d_fft_tw), static_cast<void*>(p->d_fft_pi), static_cast<void*>(p->d_fft_pj),
+                    static_cast<void*>(p->d_fft_pA), static_cast<void*>(p->d_fft_pB), static_cast<void*>(p->d_fft_boff),
+                    static_cast<void*>(p->d_fft_K), static_cast<void*>(p->d_fft_X)})
+    release(p, ptr);
+  p->d_fft_tw = nullptr;
+  p->d_fft_pi = p->d_fft_pj = nullptr;
+  p->d_fft_pA = p->d_fft_pB = nullptr;
+  p->d_fft_boff = nullptr;
+  p->d_fft_K = p->d_fft_X = nullptr;
+  p->fft_npairs = 0;
+}
+
+// Ring-FFT set-up of an FP64 plan: the belt ring pairs (output ring major), the list of the other
+// ring pairs for the per-pair kernel, twiddles, workspace, and the spectra of the belt pairs' kernels.
+hipError_t build_ring_fft(conv_real_plan* p) {
+  const int N = p->nside;
+  const convreal::RingGrid g = convreal::make_ring_grid(N);
+  std::vector<int> jlo, jhi;
+  convreal::neighbour_rings(g, p->dcut2, jlo, jhi);
+  std::vector<long long> poff(g.nrings + 1, 0);
+  for (int r = 0; r < g.nrings; ++r) poff[r + 1] = poff[r] + (jhi[r] - jlo[r] + 1);
+  std::vector<double> pA(p->npairs_ring), pB(p->npairs_ring);
+  hipError_t e;
+  if ((e = hipMemcpy(pA.data(), p->d_pA, sizeof(double) * pA.size(), hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(pB.data(), p->d_pB, sizeof(double) * pB.size(), hipMemcpyDeviceToHost)) != hipSuccess)
+    return e;
+  const int blo = N - 1, bhi = 3 * N - 1;   // belt rings (0-based): 4 N pixels each
+  std::vector<int> fi, fj;
+  std::vector<double> fA, fB;
+  std::vector<long long> boff(1, 0);
+  for (int i = blo; i <= bhi; ++i) {
+    for (int j = std::max(jlo[i], blo); j <= std::min(jhi[i], bhi); ++j) {
+      const long long k = poff[i] + (j - jlo[i]);
+      fi.push_back(i);
+      fj.push_back(j);
+      fA.push_back(pA[k]);
+      fB.push_back(pB[k]);
+    }
+    boff.push_back(static_cast<long long>(fi.size()));
+  }
+  std::vector<long long> roff(g.nrings + 1, 0), ridx;
+  std::vector<int> rtile_ring, rtile_a0;
+  for (int r = 0; r < g.nrings; ++r) {
+    const bool belt_row = r >= blo && r <= bhi;
+    for (long long k = poff[r]; k < poff[r + 1]; ++k) {
+      const int j = jlo[r] + static_cast<int>(k - poff[r]);
+      if (!belt_row || j < blo || j > bhi) ridx.push_back(k);
+    }
+    roff[r + 1] = static_cast<long long>(ridx.size());
+    if (roff[r + 1] > roff[r])
+      for (int a0 = 0; a0 < g.n[r]; a0 += kTile) {
+        rtile_ring.push_back(r);
+        rtile_a0.push_back(a0);
+      }
+  }
+  const int n = 4 * N;
+  int logn = 0;
+  while ((1 << logn) < n) ++logn;
+  std::vector<double2> tw(static_cast<size_t>(n / 2));
+  for (int m = 0; m < n / 2; ++m) {
+    const double ang = 2.0 * M_PI * static_cast<double>(m) / static_cast<double>(n);
+    tw[m] = make_double2(std::cos(ang), -std::sin(ang));
+  }
+  const size_t nbins = static_cast<size_t>(n / 2 + 1);
+  p->belt_lo = blo;
+  p->belt_hi = bhi;
+  p->fft_n = n;
+  p->fft_logn = logn;
+  p->fft_npairs = static_cast<long long>(fi.size());
+  release(p, p->d_rest_off);
+  release(p, p->d_rest_idx);
+  release(p, p->d_rtile_ring);
+  release(p, p->d_rtile_a0);
+  p->n_rtiles = static_cast<int>(rtile_ring.size());
+  if ((e = dev_upload(p, &p->d_rest_off, roff)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rest_idx, ridx)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rtile_ring, rtile_ring)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_rtile_a0, rtile_a0)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_fft_tw, tw)) != hipSuccess || (e = dev_upload(p, &p->d_fft_pi, fi)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_fft_pj, fj)) != hipSuccess || (e = dev_upload(p, &p->d_fft_pA, fA)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_fft_pB, fB)) != hipSuccess || (e = dev_upload(p, &p->d_fft_boff, boff)) != hipSuccess ||
+      (e = dev_alloc(p, &p->d_fft_K, nbins * fi.size())) != hipSuccess ||
+      (e = dev_alloc(p, &p->d_fft_X, nbins * static_cast<size_t>(bhi - blo + 1))) != hipSuccess ||
+      (e = convreal::ring_fft_spectra(p)) != hipSuccess ||
+      (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
+      (e = convreal::launch_pair_count(p, true, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess)
+    return e;
+  unsigned long long cnt = 0;
+  if ((e = hipMemcpy(&cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost)) != hipSuccess) return e;
+  p->pairs_rest = static_cast<long long>(cnt);
+  return hipSuccess;
+}
+
+}  // namespace
+
+int conv_real_set_method(conv_real_plan* plan, int method) {
+  if (!plan || plan->magic != kMagic) { set_error("conv_real_set_method: invalid plan"); return CONV_REAL_EINVAL; }
+  if (plan->precision != CONV_REAL_F64) {
+    set_error("conv_real_set_method: FP64 plans only");
+    return CONV_REAL_EINVAL;
+  }
+  if (method != CONV_REAL_METHOD_DIRECT && method != CONV_REAL_METHOD_RING_FFT) {
+    set_error("conv_real_set_method: method must be CONV_REAL_METHOD_DIRECT or _RING_FFT");
+    return CONV_REAL_EINVAL;
+  }
+  const int N = plan->nside;
+  if (method == CONV_REAL_METHOD_RING_FFT && ((N & (N - 1)) != 0 || N > 2048)) {
+    set_error("conv_real_set_method: the ring FFTs need a power-of-two nside <= 2048");
+    return CONV_REAL_EINVAL;
+  }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_set_method: hipSetDevice");
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "conv_real_set_method: synchronise");
+  if (method == CONV_REAL_METHOD_DIRECT) {
+    release_ring_fft(plan);
+    plan->method = method;
+    return CONV_REAL_OK;
+  }
+  if (!plan->d_fft_K && (e = build_ring_fft(plan)) != hipSuccess) {
+    release_ring_fft(plan);
+    plan->method = CONV_REAL_METHOD_DIRECT;
+    return hip_fail(e, "conv_real_set_method: ring-FFT set-up");
+  }
+  plan->method = method;
+  return CONV_REAL_OK;
+}
+
+int conv_real_get_method(const conv_real_plan* plan, int* method) {
+  if (!plan || plan->magic != kMagic || !method) { set_error("conv_real_get_method: invalid argument"); return CONV_REAL_EINVAL; }
+  *method = plan->method;
+  return CONV_REAL_OK;
+}
+
 int conv_real_apply(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps, void* stream) {
   if (!plan || plan->magic != kMagic) { set_error("conv_real_apply: invalid plan"); return CONV_REAL_EINVAL; }
   if (!maps_in || !maps_out) { set_error("conv_real_apply: NULL map pointer"); return CONV_REAL_EINVAL; }
@@ -871,6 +1008,8 @@ int conv_real_apply(conv_real_plan* plan, const void* maps_in, void* maps_out, i
   if (plan->precision == CONV_REAL_MIXED)
     e = convreal::launch_mixed(plan, static_cast<const float*>(maps_in), static_cast<float*>(maps_out), nmaps,
                                static_cast<hipStream_t>(stream));
+  else if (plan->method == CONV_REAL_METHOD_RING_FFT)
+    e = convreal::launch_ring_fft(plan, maps_in, maps_out, nmaps, static_cast<hipStream_t>(stream));
   else
     e = convreal::launch_pair_accumulate(plan, maps_in, maps_out, nmaps, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "conv_real_apply: launch");

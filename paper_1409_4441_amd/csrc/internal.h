@@ -226,6 +226,20 @@ struct conv_real_plan {
   std::vector<double> cost_belt;   // per belt band: estimated cycles per 16-pixel column block
   std::vector<double> cost_cap;    // per cap work item (4 tiles): estimated cycles
 
+  // ring-FFT method (FP64 plans): belt ring pairs through per-ring FFTs, the rest per pair
+  int method = 0;              // CONV_REAL_METHOD_DIRECT or CONV_REAL_METHOD_RING_FFT
+  int fft_n = 0;               // belt ring length 4 Nside (a power of two)
+  int fft_logn = 0;
+  long long fft_npairs = 0;    // belt ring pairs (output ring, input ring), output-ring major
+  double2* d_fft_tw = nullptr; // n / 2 twiddles exp(-2 pi i m / n)
+  int* d_fft_pi = nullptr;     // per belt pair: output ring, input ring, chord constants
+  int* d_fft_pj = nullptr;
+  double* d_fft_pA = nullptr;
+  double* d_fft_pB = nullptr;
+  long long* d_fft_boff = nullptr;  // per belt output ring: first belt pair (nbelt + 1)
+  double2* d_fft_K = nullptr;  // per belt pair: n / 2 + 1 frequencies of k_ij
+  double2* d_fft_X = nullptr;  // per belt ring: n / 2 + 1 frequencies of one map's ring (workspace)
+
   convreal::Recorder* rec = nullptr;  // set only inside conv_real_profile
   std::vector<void*> owned;    // every device allocation, freed by destroy
 };
@@ -253,6 +267,10 @@ hipError_t launch_pair_accumulate(const conv_real_plan* p, const void* x, void* 
                                   hipStream_t st);
 hipError_t launch_remainder(const conv_real_plan* p, const float* x, float* y, int nmaps,
                             hipStream_t st);
+hipError_t launch_remainder_f64(const conv_real_plan* p, const double* x, double* y, int nmaps, hipStream_t st);
+// ring-FFT method: spectra of the belt pairs' kernels (set-up), and an apply of FP64 maps
+hipError_t ring_fft_spectra(const conv_real_plan* p);
+hipError_t launch_ring_fft(const conv_real_plan* p, const void* x, void* y, int nmaps, hipStream_t st);
 hipError_t build_belt_weights(conv_real_plan* p);
 size_t belt_stage_bytes(int seg);
 hipError_t set_lds_limits(int nseg);

@@ -371,6 +371,11 @@ hipError_t launch_pair_accumulate(const conv_real_plan* p, const void* x, void* 
                      "pair_accumulate_kernel<float>", p->pairs);
 }
 
+hipError_t launch_remainder_f64(const conv_real_plan* p, const double* x, double* y, int nmaps, hipStream_t st) {
+  const PairArgs a = make_args(p, true);
+  return launch_loop(p, a, x, y, nmaps, st, "pair_accumulate_kernel<double> (cap-touching pairs)", p->pairs_rest);
+}
+
 hipError_t launch_remainder(const conv_real_plan* p, const float* x, float* y, int nmaps,
                             hipStream_t st) {
   const PairArgs a = make_args(p, true);

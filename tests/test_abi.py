@@ -79,6 +79,9 @@ def test_apply_and_pairs_reject_bad_plan():
     n = ctypes.c_longlong()
     assert cr.lib.conv_real_pairs(None, ctypes.byref(n)) == cr.EINVAL
     assert cr.lib.conv_real_destroy(None) == cr.OK
+    m = ctypes.c_int()
+    assert cr.lib.conv_real_set_method(None, 1) == cr.EINVAL
+    assert cr.lib.conv_real_get_method(None, ctypes.byref(m)) == cr.EINVAL
 
 
 def test_tabulate_rejects_bad_arguments():
