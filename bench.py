@@ -7,6 +7,8 @@ inputs already in HBM. Prints ONE JSON line:
   value          pixel pairs per second of the timed path (exact pair count x maps / wall time)
   maps_per_s     maps per second
   plain_fp64     the plain FP64 per-pair kernel on the same map, timed beside it
+  ring_fft_fp64  the FP64 ring-FFT method (belt ring pairs in Fourier space, cap-touching pairs per
+                 pair) on the same map promoted to FP64, timed beside it
   roofline       the kernel that takes most of the step, timed with HIP events recorded between
                  the library's kernels on the stream they run on (conv_real_profile)
   cpu_baseline   the CPU oracle timed on a bounded sample of output pixels of the same workload
@@ -46,6 +48,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=400, help="output pixels the oracle sums")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-ringfft", action="store_true", help="skip the FP64 ring-FFT measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-map batched measurement")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--weight-store", default="auto", choices=["auto", "on", "off"],
@@ -327,6 +330,25 @@ def main():
                  "rel_rms_timed_path_vs_plain": diff,
                  "kernel": "pair_accumulate_kernel<float> (FP64 per pair)"}
 
+    ring_fft = None
+    if not args.no_ringfft and args.precision != "f64" and (w.nside & (w.nside - 1)) == 0 and w.nside <= 2048:
+        xd = x.double()
+        yd = torch.empty_like(xd)
+        with cr.Plan(w.nside, table, w.theta_cut, "f64") as pd:
+            t1 = time.perf_counter()
+            pd.set_method("ring_fft")
+            setup_s = time.perf_counter() - t1
+            wall_d, ms_d = time_applies(pd, xd, yd, args.plain_steps, 1, stream)
+            kern_d = kernel_table(pd, xd, yd, 1, stream)
+        diff_d = torch.sqrt(torch.sum((y.double() - yd) ** 2) / torch.sum(yd ** 2)).item()
+        ring_fft = {"ms_per_map": 1e3 * wall_d / (args.plain_steps * nmaps),
+                    "pixel_pairs_per_s": pairs_per_map * nmaps * args.plain_steps / wall_d,
+                    "maps_per_s": nmaps * args.plain_steps / wall_d, "setup_s": setup_s, "kernels": kern_d,
+                    "rel_rms_timed_path_vs_ring_fft": diff_d,
+                    "method": "FP64 maps: belt ring pairs as per-frequency products of ring spectra, "
+                              "cap-touching ring pairs per pair"}
+        del xd, yd
+
     if args.copy_probe:
         # one plain device-to-device copy of the map: a kernel of known traffic (read + write of
         # x.nbytes) whose HBM counters scale the counters of the library's kernels
@@ -363,6 +385,7 @@ def main():
         "kernels": kernels,
         "rel_rms_vs_oracle_sample": err,
         "plain_fp64": plain,
+        "ring_fft_fp64": ring_fft,
         "weight_store": store,
         "batched": bat,
         "roofline": roofline, "cpu_baseline": cpu,
