@@ -251,6 +251,94 @@ __global__ __launch_bounds__(kTile * kGroups) void pair_accumulate_kernel(PairAr
   }
 }
 
+// Ring pairs that touch a polar cap, over the fundamental domain of the pixelization's symmetry
+// group (quarter turns, the reflection phi -> -phi, the north/south mirror: 16 elements that map
+// every ring onto itself or its mirror and keep every chord): one thread per domain pixel a of a
+// north-half ring computes each weight Ktilde(d(a, b)) once (the same walk, membership test and
+// interpolation as accumulate_pixel) and applies it to the 16 images of input pixel b, which give
+// the 16 images of a. Images that coincide (pixels on a reflection axis, the equator ring's mirror)
+// are written once. Belt rings get y +=, cap rings y =. One FP64 map per launch.
+template <bool kCoef>
+__global__ __launch_bounds__(kTile) void cap_sym_kernel(PairArgs a, const double* __restrict__ x,
+                                                        double* __restrict__ y, int nrings) {
+  extern __shared__ double s_tab[];
+  const int nwords = kCoef ? 4 * (a.n_tab - 2) : a.n_tab;
+  const double* src = kCoef ? a.coef : a.table;
+  for (int k = threadIdx.x; k < nwords; k += blockDim.x) s_tab[k] = src[k];
+  __syncthreads();
+  using convreal::ldu;
+  const int tile = static_cast<int>(blockIdx.x);
+  const int r = ldu(ldu(a.tile_ring)[tile]);
+  const int ai = ldu(ldu(a.tile_a0)[tile]) + static_cast<int>(threadIdx.x);
+  const int ni = ldu(ldu(a.rn)[r]);
+  const int ci = ldu(ldu(a.rc)[r]);
+  const int F = (ni / 4 - ci) / 2 + 1;   // fundamental domain [0, F) of the ring
+  if (ai >= F) return;
+  const int twoa_ci = 2 * ai + ci;
+  const double ih2 = a.inv_h * a.inv_h;
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  const long long k0 = ldu(ldu(a.off)[r]), k1 = ldu(ldu(a.off)[r + 1]);
+  const long long* idx = ldu(a.idx);
+  for (long long kk = k0; kk < k1; ++kk) {
+    const long long k = idx ? ldu(idx[kk]) : kk;
+    RingWalk w;
+    if (!ring_walk(a, k, ni, twoa_ci, w)) continue;
+    const int j = ldu(ldu(a.pj)[k]);
+    const double* xj = x + w.sj;
+    const double* xm = x + ldu(ldu(a.rstart)[nrings - 1 - j]);   // mirror ring: same pixels
+    const int q4 = w.nj / 4;
+    int bm = first_index(w);
+    double sa = 0.0, ca = 1.0;
+    for (int t = 0; t < w.nb; ++t) {
+      if ((t & 63) == 0) seed_alpha(w, twoa_ci, ni, t, sa, ca);
+      const double d2 = fma(w.B, sa * sa, w.A);
+      if (d2 <= a.dcut2) {
+        const double kt = table_value<kCoef>(s_tab, a.n_tab, sqrt_refined(scaled_q(d2, ih2)));
+        const int bf = w.nj - bm - w.cj;   // reflected pixel, in [0, n_j]
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int i0 = bm + q * q4;
+          i0 = i0 >= w.nj ? i0 - w.nj : i0;
+          int i1 = bf + q * q4;
+          i1 = i1 >= w.nj ? i1 - w.nj : i1;
+          i1 = i1 >= w.nj ? i1 - w.nj : i1;
+          acc[q] = fma(kt, xj[i0], acc[q]);
+          acc[4 + q] = fma(kt, xj[i1], acc[4 + q]);
+          acc[8 + q] = fma(kt, xm[i0], acc[8 + q]);
+          acc[12 + q] = fma(kt, xm[i1], acc[12 + q]);
+        }
+      }
+      const double sa2 = sa * w.cd - ca * w.sd;
+      ca = ca * w.cd + sa * w.sd;
+      sa = sa2;
+      if (++bm == w.nj) bm = 0;
+    }
+  }
+  const int quarter = ni / 4;
+  const bool on_axis = (twoa_ci % quarter) == 0;   // the reflected images repeat the rotated ones
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int rr = h ? nrings - 1 - r : r;
+    if (h && rr == r) continue;
+    double* yr = y + ldu(ldu(a.rstart)[rr]);
+    const bool add = rr >= a.belt_lo && rr <= a.belt_hi;
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      if (f && on_axis) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int P = f ? (ni - ai - ci + q * quarter) : (ai + q * quarter);
+        P %= ni;
+        if (P < 0) P += ni;
+        const double v = a.omega * acc[8 * h + 4 * f + q];
+        yr[P] = add ? yr[P] + v : v;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kTile) void pair_count_kernel(PairArgs a,
                                                            unsigned long long* __restrict__ total) {
   __shared__ unsigned long long s_red[kTile];
@@ -374,6 +462,27 @@ hipError_t launch_pair_accumulate(const conv_real_plan* p, const void* x, void* 
 hipError_t launch_remainder_f64(const conv_real_plan* p, const double* x, double* y, int nmaps, hipStream_t st) {
   const PairArgs a = make_args(p, true);
   return launch_loop(p, a, x, y, nmaps, st, "pair_accumulate_kernel<double> (cap-touching pairs)", p->pairs_rest);
+}
+
+hipError_t launch_cap_sym_f64(const conv_real_plan* p, const double* x, double* y, int nmaps, hipStream_t st) {
+  PairArgs a = make_args(p, true);
+  a.tile_ring = p->d_stile_ring;
+  a.tile_a0 = p->d_stile_a0;
+  a.ntiles = p->n_stiles;
+  if (a.ntiles == 0) return hipSuccess;
+  const bool coef = a.coef != nullptr;
+  const size_t lds = coef ? sizeof(double) * 4 * static_cast<size_t>(a.n_tab - 2) : sizeof(double) * static_cast<size_t>(a.n_tab);
+  for (int m = 0; m < nmaps; ++m) {
+    const size_t off = static_cast<size_t>(m) * static_cast<size_t>(p->npix);
+    if (coef)
+      hipLaunchKernelGGL(cap_sym_kernel<true>, dim3(a.ntiles), dim3(kTile), lds, st, a, x + off, y + off, p->nrings);
+    else
+      hipLaunchKernelGGL(cap_sym_kernel<false>, dim3(a.ntiles), dim3(kTile), lds, st, a, x + off, y + off, p->nrings);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    convreal::mark(p, st, "cap_sym_kernel (cap-touching pairs, 16 symmetric images)", p->pairs_rest);
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_remainder(const conv_real_plan* p, const float* x, float* y, int nmaps,

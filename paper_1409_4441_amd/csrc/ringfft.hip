@@ -10,7 +10,9 @@
 // the per-pair sum. In Fourier space it is a product per frequency, so a belt output ring costs one
 // multiply-add per frequency and neighbour ring plus one inverse FFT, whatever the number of pixels
 // inside the cut: the cost grows linearly with theta_cut instead of quadratically (the scaling of the
-// paper's real-space convolver, Eq. 7). The spectra of all k_ij are computed once per plan.
+// paper's real-space convolver, Eq. 7). The spectra of all k_ij are computed once per plan. Pairs
+// that touch a polar cap (rings of different lengths) are summed per pair, each weight once for its
+// 16 symmetric images (cap_sym_kernel).
 //
 // FFTs: radix-2 decimation in time in LDS, FP64, n a power of two up to 8192 (128 KB of LDS); the
 // input is placed in bit-reversed order and log2 n butterfly stages follow. Real sequences keep the
@@ -203,7 +205,8 @@ hipError_t ring_fft_apply_one(const conv_real_plan* p, const T* x, T* y, hipStre
 }
 
 // Belt ring pairs of every map through the ring FFTs (one map at a time: the spectra of x are a
-// per-plan workspace), then the cap-touching pairs per pair, added to the belt rings.
+// per-plan workspace), then the cap-touching pairs over the symmetry group's fundamental domain,
+// added to the belt rings.
 hipError_t launch_ring_fft(const conv_real_plan* p, const void* x, void* y, int nmaps, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (p->belt_hi >= p->belt_lo) {
@@ -213,7 +216,7 @@ hipError_t launch_ring_fft(const conv_real_plan* p, const void* x, void* y, int 
     }
     if (e != hipSuccess) return e;
   }
-  return launch_remainder_f64(p, static_cast<const double*>(x), static_cast<double*>(y), nmaps, st);
+  return launch_cap_sym_f64(p, static_cast<const double*>(x), static_cast<double*>(y), nmaps, st);
 }
 
 }  // namespace convreal
