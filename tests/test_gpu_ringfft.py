@@ -53,6 +53,20 @@ def test_ring_fft_matches_oracle(cuda_device, nside, tc_deg):
     _check(y, ref)
 
 
+@pytest.mark.parametrize("n_tab", [2050, 3000])
+def test_ring_fft_table_forms(cuda_device, n_tab):
+    """The cap-touching pairs' kernel stages the table as cubic coefficients up to 2048 segments and
+    as nodes beyond; the spectra always interpolate from the nodes."""
+    nside, sigma = 8, 5.0 * DEG
+    tc = 4 * sigma
+    T = _table(sigma, tc, n_tab=n_tab, lmax=64)
+    x = synth.white_noise(nside, 2, seed=n_tab)
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        plan.set_method("ring_fft")
+        y = _run(plan, x)
+    _check(y, oc.convolve_sampled(nside, T, tc, x, np.arange(x.shape[1])))
+
+
 def test_ring_fft_equals_direct_and_oracle_nside128(cuda_device):
     nside, sigma = 128, 2.0 * DEG
     tc = 5 * sigma
