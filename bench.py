@@ -346,7 +346,8 @@ def main():
                     "maps_per_s": nmaps * args.plain_steps / wall_d, "setup_s": setup_s, "kernels": kern_d,
                     "rel_rms_timed_path_vs_ring_fft": diff_d,
                     "method": "FP64 maps: belt ring pairs as per-frequency products of ring spectra, "
-                              "cap-touching ring pairs per pair, each weight once for its 16 symmetric images"}
+                              "cap-touching ring pairs on the FP64 matrix cores, each weight once for its 16 "
+                              "symmetric images"}
         del xd, yd
 
     if args.copy_probe:

@@ -859,10 +859,10 @@ void release_ring_fft(conv_real_plan* p) {
   for (void* ptr : {static_cast<void*>(p->d_fft_tw), static_cast<void*>(p->d_fft_pi), static_cast<void*>(p->d_fft_pj),
                     static_cast<void*>(p->d_fft_pA), static_cast<void*>(p->d_fft_pB), static_cast<void*>(p->d_fft_boff),
                     static_cast<void*>(p->d_fft_K), static_cast<void*>(p->d_fft_X),
-                    static_cast<void*>(p->d_stile_ring), static_cast<void*>(p->d_stile_a0)})
+                    static_cast<void*>(p->d_mtile_ring), static_cast<void*>(p->d_mtile_a0)})
     release(p, ptr);
-  p->d_stile_ring = p->d_stile_a0 = nullptr;
-  p->n_stiles = 0;
+  p->d_mtile_ring = p->d_mtile_a0 = nullptr;
+  p->n_mtiles = 0;
   p->d_fft_tw = nullptr;
   p->d_fft_pi = p->d_fft_pj = nullptr;
   p->d_fft_pA = p->d_fft_pB = nullptr;
@@ -915,13 +915,13 @@ hipError_t build_ring_fft(conv_real_plan* p) {
       }
   }
   // the cap-touching pairs by symmetry: fundamental domains of the north-half rings that have them
-  std::vector<int> stile_ring, stile_a0;
+  std::vector<int> mtile_ring, mtile_a0;
   for (int r = 0; r <= (g.nrings - 1) / 2; ++r) {
     if (roff[r + 1] == roff[r]) continue;
     const int F = (g.n[r] / 4 - g.c[r]) / 2 + 1;
-    for (int a0 = 0; a0 < F; a0 += kTile) {
-      stile_ring.push_back(r);
-      stile_a0.push_back(a0);
+    for (int a0 = 0; a0 < F; a0 += 16) {
+      mtile_ring.push_back(r);
+      mtile_a0.push_back(a0);
     }
   }
   const int n = 4 * N;
@@ -943,13 +943,13 @@ hipError_t build_ring_fft(conv_real_plan* p) {
   release(p, p->d_rtile_ring);
   release(p, p->d_rtile_a0);
   p->n_rtiles = static_cast<int>(rtile_ring.size());
-  p->n_stiles = static_cast<int>(stile_ring.size());
+  p->n_mtiles = static_cast<int>(mtile_ring.size());
   if ((e = dev_upload(p, &p->d_rest_off, roff)) != hipSuccess ||
       (e = dev_upload(p, &p->d_rest_idx, ridx)) != hipSuccess ||
       (e = dev_upload(p, &p->d_rtile_ring, rtile_ring)) != hipSuccess ||
       (e = dev_upload(p, &p->d_rtile_a0, rtile_a0)) != hipSuccess ||
-      (e = dev_upload(p, &p->d_stile_ring, stile_ring)) != hipSuccess ||
-      (e = dev_upload(p, &p->d_stile_a0, stile_a0)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_mtile_ring, mtile_ring)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_mtile_a0, mtile_a0)) != hipSuccess ||
       (e = dev_upload(p, &p->d_fft_tw, tw)) != hipSuccess || (e = dev_upload(p, &p->d_fft_pi, fi)) != hipSuccess ||
       (e = dev_upload(p, &p->d_fft_pj, fj)) != hipSuccess || (e = dev_upload(p, &p->d_fft_pA, fA)) != hipSuccess ||
       (e = dev_upload(p, &p->d_fft_pB, fB)) != hipSuccess || (e = dev_upload(p, &p->d_fft_boff, boff)) != hipSuccess ||

@@ -239,9 +239,9 @@ struct conv_real_plan {
   long long* d_fft_boff = nullptr;  // per belt output ring: first belt pair (nbelt + 1)
   double2* d_fft_K = nullptr;  // per belt pair: n / 2 + 1 frequencies of k_ij
   double2* d_fft_X = nullptr;  // per belt ring: n / 2 + 1 frequencies of one map's ring (workspace)
-  int* d_stile_ring = nullptr; // cap-touching pairs by symmetry: tiles of 256 fundamental-domain
-  int* d_stile_a0 = nullptr;   // pixels of the north-half rings that have such pairs
-  int n_stiles = 0;
+  int* d_mtile_ring = nullptr; // cap-touching pairs by symmetry: tiles of 16 fundamental-domain pixels
+  int* d_mtile_a0 = nullptr;   // (one wave each) of the north-half rings that have such pairs
+  int n_mtiles = 0;
 
   convreal::Recorder* rec = nullptr;  // set only inside conv_real_profile
   std::vector<void*> owned;    // every device allocation, freed by destroy
@@ -271,7 +271,7 @@ hipError_t launch_pair_accumulate(const conv_real_plan* p, const void* x, void* 
 hipError_t launch_remainder(const conv_real_plan* p, const float* x, float* y, int nmaps,
                             hipStream_t st);
 hipError_t launch_remainder_f64(const conv_real_plan* p, const double* x, double* y, int nmaps, hipStream_t st);
-hipError_t launch_cap_sym_f64(const conv_real_plan* p, const double* x, double* y, int nmaps, hipStream_t st);
+hipError_t launch_cap_mfma64(const conv_real_plan* p, const double* x, double* y, int nmaps, hipStream_t st);
 // ring-FFT method: spectra of the belt pairs' kernels (set-up), and an apply of FP64 maps
 hipError_t ring_fft_spectra(const conv_real_plan* p);
 hipError_t launch_ring_fft(const conv_real_plan* p, const void* x, void* y, int nmaps, hipStream_t st);

@@ -253,89 +253,110 @@ __global__ __launch_bounds__(kTile * kGroups) void pair_accumulate_kernel(PairAr
 
 // Ring pairs that touch a polar cap, over the fundamental domain of the pixelization's symmetry
 // group (quarter turns, the reflection phi -> -phi, the north/south mirror: 16 elements that map
-// every ring onto itself or its mirror and keep every chord): one thread per domain pixel a of a
-// north-half ring computes each weight Ktilde(d(a, b)) once (the same walk, membership test and
-// interpolation as accumulate_pixel) and applies it to the 16 images of input pixel b, which give
-// the 16 images of a. Images that coincide (pixels on a reflection axis, the equator ring's mirror)
-// are written once. Belt rings get y +=, cap rings y =. One FP64 map per launch.
+// every ring onto itself or its mirror and keep every chord), on the FP64 matrix cores: each weight
+// Ktilde(d(a, b)) is evaluated once and applied to the 16 images of input pixel b, which give the 16
+// images of output pixel a. One wave per 16 consecutive domain pixels (rows) of a north-half ring; per ring pair, the 16 rows' windows are joined and walked 4 inputs at a
+// time, each step one v_mfma_f64_16x16x4 of W[row][k] (weight of row pixel a and input pixel
+// b0 + 4s + k, lane row + 16 k, zero outside the row's own window or the cut) by X[k][image] (input
+// pixel b0 + 4s + k mapped by image = lane & 15, loaded once for all 16 rows). Lane l's results are
+// rows 4 i + (l >> 4), image l & 15 (the FP64 instruction's output order: register i of the lanes
+// 16 q .. 16 q + 15 holds row 4 i + q). Weights: alpha seeded from the exact numerator every 16 steps and
+// rotated by 4 pixels between; the same membership test and interpolation as accumulate_pixel.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaWaves = 16;   // tiles per workgroup (the table is staged once for all of them)
+
 template <bool kCoef>
-__global__ __launch_bounds__(kTile) void cap_sym_kernel(PairArgs a, const double* __restrict__ x,
-                                                        double* __restrict__ y, int nrings) {
+__global__ __launch_bounds__(64 * kMfmaWaves) void cap_mfma64_kernel(PairArgs a, const double* __restrict__ x,
+                                                           double* __restrict__ y, int nrings) {
   extern __shared__ double s_tab[];
   const int nwords = kCoef ? 4 * (a.n_tab - 2) : a.n_tab;
   const double* src = kCoef ? a.coef : a.table;
   for (int k = threadIdx.x; k < nwords; k += blockDim.x) s_tab[k] = src[k];
   __syncthreads();
   using convreal::ldu;
-  const int tile = static_cast<int>(blockIdx.x);
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) >> 6);
+  const int tile = static_cast<int>(blockIdx.x) * kMfmaWaves + wave;
+  if (tile >= a.ntiles) return;
+  const int lane = static_cast<int>(threadIdx.x) & 63;
+  const int row = lane & 15, kq = lane >> 4;
   const int r = ldu(ldu(a.tile_ring)[tile]);
-  const int ai = ldu(ldu(a.tile_a0)[tile]) + static_cast<int>(threadIdx.x);
+  const int a0 = ldu(ldu(a.tile_a0)[tile]);
   const int ni = ldu(ldu(a.rn)[r]);
   const int ci = ldu(ldu(a.rc)[r]);
-  const int F = (ni / 4 - ci) / 2 + 1;   // fundamental domain [0, F) of the ring
-  if (ai >= F) return;
+  const int F = (ni / 4 - ci) / 2 + 1;
+  const int ai = a0 + row;                  // this lane's row pixel (a weight row when ai < F)
   const int twoa_ci = 2 * ai + ci;
   const double ih2 = a.inv_h * a.inv_h;
-  double acc[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  // B operand: this lane's image of the input pixels
+  const int img = lane & 15, ih = img >> 3, ifl = (img >> 2) & 1, iq = img & 3;
+  doublex4 acc = {0.0, 0.0, 0.0, 0.0};
   const long long k0 = ldu(ldu(a.off)[r]), k1 = ldu(ldu(a.off)[r + 1]);
   const long long* idx = ldu(a.idx);
   for (long long kk = k0; kk < k1; ++kk) {
     const long long k = idx ? ldu(idx[kk]) : kk;
     RingWalk w;
-    if (!ring_walk(a, k, ni, twoa_ci, w)) continue;
-    const int j = ldu(ldu(a.pj)[k]);
-    const double* xj = x + w.sj;
-    const double* xm = x + ldu(ldu(a.rstart)[nrings - 1 - j]);   // mirror ring: same pixels
-    const int q4 = w.nj / 4;
-    int bm = first_index(w);
-    double sa = 0.0, ca = 1.0;
-    for (int t = 0; t < w.nb; ++t) {
-      if ((t & 63) == 0) seed_alpha(w, twoa_ci, ni, t, sa, ca);
-      const double d2 = fma(w.B, sa * sa, w.A);
-      if (d2 <= a.dcut2) {
-        const double kt = table_value<kCoef>(s_tab, a.n_tab, sqrt_refined(scaled_q(d2, ih2)));
-        const int bf = w.nj - bm - w.cj;   // reflected pixel, in [0, n_j]
+    const bool has = ai < F && ring_walk(a, k, ni, twoa_ci, w);
+    int lo = has ? w.blo : 0x3fffffff, hi = has ? w.blo + w.nb - 1 : -0x3fffffff;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          int i0 = bm + q * q4;
-          i0 = i0 >= w.nj ? i0 - w.nj : i0;
-          int i1 = bf + q * q4;
-          i1 = i1 >= w.nj ? i1 - w.nj : i1;
-          i1 = i1 >= w.nj ? i1 - w.nj : i1;
-          acc[q] = fma(kt, xj[i0], acc[q]);
-          acc[4 + q] = fma(kt, xj[i1], acc[4 + q]);
-          acc[8 + q] = fma(kt, xm[i0], acc[8 + q]);
-          acc[12 + q] = fma(kt, xm[i1], acc[12 + q]);
-        }
-      }
-      const double sa2 = sa * w.cd - ca * w.sd;
-      ca = ca * w.cd + sa * w.sd;
+    for (int o = 1; o < 16; o <<= 1) {
+      lo = min(lo, __shfl_xor(lo, o));
+      hi = max(hi, __shfl_xor(hi, o));
+    }
+    const int b0 = __builtin_amdgcn_readfirstlane(lo), bend = __builtin_amdgcn_readfirstlane(hi);
+    if (bend < b0) continue;
+    const int j = ldu(ldu(a.pj)[k]);
+    const int nj = ldu(ldu(a.rn)[j]);
+    const int cj = ldu(ldu(a.rc)[j]);
+    const double A = ldu(ldu(a.pA)[k]), B = ldu(ldu(a.pB)[k]);
+    const double* xs = x + ldu(ldu(a.rstart)[ih ? nrings - 1 - j : j]);
+    const int q4 = nj / 4;
+    // rotation by 4 input pixels: alpha -> alpha - 4 pi / n_j
+    double s4, c4;
+    sincospi(4.0 / static_cast<double>(nj), &s4, &c4);
+    const int wlo = has ? w.blo : 1, whi = has ? w.blo + w.nb - 1 : 0;
+    RingWalk ws;   // the union's first pixel, for the seeds
+    ws.nj = nj;
+    ws.cj = cj;
+    ws.blo = b0;
+    const int ns = (bend - b0 + 4) >> 2;
+    double sa = 0.0, ca = 1.0;
+    for (int st = 0; st < ns; ++st) {
+      const int b = b0 + 4 * st + kq;
+      if ((st & 15) == 0) seed_alpha(ws, twoa_ci, ni, 4 * st + kq, sa, ca);
+      const double d2 = fma(B, sa * sa, A);
+      double wv = 0.0;
+      if (b >= wlo && b <= whi && d2 <= a.dcut2)
+        wv = table_value<kCoef>(s_tab, a.n_tab, sqrt_refined(scaled_q(d2, ih2)));
+      // input pixel b0 + 4 st + (lane >> 4) (the B operand's k), mapped by this lane's image
+      int bw = b;   // b lies in (-n_j, 2 n_j + 3): windows start above -n_j and end below 1.5 n_j
+      bw = bw < 0 ? bw + nj : bw;
+      bw = bw >= nj ? bw - nj : bw;
+      bw = bw >= nj ? bw - nj : bw;
+      int iw = (ifl ? nj - bw - cj : bw) + iq * q4;
+      iw = iw >= nj ? iw - nj : iw;
+      const double xv = xs[iw];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, xv, acc, 0, 0, 0);
+      const double sa2 = sa * c4 - ca * s4;
+      ca = ca * c4 + sa * s4;
       sa = sa2;
-      if (++bm == w.nj) bm = 0;
     }
   }
+  // lane holds rows 4 u + kq of image img
   const int quarter = ni / 4;
-  const bool on_axis = (twoa_ci % quarter) == 0;   // the reflected images repeat the rotated ones
+  const int rr = ih ? nrings - 1 - r : r;
+  if (ih && rr == r) return;
+  double* yr = y + ldu(ldu(a.rstart)[rr]);
+  const bool add = rr >= a.belt_lo && rr <= a.belt_hi;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int rr = h ? nrings - 1 - r : r;
-    if (h && rr == r) continue;
-    double* yr = y + ldu(ldu(a.rstart)[rr]);
-    const bool add = rr >= a.belt_lo && rr <= a.belt_hi;
-#pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      if (f && on_axis) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int P = f ? (ni - ai - ci + q * quarter) : (ai + q * quarter);
-        P %= ni;
-        if (P < 0) P += ni;
-        const double v = a.omega * acc[8 * h + 4 * f + q];
-        yr[P] = add ? yr[P] + v : v;
-      }
-    }
+  for (int u = 0; u < 4; ++u) {
+    const int ao = a0 + 4 * u + kq;
+    if (ao >= F) continue;
+    if (ifl && ((2 * ao + ci) % quarter) == 0) continue;   // reflected image repeats a rotated one
+    int P = ifl ? (ni - ao - ci + iq * quarter) : (ao + iq * quarter);
+    P %= ni;
+    if (P < 0) P += ni;
+    const double v = a.omega * acc[u];
+    yr[P] = add ? yr[P] + v : v;
   }
 }
 
@@ -464,23 +485,26 @@ hipError_t launch_remainder_f64(const conv_real_plan* p, const double* x, double
   return launch_loop(p, a, x, y, nmaps, st, "pair_accumulate_kernel<double> (cap-touching pairs)", p->pairs_rest);
 }
 
-hipError_t launch_cap_sym_f64(const conv_real_plan* p, const double* x, double* y, int nmaps, hipStream_t st) {
+hipError_t launch_cap_mfma64(const conv_real_plan* p, const double* x, double* y, int nmaps, hipStream_t st) {
   PairArgs a = make_args(p, true);
-  a.tile_ring = p->d_stile_ring;
-  a.tile_a0 = p->d_stile_a0;
-  a.ntiles = p->n_stiles;
+  a.tile_ring = p->d_mtile_ring;
+  a.tile_a0 = p->d_mtile_a0;
+  a.ntiles = p->n_mtiles;
   if (a.ntiles == 0) return hipSuccess;
   const bool coef = a.coef != nullptr;
   const size_t lds = coef ? sizeof(double) * 4 * static_cast<size_t>(a.n_tab - 2) : sizeof(double) * static_cast<size_t>(a.n_tab);
+  const unsigned grid = static_cast<unsigned>((a.ntiles + kMfmaWaves - 1) / kMfmaWaves);
   for (int m = 0; m < nmaps; ++m) {
     const size_t off = static_cast<size_t>(m) * static_cast<size_t>(p->npix);
     if (coef)
-      hipLaunchKernelGGL(cap_sym_kernel<true>, dim3(a.ntiles), dim3(kTile), lds, st, a, x + off, y + off, p->nrings);
+      hipLaunchKernelGGL(cap_mfma64_kernel<true>, dim3(grid), dim3(64 * kMfmaWaves), lds, st, a, x + off, y + off,
+                         p->nrings);
     else
-      hipLaunchKernelGGL(cap_sym_kernel<false>, dim3(a.ntiles), dim3(kTile), lds, st, a, x + off, y + off, p->nrings);
+      hipLaunchKernelGGL(cap_mfma64_kernel<false>, dim3(grid), dim3(64 * kMfmaWaves), lds, st, a, x + off, y + off,
+                         p->nrings);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    convreal::mark(p, st, "cap_sym_kernel (cap-touching pairs, 16 symmetric images)", p->pairs_rest);
+    convreal::mark(p, st, "cap_mfma64_kernel (cap-touching pairs, FP64 matrix cores)", p->pairs_rest);
   }
   return hipSuccess;
 }

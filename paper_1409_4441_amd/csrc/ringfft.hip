@@ -12,7 +12,7 @@
 // inside the cut: the cost grows linearly with theta_cut instead of quadratically (the scaling of the
 // paper's real-space convolver, Eq. 7). The spectra of all k_ij are computed once per plan. Pairs
 // that touch a polar cap (rings of different lengths) are summed per pair, each weight once for its
-// 16 symmetric images (cap_sym_kernel).
+// 16 symmetric images on the FP64 matrix cores (cap_mfma64_kernel).
 //
 // FFTs: radix-2 decimation in time in LDS, FP64, n a power of two up to 8192 (128 KB of LDS); the
 // input is placed in bit-reversed order and log2 n butterfly stages follow. Real sequences keep the
@@ -216,7 +216,7 @@ hipError_t launch_ring_fft(const conv_real_plan* p, const void* x, void* y, int 
     }
     if (e != hipSuccess) return e;
   }
-  return launch_cap_sym_f64(p, static_cast<const double*>(x), static_cast<double*>(y), nmaps, st);
+  return launch_cap_mfma64(p, static_cast<const double*>(x), static_cast<double*>(y), nmaps, st);
 }
 
 }  // namespace convreal
