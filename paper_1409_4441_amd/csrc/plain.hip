@@ -255,13 +255,16 @@ __global__ __launch_bounds__(kTile * kGroups) void pair_accumulate_kernel(PairAr
 // group (quarter turns, the reflection phi -> -phi, the north/south mirror: 16 elements that map
 // every ring onto itself or its mirror and keep every chord), on the FP64 matrix cores: each weight
 // Ktilde(d(a, b)) is evaluated once and applied to the 16 images of input pixel b, which give the 16
-// images of output pixel a. One wave per 16 consecutive domain pixels (rows) of a north-half ring; per ring pair, the 16 rows' windows are joined and walked 4 inputs at a
-// time, each step one v_mfma_f64_16x16x4 of W[row][k] (weight of row pixel a and input pixel
-// b0 + 4s + k, lane row + 16 k, zero outside the row's own window or the cut) by X[k][image] (input
-// pixel b0 + 4s + k mapped by image = lane & 15, loaded once for all 16 rows). Lane l's results are
-// rows 4 i + (l >> 4), image l & 15 (the FP64 instruction's output order: register i of the lanes
-// 16 q .. 16 q + 15 holds row 4 i + q). Weights: alpha seeded from the exact numerator every 16 steps and
-// rotated by 4 pixels between; the same membership test and interpolation as accumulate_pixel.
+// images of output pixel a. One wave per 16 consecutive domain pixels (rows) of a north-half ring.
+// Per ring pair the 16 rows' windows are joined and walked 4 inputs at a time, each step one
+// v_mfma_f64_16x16x4 of W[row][k] (weight of row pixel a and input pixel b0 + 4s + k in lane
+// row + 16 k, zero outside the row's own window or the cut) by X[k][image] (input pixel b0 + 4s + k
+// mapped by image = lane & 15, loaded once for all 16 rows). Lane l's results are rows 4 i + (l >> 4)
+// of image l & 15 (the FP64 instruction's output order: register i of lanes 16 q .. 16 q + 15 holds
+// row 4 i + q). Weights: alpha seeded from the exact numerator every 16 steps and rotated by 4 pixels
+// between; the same membership test and interpolation as accumulate_pixel. Images that coincide
+// (pixels on a reflection axis, the equator ring's mirror) are written once; belt rings get y +=,
+// cap rings y =. One FP64 map per launch.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaWaves = 16;   // tiles per workgroup (the table is staged once for all of them)
 
