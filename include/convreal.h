@@ -203,8 +203,9 @@ int conv_real_get_weight_store(const conv_real_plan* plan, int* active, long lon
  *                              spectrum and the pair's kernel spectrum (computed once here, FP64,
  *                              (n/2 + 1) x 16 bytes per belt ring pair, n = 4 Nside), one inverse
  *                              FFT per output ring; ring pairs touching a polar cap summed per
- *                              pair. Same pairs and kernel values as DIRECT; results differ by FP64
- *                              rounding only. Requires a power-of-two nside <= 2048 (EINVAL
+ *                              pair, each weight once for the 16 images of its symmetry orbit (FP64
+ *                              matrix cores). Same pairs and kernel values as DIRECT; results differ
+ *                              by FP64 rounding only. Requires a power-of-two nside <= 2048 (EINVAL
  *                              otherwise) and a device that can hold the spectra (ENOMEM).
  * Synchronous and allocating (not while an apply on the plan may run); conv_real_apply then uses the
  * method, one map at a time for the belt part. FP64 plans only (EINVAL otherwise).
