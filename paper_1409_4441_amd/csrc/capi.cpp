@@ -886,10 +886,12 @@ hipError_t build_ring_fft(conv_real_plan* p) {
       (e = hipMemcpy(pB.data(), p->d_pB, sizeof(double) * pB.size(), hipMemcpyDeviceToHost)) != hipSuccess)
     return e;
   const int blo = N - 1, bhi = 3 * N - 1;   // belt rings (0-based): 4 N pixels each
+  // kernel spectra of the north belt output rings through the equator; a south ring uses its
+  // mirror's (same chord constants and azimuth offsets, input rings mirrored)
   std::vector<int> fi, fj;
   std::vector<double> fA, fB;
   std::vector<long long> boff(1, 0);
-  for (int i = blo; i <= bhi; ++i) {
+  for (int i = blo; i <= (g.nrings - 1) / 2; ++i) {
     for (int j = std::max(jlo[i], blo); j <= std::min(jhi[i], bhi); ++j) {
       const long long k = poff[i] + (j - jlo[i]);
       fi.push_back(i);

@@ -230,13 +230,13 @@ struct conv_real_plan {
   int method = 0;              // CONV_REAL_METHOD_DIRECT or CONV_REAL_METHOD_RING_FFT
   int fft_n = 0;               // belt ring length 4 Nside (a power of two)
   int fft_logn = 0;
-  long long fft_npairs = 0;    // belt ring pairs (output ring, input ring), output-ring major
+  long long fft_npairs = 0;    // belt ring pairs (north output ring, input ring), output-ring major
   double2* d_fft_tw = nullptr; // n / 2 twiddles exp(-2 pi i m / n)
   int* d_fft_pi = nullptr;     // per belt pair: output ring, input ring, chord constants
   int* d_fft_pj = nullptr;
   double* d_fft_pA = nullptr;
   double* d_fft_pB = nullptr;
-  long long* d_fft_boff = nullptr;  // per belt output ring: first belt pair (nbelt + 1)
+  long long* d_fft_boff = nullptr;  // per north belt output ring: first belt pair (+ 1 entry)
   double2* d_fft_K = nullptr;  // per belt pair: n / 2 + 1 frequencies of k_ij
   double2* d_fft_X = nullptr;  // per belt ring: n / 2 + 1 frequencies of one map's ring (workspace)
   int* d_mtile_ring = nullptr; // cap-touching pairs by symmetry: tiles of 16 fundamental-domain pixels

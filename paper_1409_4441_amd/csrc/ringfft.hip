@@ -63,11 +63,12 @@ struct FftArgs {
   const double* pB;
   const int* rc;           // per ring: azimuth offset numerator
   const long long* rstart; // per ring: first pixel
-  const long long* boff;   // per belt output ring (from belt_lo): first belt pair, nbelt + 1 entries
+  const long long* boff;   // per north belt output ring (from belt_lo): first belt pair, + 1 entry
   double2* K;              // per belt pair: nbins spectrum of k_ij
   double2* X;              // per belt ring (from belt_lo): nbins spectrum of x
   int n, logn, nbins;
   int belt_lo;
+  int nrings;
   int n_tab;
   double inv_h;
   double dcut2;
@@ -114,32 +115,68 @@ __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_forward_kernel(FftArg
   for (int f = threadIdx.x; f < a.nbins; f += blockDim.x) out[f] = s_fft[f];
 }
 
-// Apply, one workgroup per belt output ring i: Y = sum_j K_ij X_j per frequency, then y_i = Omega x
-// the inverse FFT of Y (through the forward transform: ifft(Y) = conj(fft(conj(Y))) / n, whose real
-// part is Re(fft(conj(Y))) / n). Belt rings are written (=); cap-touching pairs are added later.
+// conj(Y) at f into the transform's input, and at n - f the conjugate of that (Hermitian spectrum of a
+// real sequence)
+__device__ __forceinline__ void put_conj(double2* s, double2 v, int f, int n, int logn) {
+  s[bitrev(f, logn)] = double2{v.x, -v.y};
+  if (f > 0 && f < n - f) s[bitrev(n - f, logn)] = v;
+}
+
+// y = Omega x the inverse FFT of the spectrum in s (ifft(Y) = conj(fft(conj(Y))) / n, whose real part
+// is Re(fft(conj(Y))) / n)
+template <typename T>
+__device__ __forceinline__ void inverse_out(double2* s, const FftArgs& a, T* __restrict__ yr) {
+  __syncthreads();
+  fft_stages(s, a.n, a.tw);
+  const double scale = a.omega / static_cast<double>(a.n);
+  for (int m = threadIdx.x; m < a.n; m += blockDim.x) yr[m] = static_cast<T>(scale * s[m].x);
+  __syncthreads();
+}
+
+constexpr int kMaxBinsPerThread = 5;   // (8192 / 2 + 1) frequencies over 1024 threads
+
+// Apply, one workgroup per north belt output ring i and its mirror ring m: Y_i = sum_j K_ij X_j and
+// Y_m = sum_j K_ij X_mirror(j) per frequency (the mirror pair (m, mirror(j)) has the same chord
+// constants and azimuth offsets, so the same kernel spectrum, read once for both), then the inverse
+// FFTs. Belt rings are written (=); cap-touching pairs are added later.
 template <typename T>
 __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_inverse_kernel(FftArgs a, T* __restrict__ y) {
   extern __shared__ double2 s_fft[];
   const int ib = static_cast<int>(blockIdx.x);
   const int i = a.belt_lo + ib;
+  const int mi = a.nrings - 1 - i;
+  const bool pair = mi != i;
   const long long q0 = a.boff[ib], q1 = a.boff[ib + 1];
-  for (int f = threadIdx.x; f < a.nbins; f += blockDim.x) {
-    double2 acc = double2{0.0, 0.0};
+  double2 ym[kMaxBinsPerThread];
+#pragma unroll
+  for (int u = 0; u < kMaxBinsPerThread; ++u) {
+    const int f = threadIdx.x + u * blockDim.x;
+    if (f >= a.nbins) break;
+    double2 acc = double2{0.0, 0.0}, accm = double2{0.0, 0.0};
     for (long long q = q0; q < q1; ++q) {
       const double2 k = a.K[q * a.nbins + f];
-      const double2 xv = a.X[static_cast<long long>(a.pj[q] - a.belt_lo) * a.nbins + f];
+      const int j = a.pj[q];
+      const double2 xv = a.X[static_cast<long long>(j - a.belt_lo) * a.nbins + f];
       acc.x = fma(k.x, xv.x, fma(-k.y, xv.y, acc.x));
       acc.y = fma(k.x, xv.y, fma(k.y, xv.x, acc.y));
+      if (pair) {
+        const double2 xw = a.X[static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins + f];
+        accm.x = fma(k.x, xw.x, fma(-k.y, xw.y, accm.x));
+        accm.y = fma(k.x, xw.y, fma(k.y, xw.x, accm.y));
+      }
     }
-    // conj(Y) at f, and at n - f the conjugate of that (Hermitian spectrum of a real sequence)
-    s_fft[bitrev(f, a.logn)] = double2{acc.x, -acc.y};
-    if (f > 0 && f < a.n - f) s_fft[bitrev(a.n - f, a.logn)] = acc;
+    put_conj(s_fft, acc, f, a.n, a.logn);
+    ym[u] = accm;
   }
-  __syncthreads();
-  fft_stages(s_fft, a.n, a.tw);
-  T* yr = y + a.rstart[i];
-  const double scale = a.omega / static_cast<double>(a.n);
-  for (int m = threadIdx.x; m < a.n; m += blockDim.x) yr[m] = static_cast<T>(scale * s_fft[m].x);
+  inverse_out(s_fft, a, y + a.rstart[i]);
+  if (!pair) return;
+#pragma unroll
+  for (int u = 0; u < kMaxBinsPerThread; ++u) {
+    const int f = threadIdx.x + u * blockDim.x;
+    if (f >= a.nbins) break;
+    put_conj(s_fft, ym[u], f, a.n, a.logn);
+  }
+  inverse_out(s_fft, a, y + a.rstart[mi]);
 }
 
 FftArgs make_fft_args(const conv_real_plan* p) {
@@ -159,6 +196,7 @@ FftArgs make_fft_args(const conv_real_plan* p) {
   a.logn = p->fft_logn;
   a.nbins = p->fft_n / 2 + 1;
   a.belt_lo = p->belt_lo;
+  a.nrings = p->nrings;
   a.n_tab = p->n_tab;
   a.inv_h = p->inv_h;
   a.dcut2 = p->dcut2;
@@ -189,6 +227,7 @@ hipError_t ring_fft_apply_one(const conv_real_plan* p, const T* x, T* y, hipStre
   const FftArgs a = make_fft_args(p);
   const size_t lds = sizeof(double2) * static_cast<size_t>(p->fft_n);
   const unsigned nbelt = static_cast<unsigned>(p->belt_hi - p->belt_lo + 1);
+  const unsigned nnorth = static_cast<unsigned>((p->nrings - 1) / 2 - p->belt_lo + 1);   // through the equator
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_fft_forward_kernel<T>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e == hipSuccess)
@@ -198,7 +237,7 @@ hipError_t ring_fft_apply_one(const conv_real_plan* p, const T* x, T* y, hipStre
   hipLaunchKernelGGL(ring_fft_forward_kernel<T>, dim3(nbelt), dim3(fft_threads(p->fft_n)), lds, st, a, x);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   mark(p, st, "ring_fft_forward_kernel", 0);
-  hipLaunchKernelGGL(ring_fft_inverse_kernel<T>, dim3(nbelt), dim3(fft_threads(p->fft_n)), lds, st, a, y);
+  hipLaunchKernelGGL(ring_fft_inverse_kernel<T>, dim3(nnorth), dim3(fft_threads(p->fft_n)), lds, st, a, y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   mark(p, st, "ring_fft_inverse_kernel", p->pairs - p->pairs_rest);
   return hipSuccess;
