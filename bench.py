@@ -258,7 +258,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}, "
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}, "
               f"WORLD_SIZE={world}); the real-space convolution of one map runs on one device, "
               "and sharding by latitude band is not implemented.", file=sys.stderr)
         sys.exit(2)
