@@ -322,26 +322,39 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void cap_mfma64_kernel(PairArgs a,
     ws.cj = cj;
     ws.blo = b0;
     const int ns = (bend - b0 + 4) >> 2;
-    double sa = 0.0, ca = 1.0;
-    for (int st = 0; st < ns; ++st) {
+    // weight of step st (alpha's sine sa) for this lane's row and input b0 + 4 st + kq, evaluated on
+    // every lane and zeroed outside the row's window or the cut; the B operand's input of step st
+    auto weight = [&](int st, double sa) {
       const int b = b0 + 4 * st + kq;
-      if ((st & 15) == 0) seed_alpha(ws, twoa_ci, ni, 4 * st + kq, sa, ca);
       const double d2 = fma(B, sa * sa, A);
-      double wv = 0.0;
-      if (b >= wlo && b <= whi && d2 <= a.dcut2)
-        wv = table_value<kCoef>(s_tab, a.n_tab, sqrt_refined(scaled_q(d2, ih2)));
-      // input pixel b0 + 4 st + (lane >> 4) (the B operand's k), mapped by this lane's image
-      int bw = b;   // b lies in (-n_j, 2 n_j + 3): windows start above -n_j and end below 1.5 n_j
+      const double kv = table_value<kCoef>(s_tab, a.n_tab, sqrt_refined(scaled_q(d2, ih2)));
+      return (b >= wlo && b <= whi && d2 <= a.dcut2) ? kv : 0.0;
+    };
+    auto input = [&](int st) {
+      int bw = b0 + 4 * st + kq;   // in (-n_j, 2 n_j + 3): windows start above -n_j and end below 1.5 n_j
       bw = bw < 0 ? bw + nj : bw;
       bw = bw >= nj ? bw - nj : bw;
       bw = bw >= nj ? bw - nj : bw;
       int iw = (ifl ? nj - bw - cj : bw) + iq * q4;
       iw = iw >= nj ? iw - nj : iw;
-      const double xv = xs[iw];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wv, xv, acc, 0, 0, 0);
-      const double sa2 = sa * c4 - ca * s4;
-      ca = ca * c4 + sa * s4;
-      sa = sa2;
+      return xs[iw];
+    };
+    double sa = 0.0, ca = 1.0;
+    int st = 0;
+    // two steps per iteration (seeds fall on even steps), so that their arithmetic overlaps
+    for (; st + 1 < ns; st += 2) {
+      if ((st & 15) == 0) seed_alpha(ws, twoa_ci, ni, 4 * st + kq, sa, ca);
+      const double sb = sa * c4 - ca * s4, cb = ca * c4 + sa * s4;
+      const double x0 = input(st), x1 = input(st + 1);
+      const double w0 = weight(st, sa), w1 = weight(st + 1, sb);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(w0, x0, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(w1, x1, acc, 0, 0, 0);
+      sa = sb * c4 - cb * s4;
+      ca = cb * c4 + sb * s4;
+    }
+    if (st < ns) {
+      if ((st & 15) == 0) seed_alpha(ws, twoa_ci, ni, 4 * st + kq, sa, ca);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(weight(st, sa), input(st), acc, 0, 0, 0);
     }
   }
   // lane holds rows 4 u + kq of image img
