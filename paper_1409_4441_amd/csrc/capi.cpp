@@ -867,7 +867,8 @@ void release_ring_fft(conv_real_plan* p) {
   p->d_fft_pi = p->d_fft_pj = nullptr;
   p->d_fft_pA = p->d_fft_pB = nullptr;
   p->d_fft_boff = nullptr;
-  p->d_fft_K = p->d_fft_X = nullptr;
+  p->d_fft_K = nullptr;
+  p->d_fft_X = nullptr;
   p->fft_npairs = 0;
 }
 
@@ -891,15 +892,20 @@ hipError_t build_ring_fft(conv_real_plan* p) {
   std::vector<int> fi, fj;
   std::vector<double> fA, fB;
   std::vector<long long> boff(1, 0);
+  // per output ring: the input rings with its own azimuth offset first, then those with the other one
+  // (whose spectra carry the same half-pixel phase, applied once per frequency)
   for (int i = blo; i <= (g.nrings - 1) / 2; ++i) {
-    for (int j = std::max(jlo[i], blo); j <= std::min(jhi[i], bhi); ++j) {
-      const long long k = poff[i] + (j - jlo[i]);
-      fi.push_back(i);
-      fj.push_back(j);
-      fA.push_back(pA[k]);
-      fB.push_back(pB[k]);
+    for (int same = 1; same >= 0; --same) {
+      for (int j = std::max(jlo[i], blo); j <= std::min(jhi[i], bhi); ++j) {
+        if ((g.c[j] == g.c[i]) != (same == 1)) continue;
+        const long long k = poff[i] + (j - jlo[i]);
+        fi.push_back(i);
+        fj.push_back(j);
+        fA.push_back(pA[k]);
+        fB.push_back(pB[k]);
+      }
+      boff.push_back(static_cast<long long>(fi.size()));
     }
-    boff.push_back(static_cast<long long>(fi.size()));
   }
   std::vector<long long> roff(g.nrings + 1, 0), ridx;
   std::vector<int> rtile_ring, rtile_a0;

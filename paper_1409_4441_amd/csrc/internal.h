@@ -236,8 +236,9 @@ struct conv_real_plan {
   int* d_fft_pj = nullptr;
   double* d_fft_pA = nullptr;
   double* d_fft_pB = nullptr;
-  long long* d_fft_boff = nullptr;  // per north belt output ring: first belt pair (+ 1 entry)
-  double2* d_fft_K = nullptr;  // per belt pair: n / 2 + 1 frequencies of k_ij
+  long long* d_fft_boff = nullptr;  // per north belt output ring: first belt pair, first pair whose input ring
+                                    // has the other azimuth offset (+ 1 entry)
+  double* d_fft_K = nullptr;   // per belt pair: n / 2 + 1 real spectrum amplitudes of k_ij (phase removed)
   double2* d_fft_X = nullptr;  // per belt ring: n / 2 + 1 frequencies of one map's ring (workspace)
   int* d_mtile_ring = nullptr; // cap-touching pairs by symmetry: tiles of 16 fundamental-domain pixels
   int* d_mtile_a0 = nullptr;   // (one wave each) of the north-half rings that have such pairs

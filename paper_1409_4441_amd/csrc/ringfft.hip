@@ -10,7 +10,11 @@
 // the per-pair sum. In Fourier space it is a product per frequency, so a belt output ring costs one
 // multiply-add per frequency and neighbour ring plus one inverse FFT, whatever the number of pixels
 // inside the cut: the cost grows linearly with theta_cut instead of quadratically (the scaling of the
-// paper's real-space convolver, Eq. 7). The spectra of all k_ij are computed once per plan. Pairs
+// paper's real-space convolver, Eq. 7). The spectra of all k_ij are computed once per plan. Since
+// Ktilde depends on sin^2(alpha) only, k_ij is the sampling at a - b + (c_i - c_j) / 2 of an even
+// n-periodic function, so its spectrum is exp(i pi f (c_i - c_j) / n) times a real amplitude: the plan
+// keeps the amplitude (8 bytes a frequency), and an output ring applies the phase once per frequency to
+// the sum over its input rings of the other azimuth offset (c_i - c_j is 0 or 2 c_i - 1). Pairs
 // that touch a polar cap (rings of different lengths) are summed per pair, each weight once for its
 // 16 symmetric images on the FP64 matrix cores (cap_mfma64_kernel).
 //
@@ -63,8 +67,9 @@ struct FftArgs {
   const double* pB;
   const int* rc;           // per ring: azimuth offset numerator
   const long long* rstart; // per ring: first pixel
-  const long long* boff;   // per north belt output ring (from belt_lo): first belt pair, + 1 entry
-  double2* K;              // per belt pair: nbins spectrum of k_ij
+  const long long* boff;   // per north belt output ring (from belt_lo): first belt pair and first pair of an
+                           // input ring with the other azimuth offset (2 entries a ring), + 1 entry
+  double* K;               // per belt pair: nbins real amplitudes of the spectrum of k_ij
   double2* X;              // per belt ring (from belt_lo): nbins spectrum of x
   int n, logn, nbins;
   int belt_lo;
@@ -81,7 +86,8 @@ __device__ double ktilde(const double* __restrict__ tab, int n_tab, double d2, d
   return convreal::interp_f64(tab, n_tab, sqrt(d2), inv_h);
 }
 
-// Plan time, one workgroup per belt pair q: spectrum of k_q.
+// Plan time, one workgroup per belt pair q: spectrum of k_q, times exp(-i pi f (c_i - c_j) / n) (real up
+// to rounding; its real part is kept).
 __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_spectra_kernel(FftArgs a) {
   extern __shared__ double2 s_fft[];
   const long long q = blockIdx.x;
@@ -97,8 +103,12 @@ __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_spectra_kernel(FftArg
   }
   __syncthreads();
   fft_stages(s_fft, a.n, a.tw);
-  double2* out = a.K + q * a.nbins;
-  for (int f = threadIdx.x; f < a.nbins; f += blockDim.x) out[f] = s_fft[f];
+  double* out = a.K + q * a.nbins;
+  for (int f = threadIdx.x; f < a.nbins; f += blockDim.x) {
+    double sp, cp;
+    sincospi(static_cast<double>(f * dc) / static_cast<double>(a.n), &sp, &cp);
+    out[f] = fma(s_fft[f].x, cp, s_fft[f].y * sp);
+  }
 }
 
 // Apply, one workgroup per belt ring j: spectrum of x_j.
@@ -137,8 +147,9 @@ constexpr int kMaxBinsPerThread = 5;   // (8192 / 2 + 1) frequencies over 1024 t
 
 // Apply, one workgroup per north belt output ring i and its mirror ring m: Y_i = sum_j K_ij X_j and
 // Y_m = sum_j K_ij X_mirror(j) per frequency (the mirror pair (m, mirror(j)) has the same chord
-// constants and azimuth offsets, so the same kernel spectrum, read once for both), then the inverse
-// FFTs. Belt rings are written (=); cap-touching pairs are added later.
+// constants and azimuth offsets, so the same kernel spectrum, read once for both), the half-pixel phase
+// applied once to the sum over input rings of the other azimuth offset, then the inverse FFTs. Belt
+// rings are written (=); cap-touching pairs are added later.
 template <typename T>
 __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_inverse_kernel(FftArgs a, T* __restrict__ y) {
   extern __shared__ double2 s_fft[];
@@ -146,27 +157,38 @@ __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_inverse_kernel(FftArg
   const int i = a.belt_lo + ib;
   const int mi = a.nrings - 1 - i;
   const bool pair = mi != i;
-  const long long q0 = a.boff[ib], q1 = a.boff[ib + 1];
+  const long long q0 = a.boff[2 * ib], qm = a.boff[2 * ib + 1], q1 = a.boff[2 * ib + 2];
+  const int dc = qm < q1 ? a.rc[i] - a.rc[a.pj[qm]] : 0;
   double2 ym[kMaxBinsPerThread];
 #pragma unroll
   for (int u = 0; u < kMaxBinsPerThread; ++u) {
     const int f = threadIdx.x + u * blockDim.x;
     if (f >= a.nbins) break;
-    double2 acc = double2{0.0, 0.0}, accm = double2{0.0, 0.0};
-    for (long long q = q0; q < q1; ++q) {
-      const double2 k = a.K[q * a.nbins + f];
-      const int j = a.pj[q];
-      const double2 xv = a.X[static_cast<long long>(j - a.belt_lo) * a.nbins + f];
-      acc.x = fma(k.x, xv.x, fma(-k.y, xv.y, acc.x));
-      acc.y = fma(k.x, xv.y, fma(k.y, xv.x, acc.y));
-      if (pair) {
-        const double2 xw = a.X[static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins + f];
-        accm.x = fma(k.x, xw.x, fma(-k.y, xw.y, accm.x));
-        accm.y = fma(k.x, xw.y, fma(k.y, xw.x, accm.y));
+    double2 acc[2], accm[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      acc[g] = double2{0.0, 0.0};
+      accm[g] = double2{0.0, 0.0};
+      const long long qb = g == 0 ? q0 : qm, qe = g == 0 ? qm : q1;
+      for (long long q = qb; q < qe; ++q) {
+        const double k = a.K[q * a.nbins + f];
+        const int j = a.pj[q];
+        const double2 xv = a.X[static_cast<long long>(j - a.belt_lo) * a.nbins + f];
+        acc[g].x = fma(k, xv.x, acc[g].x);
+        acc[g].y = fma(k, xv.y, acc[g].y);
+        if (pair) {
+          const double2 xw = a.X[static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins + f];
+          accm[g].x = fma(k, xw.x, accm[g].x);
+          accm[g].y = fma(k, xw.y, accm[g].y);
+        }
       }
     }
-    put_conj(s_fft, acc, f, a.n, a.logn);
-    ym[u] = accm;
+    double sp, cp;
+    sincospi(static_cast<double>(f * dc) / static_cast<double>(a.n), &sp, &cp);
+    const double2 ph = double2{cp, sp};
+    const double2 t = cmul(ph, acc[1]), tm = cmul(ph, accm[1]);
+    put_conj(s_fft, double2{acc[0].x + t.x, acc[0].y + t.y}, f, a.n, a.logn);
+    ym[u] = double2{accm[0].x + tm.x, accm[0].y + tm.y};
   }
   inverse_out(s_fft, a, y + a.rstart[i]);
   if (!pair) return;
