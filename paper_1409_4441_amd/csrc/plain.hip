@@ -290,6 +290,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void cap_mfma64_kernel(PairArgs a,
   const int ai = a0 + row;                  // this lane's row pixel (a weight row when ai < F)
   const int twoa_ci = 2 * ai + ci;
   const double ih2 = a.inv_h * a.inv_h;
+  const double inv_2ni = 1.0 / (2.0 * ni);
   // B operand: this lane's image of the input pixels
   const int img = lane & 15, ih = img >> 3, ifl = (img >> 2) & 1, iq = img & 3;
   doublex4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -297,9 +298,25 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void cap_mfma64_kernel(PairArgs a,
   const long long* idx = ldu(a.idx);
   for (long long kk = k0; kk < k1; ++kk) {
     const long long k = idx ? ldu(idx[kk]) : kk;
-    RingWalk w;
-    const bool has = ai < F && ring_walk(a, k, ni, twoa_ci, w);
-    int lo = has ? w.blo : 0x3fffffff, hi = has ? w.blo + w.nb - 1 : -0x3fffffff;
+    const int j = ldu(ldu(a.pj)[k]);
+    const int nj = ldu(ldu(a.rn)[j]);
+    const int cj = ldu(ldu(a.rc)[j]);
+    const double hw = ldu(ldu(a.phw)[k]);
+    // this row's window [blo, blo + nb) of ring j: the bounds of ring_walk, the centre through the
+    // tile's reciprocal of 2 n_i (the window keeps its 1e-7 margin; the cut test decides membership)
+    int blo = 0, nb = 0;
+    if (ai < F) {
+      const double bc = (static_cast<double>(twoa_ci) * nj - static_cast<double>(cj) * ni) * inv_2ni;
+      if (2.0 * hw >= static_cast<double>(nj)) {
+        blo = static_cast<int>(floor(bc)) - nj / 2;
+        nb = nj;
+      } else {
+        blo = static_cast<int>(ceil(bc - hw - 1e-7));
+        nb = min(static_cast<int>(floor(bc + hw + 1e-7)) - blo + 1, nj);
+      }
+    }
+    const bool has = nb > 0;
+    int lo = has ? blo : 0x3fffffff, hi = has ? blo + nb - 1 : -0x3fffffff;
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) {
       lo = min(lo, __shfl_xor(lo, o));
@@ -307,54 +324,66 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void cap_mfma64_kernel(PairArgs a,
     }
     const int b0 = __builtin_amdgcn_readfirstlane(lo), bend = __builtin_amdgcn_readfirstlane(hi);
     if (bend < b0) continue;
-    const int j = ldu(ldu(a.pj)[k]);
-    const int nj = ldu(ldu(a.rn)[j]);
-    const int cj = ldu(ldu(a.rc)[j]);
     const double A = ldu(ldu(a.pA)[k]), B = ldu(ldu(a.pB)[k]);
     const double* xs = x + ldu(ldu(a.rstart)[ih ? nrings - 1 - j : j]);
-    const int q4 = nj / 4;
-    // rotation by 4 input pixels: alpha -> alpha - 4 pi / n_j
-    double s4, c4;
-    sincospi(4.0 / static_cast<double>(nj), &s4, &c4);
-    const int wlo = has ? w.blo : 1, whi = has ? w.blo + w.nb - 1 : 0;
-    RingWalk ws;   // the union's first pixel, for the seeds
-    ws.nj = nj;
-    ws.cj = cj;
-    ws.blo = b0;
+    // rotation by 4 input pixels (alpha -> alpha - 4 pi / n_j) from the ring's sin and cos of pi / n_j
+    // by two angle doublings
+    const double sd = ldu(ldu(a.rsd)[j]), cd = ldu(ldu(a.rcd)[j]);
+    const double s2 = 2.0 * sd * cd, c2 = fma(-2.0 * sd, sd, 1.0);
+    const double s4 = 2.0 * s2 * c2, c4 = fma(-2.0 * s2, s2, 1.0);
+    // alpha seeds: numerator (2a + c_i) n_j - (2b + c_j) n_i reduced modulo m2 = 2 n_i n_j (exact
+    // integers in FP64), sin and cos of pi num / m2
+    const double m2 = 2.0 * static_cast<double>(ni) * static_cast<double>(nj);
+    const double inv_m2 = 1.0 / m2;
+    const double num0 = static_cast<double>(twoa_ci) * nj - static_cast<double>(2 * (b0 + kq) + cj) * ni;
+    const double dnum = 8.0 * static_cast<double>(ni);   // numerator step per matrix step (4 pixels)
     const int ns = (bend - b0 + 4) >> 2;
-    // weight of step st (alpha's sine sa) for this lane's row and input b0 + 4 st + kq, evaluated on
-    // every lane and zeroed outside the row's window or the cut; the B operand's input of step st
-    auto weight = [&](int st, double sa) {
-      const int b = b0 + 4 * st + kq;
+    // step state: rel = b - blo of this lane's input b = b0 + 4 st + kq (outside the row's window when
+    // unsigned rel > span; a row with no window never matches), iw = index in ring j of b's image
+    const unsigned span = has ? static_cast<unsigned>(nb - 1) : 0u;
+    int rel = has ? b0 + kq - blo : -0x40000000;
+    int bw = b0 + kq;   // in (-n_j, n_j + 3): windows start above -n_j and below n_j
+    bw = bw < 0 ? bw + nj : bw;
+    bw = bw >= nj ? bw - nj : bw;
+    int iw = (ifl ? nj - bw - cj : bw) + iq * (nj / 4);
+    iw = iw >= nj ? iw - nj : iw;
+    const int d4 = ifl ? -4 : 4, wrap = ifl ? -nj : nj;
+    auto next_input = [&]() {
+      const double v = xs[iw];
+      iw += d4;
+      iw -= static_cast<unsigned>(iw) >= static_cast<unsigned>(nj) ? wrap : 0;
+      return v;
+    };
+    // weight of this lane's row and input at alpha's sine sa, zeroed outside the window or the cut
+    auto next_weight = [&](double sa) {
       const double d2 = fma(B, sa * sa, A);
       const double kv = table_value<kCoef>(s_tab, a.n_tab, sqrt_refined(scaled_q(d2, ih2)));
-      return (b >= wlo && b <= whi && d2 <= a.dcut2) ? kv : 0.0;
+      const bool in = static_cast<unsigned>(rel) <= span && d2 <= a.dcut2;
+      rel += 4;
+      return in ? kv : 0.0;
     };
-    auto input = [&](int st) {
-      int bw = b0 + 4 * st + kq;   // in (-n_j, 2 n_j + 3): windows start above -n_j and end below 1.5 n_j
-      bw = bw < 0 ? bw + nj : bw;
-      bw = bw >= nj ? bw - nj : bw;
-      bw = bw >= nj ? bw - nj : bw;
-      int iw = (ifl ? nj - bw - cj : bw) + iq * q4;
-      iw = iw >= nj ? iw - nj : iw;
-      return xs[iw];
+    auto seed = [&](int st, double& sa, double& ca) {
+      const double num = fma(-dnum, static_cast<double>(st), num0);
+      const double rr = fma(-rint(num * inv_m2), m2, num);
+      sincospi(rr * inv_m2, &sa, &ca);
     };
     double sa = 0.0, ca = 1.0;
     int st = 0;
     // two steps per iteration (seeds fall on even steps), so that their arithmetic overlaps
     for (; st + 1 < ns; st += 2) {
-      if ((st & 15) == 0) seed_alpha(ws, twoa_ci, ni, 4 * st + kq, sa, ca);
+      if ((st & 15) == 0) seed(st, sa, ca);
       const double sb = sa * c4 - ca * s4, cb = ca * c4 + sa * s4;
-      const double x0 = input(st), x1 = input(st + 1);
-      const double w0 = weight(st, sa), w1 = weight(st + 1, sb);
+      const double x0 = next_input(), x1 = next_input();
+      const double w0 = next_weight(sa), w1 = next_weight(sb);
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(w0, x0, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(w1, x1, acc, 0, 0, 0);
       sa = sb * c4 - cb * s4;
       ca = cb * c4 + sb * s4;
     }
     if (st < ns) {
-      if ((st & 15) == 0) seed_alpha(ws, twoa_ci, ni, 4 * st + kq, sa, ca);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(weight(st, sa), input(st), acc, 0, 0, 0);
+      if ((st & 15) == 0) seed(st, sa, ca);
+      const double x0 = next_input();
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(next_weight(sa), x0, acc, 0, 0, 0);
     }
   }
   // lane holds rows 4 u + kq of image img
