@@ -907,6 +907,12 @@ hipError_t build_ring_fft(conv_real_plan* p) {
       boff.push_back(static_cast<long long>(fi.size()));
     }
   }
+  // the apply kernels walk each offset group as j, j + 2, ... and take the belt offsets to alternate
+  for (size_t t = 0; t + 1 < boff.size(); ++t)
+    for (long long q = boff[t]; q + 1 < boff[t + 1]; ++q)
+      if (fj[q + 1] != fj[q] + 2) return hipErrorInvalidValue;
+  for (int r = blo; r < bhi; ++r)
+    if (g.c[r + 1] + g.c[r] != 1) return hipErrorInvalidValue;
   std::vector<long long> roff(g.nrings + 1, 0), ridx;
   std::vector<int> rtile_ring, rtile_a0;
   for (int r = 0; r < g.nrings; ++r) {

@@ -20,7 +20,8 @@
 //
 // FFTs: radix-2 decimation in time in LDS, FP64, n a power of two up to 8192 (128 KB of LDS); the
 // input is placed in bit-reversed order and log2 n butterfly stages follow. Real sequences keep the
-// n / 2 + 1 frequencies of their Hermitian spectra; the inverse rebuilds the full spectrum.
+// n / 2 + 1 frequencies of their Hermitian spectra; every transform carries two real rings, one as the
+// real and one as the imaginary part.
 // Twiddles exp(-2 pi i m / n), m < n / 2, come from a table written by the host.
 #include <hip/hip_runtime.h>
 
@@ -73,6 +74,8 @@ struct FftArgs {
   double2* X;              // per belt ring (from belt_lo): nbins spectrum of x
   int n, logn, nbins;
   int belt_lo;
+  int nbelt;              // belt rings (from belt_lo)
+  int nnorth;             // belt output rings from belt_lo through the equator
   int nrings;
   int n_tab;
   double inv_h;
@@ -111,94 +114,173 @@ __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_spectra_kernel(FftArg
   }
 }
 
-// Apply, one workgroup per belt ring j: spectrum of x_j.
+// Apply, one workgroup per two belt rings (belt rings 2 b and 2 b + 1 from belt_lo; the last alone when
+// their count is odd): one complex FFT of z = x_a + i x_b, split by the Hermitian symmetry of real
+// sequences, X_a(f) = (Z(f) + conj Z(n - f)) / 2 and X_b(f) = (Z(f) - conj Z(n - f)) / (2 i).
 template <typename T>
 __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_forward_kernel(FftArgs a, const T* __restrict__ x) {
   extern __shared__ double2 s_fft[];
-  const int r = a.belt_lo + static_cast<int>(blockIdx.x);
-  const T* xr = x + a.rstart[r];
+  const int ra = 2 * static_cast<int>(blockIdx.x);
+  const bool two = ra + 1 < a.nbelt;
+  const T* xa = x + a.rstart[a.belt_lo + ra];
+  const T* xb = x + a.rstart[a.belt_lo + (two ? ra + 1 : ra)];
   for (int m = threadIdx.x; m < a.n; m += blockDim.x)
-    s_fft[bitrev(m, a.logn)] = double2{static_cast<double>(xr[m]), 0.0};
+    s_fft[bitrev(m, a.logn)] = double2{static_cast<double>(xa[m]), two ? static_cast<double>(xb[m]) : 0.0};
   __syncthreads();
   fft_stages(s_fft, a.n, a.tw);
-  double2* out = a.X + static_cast<long long>(blockIdx.x) * a.nbins;
-  for (int f = threadIdx.x; f < a.nbins; f += blockDim.x) out[f] = s_fft[f];
+  double2* oa = a.X + static_cast<long long>(ra) * a.nbins;
+  double2* ob = oa + a.nbins;
+  for (int f = threadIdx.x; f < a.nbins; f += blockDim.x) {
+    const double2 z = s_fft[f], w = s_fft[(a.n - f) & (a.n - 1)];
+    oa[f] = double2{0.5 * (z.x + w.x), 0.5 * (z.y - w.y)};
+    if (two) ob[f] = double2{0.5 * (z.y + w.y), 0.5 * (w.x - z.x)};
+  }
 }
 
-// conj(Y) at f into the transform's input, and at n - f the conjugate of that (Hermitian spectrum of a
-// real sequence)
-__device__ __forceinline__ void put_conj(double2* s, double2 v, int f, int n, int logn) {
-  s[bitrev(f, logn)] = double2{v.x, -v.y};
-  if (f > 0 && f < n - f) s[bitrev(n - f, logn)] = v;
-}
+constexpr int kMaxBins = 4;   // frequencies below n / 2 per thread (n / 2 <= 4 x 1024)
 
-// y = Omega x the inverse FFT of the spectrum in s (ifft(Y) = conj(fft(conj(Y))) / n, whose real part
-// is Re(fft(conj(Y))) / n)
-template <typename T>
-__device__ __forceinline__ void inverse_out(double2* s, const FftArgs& a, T* __restrict__ yr) {
-  __syncthreads();
-  fft_stages(s, a.n, a.tw);
-  const double scale = a.omega / static_cast<double>(a.n);
-  for (int m = threadIdx.x; m < a.n; m += blockDim.x) yr[m] = static_cast<T>(scale * s[m].x);
-  __syncthreads();
-}
-
-constexpr int kMaxBinsPerThread = 5;   // (8192 / 2 + 1) frequencies over 1024 threads
-
-// Apply, one workgroup per north belt output ring i and its mirror ring m: Y_i = sum_j K_ij X_j and
-// Y_m = sum_j K_ij X_mirror(j) per frequency (the mirror pair (m, mirror(j)) has the same chord
-// constants and azimuth offsets, so the same kernel spectrum, read once for both), the half-pixel phase
-// applied once to the sum over input rings of the other azimuth offset, then the inverse FFTs. Belt
-// rings are written (=); cap-touching pairs are added later.
+// Apply, one workgroup per two north belt output rings i and i + 2 (the same azimuth offset, so the
+// same split of their input rings into offset groups; the blocks of i + 1 and i + 3 read nearly the
+// same input spectra, and the launch keeps such blocks on one XCD) and their mirror rings m:
+//   Y_i = sum_j K_ij X_j,  Y_m = sum_j K_ij X_mirror(j)
+// per frequency (the mirror pair (m, mirror(j)) has the same chord constants and azimuth offsets, so
+// the same kernel spectrum, read once for both). Each input spectrum is loaded once for both output
+// rings. The group of input rings with the other azimuth offset is summed first and turned by the
+// half-pixel phase. At f = n / 2 only the same-offset group contributes (the other group's amplitude
+// vanishes there: its kernel is odd under the half-pixel reflection), summed by wave 0. The two real
+// outputs of a ring and its mirror come from one complex inverse FFT of Z = Y_i + i Y_m:
+// conj(Z) is transformed forward, y_i = Re / n and y_m = -Im / n. Belt rings are written (=);
+// cap-touching pairs are added later.
 template <typename T>
 __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_inverse_kernel(FftArgs a, T* __restrict__ y) {
   extern __shared__ double2 s_fft[];
-  const int ib = static_cast<int>(blockIdx.x);
-  const int i = a.belt_lo + ib;
-  const int mi = a.nrings - 1 - i;
-  const bool pair = mi != i;
-  const long long q0 = a.boff[2 * ib], qm = a.boff[2 * ib + 1], q1 = a.boff[2 * ib + 2];
-  const int dc = qm < q1 ? a.rc[i] - a.rc[a.pj[qm]] : 0;
-  double2 ym[kMaxBinsPerThread];
+  const int nblk = 2 * ((a.nnorth + 3) / 4);
+  const int b = convreal::xcd_remap(static_cast<int>(blockIdx.x), nblk);
+  const int ib = 4 * (b >> 1) + (b & 1);
+  if (ib >= a.nnorth) return;
+  const int nr = ib + 2 < a.nnorth ? 2 : 1;
+  const int half = a.n / 2;
+  const int i0 = a.belt_lo + ib;
+  // per output ring r and offset group g (0: same offset, 1: the other): pairs [qb, qe), input rings
+  // jf, jf + 2, ..., jl
+  long long qb[2][2];
+  int jf[2][2], jl[2][2];
 #pragma unroll
-  for (int u = 0; u < kMaxBinsPerThread; ++u) {
-    const int f = threadIdx.x + u * blockDim.x;
-    if (f >= a.nbins) break;
-    double2 acc[2], accm[2];
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
-      acc[g] = double2{0.0, 0.0};
-      accm[g] = double2{0.0, 0.0};
-      const long long qb = g == 0 ? q0 : qm, qe = g == 0 ? qm : q1;
-      for (long long q = qb; q < qe; ++q) {
-        const double k = a.K[q * a.nbins + f];
-        const int j = a.pj[q];
-        const double2 xv = a.X[static_cast<long long>(j - a.belt_lo) * a.nbins + f];
-        acc[g].x = fma(k, xv.x, acc[g].x);
-        acc[g].y = fma(k, xv.y, acc[g].y);
-        if (pair) {
-          const double2 xw = a.X[static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins + f];
-          accm[g].x = fma(k, xw.x, accm[g].x);
-          accm[g].y = fma(k, xw.y, accm[g].y);
+      const int row = 2 * (ib + 2 * r) + g;
+      const long long q0 = r < nr ? a.boff[row] : 0, q1 = r < nr ? a.boff[row + 1] : 0;
+      qb[r][g] = q0;
+      jf[r][g] = q1 > q0 ? a.pj[q0] : 0x3fffffff;
+      jl[r][g] = q1 > q0 ? a.pj[q0] + 2 * static_cast<int>(q1 - q0 - 1) : -0x3fffffff;
+    }
+  double2 acc[2][kMaxBins], accm[2][kMaxBins];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int u = 0; u < kMaxBins; ++u) {
+      acc[r][u] = double2{0.0, 0.0};
+      accm[r][u] = double2{0.0, 0.0};
+    }
+#pragma unroll
+  for (int gg = 0; gg < 2; ++gg) {
+    const int g = 1 - gg;
+    const int ju = min(jf[0][g], jf[1][g]), jv = max(jl[0][g], jl[1][g]);
+    for (int j = ju; j <= jv; j += 2) {
+      const double2* xr = a.X + static_cast<long long>(j - a.belt_lo) * a.nbins;
+      const double2* xm = a.X + static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins;
+      double2 xv[kMaxBins], xw[kMaxBins];
+#pragma unroll
+      for (int u = 0; u < kMaxBins; ++u) {
+        const int f = threadIdx.x + u * blockDim.x;
+        if (f < half) {
+          xv[u] = xr[f];
+          xw[u] = xm[f];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        if (j < jf[r][g] || j > jl[r][g]) continue;
+        const double* kr = a.K + (qb[r][g] + ((j - jf[r][g]) >> 1)) * a.nbins;
+#pragma unroll
+        for (int u = 0; u < kMaxBins; ++u) {
+          const int f = threadIdx.x + u * blockDim.x;
+          if (f >= half) continue;
+          const double k = kr[f];
+          acc[r][u].x = fma(k, xv[u].x, acc[r][u].x);
+          acc[r][u].y = fma(k, xv[u].y, acc[r][u].y);
+          accm[r][u].x = fma(k, xw[u].x, accm[r][u].x);
+          accm[r][u].y = fma(k, xw[u].y, accm[r][u].y);
         }
       }
     }
-    double sp, cp;
-    sincospi(static_cast<double>(f * dc) / static_cast<double>(a.n), &sp, &cp);
-    const double2 ph = double2{cp, sp};
-    const double2 t = cmul(ph, acc[1]), tm = cmul(ph, accm[1]);
-    put_conj(s_fft, double2{acc[0].x + t.x, acc[0].y + t.y}, f, a.n, a.logn);
-    ym[u] = double2{accm[0].x + tm.x, accm[0].y + tm.y};
-  }
-  inverse_out(s_fft, a, y + a.rstart[i]);
-  if (!pair) return;
+    if (g == 1) {
+      // the other group's phase exp(i pi f (c_i - c_j) / n), c_i - c_j = 2 c_i - 1 (belt offsets alternate)
+      const int dc = 2 * a.rc[i0] - 1;
 #pragma unroll
-  for (int u = 0; u < kMaxBinsPerThread; ++u) {
-    const int f = threadIdx.x + u * blockDim.x;
-    if (f >= a.nbins) break;
-    put_conj(s_fft, ym[u], f, a.n, a.logn);
+      for (int u = 0; u < kMaxBins; ++u) {
+        const int f = threadIdx.x + u * blockDim.x;
+        double sp, cp;
+        sincospi(static_cast<double>(f * dc) / static_cast<double>(a.n), &sp, &cp);
+        const double2 ph = double2{cp, sp};
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          acc[r][u] = cmul(ph, acc[r][u]);
+          accm[r][u] = cmul(ph, accm[r][u]);
+        }
+      }
+    }
   }
-  inverse_out(s_fft, a, y + a.rstart[mi]);
+  // f = n / 2 (real): wave 0, lanes striding over the same-offset pairs
+  double yn[2] = {0.0, 0.0}, ynm[2] = {0.0, 0.0};
+  if (threadIdx.x < 64) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const long long q1 = r < nr ? a.boff[2 * (ib + 2 * r) + 1] : 0;
+      for (long long q = qb[r][0] + threadIdx.x; q < q1; q += 64) {
+        const int j = a.pj[q];
+        const double k = a.K[q * a.nbins + half];
+        yn[r] = fma(k, a.X[static_cast<long long>(j - a.belt_lo) * a.nbins + half].x, yn[r]);
+        ynm[r] = fma(k, a.X[static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins + half].x, ynm[r]);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        yn[r] += __shfl_xor(yn[r], o);
+        ynm[r] += __shfl_xor(ynm[r], o);
+      }
+    }
+  }
+  const double scale = a.omega / static_cast<double>(a.n);
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    if (r >= nr) break;
+    const int i = i0 + 2 * r, mi = a.nrings - 1 - i;
+    // conj(Z): Z(f) = Y(f) + i M(f) and Z(n - f) = conj Y(f) + i conj M(f); Y(0), M(0) real
+#pragma unroll
+    for (int u = 0; u < kMaxBins; ++u) {
+      const int f = threadIdx.x + u * blockDim.x;
+      if (f >= half) continue;
+      const double2 Y = acc[r][u], M = accm[r][u];
+      if (f == 0) {
+        s_fft[0] = double2{Y.x, -M.x};
+      } else {
+        s_fft[bitrev(f, a.logn)] = double2{Y.x - M.y, -(Y.y + M.x)};
+        s_fft[bitrev(a.n - f, a.logn)] = double2{Y.x + M.y, Y.y - M.x};
+      }
+    }
+    if (threadIdx.x == 0) s_fft[bitrev(half, a.logn)] = double2{yn[r], -ynm[r]};
+    __syncthreads();
+    fft_stages(s_fft, a.n, a.tw);
+    T* yr = y + a.rstart[i];
+    T* ym = y + a.rstart[mi];
+    for (int m = threadIdx.x; m < a.n; m += blockDim.x) {
+      const double2 v = s_fft[m];
+      yr[m] = static_cast<T>(scale * v.x);
+      if (mi != i) ym[m] = static_cast<T>(-scale * v.y);
+    }
+    __syncthreads();
+  }
 }
 
 FftArgs make_fft_args(const conv_real_plan* p) {
@@ -218,6 +300,8 @@ FftArgs make_fft_args(const conv_real_plan* p) {
   a.logn = p->fft_logn;
   a.nbins = p->fft_n / 2 + 1;
   a.belt_lo = p->belt_lo;
+  a.nbelt = p->belt_hi - p->belt_lo + 1;
+  a.nnorth = (p->nrings - 1) / 2 - p->belt_lo + 1;
   a.nrings = p->nrings;
   a.n_tab = p->n_tab;
   a.inv_h = p->inv_h;
@@ -256,10 +340,11 @@ hipError_t ring_fft_apply_one(const conv_real_plan* p, const T* x, T* y, hipStre
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_fft_inverse_kernel<T>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ring_fft_forward_kernel<T>, dim3(nbelt), dim3(fft_threads(p->fft_n)), lds, st, a, x);
+  hipLaunchKernelGGL(ring_fft_forward_kernel<T>, dim3((nbelt + 1) / 2), dim3(fft_threads(p->fft_n)), lds, st, a, x);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   mark(p, st, "ring_fft_forward_kernel", 0);
-  hipLaunchKernelGGL(ring_fft_inverse_kernel<T>, dim3(nnorth), dim3(fft_threads(p->fft_n)), lds, st, a, y);
+  hipLaunchKernelGGL(ring_fft_inverse_kernel<T>, dim3(2 * ((nnorth + 3) / 4)), dim3(fft_threads(p->fft_n)), lds, st,
+                     a, y);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   mark(p, st, "ring_fft_inverse_kernel", p->pairs - p->pairs_rest);
   return hipSuccess;
