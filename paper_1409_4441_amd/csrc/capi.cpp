@@ -858,7 +858,7 @@ namespace {
 void release_ring_fft(conv_real_plan* p) {
   for (void* ptr : {static_cast<void*>(p->d_fft_tw), static_cast<void*>(p->d_fft_pi), static_cast<void*>(p->d_fft_pj),
                     static_cast<void*>(p->d_fft_pA), static_cast<void*>(p->d_fft_pB), static_cast<void*>(p->d_fft_boff),
-                    static_cast<void*>(p->d_fft_K), static_cast<void*>(p->d_fft_X),
+                    static_cast<void*>(p->d_fft_K), static_cast<void*>(p->d_fft_X), static_cast<void*>(p->d_fft_Y),
                     static_cast<void*>(p->d_mtile_ring), static_cast<void*>(p->d_mtile_a0)})
     release(p, ptr);
   p->d_mtile_ring = p->d_mtile_a0 = nullptr;
@@ -869,6 +869,7 @@ void release_ring_fft(conv_real_plan* p) {
   p->d_fft_boff = nullptr;
   p->d_fft_K = nullptr;
   p->d_fft_X = nullptr;
+  p->d_fft_Y = nullptr;
   p->fft_npairs = 0;
 }
 
@@ -969,6 +970,7 @@ hipError_t build_ring_fft(conv_real_plan* p) {
       (e = dev_upload(p, &p->d_fft_pB, fB)) != hipSuccess || (e = dev_upload(p, &p->d_fft_boff, boff)) != hipSuccess ||
       (e = dev_alloc(p, &p->d_fft_K, nbins * fi.size())) != hipSuccess ||
       (e = dev_alloc(p, &p->d_fft_X, nbins * static_cast<size_t>(bhi - blo + 1))) != hipSuccess ||
+      (e = dev_alloc(p, &p->d_fft_Y, nbins * static_cast<size_t>(bhi - blo + 1))) != hipSuccess ||
       (e = convreal::ring_fft_spectra(p)) != hipSuccess ||
       (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
       (e = convreal::launch_pair_count(p, true, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess)

@@ -240,6 +240,7 @@ struct conv_real_plan {
                                     // has the other azimuth offset (+ 1 entry)
   double* d_fft_K = nullptr;   // per belt pair: n / 2 + 1 real spectrum amplitudes of k_ij (phase removed)
   double2* d_fft_X = nullptr;  // per belt ring: n / 2 + 1 frequencies of one map's ring (workspace)
+  double2* d_fft_Y = nullptr;  // per belt ring: n / 2 + 1 frequencies of its output (workspace)
   int* d_mtile_ring = nullptr; // cap-touching pairs by symmetry: tiles of 16 fundamental-domain pixels
   int* d_mtile_a0 = nullptr;   // (one wave each) of the north-half rings that have such pairs
   int n_mtiles = 0;

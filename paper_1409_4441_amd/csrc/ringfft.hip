@@ -72,6 +72,7 @@ struct FftArgs {
                            // input ring with the other azimuth offset (2 entries a ring), + 1 entry
   double* K;               // per belt pair: nbins real amplitudes of the spectrum of k_ij
   double2* X;              // per belt ring (from belt_lo): nbins spectrum of x
+  double2* Y;              // per belt ring (from belt_lo): nbins spectrum of its belt-pair output
   int n, logn, nbins;
   int belt_lo;
   int nbelt;              // belt rings (from belt_lo)
@@ -137,149 +138,120 @@ __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_forward_kernel(FftArg
   }
 }
 
-constexpr int kMaxBins = 4;   // frequencies below n / 2 per thread (n / 2 <= 4 x 1024)
+constexpr int kAccThreads = 256;   // frequencies per workgroup (at most)
+constexpr long long kAccFill = 1 << 18;   // threads that keep every CU busy (256 CUs x 16 waves x 64)
 
-// Apply, one workgroup per two north belt output rings i and i + 2 (the same azimuth offset, so the
-// same split of their input rings into offset groups; the blocks of i + 1 and i + 3 read nearly the
-// same input spectra, and the launch keeps such blocks on one XCD) and their mirror rings m:
-//   Y_i = sum_j K_ij X_j,  Y_m = sum_j K_ij X_mirror(j)
-// per frequency (the mirror pair (m, mirror(j)) has the same chord constants and azimuth offsets, so
-// the same kernel spectrum, read once for both). Each input spectrum is loaded once for both output
-// rings. The group of input rings with the other azimuth offset is summed first and turned by the
-// half-pixel phase. At f = n / 2 only the same-offset group contributes (the other group's amplitude
-// vanishes there: its kernel is odd under the half-pixel reflection), summed by wave 0. The two real
-// outputs of a ring and its mirror come from one complex inverse FFT of Z = Y_i + i Y_m:
-// conj(Z) is transformed forward, y_i = Re / n and y_m = -Im / n. Belt rings are written (=);
-// cap-touching pairs are added later.
-template <typename T>
-__global__ __launch_bounds__(kFftMaxThreads) void ring_fft_inverse_kernel(FftArgs a, T* __restrict__ y) {
-  extern __shared__ double2 s_fft[];
-  const int nblk = 2 * ((a.nnorth + 3) / 4);
-  const int b = convreal::xcd_remap(static_cast<int>(blockIdx.x), nblk);
-  const int ib = 4 * (b >> 1) + (b & 1);
-  if (ib >= a.nnorth) return;
-  const int nr = ib + 2 < a.nnorth ? 2 : 1;
-  const int half = a.n / 2;
-  const int i0 = a.belt_lo + ib;
-  // per output ring r and offset group g (0: same offset, 1: the other): pairs [qb, qe), input rings
-  // jf, jf + 2, ..., jl
-  long long qb[2][2];
-  int jf[2][2], jl[2][2];
+// Apply, per frequency: Y_i = sum_j K_ij X_j and Y_m = sum_j K_ij X_mirror(j) for the north belt output
+// rings i and their mirror rings m (the mirror pair (m, mirror(j)) has the same chord constants and
+// azimuth offsets, so the same kernel spectrum, read once for both). One workgroup per run of
+// frequencies (one a thread) and group of kAccRings north rings i0, i0 + 2, ... (the same azimuth
+// offset, so the same split of the input rings into offset groups): each input spectrum value is
+// loaded once for all of them. The input rings with the other azimuth offset are summed first and
+// turned by the half-pixel phase. Work items are numbered ring group fastest, so that consecutive ones
+// share input spectra, and each XCD takes a contiguous run. kAccRings is the largest of 8, 4, 2, 1 that
+// still gives the launch kAccFill threads.
+template <int kAccRings>
+__global__ __launch_bounds__(kAccThreads) void ring_fft_accumulate_kernel(FftArgs a, int nchunks, int chunk_len,
+                                                                          int ngroups) {
+  const int item = convreal::xcd_remap(static_cast<int>(blockIdx.x), nchunks * ngroups);
+  const int grp = item % ngroups, chunk = item / ngroups;
+  const int ib0 = 2 * kAccRings * (grp >> 1) + (grp & 1);
+  if (ib0 >= a.nnorth) return;
+  const int nr = min(kAccRings, (a.nnorth - ib0 + 1) / 2);   // rings ib0 + 2 r below nnorth
+  const int f = chunk * chunk_len + static_cast<int>(threadIdx.x);
+  const bool live = static_cast<int>(threadIdx.x) < chunk_len && f < a.nbins;
+  const int fl = live ? f : 0;   // idle lanes read frequency 0 and store nothing
+  double2 acc[kAccRings], accm[kAccRings];
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      const int row = 2 * (ib + 2 * r) + g;
-      const long long q0 = r < nr ? a.boff[row] : 0, q1 = r < nr ? a.boff[row + 1] : 0;
-      qb[r][g] = q0;
-      jf[r][g] = q1 > q0 ? a.pj[q0] : 0x3fffffff;
-      jl[r][g] = q1 > q0 ? a.pj[q0] + 2 * static_cast<int>(q1 - q0 - 1) : -0x3fffffff;
-    }
-  double2 acc[2][kMaxBins], accm[2][kMaxBins];
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int u = 0; u < kMaxBins; ++u) {
-      acc[r][u] = double2{0.0, 0.0};
-      accm[r][u] = double2{0.0, 0.0};
-    }
+  for (int r = 0; r < kAccRings; ++r) {
+    acc[r] = double2{0.0, 0.0};
+    accm[r] = double2{0.0, 0.0};
+  }
 #pragma unroll
   for (int gg = 0; gg < 2; ++gg) {
-    const int g = 1 - gg;
-    const int ju = min(jf[0][g], jf[1][g]), jv = max(jl[0][g], jl[1][g]);
+    const int g = 1 - gg;   // 1: the other azimuth offset, 0: the same
+    // per ring: pairs [qb, qb + cnt) with input rings jf, jf + 2, ...; their union
+    long long qb[kAccRings];
+    int jf[kAccRings], jl[kAccRings];
+    int ju = 0x3fffffff, jv = -0x3fffffff;
+#pragma unroll
+    for (int r = 0; r < kAccRings; ++r) {
+      const int row = 2 * (ib0 + 2 * r) + g;
+      const long long q0 = r < nr ? a.boff[row] : 0, q1 = r < nr ? a.boff[row + 1] : 0;
+      qb[r] = q0;
+      jf[r] = q1 > q0 ? a.pj[q0] : 0x3fffffff;
+      jl[r] = q1 > q0 ? a.pj[q0] + 2 * static_cast<int>(q1 - q0 - 1) : -0x3fffffff;
+      ju = min(ju, jf[r]);
+      jv = max(jv, jl[r]);
+    }
     for (int j = ju; j <= jv; j += 2) {
-      const double2* xr = a.X + static_cast<long long>(j - a.belt_lo) * a.nbins;
-      const double2* xm = a.X + static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins;
-      double2 xv[kMaxBins], xw[kMaxBins];
+      const double2 xv = a.X[static_cast<long long>(j - a.belt_lo) * a.nbins + fl];
+      const double2 xw = a.X[static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins + fl];
 #pragma unroll
-      for (int u = 0; u < kMaxBins; ++u) {
-        const int f = threadIdx.x + u * blockDim.x;
-        if (f < half) {
-          xv[u] = xr[f];
-          xw[u] = xm[f];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        if (j < jf[r][g] || j > jl[r][g]) continue;
-        const double* kr = a.K + (qb[r][g] + ((j - jf[r][g]) >> 1)) * a.nbins;
-#pragma unroll
-        for (int u = 0; u < kMaxBins; ++u) {
-          const int f = threadIdx.x + u * blockDim.x;
-          if (f >= half) continue;
-          const double k = kr[f];
-          acc[r][u].x = fma(k, xv[u].x, acc[r][u].x);
-          acc[r][u].y = fma(k, xv[u].y, acc[r][u].y);
-          accm[r][u].x = fma(k, xw[u].x, accm[r][u].x);
-          accm[r][u].y = fma(k, xw[u].y, accm[r][u].y);
-        }
+      for (int r = 0; r < kAccRings; ++r) {
+        if (j < jf[r] || j > jl[r]) continue;
+        const double k = a.K[(qb[r] + ((j - jf[r]) >> 1)) * a.nbins + fl];
+        acc[r].x = fma(k, xv.x, acc[r].x);
+        acc[r].y = fma(k, xv.y, acc[r].y);
+        accm[r].x = fma(k, xw.x, accm[r].x);
+        accm[r].y = fma(k, xw.y, accm[r].y);
       }
     }
     if (g == 1) {
       // the other group's phase exp(i pi f (c_i - c_j) / n), c_i - c_j = 2 c_i - 1 (belt offsets alternate)
-      const int dc = 2 * a.rc[i0] - 1;
+      const int dc = 2 * a.rc[a.belt_lo + ib0] - 1;
+      double sp, cp;
+      sincospi(static_cast<double>(fl * dc) / static_cast<double>(a.n), &sp, &cp);
+      const double2 ph = double2{cp, sp};
 #pragma unroll
-      for (int u = 0; u < kMaxBins; ++u) {
-        const int f = threadIdx.x + u * blockDim.x;
-        double sp, cp;
-        sincospi(static_cast<double>(f * dc) / static_cast<double>(a.n), &sp, &cp);
-        const double2 ph = double2{cp, sp};
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-          acc[r][u] = cmul(ph, acc[r][u]);
-          accm[r][u] = cmul(ph, accm[r][u]);
-        }
+      for (int r = 0; r < kAccRings; ++r) {
+        acc[r] = cmul(ph, acc[r]);
+        accm[r] = cmul(ph, accm[r]);
       }
     }
   }
-  // f = n / 2 (real): wave 0, lanes striding over the same-offset pairs
-  double yn[2] = {0.0, 0.0}, ynm[2] = {0.0, 0.0};
-  if (threadIdx.x < 64) {
+  if (!live) return;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const long long q1 = r < nr ? a.boff[2 * (ib + 2 * r) + 1] : 0;
-      for (long long q = qb[r][0] + threadIdx.x; q < q1; q += 64) {
-        const int j = a.pj[q];
-        const double k = a.K[q * a.nbins + half];
-        yn[r] = fma(k, a.X[static_cast<long long>(j - a.belt_lo) * a.nbins + half].x, yn[r]);
-        ynm[r] = fma(k, a.X[static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins + half].x, ynm[r]);
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        yn[r] += __shfl_xor(yn[r], o);
-        ynm[r] += __shfl_xor(ynm[r], o);
-      }
-    }
-  }
-  const double scale = a.omega / static_cast<double>(a.n);
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
+  for (int r = 0; r < kAccRings; ++r) {
     if (r >= nr) break;
-    const int i = i0 + 2 * r, mi = a.nrings - 1 - i;
-    // conj(Z): Z(f) = Y(f) + i M(f) and Z(n - f) = conj Y(f) + i conj M(f); Y(0), M(0) real
-#pragma unroll
-    for (int u = 0; u < kMaxBins; ++u) {
-      const int f = threadIdx.x + u * blockDim.x;
-      if (f >= half) continue;
-      const double2 Y = acc[r][u], M = accm[r][u];
-      if (f == 0) {
-        s_fft[0] = double2{Y.x, -M.x};
-      } else {
-        s_fft[bitrev(f, a.logn)] = double2{Y.x - M.y, -(Y.y + M.x)};
-        s_fft[bitrev(a.n - f, a.logn)] = double2{Y.x + M.y, Y.y - M.x};
-      }
+    const int i = a.belt_lo + ib0 + 2 * r, mi = a.nrings - 1 - i;
+    a.Y[static_cast<long long>(i - a.belt_lo) * a.nbins + f] = acc[r];
+    if (mi != i) a.Y[static_cast<long long>(mi - a.belt_lo) * a.nbins + f] = accm[r];
+  }
+}
+
+// Apply, one workgroup per north belt output ring i and its mirror ring m (the equator ring alone): both
+// real outputs from one complex inverse FFT of Z = Y_i + i Y_m. conj(Z) is transformed forward, and
+// y_i = Re / n, y_m = -Im / n, with Z(f) = Y(f) + i M(f) and Z(n - f) = conj Y(f) + i conj M(f); at
+// f = 0 and n / 2 the spectra of real rings are real (the other offset group's amplitude vanishes at
+// n / 2: its kernel is odd under the half-pixel reflection there), so only their real parts enter. Belt
+// rings are written (=); cap-touching pairs are added later.
+template <typename T>
+__global__ __launch_bounds__(kFftMaxThreads) void ring_fft_inverse_kernel(FftArgs a, T* __restrict__ y) {
+  extern __shared__ double2 s_fft[];
+  const int ib = static_cast<int>(blockIdx.x);
+  const int i = a.belt_lo + ib, mi = a.nrings - 1 - i;
+  const int half = a.n / 2;
+  const double2* Yi = a.Y + static_cast<long long>(ib) * a.nbins;
+  const double2* Ym = a.Y + static_cast<long long>(mi - a.belt_lo) * a.nbins;
+  for (int f = threadIdx.x; f <= half; f += blockDim.x) {
+    const double2 Y = Yi[f], M = mi != i ? Ym[f] : double2{0.0, 0.0};
+    if (f == 0 || f == half) {
+      s_fft[bitrev(f, a.logn)] = double2{Y.x, -M.x};
+    } else {
+      s_fft[bitrev(f, a.logn)] = double2{Y.x - M.y, -(Y.y + M.x)};
+      s_fft[bitrev(a.n - f, a.logn)] = double2{Y.x + M.y, Y.y - M.x};
     }
-    if (threadIdx.x == 0) s_fft[bitrev(half, a.logn)] = double2{yn[r], -ynm[r]};
-    __syncthreads();
-    fft_stages(s_fft, a.n, a.tw);
-    T* yr = y + a.rstart[i];
-    T* ym = y + a.rstart[mi];
-    for (int m = threadIdx.x; m < a.n; m += blockDim.x) {
-      const double2 v = s_fft[m];
-      yr[m] = static_cast<T>(scale * v.x);
-      if (mi != i) ym[m] = static_cast<T>(-scale * v.y);
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+  fft_stages(s_fft, a.n, a.tw);
+  const double scale = a.omega / static_cast<double>(a.n);
+  T* yr = y + a.rstart[i];
+  T* ym = y + a.rstart[mi];
+  for (int m = threadIdx.x; m < a.n; m += blockDim.x) {
+    const double2 v = s_fft[m];
+    yr[m] = static_cast<T>(scale * v.x);
+    if (mi != i) ym[m] = static_cast<T>(-scale * v.y);
   }
 }
 
@@ -296,6 +268,7 @@ FftArgs make_fft_args(const conv_real_plan* p) {
   a.boff = p->d_fft_boff;
   a.K = p->d_fft_K;
   a.X = p->d_fft_X;
+  a.Y = p->d_fft_Y;
   a.n = p->fft_n;
   a.logn = p->fft_logn;
   a.nbins = p->fft_n / 2 + 1;
@@ -343,10 +316,31 @@ hipError_t ring_fft_apply_one(const conv_real_plan* p, const T* x, T* y, hipStre
   hipLaunchKernelGGL(ring_fft_forward_kernel<T>, dim3((nbelt + 1) / 2), dim3(fft_threads(p->fft_n)), lds, st, a, x);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   mark(p, st, "ring_fft_forward_kernel", 0);
-  hipLaunchKernelGGL(ring_fft_inverse_kernel<T>, dim3(2 * ((nnorth + 3) / 4)), dim3(fft_threads(p->fft_n)), lds, st,
-                     a, y);
+  const int nchunks = (a.nbins + kAccThreads - 1) / kAccThreads;
+  const int chunk_len = (a.nbins + nchunks - 1) / nchunks;
+  auto groups = [&](int rings) { return 2 * ((a.nnorth + 2 * rings - 1) / (2 * rings)); };
+  int rings = 8;
+  while (rings > 1 && static_cast<long long>(a.nbins) * groups(rings) < kAccFill) rings /= 2;
+  const int ngroups = groups(rings);
+  const dim3 grid(static_cast<unsigned>(nchunks * ngroups));
+  switch (rings) {
+    case 8:
+      hipLaunchKernelGGL(ring_fft_accumulate_kernel<8>, grid, dim3(kAccThreads), 0, st, a, nchunks, chunk_len, ngroups);
+      break;
+    case 4:
+      hipLaunchKernelGGL(ring_fft_accumulate_kernel<4>, grid, dim3(kAccThreads), 0, st, a, nchunks, chunk_len, ngroups);
+      break;
+    case 2:
+      hipLaunchKernelGGL(ring_fft_accumulate_kernel<2>, grid, dim3(kAccThreads), 0, st, a, nchunks, chunk_len, ngroups);
+      break;
+    default:
+      hipLaunchKernelGGL(ring_fft_accumulate_kernel<1>, grid, dim3(kAccThreads), 0, st, a, nchunks, chunk_len, ngroups);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  mark(p, st, "ring_fft_inverse_kernel", p->pairs - p->pairs_rest);
+  mark(p, st, "ring_fft_accumulate_kernel", p->pairs - p->pairs_rest);
+  hipLaunchKernelGGL(ring_fft_inverse_kernel<T>, dim3(nnorth), dim3(fft_threads(p->fft_n)), lds, st, a, y);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  mark(p, st, "ring_fft_inverse_kernel", 0);
   return hipSuccess;
 }
 

@@ -86,6 +86,21 @@ def test_ring_fft_equals_direct_and_oracle_nside128(cuda_device):
     _check(y_fft[:, pix], ref)
 
 
+def test_ring_fft_nside1024_groups_of_eight(cuda_device):
+    """At Nside 1024 the belt sums run on groups of eight output rings per workgroup (small grids use
+    one): equal to the direct method to rounding, and to the oracle on sampled pixels."""
+    nside, tc = 1024, 30.0 / 60.0 * DEG
+    T = _table(tc / 4, tc, n_tab=1024, lmax=1024)
+    x = synth.white_noise(nside, 1, seed=77)
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        y_direct = _run(plan, x)
+        plan.set_method("ring_fft")
+        y_fft = _run(plan, x)
+    _check(y_fft, y_direct)
+    pix = np.random.default_rng(8).choice(x.shape[1], 400, replace=False)
+    _check(y_fft[:, pix], oc.convolve_sampled(nside, T, tc, x, pix))
+
+
 def test_ring_fft_only_where_defined(cuda_device):
     T = _table(3 * DEG, 9 * DEG)
     with cr.Plan(8, T, 9 * DEG, "f32") as plan:
