@@ -201,8 +201,9 @@ int conv_real_get_weight_store(const conv_real_plan* plan, int* active, long lon
  *   CONV_REAL_METHOD_DIRECT    every pixel pair summed directly (the default)
  *   CONV_REAL_METHOD_RING_FFT  belt ring pairs as a product per frequency of the input ring's
  *                              spectrum and the pair's kernel spectrum (computed once here, FP64,
- *                              (n/2 + 1) x 16 bytes per belt ring pair, n = 4 Nside), one inverse
- *                              FFT per output ring; ring pairs touching a polar cap summed per
+ *                              (n/2 + 1) x 8 bytes per belt ring pair of a north output ring, n =
+ *                              4 Nside; plus two spectrum workspaces of (n/2 + 1) x 16 bytes per belt
+ *                              ring), inverse FFTs per output ring; ring pairs touching a polar cap summed per
  *                              pair, each weight once for the 16 images of its symmetry orbit (FP64
  *                              matrix cores). Same pairs and kernel values as DIRECT; results differ
  *                              by FP64 rounding only. Requires a power-of-two nside <= 2048 (EINVAL
