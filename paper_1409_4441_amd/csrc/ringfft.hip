@@ -187,10 +187,18 @@ __global__ __launch_bounds__(kAccThreads) void ring_fft_accumulate_kernel(FftArg
     for (int j = ju; j <= jv; j += 2) {
       const double2 xv = a.X[static_cast<long long>(j - a.belt_lo) * a.nbins + fl];
       const double2 xw = a.X[static_cast<long long>(a.nrings - 1 - j - a.belt_lo) * a.nbins + fl];
+      // every ring's amplitude is loaded before any is used (a ring outside its range reads pair 0,
+      // which always exists, and takes 0), so that the loads overlap
+      double kv[kAccRings];
 #pragma unroll
       for (int r = 0; r < kAccRings; ++r) {
-        if (j < jf[r] || j > jl[r]) continue;
-        const double k = a.K[(qb[r] + ((j - jf[r]) >> 1)) * a.nbins + fl];
+        const bool in = j >= jf[r] && j <= jl[r];
+        kv[r] = a.K[(in ? qb[r] + ((j - jf[r]) >> 1) : 0) * a.nbins + fl];
+        kv[r] = in ? kv[r] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < kAccRings; ++r) {
+        const double k = kv[r];
         acc[r].x = fma(k, xv.x, acc[r].x);
         acc[r].y = fma(k, xv.y, acc[r].y);
         accm[r].x = fma(k, xw.x, accm[r].x);
