@@ -112,7 +112,9 @@ int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_
  *   nmaps      >= 1
  *   stream     hipStream_t to launch on (NULL = default stream)
  *
- * Asynchronous on stream; no host synchronisation, no allocation.
+ * Asynchronous on stream; no host synchronisation, no allocation. Applies of one plan must not run
+ * at the same time on different streams: the plan's work-queue counters and (ring-FFT method) its
+ * spectrum workspaces are per plan.
  */
 int conv_real_apply(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps,
                     void* stream);
