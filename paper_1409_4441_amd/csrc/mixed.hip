@@ -446,13 +446,18 @@ __device__ __forceinline__ void load_inputs(const float* __restrict__ xj, int po
     for (int e = 0; e < E; ++e)
       v[e] = __uint_as_float((fwd & __float_as_uint(L[e])) | (~fwd & __float_as_uint(L[E - 1 - e]))) * sx;
   } else {
+    int ix[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       int idx = p0 + dir * e;
       idx = idx < 0 ? idx + nj : idx;
-      idx = idx >= nj ? idx - nj : idx;
-      v[e] = xj[idx] * sx;
+      ix[e] = idx >= nj ? idx - nj : idx;
     }
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = xj[ix[e]];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] *= sx;
   }
   split_fp16<E>(v, xhi, xlo);
 }
@@ -757,12 +762,17 @@ struct StoreIter {
     }
     const float* xj = xm + xoff;
     for (int q = 0; q < nk; ++q) {
+      // indices first, then all loads, then the scaling; the scheduling barrier keeps the compiler
+      // from pairing each load with its use, so that the 8 loads are in flight together
+      int ix[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ix[e] = mod_any(pofs + L.dir * (first + 32 * q + 16 * (e >> 2) + (e & 3)), nj, rcp_n);
       float v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int bb = first + 32 * q + 16 * (e >> 2) + (e & 3);
-        v[e] = xj[mod_any(pofs + L.dir * bb, nj, rcp_n)] * sx;
-      }
+      for (int e = 0; e < 8; ++e) v[e] = xj[ix[e]];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] *= sx;
       half8 xhi, xlo;
       split_fp16<8>(v, xhi, xlo);
 #pragma unroll
@@ -934,9 +944,15 @@ __device__ __forceinline__ void cap_rows_fly(const convreal::MixedDesc* __restri
         const int bA = b0 + 32 * q + 8 * L.kgrp;
         half8 xhi, xlo;
         {
+          int ix[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) ix[e] = mod_any(pofs + L.dir * (bA + e), nj, rcp_n);
           float v[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = xj[mod_any(pofs + L.dir * (bA + e), nj, rcp_n)] * sx;
+          for (int e = 0; e < 8; ++e) v[e] = xj[ix[e]];
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int e = 0; e < 8; ++e) v[e] *= sx;
           split_fp16<8>(v, xhi, xlo);
         }
         double qv[8];
