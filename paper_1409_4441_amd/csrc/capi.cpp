@@ -859,8 +859,10 @@ void release_ring_fft(conv_real_plan* p) {
   for (void* ptr : {static_cast<void*>(p->d_fft_tw), static_cast<void*>(p->d_fft_pi), static_cast<void*>(p->d_fft_pj),
                     static_cast<void*>(p->d_fft_pA), static_cast<void*>(p->d_fft_pB), static_cast<void*>(p->d_fft_boff),
                     static_cast<void*>(p->d_fft_K), static_cast<void*>(p->d_fft_X), static_cast<void*>(p->d_fft_Y),
-                    static_cast<void*>(p->d_mtile_ring), static_cast<void*>(p->d_mtile_a0)})
+                    static_cast<void*>(p->d_mtile_ring), static_cast<void*>(p->d_mtile_a0),
+                    static_cast<void*>(p->d_fft_cpair)})
     release(p, ptr);
+  p->d_fft_cpair = nullptr;
   p->d_mtile_ring = p->d_mtile_a0 = nullptr;
   p->n_mtiles = 0;
   p->d_fft_tw = nullptr;
@@ -882,10 +884,11 @@ hipError_t build_ring_fft(conv_real_plan* p) {
   convreal::neighbour_rings(g, p->dcut2, jlo, jhi);
   std::vector<long long> poff(g.nrings + 1, 0);
   for (int r = 0; r < g.nrings; ++r) poff[r + 1] = poff[r] + (jhi[r] - jlo[r] + 1);
-  std::vector<double> pA(p->npairs_ring), pB(p->npairs_ring);
+  std::vector<double> pA(p->npairs_ring), pB(p->npairs_ring), phw(p->npairs_ring);
   hipError_t e;
   if ((e = hipMemcpy(pA.data(), p->d_pA, sizeof(double) * pA.size(), hipMemcpyDeviceToHost)) != hipSuccess ||
-      (e = hipMemcpy(pB.data(), p->d_pB, sizeof(double) * pB.size(), hipMemcpyDeviceToHost)) != hipSuccess)
+      (e = hipMemcpy(pB.data(), p->d_pB, sizeof(double) * pB.size(), hipMemcpyDeviceToHost)) != hipSuccess ||
+      (e = hipMemcpy(phw.data(), p->d_phw, sizeof(double) * phw.size(), hipMemcpyDeviceToHost)) != hipSuccess)
     return e;
   const int blo = N - 1, bhi = 3 * N - 1;   // belt rings (0-based): 4 N pixels each
   // kernel spectra of the north belt output rings through the equator; a south ring uses its
@@ -915,12 +918,25 @@ hipError_t build_ring_fft(conv_real_plan* p) {
   for (int r = blo; r < bhi; ++r)
     if (g.c[r + 1] + g.c[r] != 1) return hipErrorInvalidValue;
   std::vector<long long> roff(g.nrings + 1, 0), ridx;
+  std::vector<convreal::CapPair64> rrec;   // the listed pairs as the FP64 cap kernel reads them
   std::vector<int> rtile_ring, rtile_a0;
   for (int r = 0; r < g.nrings; ++r) {
     const bool belt_row = r >= blo && r <= bhi;
     for (long long k = poff[r]; k < poff[r + 1]; ++k) {
       const int j = jlo[r] + static_cast<int>(k - poff[r]);
-      if (!belt_row || j < blo || j > bhi) ridx.push_back(k);
+      if (belt_row && j >= blo && j <= bhi) continue;
+      ridx.push_back(k);
+      convreal::CapPair64 c{};
+      c.A = pA[k];
+      c.B = pB[k];
+      c.hw = phw[k];
+      c.sd = std::sin(M_PI / g.n[j]);   // the per-ring tables' values
+      c.cd = std::cos(M_PI / g.n[j]);
+      c.nj = g.n[j];
+      c.cj = g.c[j];
+      c.xoff = static_cast<int>(g.start[j]);
+      c.xoff_m = static_cast<int>(g.start[g.nrings - 1 - j]);
+      rrec.push_back(c);
     }
     roff[r + 1] = static_cast<long long>(ridx.size());
     if (roff[r + 1] > roff[r])
@@ -961,6 +977,7 @@ hipError_t build_ring_fft(conv_real_plan* p) {
   p->n_mtiles = static_cast<int>(mtile_ring.size());
   if ((e = dev_upload(p, &p->d_rest_off, roff)) != hipSuccess ||
       (e = dev_upload(p, &p->d_rest_idx, ridx)) != hipSuccess ||
+      (e = dev_upload(p, &p->d_fft_cpair, rrec)) != hipSuccess ||
       (e = dev_upload(p, &p->d_rtile_ring, rtile_ring)) != hipSuccess ||
       (e = dev_upload(p, &p->d_rtile_a0, rtile_a0)) != hipSuccess ||
       (e = dev_upload(p, &p->d_mtile_ring, mtile_ring)) != hipSuccess ||

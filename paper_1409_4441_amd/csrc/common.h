@@ -26,6 +26,18 @@ __device__ __forceinline__ T ldu(const T& ref) {
   return *(const __attribute__((address_space(4))) T*)(&ref);
 }
 
+// ldu for a record, word by word (the words merge into one wide scalar load)
+template <typename T>
+__device__ __forceinline__ T ldu_record(const T& ref) {
+  static_assert(sizeof(T) % 4 == 0, "records are whole 32-bit words");
+  T out;
+  const __attribute__((address_space(4))) unsigned* src = (const __attribute__((address_space(4))) unsigned*)(&ref);
+  unsigned* dst = reinterpret_cast<unsigned*>(&out);
+#pragma unroll
+  for (int k = 0; k < static_cast<int>(sizeof(T) / 4); ++k) dst[k] = src[k];
+  return out;
+}
+
 // Blocks are dealt round-robin to the 8 XCDs of the MI355X; give each XCD a contiguous run of
 // work items so that items sharing neighbour rings share an L2. Bijective on [0, n).
 __device__ __forceinline__ int xcd_remap(int b, int n) {

@@ -66,6 +66,22 @@ struct CapPair {
 };
 static_assert(sizeof(CapPair) == 64, "CapPair is one 64-byte record");
 
+// One cap-touching ring pair as the ring-FFT method's FP64 cap kernel reads it: one 64-byte record,
+// fetched with a single scalar load per pair and tile (pixel offsets fit 32 bits: Nside <= 2048).
+struct CapPair64 {
+  double A;          // (z_i - z_j)^2 + (s_i - s_j)^2
+  double B;          // 4 s_i s_j
+  double hw;         // window half-width in pixels of ring j
+  double sd;         // sin(pi / n_j)
+  double cd;         // cos(pi / n_j)
+  int nj;            // pixels of ring j
+  int cj;            // azimuth offset numerator of ring j
+  int xoff;          // first pixel of ring j
+  int xoff_m;        // first pixel of the north/south mirror of ring j
+  int pad[2];
+};
+static_assert(sizeof(CapPair64) == 64, "CapPair64 is one 64-byte record");
+
 // Everything the mixed path's device routines read about one plan (lives in device memory).
 struct MixedDesc {
   // geometry
@@ -241,6 +257,7 @@ struct conv_real_plan {
   double* d_fft_K = nullptr;   // per belt pair: n / 2 + 1 real spectrum amplitudes of k_ij (phase removed)
   double2* d_fft_X = nullptr;  // per belt ring: n / 2 + 1 frequencies of one map's ring (workspace)
   double2* d_fft_Y = nullptr;  // per belt ring: n / 2 + 1 frequencies of its output (workspace)
+  convreal::CapPair64* d_fft_cpair = nullptr;  // per listed cap-touching pair (d_rest_idx order)
   int* d_mtile_ring = nullptr; // cap-touching pairs by symmetry: tiles of 16 fundamental-domain pixels
   int* d_mtile_a0 = nullptr;   // (one wave each) of the north-half rings that have such pairs
   int n_mtiles = 0;

@@ -59,18 +59,7 @@ constexpr int kNKMax = 4;  // largest K-chunk count of a belt weight block
 using convreal::buffer_resource;
 using convreal::kNoLoad;
 using convreal::ldu;
-
-// ldu for a record, word by word (the words merge into one wide scalar load)
-template <typename T>
-__device__ __forceinline__ T ldu_record(const T& ref) {
-  static_assert(sizeof(T) % 4 == 0, "records are whole 32-bit words");
-  T out;
-  const __attribute__((address_space(4))) unsigned* src = (const __attribute__((address_space(4))) unsigned*)(&ref);
-  unsigned* dst = reinterpret_cast<unsigned*>(&out);
-#pragma unroll
-  for (int k = 0; k < static_cast<int>(sizeof(T) / 4); ++k) dst[k] = src[k];
-  return out;
-}
+using convreal::ldu_record;
 
 // power of two s with max|x| * s in [2^12, 2^13)
 __device__ __forceinline__ float map_scale(unsigned bits) {

@@ -51,6 +51,7 @@ struct PairArgs {
   const double* phw;
   const int* tile_ring;
   const int* tile_a0;
+  const convreal::CapPair64* cpair;   // per listed pair (the FP64 cap kernel), else nullptr
   int ntiles;
   int n_tab;
   int belt_lo;            // rings [belt_lo, belt_hi] get y += (remainder mode); others y =
@@ -295,13 +296,15 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void cap_mfma64_kernel(PairArgs a,
   const int img = lane & 15, ih = img >> 3, ifl = (img >> 2) & 1, iq = img & 3;
   doublex4 acc = {0.0, 0.0, 0.0, 0.0};
   const long long k0 = ldu(ldu(a.off)[r]), k1 = ldu(ldu(a.off)[r + 1]);
-  const long long* idx = ldu(a.idx);
+  const convreal::CapPair64* cpair = ldu(a.cpair);
+  convreal::CapPair64 Pn;   // record kk, loaded one pair ahead of its use
+  if (k0 < k1) Pn = convreal::ldu_record(cpair[k0]);
   for (long long kk = k0; kk < k1; ++kk) {
-    const long long k = idx ? ldu(idx[kk]) : kk;
-    const int j = ldu(ldu(a.pj)[k]);
-    const int nj = ldu(ldu(a.rn)[j]);
-    const int cj = ldu(ldu(a.rc)[j]);
-    const double hw = ldu(ldu(a.phw)[k]);
+    const convreal::CapPair64 P = Pn;
+    if (kk + 1 < k1) Pn = convreal::ldu_record(cpair[kk + 1]);
+    const int nj = P.nj;
+    const int cj = P.cj;
+    const double hw = P.hw;
     // this row's window [blo, blo + nb) of ring j: the bounds of ring_walk, the centre through the
     // tile's reciprocal of 2 n_i (the window keeps its 1e-7 margin; the cut test decides membership)
     int blo = 0, nb = 0;
@@ -324,11 +327,11 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void cap_mfma64_kernel(PairArgs a,
     }
     const int b0 = __builtin_amdgcn_readfirstlane(lo), bend = __builtin_amdgcn_readfirstlane(hi);
     if (bend < b0) continue;
-    const double A = ldu(ldu(a.pA)[k]), B = ldu(ldu(a.pB)[k]);
-    const double* xs = x + ldu(ldu(a.rstart)[ih ? nrings - 1 - j : j]);
+    const double A = P.A, B = P.B;
+    const double* xs = x + (ih ? P.xoff_m : P.xoff);
     // rotation by 4 input pixels (alpha -> alpha - 4 pi / n_j) from the ring's sin and cos of pi / n_j
     // by two angle doublings
-    const double sd = ldu(ldu(a.rsd)[j]), cd = ldu(ldu(a.rcd)[j]);
+    const double sd = P.sd, cd = P.cd;
     const double s2 = 2.0 * sd * cd, c2 = fma(-2.0 * sd, sd, 1.0);
     const double s4 = 2.0 * s2 * c2, c4 = fma(-2.0 * s2, s2, 1.0);
     // alpha seeds: numerator (2a + c_i) n_j - (2b + c_j) n_i reduced modulo m2 = 2 n_i n_j (exact
@@ -436,6 +439,7 @@ PairArgs make_args(const conv_real_plan* p, bool remainder) {
   a.pA = p->d_pA;
   a.pB = p->d_pB;
   a.phw = p->d_phw;
+  a.cpair = nullptr;
   if (remainder) {
     a.off = p->d_rest_off;
     a.idx = p->d_rest_idx;
@@ -534,6 +538,7 @@ hipError_t launch_cap_mfma64(const conv_real_plan* p, const double* x, double* y
   PairArgs a = make_args(p, true);
   a.tile_ring = p->d_mtile_ring;
   a.tile_a0 = p->d_mtile_a0;
+  a.cpair = p->d_fft_cpair;
   a.ntiles = p->n_mtiles;
   if (a.ntiles == 0) return hipSuccess;
   const bool coef = a.coef != nullptr;
