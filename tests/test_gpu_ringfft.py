@@ -86,10 +86,12 @@ def test_ring_fft_equals_direct_and_oracle_nside128(cuda_device):
     _check(y_fft[:, pix], ref)
 
 
-def test_ring_fft_nside1024_groups_of_eight(cuda_device):
-    """At Nside 1024 the belt sums run on groups of eight output rings per workgroup (small grids use
-    one): equal to the direct method to rounding, and to the oracle on sampled pixels."""
-    nside, tc = 1024, 30.0 / 60.0 * DEG
+@pytest.mark.parametrize("nside", [512, 1024])
+def test_ring_fft_ring_groups(cuda_device, nside):
+    """The belt sums run on groups of output rings per workgroup, as many as still fill the chip: two
+    at Nside 512, eight at Nside 1024 (one on the smaller grids above). Equal to the direct method to
+    rounding, and to the oracle on sampled pixels."""
+    tc = 30.0 / 60.0 * DEG
     T = _table(tc / 4, tc, n_tab=1024, lmax=1024)
     x = synth.white_noise(nside, 1, seed=77)
     with cr.Plan(nside, T, tc, "f64") as plan:
