@@ -267,10 +267,13 @@ __global__ __launch_bounds__(kTile * kGroups) void pair_accumulate_kernel(PairAr
 // (pixels on a reflection axis, the equator ring's mirror) are written once; belt rings get y +=,
 // cap rings y =. One FP64 map per launch.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
-constexpr int kMfmaWaves = 16;   // tiles per workgroup (the table is staged once for all of them)
+// tiles per workgroup (the table is staged once for all of them): the 64 KB table allows two
+// workgroups per CU, so 12 waves each give 6 waves per SIMD (register budget 80; 16 waves gave 4, and
+// 10 waves 5; 12 was fastest at Nside 2048)
+constexpr int kMfmaWaves = 12;
 
 template <bool kCoef>
-__global__ __launch_bounds__(64 * kMfmaWaves) void cap_mfma64_kernel(PairArgs a, const double* __restrict__ x,
+__global__ __launch_bounds__(64 * kMfmaWaves, kMfmaWaves / 2) void cap_mfma64_kernel(PairArgs a, const double* __restrict__ x,
                                                            double* __restrict__ y, int nrings) {
   extern __shared__ double s_tab[];
   const int nwords = kCoef ? 4 * (a.n_tab - 2) : a.n_tab;
