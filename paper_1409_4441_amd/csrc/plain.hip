@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kTile * kGroups) void pair_accumulate_kernel(PairAr
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 // tiles per workgroup (the table is staged once for all of them): the 64 KB table allows two
 // workgroups per CU, so 12 waves each give 6 waves per SIMD (register budget 80; 16 waves gave 4, and
-// 10 waves 5; 12 was fastest at Nside 2048)
+// 10 waves 5; 12 was fastest at Nside 2048, 14 (7 per SIMD, 72 registers) spilled and lost 19%)
 constexpr int kMfmaWaves = 12;
 
 template <bool kCoef>
