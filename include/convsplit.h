@@ -32,8 +32,8 @@ typedef struct conv_split_ctx conv_split_ctx;
  *   c_in       lmax + 1 values of the input spectrum C^in_l (host, copied); NULL means C^in = 1,
  *              the paper's choice
  *   theta_max  largest theta_cut that will be asked about, 0 < theta_max <= pi (radians)
- *   sv_cut     eigenvalue cutoff of the least-squares solve, relative to the largest (the paper
- *              uses 1e-6); 0 < sv_cut < 1
+ *   sv_cut     singular-value cutoff of the least-squares solve, relative to the largest (the
+ *              paper drops singular values below 1e-6); 0 < sv_cut < 1
  * Computes the (lmax + 1)-point Gauss-Legendre nodes with z > cos(theta_max) (the real-space
  * samples) and the Legendre operator P_{l,k} = 2 pi w_k P_l(z_k). */
 int conv_split_create(conv_split_ctx** ctx, int lmax, const double* c_in, double theta_max, double sv_cut);
@@ -48,8 +48,9 @@ int conv_split_nodes(const conv_split_ctx* ctx, double theta_cut, int* z_cut);
 /* The least-squares split of k_ell (lmax + 1 values) for (ell_cut, theta_cut) (Eqs. 3-5).
  * The identity block of the design matrix makes every row l <= ell_cut exact, so the solve is
  * the reduced problem: minimise sum_{l > ell_cut} (2l+1) C^in_l (K_l - (P x)_l)^2 over the
- * z_cut real-space samples x, through the eigen-decomposition of its normal matrix, dropping
- * eigenvalues below sv_cut times the largest; then K^_l = K_l - (P x)_l for l <= ell_cut.
+ * z_cut real-space samples x, through the singular value decomposition of the weighted matrix
+ * B = W_r^1/2 P_r (rows l > ell_cut, W_l = (2l+1) C^in_l; Householder QR, then one-sided Jacobi on R),
+ * dropping singular values below sv_cut times the largest; then K^_l = K_l - (P x)_l for l <= ell_cut.
  * Outputs (host, any may be NULL):
  *   k_hat    ell_cut + 1 values, the harmonic part K^_l
  *   k_theta  z_cut values, the real-space samples at the nodes in decreasing z

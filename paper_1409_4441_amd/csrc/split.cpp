@@ -19,53 +19,80 @@ using convreal::set_error;
 
 namespace {
 
-// Symmetric eigen-decomposition by cyclic Jacobi rotations: A (n x n, row-major, destroyed) ->
-// eigenvalues lam[n], eigenvectors as columns of V (row-major n x n). Jacobi keeps small
-// eigenvalues to high relative accuracy, which the cutoff test relies on.
-void jacobi_eigen(int n, std::vector<double>& A, std::vector<double>& lam, std::vector<double>& V) {
+// Singular values and right singular vectors of an m x n matrix B (column-major, destroyed),
+// m >= n: Householder QR, B = Q R, then one-sided Jacobi (Hestenes) rotations on the columns of R,
+// R V = U diag(s). Both steps keep small singular values to high relative accuracy (forming B^T B
+// would square the condition number), which the relative cutoff of the split relies on.
+// Outputs: s[n] (column norms, unsorted) and V (n x n row-major, columns are the vectors).
+void householder_jacobi_svd(int m, int n, std::vector<double>& B, std::vector<double>& s, std::vector<double>& V) {
+  auto b = [&](int i, int j) -> double& { return B[static_cast<size_t>(j) * m + i]; };
+  for (int k = 0; k < n; ++k) {
+    double tail2 = 0.0;
+    for (int i = k + 1; i < m; ++i) tail2 += b(i, k) * b(i, k);
+    const double norm = std::sqrt(b(k, k) * b(k, k) + tail2);
+    if (norm == 0.0) continue;
+    const double alpha = b(k, k) > 0.0 ? -norm : norm;  // reflect onto -sign(b_kk) |x| e_k
+    const double v0 = b(k, k) - alpha;                  // no cancellation: opposite signs
+    // reflector H = I - 2 v v^T / (v^T v), v = (v0, b(k+1..m-1, k))
+    const double vtv = v0 * v0 + tail2;
+    b(k, k) = alpha;
+    if (vtv == 0.0) continue;
+    for (int j = k + 1; j < n; ++j) {
+      double d = v0 * b(k, j);
+      for (int i = k + 1; i < m; ++i) d += b(i, k) * b(i, j);
+      const double f = 2.0 * d / vtv;
+      b(k, j) -= f * v0;
+      for (int i = k + 1; i < m; ++i) b(i, j) -= f * b(i, k);
+    }
+  }
+  // R: upper triangle of the first n rows, stored column-major n x n
+  std::vector<double> R(static_cast<size_t>(n) * n, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i <= j; ++i) R[static_cast<size_t>(j) * n + i] = b(i, j);
   V.assign(static_cast<size_t>(n) * n, 0.0);
   for (int i = 0; i < n; ++i) V[static_cast<size_t>(i) * n + i] = 1.0;
-  auto a = [&](int i, int j) -> double& { return A[static_cast<size_t>(i) * n + j]; };
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, diag = 0.0;
-    for (int i = 0; i < n; ++i) {
-      diag += a(i, i) * a(i, i);
-      for (int j = i + 1; j < n; ++j) off += a(i, j) * a(i, j);
-    }
-    if (off <= 1e-32 * diag || off == 0.0) break;
+  const double tol = 1e-15;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    bool rotated = false;
     for (int p = 0; p < n - 1; ++p) {
       for (int q = p + 1; q < n; ++q) {
-        const double apq = a(p, q);
-        if (std::fabs(apq) <= 1e-300) continue;
-        // rotation angle that zeroes a(p, q): tan(2 phi) = 2 a_pq / (a_qq - a_pp), smaller root
-        const double th = (a(q, q) - a(p, p)) / (2.0 * apq);
-        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
-        const double c = 1.0 / std::sqrt(t * t + 1.0);
-        const double s = t * c;
-        for (int k = 0; k < n; ++k) {  // columns p, q
-          const double akp = a(k, p), akq = a(k, q);
-          a(k, p) = c * akp - s * akq;
-          a(k, q) = s * akp + c * akq;
+        double* cp = R.data() + static_cast<size_t>(p) * n;
+        double* cq = R.data() + static_cast<size_t>(q) * n;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = 0; i < n; ++i) {
+          al += cp[i] * cp[i];
+          be += cq[i] * cq[i];
+          ga += cp[i] * cq[i];
         }
-        for (int k = 0; k < n; ++k) {  // rows p, q
-          const double apk = a(p, k), aqk = a(q, k);
-          a(p, k) = c * apk - s * aqk;
-          a(q, k) = s * apk + c * aqk;
+        if (!(std::fabs(ga) > tol * std::sqrt(al * be))) continue;
+        rotated = true;
+        // rotation that makes columns p and q orthogonal: tan(2 phi) = 2 ga / (be - al), smaller root
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t);
+        const double sn = c * t;
+        for (int i = 0; i < n; ++i) {
+          const double x = cp[i], y = cq[i];
+          cp[i] = c * x - sn * y;
+          cq[i] = sn * x + c * y;
         }
-        a(p, q) = 0.0;
-        a(q, p) = 0.0;
         for (int k = 0; k < n; ++k) {
           double& vkp = V[static_cast<size_t>(k) * n + p];
           double& vkq = V[static_cast<size_t>(k) * n + q];
           const double x = vkp, y = vkq;
-          vkp = c * x - s * y;
-          vkq = s * x + c * y;
+          vkp = c * x - sn * y;
+          vkq = sn * x + c * y;
         }
       }
     }
+    if (!rotated) break;
   }
-  lam.resize(n);
-  for (int i = 0; i < n; ++i) lam[i] = a(i, i);
+  s.resize(n);
+  for (int j = 0; j < n; ++j) {
+    double a = 0.0;
+    for (int i = 0; i < n; ++i) a += R[static_cast<size_t>(j) * n + i] * R[static_cast<size_t>(j) * n + i];
+    s[j] = std::sqrt(a);
+  }
 }
 
 // Nodes z_k and weights w_k of the n-point Gauss-Legendre rule with z_k > zmin, in decreasing z:
@@ -106,11 +133,12 @@ void gauss_legendre_above(int n, double zmin, std::vector<double>& z, std::vecto
   }
 }
 
-constexpr size_t kCacheBytes = size_t(512) << 20;  // eigen-decompositions kept per context
+constexpr size_t kCacheBytes = size_t(512) << 20;  // decompositions kept per context
 
-struct Eig {
-  std::vector<double> lam;  // n
-  std::vector<double> V;    // n x n, columns are eigenvectors
+// Singular values s_k and right singular vectors of the reduced weighted problem W_r^1/2 P_r
+struct Svd {
+  std::vector<double> s;  // n
+  std::vector<double> V;  // n x n row-major, columns are the vectors
 };
 
 }  // namespace
@@ -124,9 +152,9 @@ struct conv_split_ctx {
   int nmax = 0;
   std::vector<double> P;   // (lmax + 1) x nmax row-major: 2 pi w_k P_l(z_k)
   std::mutex mu;
-  // (z_cut, ell_cut) -> eigen-decomposition of the normal matrix; shared so that a worker keeps its
-  // entry alive when another one clears the cache
-  std::map<std::pair<int, int>, std::shared_ptr<const Eig>> cache;
+  // (z_cut, ell_cut) -> singular values and vectors of the reduced problem; shared so that a worker
+  // keeps its entry alive when another one clears the cache
+  std::map<std::pair<int, int>, std::shared_ptr<const Svd>> cache;
   size_t cache_bytes = 0;
 };
 
@@ -139,28 +167,25 @@ int count_nodes(const conv_split_ctx* c, double theta_cut) {
   return n;
 }
 
-// normal matrix of the reduced problem, sum_{l > ell_cut} W_l p_l p_l^T over the first n samples,
-// and its eigen-decomposition; it does not depend on the kernel, so it is cached per (n, ell_cut)
-std::shared_ptr<const Eig> normal_eigen(conv_split_ctx* c, int n, int ell_cut) {
+// SVD of the reduced problem's matrix B = W_r^1/2 P_r: rows l = ell_cut + 1..lmax, columns the
+// first n samples. It does not depend on the kernel, so it is cached per (n, ell_cut).
+std::shared_ptr<const Svd> reduced_svd(conv_split_ctx* c, int n, int ell_cut) {
   {
     std::lock_guard<std::mutex> g(c->mu);
     auto it = c->cache.find({n, ell_cut});
     if (it != c->cache.end()) return it->second;
   }
-  std::vector<double> M(static_cast<size_t>(n) * n, 0.0);
-  for (int l = ell_cut + 1; l <= c->lmax; ++l) {
+  const int rows = c->lmax - ell_cut;
+  const int m = std::max(rows, n);  // zero rows past the problem's own leave its singular values as they are
+  std::vector<double> B(static_cast<size_t>(m) * n, 0.0);
+  for (int r = 0; r < rows; ++r) {
+    const int l = ell_cut + 1 + r;
     const double* p = c->P.data() + static_cast<size_t>(l) * c->nmax;
-    const double wl = c->W[l];
-    for (int i = 0; i < n; ++i) {
-      const double wi = wl * p[i];
-      double* row = M.data() + static_cast<size_t>(i) * n;
-      for (int j = i; j < n; ++j) row[j] += wi * p[j];
-    }
+    const double sw = std::sqrt(c->W[l]);
+    for (int k = 0; k < n; ++k) B[static_cast<size_t>(k) * m + r] = sw * p[k];
   }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < i; ++j) M[static_cast<size_t>(i) * n + j] = M[static_cast<size_t>(j) * n + i];
-  auto e = std::make_shared<Eig>();
-  jacobi_eigen(n, M, e->lam, e->V);
+  auto e = std::make_shared<Svd>();
+  householder_jacobi_svd(m, n, B, e->s, e->V);
   std::lock_guard<std::mutex> g(c->mu);
   const size_t bytes = sizeof(double) * (static_cast<size_t>(n) * n + n);
   if (c->cache_bytes + bytes > kCacheBytes) {
@@ -172,7 +197,9 @@ std::shared_ptr<const Eig> normal_eigen(conv_split_ctx* c, int n, int ell_cut) {
   return res.first->second;
 }
 
-// solve the reduced problem; x has n entries (n = 0: nothing to solve)
+// Solve the reduced problem; x has n entries (n = 0: nothing to solve). With B = U diag(s) V^T,
+// x = sum over kept k of v_k (u_k . W_r^1/2 K_r) / s_k = sum v_k (v_k . P_r^T W_r K_r) / s_k^2, keeping
+// s_k >= sv_cut * max s.
 void solve_reduced(conv_split_ctx* c, const double* K, int ell_cut, int n, std::vector<double>& x) {
   x.assign(n, 0.0);
   if (n == 0 || ell_cut >= c->lmax) return;
@@ -182,15 +209,15 @@ void solve_reduced(conv_split_ctx* c, const double* K, int ell_cut, int n, std::
     const double f = c->W[l] * K[l];
     for (int k = 0; k < n; ++k) rhs[k] += p[k] * f;
   }
-  const std::shared_ptr<const Eig> ep = normal_eigen(c, n, ell_cut);
-  const Eig& e = *ep;
-  double lmax_ev = 0.0;
-  for (double v : e.lam) lmax_ev = std::max(lmax_ev, v);
+  const std::shared_ptr<const Svd> ep = reduced_svd(c, n, ell_cut);
+  const Svd& e = *ep;
+  double smax = 0.0;
+  for (double v : e.s) smax = std::max(smax, v);
   for (int i = 0; i < n; ++i) {
-    if (!(e.lam[i] >= c->sv_cut * lmax_ev) || !(e.lam[i] > 0.0)) continue;
+    if (!(e.s[i] >= c->sv_cut * smax) || !(e.s[i] > 0.0)) continue;
     double proj = 0.0;
     for (int k = 0; k < n; ++k) proj += e.V[static_cast<size_t>(k) * n + i] * rhs[k];
-    proj /= e.lam[i];
+    proj /= e.s[i] * e.s[i];
     for (int k = 0; k < n; ++k) x[k] += e.V[static_cast<size_t>(k) * n + i] * proj;
   }
 }

@@ -142,3 +142,46 @@ def test_search_infeasible_and_bad_arguments():
         split.Context(0, 0.1)
     with pytest.raises(cr.ConvRealError):
         split.Context(64, 4.0)
+
+
+def _paper_kernel(lmax, fwhm_arcmin):
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    c = np.zeros(lmax + 1)
+    c[2:] = 1.0 / (ell[2:] * (ell[2:] + 1.0))
+    return np.sqrt(c) * _beam(lmax, fwhm_arcmin)
+
+
+@pytest.mark.slow
+def test_table1_errors_match_oracle():
+    # the reduced solve at the paper's own operating point (lmax 4096, Table 1's cuts, where the
+    # singular-value cutoff removes about a quarter of the samples' directions): the library's
+    # Eq. 6 errors equal the oracle's SVD solve
+    lmax = 4096
+    C = np.ones(lmax + 1)
+    with split.Context(lmax, 390 * ARCMIN) as ctx:
+        for fwhm, lc, tc in [(7, 1158, 390), (10, 979, 360), (15, 961, 270)]:
+            K = _paper_kernel(lmax, fwhm)
+            _, sig = ctx.error(K, lc, tc * ARCMIN, alpha=5.0)
+            _, _, _, oktl = osplit.lsq_split_reduced(K, C, lc, tc * ARCMIN)
+            assert sig == pytest.approx(osplit.fractional_error(K, oktl, C, 5.0), rel=1e-6)
+
+
+@pytest.mark.parametrize("fwhm,bound", [(90.0, 1e-4), (60.0, 1e-5)])
+def test_search_equals_exhaustive_scan(fwhm, bound):
+    # the library's bisection finds the cheapest feasible (theta_cut, l_cut) that enumerating every
+    # pair of the grid finds
+    lmax, nside = 64, 32
+    K = _paper_kernel(lmax, fwhm)
+    m = split.CostModel(2e-4, 3e-11, 4e-9)
+    grid = [0.05, 0.08, 0.12, 0.18, 0.26]
+    best = None
+    with split.Context(lmax, max(grid)) as ctx:
+        for tc in grid:
+            for lc in range(lmax + 1):
+                if ctx.error(K, lc, tc, alpha=5.0)[1] <= bound:
+                    wall = m.eval(nside, lmax, tc, lc)[2]
+                    if best is None or wall < best[2]:
+                        best = (tc, lc, wall)
+        got = ctx.search(K, nside, bound, grid, m)
+    assert best is not None and got is not None
+    assert (got[0], got[1]) == best[:2] and got[2] == pytest.approx(best[2], rel=1e-15)
