@@ -11,7 +11,10 @@ inputs already in HBM. Prints ONE JSON line:
                  pair) on the same map promoted to FP64, timed beside it
   roofline       the kernel that takes most of the step, timed with HIP events recorded between
                  the library's kernels on the stream they run on (conv_real_profile)
-  cpu_baseline   the CPU oracle timed on a bounded sample of output pixels of the same workload
+  cpu_baseline   the C FP64 oracle on the host cores over a bounded sample of output pixels of the
+                 same workload (the NumPy oracle on one core beside it); the same sums check the
+                 timed path's accuracy, and the batched workload's maps are checked at their own
+                 sampled pixels
 """
 from __future__ import annotations
 
@@ -45,7 +48,9 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "f32", "f64"])
     ap.add_argument("--plain-steps", type=int, default=3, help="timed applies of the plain kernel")
     ap.add_argument("--profile-steps", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=400, help="output pixels the oracle sums")
+    ap.add_argument("--cpu-sample", type=int, default=100000,
+                    help="output pixels the C oracle sums (timed baseline and accuracy check)")
+    ap.add_argument("--cpu-sample-numpy", type=int, default=400, help="of those, pixels the NumPy oracle sums")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-ringfft", action="store_true", help="skip the FP64 ring-FFT measurement")
@@ -210,6 +215,7 @@ def batched(steps, stream):
         g.replay()
     torch.cuda.synchronize()
     graph_s = (time.perf_counter() - t0) / steps
+    host = [(w, m, o.cpu().numpy()) for w, m, o in zip(ws, maps, outs)]
     counts = {}
     for w in ws:
         counts[w.nside] = counts.get(w.nside, 0) + 1
@@ -221,7 +227,7 @@ def batched(steps, stream):
     batch.close()
     for p in plans:
         p.close()
-    return out
+    return out, host
 
 
 def paper_context(theta_cut, pairs_per_map, maps_per_s):
@@ -235,23 +241,90 @@ def paper_context(theta_cut, pairs_per_map, maps_per_s):
             "ratio_maps_per_s_here": maps_per_s * t}
 
 
-def cpu_baseline(w, table, x, y_gpu, nsamp):
-    """The oracle, as it stands, on nsamp sampled output pixels of the same map; single thread."""
+def check_pixels(nside: int, n: int, seed: int) -> np.ndarray:
+    """n seeded uniform output pixels plus the first, middle and last pixel of the two rings at
+    each pole and of the rings on both sides of each belt edge (sorted, unique)."""
+    N = int(nside)
+    npix = 12 * N * N
+
+    def ring_start_len(i):
+        if i < N:
+            return 2 * i * (i - 1), 4 * i
+        if i <= 3 * N:
+            return 2 * N * (N - 1) + 4 * N * (i - N), 4 * N
+        k = 4 * N - i
+        return npix - 2 * k * (k + 1), 4 * k
+
+    rings = {1, 2, N - 1, N, N + 1, 2 * N, 3 * N - 1, 3 * N, 3 * N + 1, 4 * N - 2, 4 * N - 1}
+    extra = []
+    for i in sorted(r for r in rings if 1 <= r <= 4 * N - 1):
+        s0, n_i = ring_start_len(i)
+        extra += [s0, s0 + n_i // 2, s0 + n_i - 1]
+    rnd = np.random.default_rng(seed).choice(npix, min(n, npix), replace=False)
+    return np.unique(np.concatenate([rnd, np.asarray(extra, dtype=np.int64)]))
+
+
+def _cpu_threads() -> int:
+    """Host threads for the C oracle: every core this process may use, at most 16 (a GPU machine's
+    CPU share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(w, x, y_gpu, nsamp, nsamp_numpy, batch_outputs=None):
+    """The oracle, as it stands, on the host: the C FP64 oracle on all host cores over nsamp seeded
+    output pixels of the same map (the timed baseline, and the accuracy check of the timed path on
+    those pixels), the NumPy oracle on one core over nsamp_numpy of them (timed beside it), and,
+    for the batched workload, each map's output against the C oracle at its check pixels. The
+    oracle tabulates its own kernel tables."""
     from threadpoolctl import threadpool_limits
 
     from oracle import convolve as oc
+    from oracle import csum
+    from oracle import kernel as ok
+    table = ok.tabulate(w.k_ell(), w.theta_cut, w.n_tab)
     g = np.random.default_rng(w.seed + 99)
-    pix = np.sort(g.choice(x.shape[1], nsamp, replace=False))
-    counts, _ = oc.pair_counts_sampled(w.nside, w.theta_cut, pix)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        ref = oc.convolve_sampled(w.nside, table, w.theta_cut, x.astype(np.float64), pix)
-        dt = time.perf_counter() - t0
+    npix = x.shape[1]
+    pix = np.sort(g.choice(npix, min(nsamp, npix), replace=False))
+    nt = _cpu_threads()
+    xd = x.astype(np.float64)
+    t0 = time.perf_counter()
+    ref, counts = csum.convolve_sampled(w.nside, table, w.theta_cut, xd, pix, nthreads=nt)
+    dt = time.perf_counter() - t0
     pairs = float(counts.sum()) * x.shape[0]
-    err = oc.rel_rms(y_gpu[:, pix], ref.reshape(x.shape[0], -1))
-    return {"value": pairs / dt, "unit": "pixel-pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nsamp} seeded output pixels x {x.shape[0]} map(s) of {w.name} "
-                      f"({int(counts.sum())} pairs/map), ring-exhaustive NumPy FP64, {dt:.2f} s"}, err
+    yg = y_gpu[:, pix].astype(np.float64)
+    err = max(oc.rel_rms(yg[m], ref[m]) for m in range(x.shape[0]))
+    err_max = max(float(np.max(np.abs(yg[m] - ref[m])) / np.sqrt(np.mean(ref[m] ** 2))) for m in range(x.shape[0]))
+    sub = pix[np.random.default_rng(w.seed + 98).choice(len(pix), min(nsamp_numpy, len(pix)), replace=False)]
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        ref_np = oc.convolve_sampled(w.nside, table, w.theta_cut, xd, sub).reshape(x.shape[0], -1)
+        dt_np = time.perf_counter() - t1
+    counts_np, _ = oc.pair_counts_sampled(w.nside, w.theta_cut, sub)
+    cpu = {"value": pairs / dt, "unit": "pixel-pairs/s", "cores": nt, "kind": "oracle",
+           "sample": f"{len(pix)} seeded output pixels x {x.shape[0]} map(s) of {w.name} "
+                     f"({int(counts.sum())} pairs), C FP64 oracle (oracle/csum.c) on {nt} threads, {dt:.2f} s; "
+                     f"host os.cpu_count() = {os.cpu_count()}",
+           "numpy_oracle": {"value": float(counts_np.sum()) * x.shape[0] / dt_np, "unit": "pixel-pairs/s",
+                            "cores": 1, "sample": f"{len(sub)} of those pixels, ring-exhaustive NumPy FP64, "
+                                                  f"{dt_np:.2f} s"}}
+    acc = {"pixels": int(len(pix)), "rel_rms": err, "max_abs_over_rms": err_max,
+           "numpy_vs_c_oracle_rel_rms": max(oc.rel_rms(ref_np[m], ref[m][np.searchsorted(pix, sub)])
+                                             for m in range(x.shape[0]))}
+    if batch_outputs is not None:
+        worst, npx = 0.0, 0
+        for k, (wb, xb, yb) in enumerate(batch_outputs):
+            tb = ok.tabulate(wb.k_ell(), wb.theta_cut, wb.n_tab)
+            pb = check_pixels(wb.nside, 300, wb.seed + 7 * k)
+            rb, _ = csum.convolve_sampled(wb.nside, tb, wb.theta_cut, xb.astype(np.float64), pb, nthreads=nt)
+            e = oc.rel_rms(yb[pb].astype(np.float64), rb[0])
+            worst, npx = max(worst, e), npx + len(pb)
+        acc["batched"] = {"maps": len(batch_outputs), "pixels": npx, "worst_map_rel_rms": worst,
+                          "pixels_per_map": "300 seeded + first/middle/last of the polar and belt-edge rings"}
+    return cpu, acc
 
 
 def main():
@@ -358,14 +431,16 @@ def main():
         torch.cuda.synchronize()
         del yc
 
-    bat = None
+    bat, bat_host = None, None
     if not args.no_batched and args.precision == "mixed":
-        bat = batched(args.batched_steps, stream)
+        bat, bat_host = batched(args.batched_steps, stream)
 
     cpu = None
-    err = None
+    acc = None
     if not args.no_cpu:
-        cpu, err = cpu_baseline(w, table, x_np, y_np, args.cpu_sample)
+        cpu, acc = cpu_baseline(w, x_np, y_np, args.cpu_sample, args.cpu_sample_numpy, bat_host)
+        if bat is not None and "batched" in acc:
+            bat["oracle_check"] = acc.pop("batched")
 
     path = {"mixed": "split-FP16 matrix cores: precomputed Toeplitz weights for belt ring pairs, cap-touching "
                      "ring pairs with weights shared by 16 symmetric images (stored or evaluated on the fly), "
@@ -384,7 +459,7 @@ def main():
         "maps_per_s": maps_per_s, "pairs_per_map": pairs_per_map, "init_s": init_s,
         "apply_ms_events": apply_ms, "achieved_hbm_gbs": hbm_gbs,
         "kernels": kernels,
-        "rel_rms_vs_oracle_sample": err,
+        "accuracy_vs_oracle": acc,
         "plain_fp64": plain,
         "ring_fft_fp64": ring_fft,
         "weight_store": store,

@@ -52,3 +52,22 @@ def test_paper_context_is_eq7():
     assert abs(c["seconds_per_map"] - 3.124) < 1e-12
     assert abs(c["maps_per_s"] - 1.0 / 3.124) < 1e-12
     assert abs(c["ratio_maps_per_s_here"] - 400.0 * 3.124) < 1e-9
+
+
+def test_check_pixels_cover_poles_and_belt_edges():
+    # the batched leg's check pixels: the seeded uniform ones plus the first, middle and last pixel
+    # of the polar rings and of the rings beside both belt edges (ring starts from the oracle's table)
+    import numpy as np
+
+    from oracle import geometry
+    for nside in (1, 2, 4, 16, 256):
+        pix = bench.check_pixels(nside, 300, 5)
+        rt = geometry.ring_table(nside)
+        npix = 12 * nside * nside
+        assert pix.min() >= 0 and pix.max() < npix and np.all(np.diff(pix) > 0)
+        N = nside
+        for i in {1, 2, N - 1, N, N + 1, 3 * N - 1, 3 * N, 3 * N + 1, 4 * N - 2, 4 * N - 1}:
+            if 1 <= i <= 4 * N - 1:
+                s0, n = int(rt["start"][i - 1]), int(rt["n"][i - 1])
+                assert {s0, s0 + n // 2, s0 + n - 1} <= set(pix.tolist()), (nside, i)
+        assert len(pix) >= min(300, npix)

@@ -166,3 +166,50 @@ def test_graph_capture_batch(cuda_device):
     batch.close()
     for p in plans:
         p.close()
+
+
+def _check_pixels(nside, n, seed):
+    """n seeded pixels plus the first, middle and last pixel of the polar rings and of the rings on
+    both sides of each belt edge."""
+    from oracle import geometry
+    rt = geometry.ring_table(nside)
+    N = nside
+    extra = []
+    for i in sorted({1, 2, N - 1, N, N + 1, 3 * N - 1, 3 * N, 3 * N + 1, 4 * N - 2, 4 * N - 1}):
+        if 1 <= i <= 4 * N - 1:
+            s0, n_i = int(rt["start"][i - 1]), int(rt["n"][i - 1])
+            extra += [s0, s0 + n_i // 2, s0 + n_i - 1]
+    rnd = np.random.default_rng(seed).choice(12 * N * N, n, replace=False)
+    return np.unique(np.concatenate([rnd, np.array(extra, dtype=np.int64)]))
+
+
+def test_batch32_full_workload_against_oracle(cuda_device):
+    """The 32-map batched workload at its own sizes (Nside 256..2048, FWHM 5'..30', theta_cut = 6 sigma,
+    residual kernels after l_cut = 0.3 / sigma), one persistent launch: every map within 1e-6 relative
+    rms of the C FP64 oracle at >= 300 sampled pixels including polar and belt-edge pixels."""
+    from oracle import csum
+    ws = synth.batch_workload()
+    maps = synth.batch_maps(ws)
+    print(f"batch32: {len(ws)} maps, nsides {sorted(set(w.nside for w in ws))}", flush=True)
+    plans, tables = [], []
+    for w in ws:
+        T = ok.tabulate(w.k_ell(), w.theta_cut, w.n_tab)
+        tables.append(T)
+        plans.append(cr.Plan(w.nside, T, w.theta_cut, "mixed"))
+    xs = [torch.from_numpy(m).to("cuda:0") for m in maps]
+    batch = cr.Batch(plans)
+    ys = batch.apply(xs)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for k, w in enumerate(ws):
+        pix = _check_pixels(w.nside, 300, 1000 + k)
+        ref, _ = csum.convolve_sampled(w.nside, tables[k], w.theta_cut, maps[k].astype(np.float64), pix, nthreads=8)
+        y = ys[k].cpu().numpy()[pix].astype(np.float64)
+        e = oc.rel_rms(y, ref[0])
+        worst = max(worst, e)
+        assert e <= 1e-6, (k, w.nside, w.theta_cut, e)
+        assert np.max(np.abs(y - ref[0])) <= 1e-5 * np.max(np.abs(ref[0])), k
+    print(f"batch32: worst map rel rms {worst:.3e}", flush=True)
+    batch.close()
+    for p in plans:
+        p.close()

@@ -118,3 +118,27 @@ def test_ring_fft_only_where_defined(cuda_device):
     with cr.Plan(8, T, 9 * DEG, "f64") as plan:
         with pytest.raises(cr.ConvRealError):
             plan.set_method("sideways")
+
+
+def test_ring_fft_nside2048(cuda_device):
+    """Nside 2048 (8192-pixel belt rings: the largest transform, 128 KB of LDS, several strided passes
+    per thread in the butterfly, spectrum and inverse loops): equal to the direct method over the full
+    map and to the C FP64 oracle at 2000 sampled pixels (polar and belt-edge rings included), both at
+    the FP64 bound."""
+    from oracle import csum, geometry
+    nside = 2048
+    tc = 30.0 / 60.0 * DEG
+    T = _table(tc / 4, tc, n_tab=2048, lmax=4096)
+    x = synth.white_noise(nside, 1, seed=2048)
+    print("ring-fft nside 2048: direct, then ring_fft", flush=True)
+    with cr.Plan(nside, T, tc, "f64") as plan:
+        y_direct = _run(plan, x)
+        plan.set_method("ring_fft")
+        y_fft = _run(plan, x)
+    _check(y_fft, y_direct)
+    rt = geometry.ring_table(nside)
+    edge = [int(rt["start"][i - 1]) + o for i in (1, 2, nside - 1, nside, nside + 1, 3 * nside, 3 * nside + 1,
+                                                  4 * nside - 1) for o in (0, 1)]
+    pix = np.unique(np.concatenate([np.random.default_rng(9).choice(x.shape[1], 2000, replace=False), edge]))
+    ref, _ = csum.convolve_sampled(nside, T, tc, x, pix, nthreads=8)
+    _check(y_fft[:, pix], ref)
