@@ -120,6 +120,25 @@ int conv_real_apply(conv_real_plan* plan, const void* maps_in, void* maps_out, i
                     void* stream);
 
 /*
+ * conv_real_apply_noalloc - conv_real_apply for callers that cannot allocate device memory or call
+ * the allocator at apply time (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, result and errors as conv_real_apply, which stays as it is.
+ *
+ * The per-launch scratch of mixed plans (the per-map max |x| that sets the FP16 split scale, and the
+ * work-queue counters: (64 + 8) x 4 bytes) is taken from a fixed 1 KiB array in device memory
+ * instead of the plan's own buffers. Each device the library runs on holds one such array until the
+ * process ends; its address is located once per device by conv_real_init. The kernels clear what
+ * must start at zero at the start of every launch, so the contents a previous call left do not
+ * matter; but every call on one device shares that device's array, so calls of this entry point that
+ * may overlap in time on one device (other streams, other threads, other plans) race and give
+ * wrong results: serialise them. Direct-method F64 and F32 plans use no scratch at all. Plans on the
+ * ring-FFT method (conv_real_set_method) need spectrum workspaces of (n/2 + 1) x 32 bytes per belt
+ * ring, beyond the fixed maximum: EINVAL. Calls no allocating routine.
+ */
+int conv_real_apply_noalloc(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps,
+                            void* stream);
+
+/*
  * conv_real_pairs - exact number of ordered pixel pairs (p, q) with
  * d_pq <= d_cut over the whole map (counted on the device at init).
  */

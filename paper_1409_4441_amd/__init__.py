@@ -42,7 +42,7 @@ EXPORTS = ("conv_real_tabulate", "conv_real_init", "conv_real_apply", "conv_real
            "conv_real_batch_autotune", "conv_real_batch_pairs", "conv_real_batch_destroy",
            "conv_real_destroy", "conv_real_strerror", "conv_real_last_error",
            "conv_real_set_weight_store", "conv_real_get_weight_store", "conv_real_set_method",
-           "conv_real_get_method")
+           "conv_real_get_method", "conv_real_apply_noalloc")
 
 
 class Tuning(ctypes.Structure):
@@ -81,6 +81,8 @@ def _load():
     lib.conv_real_init.restype = c_int
     lib.conv_real_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p]
     lib.conv_real_apply.restype = c_int
+    lib.conv_real_apply_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p]
+    lib.conv_real_apply_noalloc.restype = c_int
     lib.conv_real_pairs.argtypes = [c_void_p, ctypes.POINTER(ctypes.c_longlong)]
     lib.conv_real_pairs.restype = c_int
     lib.conv_real_profile.argtypes = [c_void_p, c_void_p, c_void_p, c_int, c_void_p,
@@ -213,6 +215,17 @@ class Plan:
         nmaps = 1 if x.dim() == 1 else x.shape[0]
         _check(lib.conv_real_apply(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                    int(nmaps), _stream_handle(stream)), "conv_real_apply")
+        return out
+
+    def apply_noalloc(self, x, out, stream=None):
+        """y = A x through conv_real_apply_noalloc: the library allocates nothing (its per-launch
+        scratch is a fixed device array shared by all such calls on the device, so calls that may
+        overlap in time race). out must be given (a preallocated tensor like x)."""
+        if out is None:
+            raise ValueError("apply_noalloc needs a preallocated out tensor")
+        out, nmaps = self._check_maps(x, out)
+        _check(lib.conv_real_apply_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                           int(nmaps), _stream_handle(stream)), "conv_real_apply_noalloc")
         return out
 
     def _check_maps(self, x, out):

@@ -709,6 +709,9 @@ int conv_real_init(conv_real_plan** plan, int nside, const double* table, int n_
   int dev = 0;
   int rc = check_device(&dev);
   if (rc != CONV_REAL_OK) return rc;
+  // the fixed scratch of conv_real_apply_noalloc, located once per device (this device is current)
+  hipError_t es = convreal::noalloc_scratch_resolve(dev);
+  if (es != hipSuccess) return hip_fail(es, "conv_real_init: hipGetSymbolAddress of the no-alloc scratch");
 
   auto* p = new (std::nothrow) conv_real_plan();
   if (!p) { set_error("conv_real_init: host allocation failed"); return CONV_REAL_ENOMEM; }
@@ -872,6 +875,7 @@ void release_ring_fft(conv_real_plan* p) {
   p->d_fft_K = nullptr;
   p->d_fft_X = nullptr;
   p->d_fft_Y = nullptr;
+  p->fft_work_bytes = 0;
   p->fft_npairs = 0;
 }
 
@@ -992,6 +996,7 @@ hipError_t build_ring_fft(conv_real_plan* p) {
       (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
       (e = convreal::launch_pair_count(p, true, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess)
     return e;
+  p->fft_work_bytes = static_cast<long long>(2 * sizeof(double2) * nbins * static_cast<size_t>(bhi - blo + 1));
   unsigned long long cnt = 0;
   if ((e = hipMemcpy(&cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost)) != hipSuccess) return e;
   p->pairs_rest = static_cast<long long>(cnt);
@@ -1062,6 +1067,39 @@ int conv_real_apply(conv_real_plan* plan, const void* maps_in, void* maps_out, i
   else
     e = convreal::launch_pair_accumulate(plan, maps_in, maps_out, nmaps, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "conv_real_apply: launch");
+  return CONV_REAL_OK;
+}
+
+int conv_real_apply_noalloc(conv_real_plan* plan, const void* maps_in, void* maps_out, int nmaps, void* stream) {
+  if (!plan || plan->magic != kMagic) { set_error("conv_real_apply_noalloc: invalid plan"); return CONV_REAL_EINVAL; }
+  if (!maps_in || !maps_out) { set_error("conv_real_apply_noalloc: NULL map pointer"); return CONV_REAL_EINVAL; }
+  if (nmaps < 1) { set_error("conv_real_apply_noalloc: nmaps must be >= 1"); return CONV_REAL_EINVAL; }
+  if (plan->precision != CONV_REAL_MIXED && plan->method == CONV_REAL_METHOD_RING_FFT) {
+    set_error("conv_real_apply_noalloc: the ring-FFT method needs " + std::to_string(plan->fft_work_bytes) +
+              " bytes of spectrum workspace, beyond the " +
+              std::to_string(sizeof(unsigned) * convreal::kNoallocScratchWords) +
+              "-byte fixed scratch; use conv_real_apply or the direct method");
+    return CONV_REAL_EINVAL;
+  }
+  const size_t elem = plan->precision == CONV_REAL_F64 ? sizeof(double) : sizeof(float);
+  const size_t bytes = static_cast<size_t>(nmaps) * static_cast<size_t>(plan->npix) * elem;
+  const char* in0 = static_cast<const char*>(maps_in);
+  const char* out0 = static_cast<const char*>(maps_out);
+  if (in0 < out0 + bytes && out0 < in0 + bytes) {
+    set_error("conv_real_apply_noalloc: maps_in and maps_out overlap");
+    return CONV_REAL_EALIAS;
+  }
+  unsigned* scr = convreal::noalloc_scratch(plan->device);
+  if (!scr) { set_error("conv_real_apply_noalloc: fixed scratch not located on the plan's device"); return CONV_REAL_EHIP; }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_real_apply_noalloc: hipSetDevice");
+  if (plan->precision == CONV_REAL_MIXED)
+    e = convreal::launch_mixed(plan, static_cast<const float*>(maps_in), static_cast<float*>(maps_out), nmaps,
+                               static_cast<hipStream_t>(stream), scr, scr + convreal::kMaxSlots);
+  else  // the direct per-pair kernels use no memory beyond the maps and the plan's tables
+    e = convreal::launch_pair_accumulate(plan, maps_in, maps_out, nmaps, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "conv_real_apply_noalloc: launch");
   return CONV_REAL_OK;
 }
 

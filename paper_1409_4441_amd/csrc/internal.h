@@ -257,6 +257,7 @@ struct conv_real_plan {
   double* d_fft_K = nullptr;   // per belt pair: n / 2 + 1 real spectrum amplitudes of k_ij (phase removed)
   double2* d_fft_X = nullptr;  // per belt ring: n / 2 + 1 frequencies of one map's ring (workspace)
   double2* d_fft_Y = nullptr;  // per belt ring: n / 2 + 1 frequencies of its output (workspace)
+  long long fft_work_bytes = 0; // bytes of the two workspaces above
   convreal::CapPair64* d_fft_cpair = nullptr;  // per listed cap-touching pair (d_rest_idx order)
   int* d_mtile_ring = nullptr; // cap-touching pairs by symmetry: tiles of 16 fundamental-domain pixels
   int* d_mtile_a0 = nullptr;   // (one wave each) of the north-half rings that have such pairs
@@ -302,6 +303,16 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
                               unsigned* counter, const Tuning& tune, int max_nseg, long long npix_max,
                               long long pairs, bool fly, hipStream_t st);
 hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st);
+// the same apply with its per-launch scratch (max |x| per map slot, then the work-queue counters)
+// at `amax` (kMaxSlots words) and `counter` (kMaxChunks words) instead of the plan's own
+hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st,
+                        unsigned* amax, unsigned* counter);
+// Fixed device scratch of conv_real_apply_noalloc: a file-scope array in device memory (each device
+// holds its own copy), resolved to its device address once per device with that device current.
+constexpr int kNoallocScratchWords = 256;   // 1 KiB: kMaxSlots + kMaxChunks words used
+constexpr int kNoallocMaxDevices = 64;
+hipError_t noalloc_scratch_resolve(int device);
+unsigned* noalloc_scratch(int device);      // nullptr until resolved on that device
 // number of weights of each cap tile in the store (counts[n_citems]), and the store's fill
 hipError_t cap_store_count(const conv_real_plan* p, long long* counts_dev);
 hipError_t cap_store_fill(const conv_real_plan* p);

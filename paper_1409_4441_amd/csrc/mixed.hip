@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "common.h"
@@ -1163,6 +1164,9 @@ __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convrea
 
 }  // namespace
 
+// Device scratch of conv_real_apply_noalloc (one copy per device; see noalloc_scratch_resolve).
+static __device__ __align__(256) unsigned scratch[convreal::kNoallocScratchWords];
+
 namespace convreal {
 
 // belt stage: two window buffers (8 shifted copies, hi and lo planes) and two weight-fragment buffers
@@ -1286,6 +1290,11 @@ hipError_t cap_store_fill(const conv_real_plan* p) {
 }
 
 hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st) {
+  return launch_mixed(p, x, y, nmaps, st, p->d_amax, p->d_counter);
+}
+
+hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st,
+                        unsigned* amax, unsigned* counter) {
   for (int m0 = 0; m0 < nmaps; m0 += kMaxSlots) {
     const int nm = nmaps - m0 < kMaxSlots ? nmaps - m0 : kMaxSlots;
     Slots S;
@@ -1294,8 +1303,8 @@ hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int n
       S.x[k] = x + static_cast<size_t>(m0 + k) * p->npix;
       S.y[k] = y + static_cast<size_t>(m0 + k) * p->npix;
     }
-    hipError_t e = launch_mixed_queue(p, S, nm, p->d_items, p->n_items, nm, p->d_qchunk_off, p->n_qchunks, p->d_amax,
-                                      p->d_counter, p->tune, p->cap_nseg, p->npix, p->pairs * nm,
+    hipError_t e = launch_mixed_queue(p, S, nm, p->d_items, p->n_items, nm, p->d_qchunk_off, p->n_qchunks, amax,
+                                      counter, p->tune, p->cap_nseg, p->npix, p->pairs * nm,
                                       p->cap_mode && !p->d_wstore, st);
     if (e != hipSuccess) return e;
     if (!p->cap_mode) {
@@ -1306,6 +1315,34 @@ hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int n
     }
   }
   return hipSuccess;
+}
+
+
+// Scratch of the apply that allocates nothing: one array per device, holding the per-slot max |x|
+// words and the work-queue counters that zero_state_kernel clears at the start of every launch.
+// Host code never passes the array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the address hipGetSymbolAddress returns for the current device.
+static_assert(kMaxSlots + kMaxChunks <= kNoallocScratchWords, "no-alloc scratch too small");
+
+static std::mutex g_scratch_mu;
+static unsigned* g_scratch_ptr[kNoallocMaxDevices] = {};
+
+hipError_t noalloc_scratch_resolve(int device) {
+  if (device < 0 || device >= kNoallocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = static_cast<unsigned*>(ptr);
+  return hipSuccess;
+}
+
+unsigned* noalloc_scratch(int device) {
+  if (device < 0 || device >= kNoallocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace convreal
