@@ -23,7 +23,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
-SOURCES = ["capi.cpp", "split.cpp", "window.hip", "tabulate.hip", "plain.hip", "mixed.hip", "ringfft.hip", "mlp.hip"]
+SOURCES = ["capi.cpp", "split.cpp", "window.hip", "tabulate.hip", "plain.hip", "mixed.hip", "ringfft.hip", "mlp.hip", "sht.hip"]
 
 
 def _run(cmd, verbose):

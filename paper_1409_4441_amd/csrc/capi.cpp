@@ -90,9 +90,33 @@ void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std
   }
 }
 
+int hip_fail(hipError_t e, const char* what) {
+  set_error(std::string(what) + ": " + hipGetErrorString(e));
+  (void)hipGetLastError();  // clear the runtime's sticky error so that later calls are not blamed
+  return e == hipErrorOutOfMemory ? CONV_REAL_ENOMEM : CONV_REAL_EHIP;
+}
+
+int check_device(int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    set_error(std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+    return CONV_REAL_ENODEV;
+  }
+  *dev_out = dev;
+  return CONV_REAL_OK;
+}
+
 }  // namespace convreal
 
 using convreal::set_error;
+using convreal::check_device;
+using convreal::DeviceGuard;
+using convreal::hip_fail;
 
 namespace {
 
@@ -105,11 +129,6 @@ bool finite_all(const double* v, long long n) {
   return true;
 }
 
-int hip_fail(hipError_t e, const char* what) {
-  set_error(std::string(what) + ": " + hipGetErrorString(e));
-  (void)hipGetLastError();  // clear the runtime's sticky error so that later calls are not blamed
-  return e == hipErrorOutOfMemory ? CONV_REAL_ENOMEM : CONV_REAL_EHIP;
-}
 
 template <typename T>
 hipError_t dev_alloc(conv_real_plan* p, T** out, size_t count) {
@@ -137,40 +156,6 @@ void free_plan(conv_real_plan* p) {
   p->magic = 0;
   delete p;
 }
-
-int check_device(int* dev_out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  hipDeviceProp_t prop;
-  e = hipGetDeviceProperties(&prop, dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
-    set_error(std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
-    return CONV_REAL_ENODEV;
-  }
-  *dev_out = dev;
-  return CONV_REAL_OK;
-}
-
-// Restores the caller's current device on scope exit.
-struct DeviceGuard {
-  int prev = -1;
-  bool changed = false;
-  hipError_t enter(int dev) {
-    hipError_t e = hipGetDevice(&prev);
-    if (e != hipSuccess) return e;
-    if (prev != dev) {
-      e = hipSetDevice(dev);
-      if (e != hipSuccess) return e;
-      changed = true;
-    }
-    return hipSuccess;
-  }
-  ~DeviceGuard() {
-    if (changed) (void)hipSetDevice(prev);
-  }
-};
 
 // Work items of one map for the persistent kernel, in the order the tuning asks for. An item is
 // (slot, kind << 30 | index): kind 0 = belt (band x pixel segment), kind 1 = cap (4 tiles).
@@ -1460,3 +1445,14 @@ int conv_real_batch_destroy(conv_real_batch* batch) {
 }
 
 }  // extern "C"
+
+int convreal::plan_info(const conv_real_plan* p, int* nside, int* precision, int* device) {
+  if (!p || p->magic != kMagic) {
+    set_error("invalid conv_real plan");
+    return CONV_REAL_EINVAL;
+  }
+  *nside = p->nside;
+  *precision = p->precision;
+  *device = p->device;
+  return CONV_REAL_OK;
+}

@@ -13,6 +13,33 @@ namespace convreal {
 
 // Per-thread message for conv_real_last_error().
 void set_error(const std::string& msg);
+// Records the message of a failed HIP call, clears the runtime's sticky error and returns the
+// matching error code (ENOMEM for out-of-memory, EHIP otherwise).
+int hip_fail(hipError_t e, const char* what);
+// The current device if it is a gfx950 (ENODEV otherwise).
+int check_device(int* dev_out);
+// Grid, precision and device of a valid plan (EINVAL otherwise).
+int plan_info(const conv_real_plan* p, int* nside, int* precision, int* device);
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  hipError_t enter(int dev) {
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != dev) {
+      e = hipSetDevice(dev);
+      if (e != hipSuccess) return e;
+      changed = true;
+    }
+    return hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
 
 // Device buffer owned by a plan.
 struct DevBuf {

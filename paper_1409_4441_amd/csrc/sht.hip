@@ -1,0 +1,791 @@
+// Spherical-harmonic transforms on the ring grid (FP64) and the hybrid apply: the harmonic half of
+// the kernel split (Eq. 1: K~_l = K^_l + P_l,theta K^_theta; Fig. 1: both halves run at once and their
+// maps are summed).
+//
+//   analysis   a_lm = Omega sum_rings lambda_lm(z_r) G_m(r),   G_m(r) = sum_{a in ring r} x_a e^{-i m phi_a}
+//   synthesis  y_a  = Re sum_m w_m F_m(r) e^{i m phi_a},       F_m(r) = sum_l b_lm lambda_lm(z_r)
+//              (w_0 = 1, w_m = 2 for m > 0: the m < 0 half of a real map)
+//
+// Ring sums. Ring r has n = 4k pixels at phi_a = pi (2a + c) / n, so G_m(r) = e^{-i m pi c / n} X[m mod n]
+// with X the n-point DFT of the ring. With a = q k + a' (q = 0..3 quarter rings), e^{-2 pi i j a / n} =
+// (-i)^{jq} e^{-2 pi i j a' / n}, so X[j] = sum_{a'} c_{j mod 4}[a'] z_j^{a'} (z_j = e^{-2 pi i j / n})
+// with four folded sequences (x0+x1+x2+x3, x0-x1+x2-x3, (x0-x2) -+ i (x1-x3)): k terms per frequency,
+// summed by Horner's rule with one complex multiply-add a term; a wave holds one residue j mod 4, so
+// every lane reads the same folded value (an LDS broadcast). Synthesis runs the same fold backwards:
+// B[j] = sum_{m = j mod n} w_m F_m e^{i m pi c / n}, and for each a' the four residue classes of j are
+// Horner sums in e^{2 pi i a' / k}, combined with i^{(j mod 4) q} into the four pixels q k + a'.
+// Only the frequencies below min(n, L + 1) are formed.
+//
+// Legendre sums. lambda_lm by the recurrence in l at fixed m,
+//   lambda_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)) sin^m theta,
+//   lambda_lm = a_lm (z lambda_{l-1,m} - b_lm lambda_{l-2,m}),
+//   a_lm = sqrt((4 l^2 - 1) / (l^2 - m^2)), b_lm = sqrt(((l-1)^2 - m^2) / (4 (l-1)^2 - 1)),
+// with (a_lm, b_lm) from a table written at set-up (read with scalar loads: the same for a whole
+// workgroup). lambda_mm below about e^-650 starts scaled by 2^(600 e) with the exponent e kept beside
+// it; every 8 steps a scaled value above 2^400 is brought down by 2^-600, and a ring contributes once
+// its exponent is 0 (scaled values are true values times 2^(600 e) <= 2^-144: dropped). The mirror
+// ring (z -> -z) has lambda_lm(-z) = (-1)^(l+m) lambda_lm(z), so one recurrence serves a ring pair:
+// analysis sums G(north) +- G(south), synthesis splits into the even and odd l + m parts.
+// A workgroup of 512 threads takes one order m and up to 512 R north rings (R per thread); analysis
+// reduces over rings every 8 values of l through LDS (each thread first adds its R rings), synthesis
+// needs no reduction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/convsht.h"
+#include "common.h"
+#include "internal.h"
+
+namespace {
+
+constexpr int kLegThreads = 512;   // Legendre kernels: 8 waves
+constexpr int kFlush = 8;          // l values between reductions (analysis) and rescale checks
+constexpr int kDftThreads = 256;   // ring sum kernels: 4 waves, one per residue class mod 4
+constexpr double kInvScale = 0x1p-600;
+constexpr double kRescaleAbove = 0x1p400;
+constexpr double kLogScale = 600.0 * 0.69314718055994530942;
+constexpr double kLogFloor = -650.0;
+static_assert(kFlush == kLegThreads / 64, "one wave reduces each l of a flush");
+static_assert(kDftThreads == 256, "four waves: one per residue class mod 4");
+
+struct ShtRing {
+  double z;          // cos theta
+  double s;          // sin theta
+  long long start;   // first pixel
+  int n;             // pixels (a multiple of 4)
+  int c;             // azimuth offset numerator: phi_a = pi (2a + c) / n
+};
+
+struct LegArgs {
+  const ShtRing* rings;
+  const double2* coef;     // per (l, m), m-major: (a_lm, b_lm); unused at l = m
+  const double* logpre;    // per m: log of the l = m normalisation
+  double2* G;              // [m][ring]: ring sums (analysis input) or F_m (synthesis output)
+  double2* alm;            // m-major alm (analysis output, synthesis input)
+  int L;
+  int nrings;
+  int nnorth;              // rings 0 .. nnorth - 1 are the north half, the last one the equator
+  double omega;
+};
+
+// wave-uniform load of a complex value (scalar load; plan tables and alm are read-only here)
+struct Pair64 {
+  double x, y;
+};
+__device__ __forceinline__ double2 ldu2(const double2& ref) {
+  const Pair64 v = convreal::ldu_record(reinterpret_cast<const Pair64&>(ref));
+  return double2{v.x, v.y};
+}
+
+__device__ __forceinline__ long long alm_base(int L, int m) {
+  return static_cast<long long>(m) * (2 * L + 3 - m) / 2;
+}
+
+// ---------------------------------------------------------------------------- ring sums (analysis)
+template <typename T>
+__global__ __launch_bounds__(kDftThreads) void sht_ring_dft_kernel(const T* __restrict__ x,
+                                                                   const ShtRing* __restrict__ rings,
+                                                                   int nrings, int L, double2* __restrict__ G) {
+  extern __shared__ double s_fold[];   // s0[k], s2[k], then (d, e) pairs [k]
+  const int r = blockIdx.x;
+  const ShtRing R = convreal::ldu_record(rings[r]);
+  const int n = R.n, k = n >> 2;
+  double* s0 = s_fold;
+  double* s2 = s_fold + k;
+  double2* de = reinterpret_cast<double2*>(s_fold + 2 * k);
+  const T* xr = x + R.start;
+  for (int a = threadIdx.x; a < k; a += blockDim.x) {
+    const double x0 = static_cast<double>(xr[a]), x1 = static_cast<double>(xr[a + k]);
+    const double x2 = static_cast<double>(xr[a + 2 * k]), x3 = static_cast<double>(xr[a + 3 * k]);
+    s0[a] = (x0 + x2) + (x1 + x3);
+    s2[a] = (x0 + x2) - (x1 + x3);
+    de[a] = double2{x0 - x2, x1 - x3};
+  }
+  __syncthreads();
+  const int nk = n < L + 1 ? n : L + 1;
+  const int kappa = threadIdx.x >> 6;          // the wave's residue class j mod 4
+  const int lane = threadIdx.x & 63;
+  for (int jq = lane; 4 * jq + kappa < nk; jq += 64) {
+    const int j = 4 * jq + kappa;
+    double zs, zc;
+    sincospi(-2.0 * static_cast<double>(j) / static_cast<double>(n), &zs, &zc);
+    double ar = 0.0, ai = 0.0;
+    if (kappa == 0 || kappa == 2) {
+      const double* cs = kappa == 0 ? s0 : s2;
+      for (int a = k - 1; a >= 0; --a) {
+        const double nr = fma(ar, zc, fma(-ai, zs, cs[a]));
+        ai = fma(ar, zs, ai * zc);
+        ar = nr;
+      }
+    } else {
+      // kappa 1: (x0 - x2) - i (x1 - x3); kappa 3: (x0 - x2) + i (x1 - x3)
+      const double sg = kappa == 1 ? -1.0 : 1.0;
+      for (int a = k - 1; a >= 0; --a) {
+        const double2 c = de[a];
+        const double nr = fma(ar, zc, fma(-ai, zs, c.x));
+        ai = fma(ar, zs, fma(ai, zc, sg * c.y));
+        ar = nr;
+      }
+    }
+    // G_m = e^{-i m pi c / n} X[j] for every m = j mod n up to L
+    for (int m = j; m <= L; m += n) {
+      const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
+      double ps, pc;
+      sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+      G[static_cast<size_t>(m) * nrings + r] = double2{ar * pc - ai * ps, ar * ps + ai * pc};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- ring sums (synthesis)
+template <typename T, bool ACC>
+__global__ __launch_bounds__(kDftThreads) void sht_ring_idft_kernel(const double2* __restrict__ F,
+                                                                    const ShtRing* __restrict__ rings,
+                                                                    int nrings, int L, T* __restrict__ y) {
+  extern __shared__ double2 s_b[];     // residue class c at s_b[c * nq + j / 4]
+  const int r = blockIdx.x;
+  const ShtRing R = convreal::ldu_record(rings[r]);
+  const int n = R.n, k = n >> 2;
+  const int nk = n < L + 1 ? n : L + 1;
+  const int nq = (nk + 3) >> 2;
+  for (int t = threadIdx.x; t < 4 * nq; t += blockDim.x) s_b[t] = double2{0.0, 0.0};
+  __syncthreads();
+  for (int j = threadIdx.x; j < nk; j += blockDim.x) {
+    double br = 0.0, bi = 0.0;
+    for (int m = j; m <= L; m += n) {
+      const double2 f = F[static_cast<size_t>(m) * nrings + r];
+      const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
+      double ps, pc;
+      sincospi(static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+      const double w = m == 0 ? 1.0 : 2.0;
+      br += w * (f.x * pc - f.y * ps);
+      bi += w * (f.x * ps + f.y * pc);
+    }
+    s_b[(j & 3) * nq + (j >> 2)] = double2{br, bi};
+  }
+  __syncthreads();
+  T* yr = y + R.start;
+  for (int ap = threadIdx.x; ap < k; ap += blockDim.x) {
+    double zs, zc;
+    sincospi(2.0 * static_cast<double>(ap) / static_cast<double>(k), &zs, &zc);
+    double ur[4], ui[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int cnt = nk > c ? (nk - c + 3) >> 2 : 0;   // j = 4 j' + c < nk
+      const double2* b = s_b + c * nq;
+      double ar = 0.0, ai = 0.0;
+      for (int jq = cnt - 1; jq >= 0; --jq) {
+        const double2 v = b[jq];
+        const double nr = fma(ar, zc, fma(-ai, zs, v.x));
+        ai = fma(ar, zs, fma(ai, zc, v.y));
+        ar = nr;
+      }
+      // times e^{2 pi i c a' / n}
+      double ps, pc;
+      sincospi(2.0 * static_cast<double>(c * ap) / static_cast<double>(n), &ps, &pc);
+      ur[c] = ar * pc - ai * ps;
+      ui[c] = ar * ps + ai * pc;
+    }
+    // pixel q k + a': Re sum_c i^{c q} U_c
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int p = (c * q) & 3;
+        v += p == 0 ? ur[c] : (p == 1 ? -ui[c] : (p == 2 ? -ur[c] : ui[c]));
+      }
+      T* dst = yr + q * k + ap;
+      if (ACC)
+        *dst = static_cast<T>(static_cast<double>(*dst) + v);
+      else
+        *dst = static_cast<T>(v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- Legendre sums
+// lambda_mm (scaled by 2^(600 e)) for one ring
+__device__ __forceinline__ void start_value(double logpre_m, int m, double s, double* p, int* e) {
+  const double lg = m == 0 ? logpre_m : fma(static_cast<double>(m), log(s), logpre_m);
+  int ee = 0;
+  if (lg < kLogFloor) ee = static_cast<int>(ceil((kLogFloor - lg) / kLogScale));
+  const double v = exp(fma(static_cast<double>(ee), kLogScale, lg));
+  *p = (m & 1) ? -v : v;
+  *e = ee;
+}
+
+template <int R>
+__global__ __launch_bounds__(kLegThreads) void sht_analysis_legendre_kernel(LegArgs a, int nblk, double2* partial) {
+  __shared__ double2 s_red[kFlush][kLegThreads];
+  const int item = blockIdx.x;
+  const int m = item / nblk;
+  const int blk = item - m * nblk;
+  const int tid = threadIdx.x;
+  const double2* Gm = a.G + static_cast<size_t>(m) * a.nrings;
+  double z[R], ser[R], sei[R], sor[R], soi[R], p0[R], p1[R];
+  int e[R], ring[R];
+  const double logpre = convreal::ldu(a.logpre[m]);
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int rn = (blk * R + j) * kLegThreads + tid;
+    ring[j] = rn;
+    z[j] = 0.0; ser[j] = sei[j] = sor[j] = soi[j] = 0.0; p0[j] = p1[j] = 0.0; e[j] = 0;
+    if (rn < a.nnorth) {
+      const ShtRing Rg = a.rings[rn];
+      z[j] = Rg.z;
+      start_value(logpre, m, Rg.s, &p1[j], &e[j]);
+      if (e[j] == 0) {
+        const int rs = a.nrings - 1 - rn;
+        const double2 gn = Gm[rn];
+        const double2 gs = rs != rn ? Gm[rs] : double2{0.0, 0.0};
+        ser[j] = gn.x + gs.x; sei[j] = gn.y + gs.y;
+        sor[j] = gn.x - gs.x; soi[j] = gn.y - gs.y;
+      }
+    }
+  }
+  const long long base = alm_base(a.L, m);
+  const double2* coef = a.coef + base;
+  double2* out = nblk == 1 ? a.alm + base : partial + static_cast<size_t>(blk) * ((a.L + 1LL) * (a.L + 2) / 2) + base;
+  const double scale = nblk == 1 ? a.omega : 1.0;
+  for (int l0 = m; l0 <= a.L; l0 += kFlush) {
+#pragma unroll
+    for (int u = 0; u < kFlush; ++u) {
+      const int l = l0 + u;
+      double tr = 0.0, ti = 0.0;
+      if (l <= a.L) {
+        if (l > m) {
+          const double2 ab = ldu2(coef[l - m]);
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            const double p2 = ab.x * fma(z[j], p1[j], -ab.y * p0[j]);
+            p0[j] = p1[j];
+            p1[j] = p2;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          // l - m has the parity of u (l0 - m is a multiple of kFlush)
+          tr = fma(p1[j], (u & 1) ? sor[j] : ser[j], tr);
+          ti = fma(p1[j], (u & 1) ? soi[j] : sei[j], ti);
+        }
+      }
+      s_red[u][tid] = double2{tr, ti};
+    }
+    __syncthreads();
+    {
+      // wave w adds the kLegThreads partial sums of l = l0 + w
+      const int w = tid >> 6, lane = tid & 63;
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q < kLegThreads / 64; ++q) {
+        const double2 v = s_red[w][lane * (kLegThreads / 64) + q];
+        sr += v.x;
+        si += v.y;
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        sr += __shfl_xor(sr, off);
+        si += __shfl_xor(si, off);
+      }
+      const int l = l0 + w;
+      if (lane == 0 && w < kFlush && l <= a.L) out[l - m] = double2{scale * sr, scale * si};
+    }
+    __syncthreads();
+    // bring scaled values back towards the FP64 range; a ring joins the sums once it is unscaled
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (e[j] > 0 && fabs(p1[j]) > kRescaleAbove) {
+        p0[j] *= kInvScale;
+        p1[j] *= kInvScale;
+        e[j] -= 1;
+        if (e[j] == 0) {
+          const int rn = ring[j], rs = a.nrings - 1 - rn;
+          const double2 gn = Gm[rn];
+          const double2 gs = rs != rn ? Gm[rs] : double2{0.0, 0.0};
+          ser[j] = gn.x + gs.x; sei[j] = gn.y + gs.y;
+          sor[j] = gn.x - gs.x; soi[j] = gn.y - gs.y;
+        }
+      }
+    }
+  }
+}
+
+// a_lm = Omega sum over ring blocks of the partial sums (several blocks per order)
+__global__ void sht_reduce_kernel(const double2* __restrict__ partial, int nblk, long long nalm, double omega,
+                                  double2* __restrict__ alm) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nalm) return;
+  double sr = 0.0, si = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    const double2 v = partial[static_cast<size_t>(b) * nalm + i];
+    sr += v.x;
+    si += v.y;
+  }
+  alm[i] = double2{omega * sr, omega * si};
+}
+
+template <int R>
+__global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(LegArgs a, int nblk) {
+  const int item = blockIdx.x;
+  const int m = item / nblk;
+  const int blk = item - m * nblk;
+  const int tid = threadIdx.x;
+  double z[R], fer[R], fei[R], forr[R], foi[R], p0[R], p1[R];
+  int e[R];
+  const double logpre = convreal::ldu(a.logpre[m]);
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int rn = (blk * R + j) * kLegThreads + tid;
+    z[j] = 0.0; p0[j] = p1[j] = 0.0; e[j] = 0;
+    fer[j] = fei[j] = forr[j] = foi[j] = 0.0;
+    if (rn < a.nnorth) {
+      const ShtRing Rg = a.rings[rn];
+      z[j] = Rg.z;
+      start_value(logpre, m, Rg.s, &p1[j], &e[j]);
+    }
+  }
+  const long long base = alm_base(a.L, m);
+  const double2* coef = a.coef + base;
+  const double2* alm = a.alm + base;
+  for (int l0 = m; l0 <= a.L; l0 += kFlush) {
+#pragma unroll
+    for (int u = 0; u < kFlush; ++u) {
+      const int l = l0 + u;
+      if (l <= a.L) {
+        if (l > m) {
+          const double2 ab = ldu2(coef[l - m]);
+#pragma unroll
+          for (int j = 0; j < R; ++j) {
+            const double p2 = ab.x * fma(z[j], p1[j], -ab.y * p0[j]);
+            p0[j] = p1[j];
+            p1[j] = p2;
+          }
+        }
+        const double2 b = ldu2(alm[l - m]);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          if (u & 1) {
+            forr[j] = fma(p1[j], b.x, forr[j]);
+            foi[j] = fma(p1[j], b.y, foi[j]);
+          } else {
+            fer[j] = fma(p1[j], b.x, fer[j]);
+            fei[j] = fma(p1[j], b.y, fei[j]);
+          }
+        }
+      }
+    }
+    // rings still scaled drop what they added (true values below 2^-144 of the scaled ones)
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (e[j] > 0) {
+        fer[j] = fei[j] = forr[j] = foi[j] = 0.0;
+        if (fabs(p1[j]) > kRescaleAbove) {
+          p0[j] *= kInvScale;
+          p1[j] *= kInvScale;
+          e[j] -= 1;
+        }
+      }
+    }
+  }
+  double2* Fm = a.G + static_cast<size_t>(m) * a.nrings;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int rn = (blk * R + j) * kLegThreads + tid;
+    if (rn < a.nnorth) {
+      const int rs = a.nrings - 1 - rn;
+      Fm[rn] = double2{fer[j] + forr[j], fei[j] + foi[j]};
+      if (rs != rn) Fm[rs] = double2{fer[j] - forr[j], fei[j] - foi[j]};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- alm helpers
+__global__ void sht_almxfl_kernel(const double2* __restrict__ in, const double* __restrict__ fl, int L,
+                                  double2* __restrict__ out) {
+  const int m = blockIdx.x;
+  const long long base = alm_base(L, m);
+  for (int l = m + threadIdx.x; l <= L; l += blockDim.x) {
+    const double f = fl[l];
+    const double2 v = in[base + l - m];
+    out[base + l - m] = double2{f * v.x, f * v.y};
+  }
+}
+
+__global__ void sht_power_kernel(const double2* __restrict__ alm, int L, double* __restrict__ cl) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l > L) return;
+  double s = 0.0;
+  for (int m = 0; m <= l; ++m) {
+    const double2 v = alm[alm_base(L, m) + l - m];
+    const double p = v.x * v.x + v.y * v.y;
+    s += m == 0 ? p : 2.0 * p;
+  }
+  cl[l] = s / (2.0 * l + 1.0);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- plan
+struct conv_sht_plan {
+  unsigned magic = 0;
+  int device = 0;
+  int nside = 0;
+  int L = 0;
+  int nrings = 0;
+  int nnorth = 0;
+  long long npix = 0;
+  long long nalm = 0;
+  int R = 1;                 // north rings per thread in the Legendre kernels
+  int nblk = 1;              // ring blocks per order
+  double omega = 0.0;
+  ShtRing* d_rings = nullptr;
+  double2* d_coef = nullptr;
+  double* d_logpre = nullptr;
+  double2* d_G = nullptr;
+  double2* d_alm = nullptr;       // workspace of conv_sht_convolve and the hybrid apply
+  double2* d_partial = nullptr;   // nblk > 1: per-block partial sums of the analysis
+  hipEvent_t ev_in = nullptr, ev_real = nullptr, ev_done = nullptr;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+constexpr unsigned kShtMagic = 0x53485450u;  // "SHTP"
+
+using convreal::DeviceGuard;
+using convreal::hip_fail;
+using convreal::set_error;
+
+bool plan_ok(const conv_sht_plan* p) { return p && p->magic == kShtMagic; }
+
+template <typename T>
+hipError_t sht_alloc(conv_sht_plan* p, T** out, size_t count) {
+  *out = nullptr;
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, (count ? count : 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  p->owned.push_back(ptr);
+  *out = static_cast<T*>(ptr);
+  return hipSuccess;
+}
+
+void free_sht(conv_sht_plan* p) {
+  for (void* ptr : p->owned) (void)hipFree(ptr);
+  if (p->ev_in) (void)hipEventDestroy(p->ev_in);
+  if (p->ev_real) (void)hipEventDestroy(p->ev_real);
+  if (p->ev_done) (void)hipEventDestroy(p->ev_done);
+  p->magic = 0;
+  delete p;
+}
+
+size_t dft_lds(int nside) { return 32 * static_cast<size_t>(nside); }
+size_t idft_lds(int nside, int L) {
+  const int nk = std::min(4 * nside, L + 1);
+  return 16 * static_cast<size_t>(4 * ((nk + 3) / 4));
+}
+
+hipError_t set_lds_attributes(int nside, int L) {
+  const int a = static_cast<int>(std::max<size_t>(dft_lds(nside), 16));
+  const int s = static_cast<int>(std::max<size_t>(idft_lds(nside, L), 16));
+  const void* fa[] = {reinterpret_cast<const void*>(&sht_ring_dft_kernel<double>),
+                      reinterpret_cast<const void*>(&sht_ring_dft_kernel<float>)};
+  const void* fs[] = {reinterpret_cast<const void*>(&sht_ring_idft_kernel<double, false>),
+                      reinterpret_cast<const void*>(&sht_ring_idft_kernel<double, true>),
+                      reinterpret_cast<const void*>(&sht_ring_idft_kernel<float, false>),
+                      reinterpret_cast<const void*>(&sht_ring_idft_kernel<float, true>)};
+  for (const void* f : fa) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, std::max(a, 65536));
+    if (e != hipSuccess) return e;
+  }
+  for (const void* f : fs) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, std::max(s, 65536));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_analysis_legendre(const conv_sht_plan* p, double2* alm, hipStream_t st) {
+  LegArgs a{p->d_rings, p->d_coef, p->d_logpre, p->d_G, alm, p->L, p->nrings, p->nnorth, p->omega};
+  const dim3 g(static_cast<unsigned>((p->L + 1) * p->nblk)), b(kLegThreads);
+  switch (p->R) {
+    case 1: hipLaunchKernelGGL(sht_analysis_legendre_kernel<1>, g, b, 0, st, a, p->nblk, p->d_partial); break;
+    case 2: hipLaunchKernelGGL(sht_analysis_legendre_kernel<2>, g, b, 0, st, a, p->nblk, p->d_partial); break;
+    case 4: hipLaunchKernelGGL(sht_analysis_legendre_kernel<4>, g, b, 0, st, a, p->nblk, p->d_partial); break;
+    default: hipLaunchKernelGGL(sht_analysis_legendre_kernel<8>, g, b, 0, st, a, p->nblk, p->d_partial); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p->nblk == 1) return e;
+  const unsigned gr = static_cast<unsigned>((p->nalm + 255) / 256);
+  hipLaunchKernelGGL(sht_reduce_kernel, dim3(gr), dim3(256), 0, st, p->d_partial, p->nblk, p->nalm, p->omega, alm);
+  return hipGetLastError();
+}
+
+hipError_t launch_synthesis_legendre(const conv_sht_plan* p, const double2* alm, hipStream_t st) {
+  LegArgs a{p->d_rings, p->d_coef, p->d_logpre, p->d_G, const_cast<double2*>(alm), p->L, p->nrings, p->nnorth,
+            p->omega};
+  const dim3 g(static_cast<unsigned>((p->L + 1) * p->nblk)), b(kLegThreads);
+  switch (p->R) {
+    case 1: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<1>, g, b, 0, st, a, p->nblk); break;
+    case 2: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<2>, g, b, 0, st, a, p->nblk); break;
+    case 4: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<4>, g, b, 0, st, a, p->nblk); break;
+    default: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<8>, g, b, 0, st, a, p->nblk); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_analysis(const conv_sht_plan* p, const void* map, int dtype, double2* alm, hipStream_t st) {
+  const size_t lds = dft_lds(p->nside);
+  if (dtype == CONV_SHT_F64)
+    hipLaunchKernelGGL(sht_ring_dft_kernel<double>, dim3(p->nrings), dim3(kDftThreads), lds, st,
+                       static_cast<const double*>(map), p->d_rings, p->nrings, p->L, p->d_G);
+  else
+    hipLaunchKernelGGL(sht_ring_dft_kernel<float>, dim3(p->nrings), dim3(kDftThreads), lds, st,
+                       static_cast<const float*>(map), p->d_rings, p->nrings, p->L, p->d_G);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_analysis_legendre(p, alm, st);
+}
+
+hipError_t launch_ring_synthesis(const conv_sht_plan* p, void* map, int dtype, int accumulate, hipStream_t st) {
+  const size_t lds = idft_lds(p->nside, p->L);
+  const dim3 g(p->nrings), b(kDftThreads);
+  if (dtype == CONV_SHT_F64) {
+    double* y = static_cast<double*>(map);
+    if (accumulate)
+      hipLaunchKernelGGL((sht_ring_idft_kernel<double, true>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y);
+    else
+      hipLaunchKernelGGL((sht_ring_idft_kernel<double, false>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y);
+  } else {
+    float* y = static_cast<float*>(map);
+    if (accumulate)
+      hipLaunchKernelGGL((sht_ring_idft_kernel<float, true>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y);
+    else
+      hipLaunchKernelGGL((sht_ring_idft_kernel<float, false>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_almxfl(const conv_sht_plan* p, const double2* in, const double* fl, double2* out, hipStream_t st) {
+  hipLaunchKernelGGL(sht_almxfl_kernel, dim3(p->L + 1), dim3(256), 0, st, in, fl, p->L, out);
+  return hipGetLastError();
+}
+
+int check_dtype(int dtype, const char* where) {
+  if (dtype != CONV_SHT_F64 && dtype != CONV_SHT_F32) {
+    set_error(std::string(where) + ": dtype must be CONV_SHT_F64 or CONV_SHT_F32");
+    return CONV_REAL_EINVAL;
+  }
+  return CONV_REAL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int conv_sht_alm_size(int lmax, long long* n) {
+  if (!n || lmax < 0 || lmax > CONV_SHT_MAX_LMAX) {
+    set_error("conv_sht_alm_size: invalid argument");
+    return CONV_REAL_EINVAL;
+  }
+  *n = (static_cast<long long>(lmax) + 1) * (lmax + 2) / 2;
+  return CONV_REAL_OK;
+}
+
+int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
+  if (!plan) { set_error("conv_sht_init: NULL plan pointer"); return CONV_REAL_EINVAL; }
+  *plan = nullptr;
+  if (nside < 1 || nside > CONV_SHT_MAX_NSIDE) { set_error("conv_sht_init: nside out of range"); return CONV_REAL_EINVAL; }
+  if (lmax < 0 || lmax > CONV_SHT_MAX_LMAX) { set_error("conv_sht_init: lmax out of range"); return CONV_REAL_EINVAL; }
+  int dev = 0;
+  int rc = convreal::check_device(&dev);
+  if (rc != CONV_REAL_OK) return rc;
+  auto* p = new (std::nothrow) conv_sht_plan();
+  if (!p) { set_error("conv_sht_init: host allocation failed"); return CONV_REAL_ENOMEM; }
+  p->magic = kShtMagic;
+  p->device = dev;
+  p->nside = nside;
+  p->L = lmax;
+  p->nrings = 4 * nside - 1;
+  p->nnorth = 2 * nside;
+  p->npix = 12LL * nside * nside;
+  p->nalm = (static_cast<long long>(lmax) + 1) * (lmax + 2) / 2;
+  p->omega = 4.0 * M_PI / static_cast<double>(p->npix);
+  p->R = 1;
+  while (p->R < 8 && static_cast<long long>(p->R) * kLegThreads < p->nnorth) p->R *= 2;
+  p->nblk = static_cast<int>((p->nnorth + static_cast<long long>(p->R) * kLegThreads - 1) /
+                             (static_cast<long long>(p->R) * kLegThreads));
+
+  // rings from the grid's exact integer numerators
+  const convreal::RingGrid g = convreal::make_ring_grid(nside);
+  std::vector<ShtRing> rings(g.nrings);
+  for (int r = 0; r < g.nrings; ++r) rings[r] = ShtRing{g.z[r], g.s[r], g.start[r], g.n[r], g.c[r]};
+  // recurrence coefficients and l = m normalisations
+  std::vector<double2> coef(static_cast<size_t>(p->nalm));
+  std::vector<double> logpre(lmax + 1);
+  double acc = 0.0;
+  for (int m = 0; m <= lmax; ++m) {
+    if (m > 0) acc += std::log((2.0 * m - 1.0) / (2.0 * m));
+    logpre[m] = 0.5 * (std::log((2.0 * m + 1.0) / (4.0 * M_PI)) + acc);
+    const long long base = static_cast<long long>(m) * (2 * lmax + 3 - m) / 2;
+    coef[base] = double2{0.0, 0.0};
+    const double mm = static_cast<double>(m) * m;
+    for (int l = m + 1; l <= lmax; ++l) {
+      const double dl = l, dl1 = l - 1.0;
+      coef[base + l - m] = double2{std::sqrt((4.0 * dl * dl - 1.0) / (dl * dl - mm)),
+                                   std::sqrt((dl1 * dl1 - mm) / (4.0 * dl1 * dl1 - 1.0))};
+    }
+  }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(dev);
+  if (e == hipSuccess) e = set_lds_attributes(nside, lmax);
+  if (e == hipSuccess) e = sht_alloc(p, &p->d_rings, rings.size());
+  if (e == hipSuccess) e = hipMemcpy(p->d_rings, rings.data(), rings.size() * sizeof(ShtRing), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = sht_alloc(p, &p->d_coef, coef.size());
+  if (e == hipSuccess) e = hipMemcpy(p->d_coef, coef.data(), coef.size() * sizeof(double2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = sht_alloc(p, &p->d_logpre, logpre.size());
+  if (e == hipSuccess) e = hipMemcpy(p->d_logpre, logpre.data(), logpre.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = sht_alloc(p, &p->d_G, static_cast<size_t>(lmax + 1) * p->nrings);
+  if (e == hipSuccess) e = sht_alloc(p, &p->d_alm, static_cast<size_t>(p->nalm));
+  if (e == hipSuccess && p->nblk > 1) e = sht_alloc(p, &p->d_partial, static_cast<size_t>(p->nalm) * p->nblk);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_real, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    rc = hip_fail(e, "conv_sht_init");
+    free_sht(p);
+    return rc;
+  }
+  *plan = p;
+  return CONV_REAL_OK;
+}
+
+int conv_sht_analysis(conv_sht_plan* plan, const void* map, int dtype, void* alm, void* stream) {
+  if (!plan_ok(plan) || !map || !alm) { set_error("conv_sht_analysis: invalid argument"); return CONV_REAL_EINVAL; }
+  int rc = check_dtype(dtype, "conv_sht_analysis");
+  if (rc != CONV_REAL_OK) return rc;
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  if (e == hipSuccess) e = launch_analysis(plan, map, dtype, static_cast<double2*>(alm), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? CONV_REAL_OK : hip_fail(e, "conv_sht_analysis");
+}
+
+int conv_sht_synthesis(conv_sht_plan* plan, const void* alm, void* map, int dtype, int accumulate, void* stream) {
+  if (!plan_ok(plan) || !map || !alm) { set_error("conv_sht_synthesis: invalid argument"); return CONV_REAL_EINVAL; }
+  int rc = check_dtype(dtype, "conv_sht_synthesis");
+  if (rc != CONV_REAL_OK) return rc;
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (e == hipSuccess) e = launch_synthesis_legendre(plan, static_cast<const double2*>(alm), st);
+  if (e == hipSuccess) e = launch_ring_synthesis(plan, map, dtype, accumulate, st);
+  return e == hipSuccess ? CONV_REAL_OK : hip_fail(e, "conv_sht_synthesis");
+}
+
+int conv_sht_almxfl(conv_sht_plan* plan, const void* alm_in, const double* fl, void* alm_out, void* stream) {
+  if (!plan_ok(plan) || !alm_in || !fl || !alm_out) { set_error("conv_sht_almxfl: invalid argument"); return CONV_REAL_EINVAL; }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  if (e == hipSuccess)
+    e = launch_almxfl(plan, static_cast<const double2*>(alm_in), fl, static_cast<double2*>(alm_out),
+                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? CONV_REAL_OK : hip_fail(e, "conv_sht_almxfl");
+}
+
+int conv_sht_convolve(conv_sht_plan* plan, const void* map_in, const double* k_ell, void* map_out, int dtype,
+                      int accumulate, void* stream) {
+  if (!plan_ok(plan) || !map_in || !k_ell || !map_out) { set_error("conv_sht_convolve: invalid argument"); return CONV_REAL_EINVAL; }
+  int rc = check_dtype(dtype, "conv_sht_convolve");
+  if (rc != CONV_REAL_OK) return rc;
+  const size_t bytes = static_cast<size_t>(plan->npix) * (dtype == CONV_SHT_F64 ? 8 : 4);
+  const char* i0 = static_cast<const char*>(map_in);
+  const char* o0 = static_cast<const char*>(map_out);
+  if (i0 < o0 + bytes && o0 < i0 + bytes) { set_error("conv_sht_convolve: maps overlap"); return CONV_REAL_EALIAS; }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (e == hipSuccess) e = launch_analysis(plan, map_in, dtype, plan->d_alm, st);
+  if (e == hipSuccess) e = launch_almxfl(plan, plan->d_alm, k_ell, plan->d_alm, st);
+  if (e == hipSuccess) e = launch_synthesis_legendre(plan, plan->d_alm, st);
+  if (e == hipSuccess) e = launch_ring_synthesis(plan, map_out, dtype, accumulate, st);
+  return e == hipSuccess ? CONV_REAL_OK : hip_fail(e, "conv_sht_convolve");
+}
+
+int conv_sht_power_spectrum(conv_sht_plan* plan, const void* alm, double* cl, void* stream) {
+  if (!plan_ok(plan) || !alm || !cl) { set_error("conv_sht_power_spectrum: invalid argument"); return CONV_REAL_EINVAL; }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plan->device);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(sht_power_kernel, dim3((plan->L + 256) / 256), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const double2*>(alm), plan->L, cl);
+    e = hipGetLastError();
+  }
+  return e == hipSuccess ? CONV_REAL_OK : hip_fail(e, "conv_sht_power_spectrum");
+}
+
+int conv_hybrid_apply(conv_real_plan* real, conv_sht_plan* sht, const double* k_hat, const void* maps_in,
+                      void* maps_out, int nmaps, void* stream, void* stream_sht) {
+  if (!plan_ok(sht) || !real || !k_hat || !maps_in || !maps_out || nmaps < 1) {
+    set_error("conv_hybrid_apply: invalid argument");
+    return CONV_REAL_EINVAL;
+  }
+  int nside = 0, precision = 0, device = 0;
+  int rc = convreal::plan_info(real, &nside, &precision, &device);
+  if (rc != CONV_REAL_OK) return rc;
+  if (nside != sht->nside || device != sht->device) {
+    set_error("conv_hybrid_apply: the two plans differ in grid or device");
+    return CONV_REAL_EINVAL;
+  }
+  const int dtype = precision == CONV_REAL_F64 ? CONV_SHT_F64 : CONV_SHT_F32;
+  const size_t elem = dtype == CONV_SHT_F64 ? 8 : 4;
+  const size_t bytes = static_cast<size_t>(nmaps) * sht->npix * elem;
+  const char* i0 = static_cast<const char*>(maps_in);
+  const char* o0 = static_cast<const char*>(maps_out);
+  if (i0 < o0 + bytes && o0 < i0 + bytes) { set_error("conv_hybrid_apply: maps_in and maps_out overlap"); return CONV_REAL_EALIAS; }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(sht->device);
+  if (e != hipSuccess) return hip_fail(e, "conv_hybrid_apply: hipSetDevice");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const hipStream_t s2 = stream_sht ? static_cast<hipStream_t>(stream_sht) : st;
+  const bool two = s2 != st;
+  for (int k = 0; k < nmaps && e == hipSuccess; ++k) {
+    const void* x = static_cast<const char*>(maps_in) + k * sht->npix * elem;
+    void* y = static_cast<char*>(maps_out) + k * sht->npix * elem;
+    if (two) {
+      // the harmonic stream starts once the inputs are ready in the caller's stream
+      if ((e = hipEventRecord(sht->ev_in, st)) != hipSuccess || (e = hipStreamWaitEvent(s2, sht->ev_in, 0)) != hipSuccess)
+        break;
+    }
+    rc = conv_real_apply(real, x, y, 1, stream);
+    if (rc != CONV_REAL_OK) return rc;
+    if ((e = launch_analysis(sht, x, dtype, sht->d_alm, s2)) != hipSuccess) break;
+    if ((e = launch_almxfl(sht, sht->d_alm, k_hat, sht->d_alm, s2)) != hipSuccess) break;
+    if ((e = launch_synthesis_legendre(sht, sht->d_alm, s2)) != hipSuccess) break;
+    if (two) {
+      if ((e = hipEventRecord(sht->ev_real, st)) != hipSuccess || (e = hipStreamWaitEvent(s2, sht->ev_real, 0)) != hipSuccess)
+        break;
+    }
+    if ((e = launch_ring_synthesis(sht, y, dtype, 1, s2)) != hipSuccess) break;
+    if (two) {
+      if ((e = hipEventRecord(sht->ev_done, s2)) != hipSuccess || (e = hipStreamWaitEvent(st, sht->ev_done, 0)) != hipSuccess)
+        break;
+    }
+  }
+  return e == hipSuccess ? CONV_REAL_OK : hip_fail(e, "conv_hybrid_apply");
+}
+
+int conv_sht_destroy(conv_sht_plan* plan) {
+  if (!plan) return CONV_REAL_OK;
+  if (!plan_ok(plan)) { set_error("conv_sht_destroy: invalid plan"); return CONV_REAL_EINVAL; }
+  DeviceGuard guard;
+  (void)guard.enter(plan->device);
+  free_sht(plan);
+  return CONV_REAL_OK;
+}
+
+}  // extern "C"

@@ -25,7 +25,7 @@ def declared_functions(header=None):
 
 
 def test_every_declared_symbol_is_exported():
-    from paper_1409_4441_amd import learn, split
+    from paper_1409_4441_amd import learn, sht, split
     names = declared_functions()
     assert len(names) >= 30
     for n in names:
@@ -33,7 +33,8 @@ def test_every_declared_symbol_is_exported():
     assert sorted(cr.EXPORTS) == declared_functions("convreal.h")
     assert sorted(split.EXPORTS) == declared_functions("convsplit.h")
     assert sorted(learn.EXPORTS) == declared_functions("convlearn.h")
-    assert sorted(set(cr.EXPORTS) | set(split.EXPORTS) | set(learn.EXPORTS)) == names
+    assert sorted(sht.EXPORTS) == declared_functions("convsht.h")
+    assert sorted(set(cr.EXPORTS) | set(split.EXPORTS) | set(learn.EXPORTS) | set(sht.EXPORTS)) == names
 
 
 def test_strerror():
@@ -103,3 +104,23 @@ def test_python_binding_validates():
     with pytest.raises(cr.ConvRealError) as e:
         cr.Plan(0, np.ones(16), 0.1, "f64")
     assert e.value.code == cr.EINVAL
+
+
+def test_sht_rejects_bad_arguments():
+    from paper_1409_4441_amd import sht
+    h = ctypes.c_void_p()
+    for nside, lmax in [(0, 8), (4096, 8), (16, -1), (16, 8193)]:
+        assert cr.lib.conv_sht_init(ctypes.byref(h), nside, lmax) == cr.EINVAL
+    assert cr.lib.conv_sht_init(None, 16, 8) == cr.EINVAL
+    n = ctypes.c_longlong()
+    assert cr.lib.conv_sht_alm_size(10, ctypes.byref(n)) == cr.OK and n.value == 66
+    assert cr.lib.conv_sht_alm_size(-1, ctypes.byref(n)) == cr.EINVAL
+    for f, args in [("conv_sht_analysis", (None, None, 0, None, None)),
+                    ("conv_sht_synthesis", (None, None, None, 0, 0, None)),
+                    ("conv_sht_almxfl", (None, None, None, None, None)),
+                    ("conv_sht_convolve", (None, None, None, None, 0, 0, None)),
+                    ("conv_sht_power_spectrum", (None, None, None, None)),
+                    ("conv_hybrid_apply", (None, None, None, None, None, 1, None, None))]:
+        assert getattr(cr.lib, f)(*args) == cr.EINVAL, f
+    assert cr.lib.conv_sht_destroy(None) == cr.OK
+    assert sht.alm_size(4) == 15
