@@ -82,7 +82,8 @@ double conv_cost_pairs(int nside, double theta_cut);
 
 /* Least-squares fit of (a, b) to n_real measured real-space times t_real[k] at pairs[k] (n_real >= 2;
  * with one point a = 0), and of c to n_sht harmonic times t_sht[k] at work_sht[k] = ell_cut^2 lmax
- * (through the origin, n_sht >= 1). Inputs are host arrays. */
+ * (through the origin, n_sht >= 1), both on relative residuals (model / t - 1), so that runs of very
+ * different length weigh alike. Times must be > 0. Inputs are host arrays. */
 int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const double* work_sht,
                   const double* t_sht, int n_sht, conv_cost_model* m);
 
@@ -90,11 +91,22 @@ int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const d
 int conv_cost_eval(const conv_cost_model* m, int nside, int lmax, double theta_cut, int ell_cut, double* t_real,
                    double* t_sht, double* wall);
 
+/* Compensation of a split: max_{l <= ell_cut} |(P x)_l| / max_l |K_l|, the part of the kernel's scale
+ * that the harmonic part must cancel at low l (the paper's fits need percent-level adjustments,
+ * Results section, discussion of Fig. 3). Splits with few real-space samples inside the cut give
+ * large, oscillating samples whose low-l content the pixel-grid sum reproduces far worse than the error
+ * model assumes. */
+int conv_split_compensation(conv_split_ctx* ctx, const double* k_ell, int ell_cut, double theta_cut, double* comp);
+
+/* Largest compensation the search accepts (max_comp >= 0; 0, the default, accepts any). */
+int conv_split_set_max_compensation(conv_split_ctx* ctx, double max_comp);
+
 /* The split search (the paper's scan): for each theta in theta_grid (n_theta values in
  * (0, theta_max]), the smallest ell_cut in {0, s, 2s, ..., lmax} (s = ell_step >= 1) whose Eq. 6
- * error is <= bound, found by bisection (the error falls as ell_cut grows); among these, the pair of
- * least modelled wall time (ties: the smaller theta). Returns CONV_REAL_OK with the pair, or
- * CONV_SPLIT_INFEASIBLE (outputs untouched). Outputs may be NULL. */
+ * error is <= bound, found by bisection (the error falls as ell_cut grows); if its compensation
+ * exceeds the context's limit, that theta keeps only ell_cut = lmax (all harmonic, error 0); among
+ * these, the pair of least modelled wall time (ties: the smaller theta). Returns CONV_REAL_OK with
+ * the pair, or CONV_SPLIT_INFEASIBLE (outputs untouched). Outputs may be NULL. */
 int conv_split_search(conv_split_ctx* ctx, const double* k_ell, int nside, double bound, double alpha,
                       const double* theta_grid, int n_theta, int ell_step, const conv_cost_model* m,
                       double* theta_cut, int* ell_cut, double* wall, double* sigma);

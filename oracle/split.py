@@ -148,22 +148,34 @@ def pairs_estimate(nside: int, theta_cut: float) -> float:
 
 
 def cost_fit(pairs, t_real, work_sht, t_sht):
-    """Measured-constant cost model in the form of Eqs. 7-8: t_real = a + b pairs (least squares;
-    a = 0 from a single point), t_sht = c ell_cut^2 lmax (least squares through the origin)."""
+    """Measured-constant cost model in the form of Eqs. 7-8: t_real = a + b pairs, t_sht = c ell_cut^2
+    lmax (through the origin), each fitted by least squares on relative residuals (model / t - 1;
+    a = 0 from a single point)."""
     pairs, t_real = np.asarray(pairs, float), np.asarray(t_real, float)
     work_sht, t_sht = np.asarray(work_sht, float), np.asarray(t_sht, float)
     if len(pairs) == 1:
         a, b = 0.0, t_real[0] / pairs[0]
     else:
-        b, a = np.polyfit(pairs, t_real, 1)
-    c = float(np.dot(work_sht, t_sht) / np.dot(work_sht, work_sht))
+        # minimise sum ((a + b p_k) / t_k - 1)^2: ordinary least squares on rows [1/t_k, p_k/t_k]
+        M = np.stack([1.0 / t_real, pairs / t_real], axis=1)
+        (a, b), *_ = np.linalg.lstsq(M, np.ones(len(pairs)), rcond=None)
+    u = work_sht / t_sht
+    c = float(np.sum(u) / np.dot(u, u))
     return float(a), float(b), c
 
 
+def compensation(K_ell, K_hat, K_tilde) -> float:
+    """What the harmonic part cancels of the real-space part at low l: by Eq. 1, (P K^_theta)_l =
+    K~_l - K^_l for l <= l_cut; its largest magnitude over the largest |K_l|."""
+    lc = len(K_hat) - 1
+    return float(np.max(np.abs(np.asarray(K_tilde)[: lc + 1] - np.asarray(K_hat))) / np.max(np.abs(K_ell)))
+
+
 def split_search(K_ell, C_in, bound: float, theta_grid, t_gpu, t_cpu, alpha: float = 5.0,
-                 sv_cut: float = 1e-6, solver=None):
+                 sv_cut: float = 1e-6, solver=None, max_comp: float = 0.0):
     """Scan theta_cut; binary-search the smallest feasible l_cut for each; keep the cheapest.
-    solver is the least-squares split to use (default: the full solve of Eq. 3).
+    solver is the least-squares split to use (default: the full solve of Eq. 3). With max_comp > 0,
+    a theta whose smallest feasible split has a compensation above max_comp keeps only l_cut = lmax.
     Returns (theta_cut, ell_cut, wall, error) or None if no pair meets the bound."""
     lmax = len(K_ell) - 1
     solve = lsq_split if solver is None else solver
@@ -171,6 +183,10 @@ def split_search(K_ell, C_in, bound: float, theta_grid, t_gpu, t_cpu, alpha: flo
     def err(lc, tc):
         _, _, _, kt = solve(K_ell, C_in, lc, tc, sv_cut)
         return fractional_error(K_ell, kt, C_in, alpha)
+
+    def comp(lc, tc):
+        kh, _, _, kt = solve(K_ell, C_in, lc, tc, sv_cut)
+        return compensation(K_ell, kh, kt)
 
     best = None
     for tc in theta_grid:
@@ -185,6 +201,8 @@ def split_search(K_ell, C_in, bound: float, theta_grid, t_gpu, t_cpu, alpha: flo
                 hi = mid
             else:
                 lo = mid
+        if max_comp > 0 and hi < lmax and comp(hi, tc) > max_comp:
+            hi = lmax
         wall = wall_time(t_gpu(tc), t_cpu(hi))
         if best is None or wall < best[2]:
             best = (tc, hi, wall, err(hi, tc))

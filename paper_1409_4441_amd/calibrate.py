@@ -3,11 +3,14 @@
     python -m paper_1409_4441_amd.calibrate [--out cost_model.json] [--quick]
 
 Real-space part: conv_real_apply of the mixed-precision path on one white-noise map, for Gaussian
-beams over Nside 256..2048, FWHM 5'..30' and theta_cut 4..8 sigma; times from HIP events around the
-applies, pair counts exact (conv_real_pairs). Fitted: t_real = a + b pairs.
-Harmonic part: the seeded-input package's host spherical-harmonic synthesis (OpenMP) at several
-(Nside, l_cut); a harmonic convolution is an analysis and a synthesis of the same size, so its time
-is taken as twice the synthesis. Fitted: t_sht = c l_cut^2 lmax with lmax = 2 Nside.
+beams over Nside 256..2048, FWHM 5'..30' and theta_cut 2..12 sigma (the range the split scan
+visits); times from HIP events around the applies, pair counts exact (conv_real_pairs). Fitted:
+t_real = a + b pairs.
+Harmonic part: the library's harmonic convolution on the GPU (conv_sht_convolve: analysis, product,
+synthesis) with band limit l_cut, at several (Nside, l_cut); fitted: t_sht = c l_cut^2 lmax with
+lmax = 2 Nside (Eq. 8's form). The two halves of a hybrid apply run at the same time on two
+streams (Fig. 1), so the model's wall time is the slower of the two; a few hybrid applies are timed
+beside the model to show how far that holds on one device.
 """
 from __future__ import annotations
 
@@ -36,7 +39,7 @@ def real_space_points(quick: bool):
     pts = []
     for nside in nsides:
         for fwhm in (5.0, 15.0, 30.0):
-            for ns in (4.0, 8.0):
+            for ns in (2.0, 4.0, 8.0, 12.0):
                 s = learn.sigma_of(fwhm)
                 tc = ns * s
                 lmax = 2 * nside
@@ -64,18 +67,66 @@ def real_space_points(quick: bool):
 
 
 def harmonic_points(quick: bool):
-    import synth
-    cases = [(256, 128), (256, 512), (512, 512), (512, 1024)] if quick else \
-        [(256, 256), (256, 512), (512, 512), (512, 1024), (1024, 1024), (1024, 2048)]
+    import torch
+
+    from paper_1409_4441_amd import sht
+    cases = [(256, 64), (256, 256), (512, 256), (512, 1024), (1024, 512), (1024, 2048)] if quick else \
+        [(256, 64), (256, 256), (256, 512), (512, 128), (512, 512), (512, 1024), (1024, 256), (1024, 1024),
+         (1024, 2048), (2048, 512), (2048, 1500), (2048, 4096)]
     pts = []
     for nside, lc in cases:
-        alm = synth.draw_alm(synth.red_spectrum(lc), seed=nside + lc)
-        synth.synthesize(nside, alm, lc)             # warm-up
-        t0 = time.perf_counter()
-        synth.synthesize(nside, alm, lc)
-        t = 2.0 * (time.perf_counter() - t0)
-        pts.append({"nside": nside, "ell_cut": lc, "lmax": 2 * nside, "seconds": t})
-        print(f"harmonic nside {nside} l_cut {lc}: {t:.3f} s", flush=True)
+        with sht.Sht(nside, lc) as t:
+            g = torch.Generator(device="cuda").manual_seed(nside + lc)
+            x = torch.randn(12 * nside * nside, device="cuda", generator=g)
+            k = torch.ones(lc + 1, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            t.convolve(x, k, out=y)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 3
+            e0.record()
+            for _ in range(reps):
+                t.convolve(x, k, out=y)
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / reps * 1e-3
+        pts.append({"nside": nside, "ell_cut": lc, "lmax": 2 * nside, "seconds": sec})
+        print(f"harmonic nside {nside} l_cut {lc}: {sec * 1e3:.2f} ms", flush=True)
+    return pts
+
+
+def hybrid_points(model):
+    """Hybrid applies (mixed real-space plan + harmonic half at band limit l_cut, two streams) timed
+    against the model's max(t_real, t_sht) and the sum of the two."""
+    import torch
+
+    import paper_1409_4441_amd as cr
+    from paper_1409_4441_amd import learn, sht
+    pts = []
+    for nside, fwhm, ns, lc in [(1024, 10.0, 8.0, 512), (2048, 5.0, 6.0, 1500), (2048, 10.0, 12.0, 800)]:
+        s = learn.sigma_of(fwhm)
+        tc = ns * s
+        table = cr.tabulate(learn.beam(2 * nside, fwhm), tc, 1024)
+        with cr.Plan(nside, table, tc, "mixed") as plan, sht.Sht(nside, lc) as t:
+            x = torch.randn((1, 12 * nside * nside), device="cuda")
+            k = torch.ones(lc + 1, dtype=torch.float64, device="cuda")
+            side = torch.cuda.Stream()
+            y = sht.hybrid_apply(plan, t, k, x, stream_sht=side)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 3
+            e0.record()
+            for _ in range(reps):
+                sht.hybrid_apply(plan, t, k, x, out=y, stream_sht=side)
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / reps * 1e-3
+            pairs = plan.pairs()
+        tr, ts, wl = model.eval(nside, 2 * nside, tc, lc)
+        pts.append({"nside": nside, "fwhm_arcmin": fwhm, "theta_cut": tc, "ell_cut": lc, "pairs": pairs,
+                    "seconds": sec, "model_t_real": tr, "model_t_sht": ts, "model_wall": wl})
+        print(f"hybrid nside {nside} fwhm {fwhm}' theta {ns} sigma l_cut {lc}: {sec * 1e3:.2f} ms "
+              f"(model max {wl * 1e3:.2f}, sum {(tr + ts) * 1e3:.2f})", flush=True)
     return pts
 
 
@@ -89,10 +140,12 @@ def main():
     harm = harmonic_points(args.quick)
     m = split.CostModel.fit([p["pairs"] for p in real], [p["seconds"] for p in real],
                             [p["ell_cut"] ** 2 * p["lmax"] for p in harm], [p["seconds"] for p in harm])
-    out = {"a": m.a, "b": m.b, "c": m.c, "threads": os.cpu_count(),
-           "real_space": real, "harmonic": harm,
+    hyb = hybrid_points(m)
+    out = {"a": m.a, "b": m.b, "c": m.c,
+           "real_space": real, "harmonic": harm, "hybrid": hyb,
            "note": "t_real = a + b pairs (mixed-precision path, one map); "
-                   "t_sht = c l_cut^2 lmax (twice the host synthesis time)"}
+                   "t_sht = c l_cut^2 lmax (GPU harmonic convolution at band limit l_cut); "
+                   "hybrid: measured two-stream applies beside the model"}
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps({"a": m.a, "b": m.b, "c": m.c}), flush=True)

@@ -332,8 +332,8 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
   // m in [ceil(delta/2 - hw - eps), floor(delta/2 + hw + eps)], delta = c_i - c_j.
   const int nbelt = bhi - blo + 1;
   const int nbands = (nbelt + 15) / 16;
-  std::vector<int> band_jf(nbands), band_nj(nbands), band_woff(nbands);
-  std::vector<int> blk_koff, blk_nk, blk_mlo, chunk_band, chunk_j, chunk_m0;
+  std::vector<int> band_nj(nbands), band_woff(nbands);
+  std::vector<int> blk_j, blk_koff, blk_nk, blk_mlo, chunk_band, chunk_j, chunk_m0;
   bool ok = true;
   int nk_max = 1;
   for (int b = 0; b < nbands && ok; ++b) {
@@ -346,8 +346,6 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
     }
     lo = std::max(lo, blo);
     hi = std::min(hi, bhi);
-    band_jf[b] = lo;
-    band_nj[b] = hi - lo + 1;
     band_woff[b] = static_cast<int>(blk_nk.size());
     for (int j = lo; j <= hi && ok; ++j) {
       int mmin = 1 << 30, mmax = -(1 << 30);
@@ -362,17 +360,25 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
       if (!ok) break;
       if (mmax < mmin) { mmin = 0; mmax = 0; }
       const int nk = (mmax - mmin + 1 + 31) / 32;
-      if (nk > 4 || 32 * nk > 4 * N) { ok = false; break; }
-      nk_max = std::max(nk_max, nk);
-      blk_koff.push_back(static_cast<int>(chunk_band.size()));
-      blk_nk.push_back(nk);
-      blk_mlo.push_back(mmin);
-      for (int q = 0; q < nk; ++q) {
-        chunk_band.push_back(b);
-        chunk_j.push_back(j);
-        chunk_m0.push_back(mmin + 32 * q);
+      if (32 * nk > 4 * N) { ok = false; break; }
+      // a window of more than kBeltBlockChunks K-chunks goes in consecutive sub-blocks of the same
+      // input ring, each staged and multiplied like a ring of its own (the LDS stage holds one)
+      for (int q0 = 0; q0 < nk; q0 += convreal::kBeltBlockChunks) {
+        const int nks = std::min(convreal::kBeltBlockChunks, nk - q0);
+        const int m0 = mmin + 32 * q0;
+        nk_max = std::max(nk_max, nks);
+        blk_j.push_back(j);
+        blk_koff.push_back(static_cast<int>(chunk_band.size()));
+        blk_nk.push_back(nks);
+        blk_mlo.push_back(m0);
+        for (int q = 0; q < nks; ++q) {
+          chunk_band.push_back(b);
+          chunk_j.push_back(j);
+          chunk_m0.push_back(m0 + 32 * q);
+        }
       }
     }
+    band_nj[b] = static_cast<int>(blk_nk.size()) - band_woff[b];
   }
   p->belt_enabled = ok ? 1 : 0;
 
@@ -395,7 +401,7 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
     p->belt_nsegs = (4 * N + 255) / 256;
     p->n_wblk = static_cast<long long>(blk_nk.size());
     p->n_chunks = static_cast<long long>(chunk_band.size());
-    if ((e = dev_upload(p, &p->d_band_jf, band_jf)) != hipSuccess ||
+    if ((e = dev_upload(p, &p->d_blk_j, blk_j)) != hipSuccess ||
         (e = dev_upload(p, &p->d_band_nj, band_nj)) != hipSuccess ||
         (e = dev_upload(p, &p->d_band_woff, band_woff)) != hipSuccess ||
         (e = dev_upload(p, &p->d_blk_koff, blk_koff)) != hipSuccess ||
@@ -526,7 +532,7 @@ hipError_t setup_mixed(conv_real_plan* p, const convreal::RingGrid& g, const std
   d.ring_n = 4 * N;
   d.npix = p->npix;
   d.wt = p->d_wt;
-  d.band_jf = p->d_band_jf;
+  d.blk_j = p->d_blk_j;
   d.band_nj = p->d_band_nj;
   d.band_woff = p->d_band_woff;
   d.blk_koff = p->d_blk_koff;

@@ -69,6 +69,9 @@ void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std
 
 constexpr int kMaxSlots = 64;  // maps per persistent mixed-path launch
 constexpr int kMaxChunks = 8;  // work-queue chunks (one per XCD)
+// K-chunks (32 window offsets) of one belt weight block: the LDS stage holds one block's window;
+// wider windows of one input ring are split into several blocks
+constexpr int kBeltBlockChunks = 4;
 // 16-row blocks per cap tile when the plan holds a weight store: the blocks of a tile share every
 // step's inputs and every ring pair's set-up, but each block adds its weight registers to every
 // pipeline slot; two blocks exceed the register file at two waves per SIMD and were measured slower
@@ -120,8 +123,8 @@ struct MixedDesc {
   long long npix;
   // belt ring pairs
   const _Float16* wt;
-  const int* band_jf;
-  const int* band_nj;
+  const int* blk_j;           // per weight block: input ring
+  const int* band_nj;         // per band: weight blocks
   const int* band_woff;
   const int* blk_koff;
   const int* blk_nk;
@@ -222,8 +225,8 @@ struct conv_real_plan {
   long long n_wblk = 0;        // weight blocks (band, input ring)
   long long n_chunks = 0;      // K-chunks over all weight blocks
   double belt_sw = 1.0;        // power-of-two weight scale
-  int* d_band_jf = nullptr;    // per band: first input ring
-  int* d_band_nj = nullptr;    // per band: number of input rings
+  int* d_blk_j = nullptr;      // per weight block: input ring
+  int* d_band_nj = nullptr;    // per band: number of weight blocks (input rings, wide windows split)
   int* d_band_woff = nullptr;  // per band: first weight block
   int* d_blk_koff = nullptr;   // per weight block: first K-chunk
   int* d_blk_nk = nullptr;     // per weight block: K-chunks

@@ -54,7 +54,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 constexpr int kFold = 4;   // ring pairs per FP32 -> FP64 fold
-constexpr int kNKMax = 4;  // largest K-chunk count of a belt weight block
+constexpr int kNKMax = convreal::kBeltBlockChunks;  // largest K-chunk count of a belt weight block
 
 // ---------------------------------------------------------------- shared helpers
 using convreal::buffer_resource;
@@ -256,7 +256,6 @@ __device__ __forceinline__ void belt_item(const convreal::MixedDesc* __restrict_
   const int band = idx / nsegs;
   const int seg = idx % nsegs;
   const int a0 = seg * SEG;
-  const int jf = ldu(d->band_jf[band]);
   const int nj = ldu(d->band_nj[band]);
   const int woff = ldu(d->band_woff[band]);
   const int lane = threadIdx.x & 63;
@@ -268,6 +267,7 @@ __device__ __forceinline__ void belt_item(const convreal::MixedDesc* __restrict_
   const half8* wt = reinterpret_cast<const half8*>(ldu(d->wt));
   const long long* rstart = ldu(d->rstart);
   const int* blk_mlo = ldu(d->blk_mlo);
+  const int* blk_j = ldu(d->blk_j);
   const int* blk_nk = ldu(d->blk_nk);
   const int* blk_koff = ldu(d->blk_koff);
 
@@ -287,7 +287,7 @@ __device__ __forceinline__ void belt_item(const convreal::MixedDesc* __restrict_
   BeltPrefetch<SEG> pf[AHEAD];
   auto load_ring = [&](int jj, BeltPrefetch<SEG>& slot) {
     const int nk1 = ldu(blk_nk[woff + jj]);
-    slot.load(xm + ldu(rstart[jf + jj]), a0 + ldu(blk_mlo[woff + jj]), SEG + 32 * nk1, ring_n,
+    slot.load(xm + ldu(rstart[ldu(blk_j[woff + jj])]), a0 + ldu(blk_mlo[woff + jj]), SEG + 32 * nk1, ring_n,
               wt + static_cast<long long>(ldu(blk_koff[woff + jj])) * 128, nk1 * 128);
   };
   load_ring(0, pf[0]);

@@ -147,6 +147,7 @@ struct conv_split_ctx {
   int lmax = 0;
   double theta_max = 0.0;
   double sv_cut = 1e-6;
+  double max_comp = 0.0;   // search: largest accepted max_{l <= l_cut} |(P x)_l| / max_l |K_l| (0: no limit)
   std::vector<double> W;   // (2l + 1) C_l
   std::vector<double> z, w;
   int nmax = 0;
@@ -264,6 +265,23 @@ int check_split(const conv_split_ctx* c, const double* k_ell, int ell_cut, doubl
   return CONV_REAL_OK;
 }
 
+// Compensation of a split: the largest |(P x)_l| for l <= ell_cut (what the harmonic part must cancel
+// of the real-space part's low-l content) over the largest |K_l|.
+double compensation_of(conv_split_ctx* c, const double* K, int ell_cut, double theta_cut) {
+  const int n = count_nodes(c, theta_cut);
+  std::vector<double> x;
+  solve_reduced(c, K, ell_cut, n, x);
+  double kmax = 0.0, cmax = 0.0;
+  for (int l = 0; l <= c->lmax; ++l) kmax = std::max(kmax, std::fabs(K[l]));
+  for (int l = 0; l <= ell_cut; ++l) {
+    const double* p = c->P.data() + static_cast<size_t>(l) * c->nmax;
+    double kr = 0.0;
+    for (int k = 0; k < n; ++k) kr += p[k] * x[k];
+    cmax = std::max(cmax, std::fabs(kr));
+  }
+  return kmax > 0.0 ? cmax / kmax : 0.0;
+}
+
 double sigma_of(conv_split_ctx* c, const double* K, int ell_cut, double theta_cut, double alpha) {
   const int n = count_nodes(c, theta_cut);
   std::vector<double> x;
@@ -308,7 +326,14 @@ bool search_one(conv_split_ctx* c, const double* K, int nside, double bound, dou
       }
       if (hi == nsteps + 1) sig_hi = 0.0;
     }
-    const int lc = cand(hi);
+    int lc = cand(hi);
+    // a split whose harmonic part must cancel more than max_comp of the kernel's scale at low l is not
+    // trusted (the pixel-grid sum cannot reproduce such large low-l content to the error model's
+    // precision): this theta then keeps only the all-harmonic split
+    if (c->max_comp > 0.0 && lc < lmax && compensation_of(c, K, lc, th) > c->max_comp) {
+      lc = lmax;
+      sig_hi = 0.0;
+    }
     double w = 0.0;
     conv_cost_eval(m, nside, lmax, th, lc, nullptr, nullptr, &w);
     if (!found || w < best_wall) {
@@ -466,6 +491,18 @@ int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const d
     set_error("conv_cost_fit: NULL argument or empty measurement set");
     return CONV_REAL_EINVAL;
   }
+  // relative residuals: every measured point weighs by 1 / t^2, so that millisecond and
+  // second-scale runs count alike
+  for (int k = 0; k < n_real; ++k)
+    if (!(t_real[k] > 0.0)) {
+      set_error("conv_cost_fit: real-space times must be > 0");
+      return CONV_REAL_EINVAL;
+    }
+  for (int k = 0; k < n_sht; ++k)
+    if (!(t_sht[k] > 0.0)) {
+      set_error("conv_cost_fit: harmonic times must be > 0");
+      return CONV_REAL_EINVAL;
+    }
   double a = 0.0, b = 0.0;
   if (n_real == 1) {
     if (!(pairs[0] > 0.0)) {
@@ -474,26 +511,28 @@ int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const d
     }
     b = t_real[0] / pairs[0];
   } else {
-    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    double s0 = 0, sx = 0, sy = 0, sxx = 0, sxy = 0;
     for (int k = 0; k < n_real; ++k) {
-      sx += pairs[k];
-      sy += t_real[k];
-      sxx += pairs[k] * pairs[k];
-      sxy += pairs[k] * t_real[k];
+      const double w = 1.0 / (t_real[k] * t_real[k]);
+      s0 += w;
+      sx += w * pairs[k];
+      sy += w * t_real[k];
+      sxx += w * pairs[k] * pairs[k];
+      sxy += w * pairs[k] * t_real[k];
     }
-    const double nn = static_cast<double>(n_real);
-    const double den = nn * sxx - sx * sx;
-    if (!(std::fabs(den) > 0.0)) {
+    const double den = s0 * sxx - sx * sx;
+    if (!(std::fabs(den) > 1e-12 * s0 * sxx)) {
       set_error("conv_cost_fit: the pair counts must not all be equal");
       return CONV_REAL_EINVAL;
     }
-    b = (nn * sxy - sx * sy) / den;
-    a = (sy - b * sx) / nn;
+    b = (s0 * sxy - sx * sy) / den;
+    a = (sy - b * sx) / s0;
   }
   double sw = 0, swt = 0;
   for (int k = 0; k < n_sht; ++k) {
-    sw += work_sht[k] * work_sht[k];
-    swt += work_sht[k] * t_sht[k];
+    const double w = 1.0 / (t_sht[k] * t_sht[k]);
+    sw += w * work_sht[k] * work_sht[k];
+    swt += w * work_sht[k] * t_sht[k];
   }
   if (!(sw > 0.0)) {
     set_error("conv_cost_fit: harmonic work must be > 0");
@@ -516,6 +555,26 @@ int conv_cost_eval(const conv_cost_model* m, int nside, int lmax, double theta_c
   if (t_real) *t_real = tr;
   if (t_sht) *t_sht = ts;
   if (wall) *wall = std::max(tr, ts);
+  return CONV_REAL_OK;
+}
+
+int conv_split_set_max_compensation(conv_split_ctx* ctx, double max_comp) {
+  if (int e = check_ctx(ctx, "conv_split_set_max_compensation")) return e;
+  if (!(max_comp >= 0.0) || !std::isfinite(max_comp)) {
+    set_error("conv_split_set_max_compensation: max_comp must be finite and >= 0");
+    return CONV_REAL_EINVAL;
+  }
+  ctx->max_comp = max_comp;
+  return CONV_REAL_OK;
+}
+
+int conv_split_compensation(conv_split_ctx* ctx, const double* k_ell, int ell_cut, double theta_cut, double* comp) {
+  if (int e = check_split(ctx, k_ell, ell_cut, theta_cut, "conv_split_compensation")) return e;
+  if (!comp) {
+    set_error("conv_split_compensation: NULL output");
+    return CONV_REAL_EINVAL;
+  }
+  *comp = compensation_of(ctx, k_ell, ell_cut, theta_cut);
   return CONV_REAL_OK;
 }
 

@@ -29,7 +29,16 @@ from . import split as _split
 
 N_PARAMS = 4546
 IN, HIDDEN, OUT = 3, 64, 2
+# Eq. 6's alpha: the paper's 5, an upper bound for this build (the measured ratio of the split's
+# power-spectrum error to Eq. 6 with alpha = 1 is 1.0-4.6 over the splits the search chooses)
 ALPHA = 5.0
+# largest compensation (max_{l <= l_cut} |(P x)_l| / max |K_l|) a split may need: the paper's fits
+# adjust the harmonic kernel at the percent level; splits needing more are not trusted
+MAX_COMP = 1e-2
+# network answers l_cut / lmax at or above this are taken as the all-harmonic split; answers in
+# [UNCERTAIN_FRAC, ALL_HARMONIC_FRAC) are left to the search
+ALL_HARMONIC_FRAC = 0.95
+UNCERTAIN_FRAC = 0.45
 ARCMIN = math.pi / (180.0 * 60.0)
 
 # Ranges of the learned map: Nside 256..2048, FWHM 5'..30', target error 1e-6..1e-4.
@@ -191,10 +200,18 @@ def draw_triples(n: int, seed: int):
     return nside, fwhm, eps
 
 
+def eval_grid():
+    """The evaluation grid of the learned split: Nside 2048, FWHM 5', 6', ..., 10', target errors
+    1e-6, 1e-5, 1e-4 (18 triples)."""
+    fw = np.repeat(np.arange(5.0, 10.01, 1.0), 3)
+    ep = np.tile([1e-6, 1e-5, 1e-4], 6)
+    return np.full(len(fw), 2048), fw, ep
+
+
 def _contexts():
     """One split context per Nside (lmax = 2 Nside), wide enough for the largest scan angle."""
     theta_max = max(THETA_SIGMAS) * sigma_of(FWHM_RANGE[1]) * 1.0001
-    return {ns: _split.Context(2 * ns, theta_max) for ns in NSIDES}
+    return {ns: _split.Context(2 * ns, theta_max, max_comp=MAX_COMP) for ns in NSIDES}
 
 
 def scan(nside, fwhm, eps, model, ctxs=None, nthreads: int = 0):
@@ -240,8 +257,16 @@ def decode(y, nside, fwhm, norm: dict):
     """Split (theta_cut, ell_cut) from network outputs; l_cut rounded and clamped to [0, lmax]."""
     y = np.atleast_2d(np.asarray(y, dtype=np.float64)) * np.asarray(norm["sd"]) + np.asarray(norm["mu"])
     lmax = 2 * np.asarray(nside)
-    theta = np.exp(y[:, 0]) * np.array([sigma_of(f) for f in np.atleast_1d(fwhm)])
-    ell = np.clip(np.rint(y[:, 1] * lmax), 0, lmax).astype(np.int64)
+    # theta_cut within the scan's range (the labels' range): the network does not extrapolate beyond it
+    lt = np.clip(y[:, 0], math.log(min(THETA_SIGMAS)), math.log(max(THETA_SIGMAS)))
+    theta = np.exp(lt) * np.array([sigma_of(f) for f in np.atleast_1d(fwhm)])
+    # the labels are binary in character: mostly a split with l_cut well below lmax, or all harmonic
+    # (l_cut = lmax). An answer near lmax is read as the latter; one in between (UNCERTAIN_FRAC) lies
+    # where the network interpolates across the feasibility edge and is marked -1 (the search decides)
+    f = y[:, 1]
+    frac = np.where(f >= ALL_HARMONIC_FRAC, 1.0, f)
+    ell = np.clip(np.rint(frac * lmax), 0, lmax).astype(np.int64)
+    ell = np.where((f >= UNCERTAIN_FRAC) & (f < ALL_HARMONIC_FRAC), -1, ell)
     return theta, ell
 
 
@@ -276,11 +301,16 @@ class Predictor:
         return decode(y, nside, fwhm, self.norm)
 
     def judge(self, nside: int, fwhm: float, eps: float, theta_cut: float, ell_cut: int):
-        """Eq. 6 error of a split and whether it meets eps."""
+        """Eq. 6 error of a split and whether it is accepted: it meets eps, and it is all harmonic or
+        its compensation is at most MAX_COMP (the search's own conditions)."""
+        if int(ell_cut) < 0:           # the network left this triple to the search
+            return float("nan"), False
         ctx = self.ctxs[int(nside)]
         th = min(max(float(theta_cut), 1e-9), ctx.theta_max)
-        _, sig = ctx.error(kernel_ell(2 * int(nside), fwhm), int(ell_cut), th, alpha=ALPHA)
-        return sig, sig <= eps
+        K = kernel_ell(2 * int(nside), fwhm)
+        _, sig = ctx.error(K, int(ell_cut), th, alpha=ALPHA)
+        ok = sig <= eps and (int(ell_cut) >= 2 * int(nside) or ctx.compensation(K, int(ell_cut), th) <= MAX_COMP)
+        return sig, ok
 
     def predict(self, nside: int, fwhm: float, eps: float):
         """(theta_cut, ell_cut, source), source "mlp" or "fallback"."""

@@ -21,7 +21,8 @@ INFEASIBLE = 1
 
 # Every entry point that include/convsplit.h declares.
 EXPORTS = ("conv_split_create", "conv_split_destroy", "conv_split_nodes", "conv_split_lsq", "conv_split_error",
-           "conv_cost_pairs", "conv_cost_fit", "conv_cost_eval", "conv_split_search", "conv_split_search_many")
+           "conv_cost_pairs", "conv_cost_fit", "conv_cost_eval", "conv_split_search", "conv_split_search_many",
+           "conv_split_compensation", "conv_split_set_max_compensation")
 
 _c_int, _c_double, _c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
 _dptr_t = ctypes.POINTER(ctypes.c_double)
@@ -38,6 +39,8 @@ def _bind():
     lib.conv_split_nodes.argtypes = [_c_void_p, _c_double, _iptr_t]
     lib.conv_split_lsq.argtypes = [_c_void_p, _dptr_t, _c_int, _c_double, _dptr_t, _dptr_t, _dptr_t, _dptr_t]
     lib.conv_split_error.argtypes = [_c_void_p, _dptr_t, _c_int, _c_double, _c_double, _dptr_t, _dptr_t]
+    lib.conv_split_compensation.argtypes = [_c_void_p, _dptr_t, _c_int, _c_double, _dptr_t]
+    lib.conv_split_set_max_compensation.argtypes = [_c_void_p, _c_double]
     lib.conv_cost_pairs.argtypes = [_c_int, _c_double]
     lib.conv_cost_pairs.restype = _c_double
     lib.conv_cost_fit.argtypes = [_dptr_t, _dptr_t, _c_int, _dptr_t, _dptr_t, _c_int, ctypes.POINTER(_Cost)]
@@ -49,7 +52,8 @@ def _bind():
                                            _c_int, ctypes.POINTER(_Cost), _c_int, _dptr_t, _iptr_t, _dptr_t,
                                            _dptr_t]
     for f in ("conv_split_create", "conv_split_destroy", "conv_split_nodes", "conv_split_lsq", "conv_split_error",
-              "conv_cost_fit", "conv_cost_eval", "conv_split_search", "conv_split_search_many"):
+              "conv_cost_fit", "conv_cost_eval", "conv_split_search", "conv_split_search_many",
+              "conv_split_compensation", "conv_split_set_max_compensation"):
         getattr(lib, f).restype = _c_int
 
 
@@ -110,9 +114,10 @@ def pairs_estimate(nside: int, theta_cut: float) -> float:
 
 
 class Context:
-    """Split model for one lmax and input weighting C_in (None: flat), theta_cut <= theta_max."""
+    """Split model for one lmax and input weighting C_in (None: flat), theta_cut <= theta_max; the
+    search accepts splits of compensation <= max_comp (0: any)."""
 
-    def __init__(self, lmax: int, theta_max: float, c_in=None, sv_cut: float = 1e-6):
+    def __init__(self, lmax: int, theta_max: float, c_in=None, sv_cut: float = 1e-6, max_comp: float = 0.0):
         self.lmax = int(lmax)
         self.theta_max = float(theta_max)
         c = None if c_in is None else _f64(c_in, self.lmax + 1, "c_in")
@@ -120,6 +125,8 @@ class Context:
         _check(lib.conv_split_create(ctypes.byref(h), self.lmax, None if c is None else _d(c), self.theta_max,
                                      float(sv_cut)), "conv_split_create")
         self._h = h
+        if max_comp:
+            _check(lib.conv_split_set_max_compensation(h, float(max_comp)), "conv_split_set_max_compensation")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value and lib is not None:
@@ -151,6 +158,14 @@ class Context:
         _check(lib.conv_split_lsq(self._h, _d(k), int(ell_cut), float(theta_cut), _d(kh), _d(kt), _d(kr), _d(ktl)),
                "conv_split_lsq")
         return kh, kt[:n], kr, ktl
+
+    def compensation(self, k_ell, ell_cut: int, theta_cut: float) -> float:
+        """max_{l <= l_cut} |(P x)_l| / max_l |K_l| of the split."""
+        k = _f64(k_ell, self.lmax + 1, "k_ell")
+        c = ctypes.c_double()
+        _check(lib.conv_split_compensation(self._h, _d(k), int(ell_cut), float(theta_cut), ctypes.byref(c)),
+               "conv_split_compensation")
+        return c.value
 
     def error(self, k_ell, ell_cut: int, theta_cut: float, alpha: float = 5.0):
         """(sigma_rms of Eq. 2, sigma of Eq. 6)."""

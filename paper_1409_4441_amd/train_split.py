@@ -6,8 +6,9 @@ Data: 2000 training and 200 held-out (Nside, FWHM, target error) triples (Nside 
 256..2048, FWHM log-uniform 5'..30', error log-uniform 1e-6..1e-4), seeded; labels are the split
 search's answers under the measured cost model (conv_split_search_many on host threads). Training:
 full-batch Adam on the library's kernels, learning rate stepped down 3e-3 -> 1e-3 -> 3e-4.
-Evaluation on the held-out triples: how often the network's split meets the bound (judged by the
-error model), its modelled wall time against the search's, and the time each takes to decide.
+Evaluation on the held-out triples and on the evaluation grid (Nside 2048, FWHM 5'..10', target
+errors 1e-6..1e-4): how often the network's split meets the bound (judged by the error model), its
+modelled wall time against the search's, and the time each takes to decide.
 """
 from __future__ import annotations
 
@@ -128,15 +129,22 @@ def main():
 
     pred = learn.Predictor(params, norm, model)
     metrics = evaluate(pred, test, test_scan, model)
+    grid = learn.eval_grid()
+    grid_metrics = evaluate(pred, grid, labels(grid, model)[:4], model)
     pred.close()
     meta = {"norm": norm, "cost_model": {"a": model.a, "b": model.b, "c": model.c},
             "train": {"n": args.n_train, "seed": TRAIN_SEED, "init_seed": INIT_SEED,
                       "schedule": [list(s) for s in SCHEDULE], "seconds": t_train,
                       "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                       "loss_every_500": [float(v) for v in hist[::500]]},
-            "test": {"seed": TEST_SEED, **metrics}}
+            "test": {"seed": TEST_SEED, **metrics},
+            "eval_grid": {"triples": "Nside 2048 x FWHM 5'..10' (1' steps) x target error 1e-6, 1e-5, 1e-4",
+                          **grid_metrics},
+            "labels": {"alpha": learn.ALPHA, "max_compensation": learn.MAX_COMP,
+                       "ell_cut_fraction_lmax": float(np.mean(lc == 2 * train[0])),
+                       "ell_cut_fraction_zero": float(np.mean(lc == 0))}}
     learn.save(args.out, params, meta)
-    print(json.dumps(meta["test"]), flush=True)
+    print(json.dumps({"test": meta["test"], "eval_grid": meta["eval_grid"], "labels": meta["labels"]}), flush=True)
 
 
 if __name__ == "__main__":

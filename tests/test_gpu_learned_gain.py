@@ -1,8 +1,9 @@
 """What the trained split network gains over the method without it (the split search), on held-out
-(Nside, FWHM, target error) triples: its split is accepted by the error model for most triples, an
-accepted split costs (in the measured cost model) no more than 5% above the search's on average,
-every returned split meets its bound (network or fallback), and the network decides far faster than
-the search. Uses the committed network parameters and cost model."""
+(Nside, FWHM, target error) triples and on the evaluation grid (Nside 2048, FWHM 5'..10', target
+errors 1e-6, 1e-5, 1e-4): its split is accepted by the error model for most triples, an accepted split
+costs (in the measured cost model) no more than 5% above the search's on average, every returned
+split meets its bound (network or fallback), and the network decides far faster than the search.
+Uses the committed network parameters and cost model."""
 import os
 import time
 
@@ -27,25 +28,31 @@ def predictor(cuda_device):
     p.close()
 
 
-def test_network_split_is_accepted_and_cheap(predictor):
-    ns, fw, ep = learn.draw_triples(N_EVAL, train_split.TEST_SEED)
+def _triples(which):
+    return learn.draw_triples(N_EVAL, train_split.TEST_SEED) if which == "held_out" else learn.eval_grid()
+
+
+@pytest.mark.parametrize("which", ["held_out", "eval_grid"])
+def test_network_split_is_accepted_and_cheap(predictor, which):
+    ns, fw, ep = _triples(which)
+    N = len(ns)
     t0 = time.perf_counter()
     th_s, lc_s, wl_s, sg_s = learn.scan(ns, fw, ep, predictor.model, ctxs=predictor.ctxs, nthreads=1)
-    t_search = (time.perf_counter() - t0) / N_EVAL
+    t_search = (time.perf_counter() - t0) / N
     assert np.all(sg_s <= ep)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     th_n, lc_n = predictor.network_split(ns, fw, ep)
-    t_net = (time.perf_counter() - t0) / N_EVAL
+    t_net = (time.perf_counter() - t0) / N
     ok, ratio = [], []
     t0 = time.perf_counter()
-    for k in range(N_EVAL):
+    for k in range(N):
         _, good = predictor.judge(int(ns[k]), float(fw[k]), float(ep[k]), float(th_n[k]), int(lc_n[k]))
         ok.append(good)
         if good:
             th = min(float(th_n[k]), predictor.ctxs[int(ns[k])].theta_max)
             ratio.append(predictor.model.eval(int(ns[k]), 2 * int(ns[k]), th, int(lc_n[k]))[2] / wl_s[k])
-    t_judge = (time.perf_counter() - t0) / N_EVAL
+    t_judge = (time.perf_counter() - t0) / N
     assert np.mean(ok) >= 0.5, np.mean(ok)
     assert np.mean(ratio) <= 1.05, np.mean(ratio)
     # deciding by the network and the error model's one evaluation against the full search

@@ -247,3 +247,45 @@ def test_split_search_equals_exhaustive_scan(fwhm, bound):
     got = split.split_search(K, C, bound, grid, t_gpu, t_cpu, solver=split.lsq_split_reduced)
     assert want is not None and got is not None
     assert got[:2] == want[:2] and got[2] == pytest.approx(want[2], rel=1e-15)
+
+
+def test_compensation_is_the_real_space_parts_low_l_content():
+    # Eq. 1: K~_l - K^_l = (P K^_theta)_l for l <= l_cut; for a kernel that samples x0 reproduce
+    # exactly, the reduced solve returns x0, so the compensation is max_{l <= l_cut} |(P x0)_l| / max |K|
+    lmax, tc = 128, 0.15
+    z, w = split.real_space_nodes(lmax, tc)
+    P = split.legendre_operator(lmax, z, w)
+    x0 = np.random.default_rng(9).standard_normal(len(z))
+    K = P @ x0
+    C = np.ones(lmax + 1)
+    for lc in (10, 30):
+        kh, x, _, kt = split.lsq_split_reduced(K, C, lc, tc)
+        want = np.max(np.abs((P @ x0)[: lc + 1])) / np.max(np.abs(K))
+        assert split.compensation(K, kh, kt) == pytest.approx(want, rel=1e-8)
+    # an all-harmonic split has nothing to cancel
+    kh, _, _, kt = split.lsq_split_reduced(K, C, lmax, tc)
+    assert split.compensation(K, kh, kt) == 0.0
+
+
+def test_cost_fit_minimises_relative_residuals():
+    # the fit minimises sum (model_k / t_k - 1)^2: at its answer the objective's gradient vanishes and
+    # every small step in (a, b) or c raises it
+    g = np.random.default_rng(4)
+    pairs = np.array([1e6, 3e7, 1e9, 2e10, 5e11])
+    t_real = (4e-5 + 2e-14 * pairs) * (1 + 0.2 * g.standard_normal(5))
+    work = np.array([1e8, 1e9, 3e10, 7e10])
+    t_sht = 1e-12 * work * (1 + 0.2 * g.standard_normal(4))
+    a, b, c = split.cost_fit(pairs, t_real, work, t_sht)
+
+    def f_real(a_, b_):
+        return np.sum(((a_ + b_ * pairs) / t_real - 1.0) ** 2)
+
+    def f_sht(c_):
+        return np.sum((c_ * work / t_sht - 1.0) ** 2)
+
+    ga = np.sum(2 * ((a + b * pairs) / t_real - 1.0) / t_real)
+    gb = np.sum(2 * ((a + b * pairs) / t_real - 1.0) * pairs / t_real)
+    assert abs(ga) * abs(a) <= 1e-9 and abs(gb) * abs(b) <= 1e-9
+    for da, db in [(1e-3, 0), (-1e-3, 0), (0, 1e-3), (0, -1e-3)]:
+        assert f_real(a * (1 + da), b * (1 + db)) > f_real(a, b)
+    assert f_sht(c * 1.001) > f_sht(c) and f_sht(c * 0.999) > f_sht(c)

@@ -185,3 +185,38 @@ def test_search_equals_exhaustive_scan(fwhm, bound):
         got = ctx.search(K, nside, bound, grid, m)
     assert best is not None and got is not None
     assert (got[0], got[1]) == best[:2] and got[2] == pytest.approx(best[2], rel=1e-15)
+
+
+def test_compensation_matches_oracle():
+    lmax = 256
+    K = _paper_kernel(lmax, 40.0)
+    C = np.ones(lmax + 1)
+    sig = 40.0 * ARCMIN / math.sqrt(8 * math.log(2))
+    with split.Context(lmax, 0.3) as ctx:
+        for lc, tc in [(255, 2 * sig), (60, 0.2), (120, 0.1), (200, 0.05)]:
+            kh, _, _, kt = osplit.lsq_split_reduced(K, C, lc, tc)
+            assert ctx.compensation(K, lc, tc) == pytest.approx(osplit.compensation(K, kh, kt), rel=1e-7, abs=1e-14)
+
+
+def test_search_with_compensation_limit_matches_oracle():
+    # with a cheap harmonic part the unconstrained scan takes l_cut just below lmax at a cut holding
+    # two real-space samples, whose harmonic part must cancel far more than the kernel's own scale;
+    # with the limit that cut keeps only the all-harmonic split, in the library as in the oracle
+    lmax, nside, fwhm, bound = 512, 256, 25.0, 1e-4
+    K = _paper_kernel(lmax, fwhm)
+    C = np.ones(lmax + 1)
+    sig = fwhm * ARCMIN / math.sqrt(8 * math.log(2))
+    grid = [k * sig for k in (2.0, 3.0, 3.5, 5.0, 8.0)]
+    m = split.CostModel(1e-4, 1e-13, 3e-12)
+    t_gpu = lambda tc: m.a + m.b * osplit.pairs_estimate(nside, tc)   # noqa: E731
+    t_cpu = lambda lc: m.c * lc * lc * lmax                             # noqa: E731
+    with split.Context(lmax, max(grid)) as free, split.Context(lmax, max(grid), max_comp=1e-2) as guarded:
+        r_free = free.search(K, nside, bound, grid, m)
+        r_guard = guarded.search(K, nside, bound, grid, m)
+        assert r_free[1] < lmax and free.compensation(K, r_free[1], r_free[0]) > 1e-2
+    want_free = osplit.split_search(K, C, bound, grid, t_gpu, t_cpu, solver=osplit.lsq_split_reduced)
+    want_guard = osplit.split_search(K, C, bound, grid, t_gpu, t_cpu, solver=osplit.lsq_split_reduced,
+                                     max_comp=1e-2)
+    assert r_free[:2] == want_free[:2]
+    assert r_guard[:2] == want_guard[:2]
+    assert r_guard[:2] != r_free[:2]
