@@ -61,8 +61,9 @@ int conv_split_nodes(const conv_split_ctx* ctx, double theta_cut, int* z_cut);
 int conv_split_lsq(conv_split_ctx* ctx, const double* k_ell, int ell_cut, double theta_cut, double* k_hat,
                    double* k_theta, double* k_real, double* k_tilde);
 
-/* Errors of that split: sigma_rms of Eq. 2 and sigma = alpha sigma_rms / sqrt(sum (2l+1) K_l^2 / 4pi)
- * of Eq. 6. Either output may be NULL. */
+/* Errors of that split: sigma_rms of Eq. 2 and sigma = alpha sigma_rms / sqrt(sum (2l+1) C^in_l K_l^2
+ * / 4pi), Eq. 6 with its normalisation weighted like the error (the fractional rms error of the output
+ * map; the printed Eq. 6 for C^in = 1, and independent of the scale of C^in). Either output may be NULL. */
 int conv_split_error(conv_split_ctx* ctx, const double* k_ell, int ell_cut, double theta_cut, double alpha,
                      double* sigma_rms, double* sigma);
 

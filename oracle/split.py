@@ -8,7 +8,7 @@ Test infrastructure (see the package docstring). Follows the paper's Estimating 
 * Eq. 3-5 A^T W A x = A^T W K_l with x = [K^_l (l <= l_cut); K^_theta (z_cut samples)],
           A = [delta_{l,j} for the harmonic columns | P_{l,k} for the real-space columns],
           W = diag((2l + 1) C_l^in), solved by SVD dropping singular values below 1e-6.
-* Eq. 6   sigma^2 = alpha^2 sigma_rms^2 / ((1 / 4 pi) sum (2l + 1) K_l^2).
+* Eq. 6   sigma^2 = alpha^2 sigma_rms^2 / ((1 / 4 pi) sum (2l + 1) C_l^in K_l^2)  (C^in = 1 as printed).
 * Eq. 7-8 cost models (the paper's GTX 480 / one-core fits, seconds, theta_cut in arcmin).
 * Search  linear scan over theta_cut; for each, binary search for the smallest l_cut meeting the
           error bound; keep the cheapest pair, the wall time being that of the slower of the two
@@ -19,7 +19,9 @@ Readings (the paper is silent or garbled on these):
   (lmax + 1)-point rule: P_{l,k} = 2 pi w_k P_l(z_k), for the nodes with z_k > cos(theta_cut)
   (their count is z_cut; the printed definition "lmax - l_cos(theta_cut)" is garbled);
 * A has lmax + 1 rows (l = 0..lmax, as in the sums of Eqs. 2 and 6) and l_cut + 1 harmonic columns;
-* W includes C_l^in (the printed W omits it; identical for the flat C_l^in = 1 the paper uses);
+* W includes C_l^in (the printed W omits it; identical for the flat C_l^in = 1 the paper uses), and so
+  does Eq. 6's normalisation (the output's power), so that sigma stays a fractional error for a Wiener
+  weighting C^in = C^2 / (C + N);
 * the singular-value cutoff is relative to the largest singular value; in the reduced solve (the
   identity block eliminated) it applies to the singular values of the weighted reduced matrix
   W_r^1/2 P_r. Applied to its normal matrix's eigenvalues (the squares) it removes far more and makes
@@ -119,10 +121,21 @@ def rms_error(K_ell, K_tilde, C_in) -> float:
 
 
 def fractional_error(K_ell, K_tilde, C_in, alpha: float = 5.0) -> float:
-    """sigma of Eq. 6."""
+    """sigma of Eq. 6. The normalisation carries the input weights of Eq. 2, (1 / 4 pi) sum (2l + 1)
+    C^in_l K_l^2 (the output map's power), so that sigma is the fractional rms error of the output; for
+    the flat C^in = 1 of the Results section this is the printed Eq. 6."""
     ell = np.arange(len(K_ell))
-    norm = np.sum((2 * ell + 1) * K_ell ** 2) / (4.0 * math.pi)
+    norm = np.sum((2 * ell + 1) * np.asarray(C_in, dtype=np.float64) * K_ell ** 2) / (4.0 * math.pi)
     return alpha * rms_error(K_ell, K_tilde, C_in) / math.sqrt(norm)
+
+
+def wiener_weights(C_ell, N_ell):
+    """Input weights for a Wiener-filter convolution (text after Eq. 2): C^in_l = C_l^2 / (C_l + N_l),
+    signal power C_l, noise power N_l (zero where both vanish)."""
+    C = np.asarray(C_ell, dtype=np.float64)
+    N = np.asarray(N_ell, dtype=np.float64) * np.ones_like(C)
+    den = C + N
+    return np.where(den > 0, C * C / np.where(den > 0, den, 1.0), 0.0)
 
 
 def cost_gpu_paper(theta_cut_arcmin: float) -> float:

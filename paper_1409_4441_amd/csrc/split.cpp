@@ -223,12 +223,14 @@ void solve_reduced(conv_split_ctx* c, const double* K, int ell_cut, int n, std::
   }
 }
 
-// Eq. 2 sigma_rms^2 * 4 pi and the Eq. 6 normalisation * 4 pi for the split with samples x
+// Eq. 2 sigma_rms^2 * 4 pi and the Eq. 6 normalisation * 4 pi for the split with samples x. The
+// normalisation carries the same input weights C^in_l as the error (the output map's power), which is
+// the printed Eq. 6 for the flat C^in = 1.
 void split_sums(const conv_split_ctx* c, const double* K, int ell_cut, int n, const std::vector<double>& x,
                 double* err_sum, double* norm_sum) {
   double es = 0.0, ns = 0.0;
   for (int l = 0; l <= c->lmax; ++l) {
-    ns += (2.0 * l + 1.0) * K[l] * K[l];
+    ns += c->W[l] * K[l] * K[l];
     if (l <= ell_cut) continue;
     const double* p = c->P.data() + static_cast<size_t>(l) * c->nmax;
     double kr = 0.0;

@@ -108,6 +108,16 @@ class CostModel:
         return tr.value, ts.value, wl.value
 
 
+def wiener_weights(signal_cl, noise_cl) -> np.ndarray:
+    """Input weights of Eqs. 2 and 6 for a Wiener-filter convolution (text after Eq. 2):
+    C^in_l = S_l^2 / (S_l + N_l) for signal power S_l and noise power N_l (scalar or per l); 0 where
+    both vanish."""
+    S = np.asarray(signal_cl, dtype=np.float64)
+    N = np.asarray(noise_cl, dtype=np.float64) * np.ones_like(S)
+    den = S + N
+    return np.where(den > 0, S * S / np.where(den > 0, den, 1.0), 0.0)
+
+
 def pairs_estimate(nside: int, theta_cut: float) -> float:
     """Npix^2 (1 - cos theta_cut) / 2."""
     return float(lib.conv_cost_pairs(int(nside), float(theta_cut)))

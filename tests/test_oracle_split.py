@@ -289,3 +289,22 @@ def test_cost_fit_minimises_relative_residuals():
     for da, db in [(1e-3, 0), (-1e-3, 0), (0, 1e-3), (0, -1e-3)]:
         assert f_real(a * (1 + da), b * (1 + db)) > f_real(a, b)
     assert f_sht(c * 1.001) > f_sht(c) and f_sht(c * 0.999) > f_sht(c)
+
+
+def test_wiener_weights_and_error_normalisation():
+    # C^in = S^2 / (S + N): S without noise, S^2 / N where noise dominates, monotone in the noise
+    S = 1.0 / np.arange(2, 200) ** 2
+    assert np.allclose(split.wiener_weights(S, 0.0), S, rtol=1e-15)
+    big = 1e6
+    assert np.allclose(split.wiener_weights(S, big), S * S / big, rtol=1e-4)
+    assert np.all(split.wiener_weights(S, 1e-4) > split.wiener_weights(S, 1e-3))
+    assert split.wiener_weights(np.zeros(3), 0.0).tolist() == [0.0, 0.0, 0.0]
+    # Eq. 6 is a fractional error: the scale of C^in drops out, C^in = 1 gives the printed form
+    lmax = 64
+    K = _beam(lmax, 200.0)
+    Kt = K * (1 + 0.01 * np.sin(np.arange(lmax + 1)))
+    C = 1.0 / (np.arange(lmax + 1) + 1.0)
+    assert split.fractional_error(K, Kt, 1e-9 * C) == pytest.approx(split.fractional_error(K, Kt, C), rel=1e-12)
+    ell = np.arange(lmax + 1)
+    printed = 5.0 * math.sqrt(np.sum((K - Kt) ** 2 * (2 * ell + 1)) / np.sum((2 * ell + 1) * K ** 2))
+    assert split.fractional_error(K, Kt, np.ones(lmax + 1)) == pytest.approx(printed, rel=1e-12)

@@ -220,3 +220,27 @@ def test_search_with_compensation_limit_matches_oracle():
     assert r_free[:2] == want_free[:2]
     assert r_guard[:2] == want_guard[:2]
     assert r_guard[:2] != r_free[:2]
+
+
+def test_wiener_weights_match_oracle_and_relax_the_split():
+    # the library's errors under Wiener weights equal the oracle's; noise dominating above l_n lowers
+    # the error of a split, so the smallest feasible l_cut at a cut does not grow
+    lmax, fwhm, ell_n = 512, 25.0, 300
+    K = _paper_kernel(lmax, fwhm)
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    c = np.zeros(lmax + 1)
+    c[2:] = 1.0 / (ell[2:] * (ell[2:] + 1.0))
+    S = c * _beam(lmax, fwhm) ** 2
+    W = split.wiener_weights(S, S[ell_n])
+    assert np.allclose(W, osplit.wiener_weights(S, S[ell_n]), rtol=1e-15)
+    tc = 20 * fwhm * ARCMIN
+    with split.Context(lmax, tc, c_in=W) as cw, split.Context(lmax, tc) as cf:
+        for lc in (120, 200, 260):
+            kh, _, _, kt = osplit.lsq_split_reduced(K, W, lc, tc)
+            assert cw.error(K, lc, tc, alpha=5.0)[1] == pytest.approx(
+                osplit.fractional_error(K, kt, W, 5.0), rel=1e-7)
+            assert cw.error(K, lc, tc)[1] < cf.error(K, lc, tc)[1]
+        m = split.CostModel(1e-4, 1e-13, 3e-12)
+        rw = cw.search(K, 256, 1e-5, [tc], m)
+        rf = cf.search(K, 256, 1e-5, [tc], m)
+        assert rw is not None and rf is not None and rw[1] <= rf[1]
