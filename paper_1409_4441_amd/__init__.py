@@ -18,7 +18,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libconvreal.so")
+# CONVREAL_LIB selects another build of the same library (e.g. one with host sanitizers)
+LIB_PATH = os.environ.get("CONVREAL_LIB") or os.path.join(_HERE, "libconvreal.so")
 
 F64 = 0
 F32 = 1

@@ -39,26 +39,38 @@ def _run(cmd, verbose):
         print("\n".join(lines))
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    objdir = os.path.join(HERE, "_build")
+# Host-side sanitizers for a checking build (every flag applies to the host pass only; the device
+# code is built as usual): AddressSanitizer and UndefinedBehaviorSanitizer, errors fatal.
+SANITIZE_COMPILE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                    "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+SANITIZE_LINK = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
+
+
+def build(verbose: bool = False, jobs: int = 8, sanitize: bool = False, out_dir: str | None = None) -> str:
+    """Compile every source and link libconvreal.so (in the package, or in out_dir). sanitize: the
+    host code with ASan + UBSan (-O1 -g), for checking runs that preload the sanitizer runtime."""
+    objdir = os.path.join(out_dir or HERE, "_build_san" if sanitize else "_build")
     os.makedirs(objdir, exist_ok=True)
+    flags = HIP_FLAGS + (["-O1", "-g"] + SANITIZE_COMPILE if sanitize else [])
     objs = []
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC] + HIP_FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + flags + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(shlex.quote(c) for c in cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         if len(procs) >= jobs:
             _drain(procs)
     _drain(procs)
-    tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    lib = os.path.join(out_dir, "libconvreal.so") if out_dir else LIB
+    tmp = lib + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + (SANITIZE_LINK if sanitize else []) +
+         ["-o", tmp] + objs, verbose)
+    os.replace(tmp, lib)
+    return lib
 
 
 def _drain(procs):
