@@ -15,6 +15,8 @@ inputs already in HBM. Prints ONE JSON line:
                  same workload (the NumPy oracle on one core beside it); the same sums check the
                  timed path's accuracy, and the batched workload's maps are checked at their own
                  sampled pixels
+  split_convolution  the whole split convolution (real-space half + harmonic half on two streams)
+                 against the full-kernel harmonic convolution, both with this library's kernels
 """
 from __future__ import annotations
 
@@ -48,13 +50,14 @@ def parse():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "f32", "f64"])
     ap.add_argument("--plain-steps", type=int, default=3, help="timed applies of the plain kernel")
     ap.add_argument("--profile-steps", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=100000,
+    ap.add_argument("--cpu-sample", type=int, default=5000000,
                     help="output pixels the C oracle sums (timed baseline and accuracy check)")
     ap.add_argument("--cpu-sample-numpy", type=int, default=400, help="of those, pixels the NumPy oracle sums")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-ringfft", action="store_true", help="skip the FP64 ring-FFT measurement")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-map batched measurement")
+    ap.add_argument("--no-split", action="store_true", help="skip the whole split convolution (hybrid) leg")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--weight-store", default="auto", choices=["auto", "on", "off"],
                     help="cap weight store of the mixed plan (auto: the library's default)")
@@ -228,6 +231,53 @@ def batched(steps, stream):
     for p in plans:
         p.close()
     return out, host
+
+
+def split_convolution(w, plan, x, stream, reps: int = 3):
+    """The whole split convolution of the workload (Eq. 1, Fig. 1): the real-space half (the timed
+    plan, the beam's residual B_l (1 - g_l) truncated at theta_cut) plus the harmonic half (B_l g_l,
+    band limit l_cut + w/2) on a second stream, against the full-kernel harmonic convolution with B_l
+    at lmax. Times from HIP events; the accuracy is the whole-map relative rms difference of the two
+    (what the split and its truncation at theta_cut cost)."""
+    import torch
+
+    import synth
+    from paper_1409_4441_amd import sht
+    beam = synth.gaussian_beam(w.lmax, w.fwhm)
+    L_h = int(math.ceil(w.ell_cut + 0.5 * w.taper_width))
+    k_hat = (beam - w.k_ell())[: L_h + 1].copy()
+    side = torch.cuda.Stream()
+    out = {"harmonic_band_limit": L_h, "lmax": w.lmax}
+    with sht.Sht(w.nside, L_h) as T, sht.Sht(w.nside, w.lmax) as F:
+        kh = torch.from_numpy(k_hat).to(x.device)
+        kb = torch.from_numpy(beam).to(x.device)
+        y = sht.hybrid_apply(plan, T, kh, x, stream=stream, stream_sht=side)
+        yf = F.convolve(x[0], kb, stream=stream)
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        e[0].record(stream)
+        for _ in range(reps):
+            sht.hybrid_apply(plan, T, kh, x, out=y, stream=stream, stream_sht=side)
+        e[1].record(stream)
+        for _ in range(reps):
+            plan.apply(x, out=y, stream=stream)
+        e[2].record(stream)
+        for _ in range(reps):
+            T.convolve(x[0], kh, out=yf, stream=stream)
+        e[3].record(stream)
+        for _ in range(reps):
+            F.convolve(x[0], kb, out=yf, stream=stream)
+        e[4].record(stream)
+        torch.cuda.synchronize()
+        sht.hybrid_apply(plan, T, kh, x, out=y, stream=stream, stream_sht=side)
+        torch.cuda.synchronize()
+        diff = torch.sqrt(torch.sum((y[0].double() - yf.double()) ** 2) / torch.sum(yf.double() ** 2)).item()
+        t = [e[k].elapsed_time(e[k + 1]) / reps for k in range(4)]
+    out.update({"hybrid_two_streams_ms": t[0], "real_space_ms": t[1], "harmonic_half_ms": t[2],
+                "full_harmonic_ms": t[3], "speedup_vs_full_harmonic": t[3] / t[0],
+                "rel_rms_vs_full_harmonic": diff,
+                "note": "harmonic half and full convolution: this library's FP64 GPU transforms"})
+    return out
 
 
 def paper_context(theta_cut, pairs_per_map, maps_per_s):
@@ -431,6 +481,10 @@ def main():
         torch.cuda.synchronize()
         del yc
 
+    split_conv = None
+    if not args.no_split and w.ell_cut > 0 and args.precision != "f64" and nmaps == 1:
+        split_conv = split_convolution(w, plan, x, stream)
+
     bat, bat_host = None, None
     if not args.no_batched and args.precision == "mixed":
         bat, bat_host = batched(args.batched_steps, stream)
@@ -464,6 +518,7 @@ def main():
         "ring_fft_fp64": ring_fft,
         "weight_store": store,
         "batched": bat,
+        "split_convolution": split_conv,
         "roofline": roofline, "cpu_baseline": cpu,
         "paper_context": paper_context(w.theta_cut, pairs_per_map, maps_per_s) if w.nside == 2048 else None,
     }

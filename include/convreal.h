@@ -174,7 +174,10 @@ int conv_real_profile(conv_real_plan* plan, const void* maps_in, void* maps_out,
  *              two of cap items (each by decreasing cost), the first workgroup of every compute
  *              unit starting on the belt queue and the other two on the cap queues (belt items
  *              use the matrix cores and LDS, cap items the vector memory path, so each CU runs
- *              both), every workgroup taking from the other queues once its own is empty
+ *              both), every workgroup taking from the other queues once its own is empty;
+ *              4: roles as in 3, with the cap items split into one queue of neighbouring rings per
+ *              XCD (each XCD's cap workgroups start on rings whose input rings overlap, so that their
+ *              re-reads share that XCD's L2)
  */
 typedef struct conv_real_tuning {
   int seg;

@@ -47,7 +47,7 @@ EXPORTS = ("conv_real_tabulate", "conv_real_init", "conv_real_apply", "conv_real
 
 
 class Tuning(ctypes.Structure):
-    """conv_real_tuning: seg (256|512), wg_per_cu (1..4), order (0..3)."""
+    """conv_real_tuning: seg (256|512), wg_per_cu (1..4), order (0..4)."""
     _fields_ = [("seg", ctypes.c_int), ("wg_per_cu", ctypes.c_int), ("order", ctypes.c_int)]
 
     def as_dict(self):

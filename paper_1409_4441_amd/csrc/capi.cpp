@@ -183,14 +183,14 @@ void plan_items(const conv_real_plan* p, const convreal::Tuning& t, std::vector<
 // decreasing cost (0) or belt and cap items alternating, each by decreasing cost (1). Order 2: one
 // chunk per XCD, each holding a contiguous, cost-balanced range of the belt items and one of the cap
 // items in the order given (neighbouring bands and rings, whose input rings overlap, share an L2),
-// alternating as in order 1.
+// alternating as in order 1. Orders 3 and 4: roles (see below).
 template <typename E, typename Cost, typename Kind>
 std::vector<int> order_queue(const std::vector<E>& belt_in, const std::vector<E>& cap_in, int order, Cost cost,
                              Kind kind, std::vector<E>& out) {
   auto desc = [&](const E& a, const E& b) { return cost(a) > cost(b); };
   out.clear();
   if (order == 2) {
-    const int nc = convreal::kMaxChunks;
+    const int nc = convreal::kXcds;
     std::vector<std::vector<E>> ch(nc);
     for (const std::vector<E>* v : {&belt_in, &cap_in}) {
       double total = 0.0, acc = 0.0;
@@ -220,6 +220,27 @@ std::vector<int> order_queue(const std::vector<E>& belt_in, const std::vector<E>
   }
   std::vector<E> belt = belt_in, cap = cap_in;
   std::stable_sort(belt.begin(), belt.end(), desc);
+  if (order == 4) {
+    // roles as in order 3 for the belt (chunk 0), the cap items in ring order split into one
+    // cost-balanced run of neighbouring rings per XCD (chunks 1..8): the cap workgroups of an XCD
+    // start on rings whose input rings overlap, so their re-reads stay in that XCD's L2
+    const int nc = convreal::kXcds;
+    double total = 0.0, acc = 0.0;
+    for (const E& e : cap) total += cost(e);
+    std::vector<std::vector<E>> ch(nc);
+    for (const E& e : cap) {
+      const int c = total > 0.0 ? std::min(nc - 1, static_cast<int>(acc / total * nc)) : 0;
+      ch[c].push_back(e);
+      acc += cost(e);
+    }
+    out = belt;
+    std::vector<int> off{0, static_cast<int>(out.size())};
+    for (const std::vector<E>& c : ch) {
+      out.insert(out.end(), c.begin(), c.end());
+      off.push_back(static_cast<int>(out.size()));
+    }
+    return off;
+  }
   std::stable_sort(cap.begin(), cap.end(), desc);
   if (order == 3) {
     // roles: chunk 0 holds the belt items by decreasing cost, chunks 1 and 2 the cap items dealt
@@ -1188,7 +1209,7 @@ constexpr int kBatchMagic = 0x43564231;  // "CVB1"
 
 bool tuning_ok(const conv_real_tuning* t) {
   return t && (t->seg == 256 || t->seg == 512) && t->wg_per_cu >= 1 && t->wg_per_cu <= 4 &&
-         (t->order >= 0 && t->order <= 3);
+         (t->order >= 0 && t->order <= 4);
 }
 
 convreal::Tuning to_internal(const conv_real_tuning* t) {
@@ -1209,7 +1230,7 @@ std::vector<conv_real_tuning> candidate_tunings() {
   std::vector<conv_real_tuning> c;
   for (int seg : {256, 512})
     for (int wg : {1, 2, 3})
-      for (int order : {0, 1, 2, 3}) c.push_back({seg, wg, order});
+      for (int order : {0, 1, 2, 3, 4}) c.push_back({seg, wg, order});
   return c;
 }
 

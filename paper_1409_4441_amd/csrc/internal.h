@@ -68,7 +68,8 @@ RingGrid make_ring_grid(int nside);
 void neighbour_rings(const RingGrid& g, double dcut2, std::vector<int>& jlo, std::vector<int>& jhi);
 
 constexpr int kMaxSlots = 64;  // maps per persistent mixed-path launch
-constexpr int kMaxChunks = 8;  // work-queue chunks (one per XCD)
+constexpr int kXcds = 8;        // accelerator complex dies of the MI355X, each with its own L2
+constexpr int kMaxChunks = 16; // work-queue chunks
 // K-chunks (32 window offsets) of one belt weight block: the LDS stage holds one block's window;
 // wider windows of one input ring are split into several blocks
 constexpr int kBeltBlockChunks = 4;
@@ -161,7 +162,9 @@ struct Tuning {
   int seg = 256;       // belt output pixels per work item: 256 or 512
   int wg_per_cu = 2;   // resident workgroups per compute unit
   int order = 0;       // 0: all items by decreasing cost; 1: belt and cap items alternating;
-                       // 2: one chunk per XCD of neighbouring rings, each by decreasing cost
+                       // 2: one chunk per XCD of neighbouring rings, each by decreasing cost;
+                       // 3: roles (a belt chunk, two cap chunks); 4: roles with the cap items in one
+                       // chunk of neighbouring rings per XCD
 };
 
 // Events recorded between kernels by conv_real_profile.

@@ -1088,7 +1088,7 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
 // items and no coefficient table), at the price of a few spilled registers
 // The queue is split into n_chunks chunks of items (chunk c: items chunk_off[c] .. chunk_off[c+1]
 // - 1, each for nrep maps), one counter each. A workgroup takes items from its home chunk
-// (blockIdx.x / home_div) % n_chunks first and then from the others, until every chunk is empty.
+// (see home below) first and then from the others, until every chunk is empty.
 // home_div = 1 with one chunk per XCD: workgroups are spread over the XCDs in turn, so the items of
 // a chunk share one L2. home_div = number of CUs with a belt chunk and two cap chunks: the first
 // workgroups fill one slot on every CU, so each CU starts with one workgroup on belt items (matrix
@@ -1108,7 +1108,13 @@ __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convrea
   _Float16* stage = reinterpret_cast<_Float16*>(lds);
   float4* s_coef = reinterpret_cast<float4*>(lds + coef_offset_bytes);
   if (threadIdx.x == 0) s_coef_owner = nullptr;
-  const int home = static_cast<int>((blockIdx.x / static_cast<unsigned>(home_div)) % static_cast<unsigned>(n_chunks));
+  // home_div > 0: chunk (block / home_div) mod n_chunks; home_div < 0 (roles with per-XCD cap
+  // chunks): the first -home_div workgroups take chunk 0, the others chunk 1 + their XCD
+  const int home =
+      home_div > 0 ? static_cast<int>((blockIdx.x / static_cast<unsigned>(home_div)) % static_cast<unsigned>(n_chunks))
+      : (static_cast<int>(blockIdx.x) < -home_div || n_chunks < 2)
+          ? 0
+          : 1 + static_cast<int>(blockIdx.x % static_cast<unsigned>(convreal::kXcds)) % (n_chunks - 1);
   unsigned empty = 0u;   // chunks this workgroup found empty (thread 0)
   for (;;) {
     if (threadIdx.x == 0) {
@@ -1233,7 +1239,7 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
     const dim3 g(static_cast<unsigned>(grid)), blk(kBlock);
     // the role order hands out home chunks by workgroup slot on a CU (the first ncu workgroups fill
     // one slot on every CU), the others by workgroup (workgroups go round the XCDs in turn)
-    const int home_div = tune.order == 3 ? ncu : 1;
+    const int home_div = tune.order == 3 ? ncu : (tune.order == 4 ? -ncu : 1);
     const int co = static_cast<int>(coef_off);
     if (tune.seg == 512 && fly)
       hipLaunchKernelGGL((mixed_persistent_kernel<512, true, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);

@@ -44,13 +44,13 @@ def test_tunings_bitwise_identical(cuda_device):
     ref = plan.apply(x).clone()
     for seg in (256, 512):
         for wg in (1, 2, 3, 4):
-            for order in (0, 1, 2, 3):
+            for order in (0, 1, 2, 3, 4):
                 plan.set_tuning(seg, wg, order)
                 assert plan.get_tuning() == {"seg": seg, "wg_per_cu": wg, "order": order}
                 y = plan.apply(x)
                 torch.cuda.synchronize()
                 assert torch.equal(y, ref), (seg, wg, order)
-    for bad in ((300, 2, 0), (256, 0, 0), (256, 5, 0), (256, 2, 4), (256, 2, -1)):
+    for bad in ((300, 2, 0), (256, 0, 0), (256, 5, 0), (256, 2, 5), (256, 2, -1)):
         with pytest.raises(cr.ConvRealError):
             plan.set_tuning(*bad)
     plan.close()
@@ -62,7 +62,7 @@ def test_autotune_and_cache(cuda_device, tmp_path):
     ref = plan.apply(x).clone()
     cache = str(tmp_path / "tune.json")
     best = plan.autotune(x, cache=cache)
-    assert best["seg"] in (256, 512) and 1 <= best["wg_per_cu"] <= 4 and best["order"] in (0, 1, 2, 3)
+    assert best["seg"] in (256, 512) and 1 <= best["wg_per_cu"] <= 4 and best["order"] in (0, 1, 2, 3, 4)
     assert plan.get_tuning() == best
     torch.cuda.synchronize()
     assert torch.equal(plan.apply(x), ref)
