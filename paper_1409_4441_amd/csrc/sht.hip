@@ -14,7 +14,9 @@
 // every lane reads the same folded value (an LDS broadcast). Synthesis runs the same fold backwards:
 // B[j] = sum_{m = j mod n} w_m F_m e^{i m pi c / n}, and for each a' the four residue classes of j are
 // Horner sums in e^{2 pi i a' / k}, combined with i^{(j mod 4) q} into the four pixels q k + a'.
-// Only the frequencies below min(n, L + 1) are formed.
+// Only the frequencies below min(n, L + 1) are formed. On a grid whose Nside is a power of two the
+// belt rings (n = 4 Nside, a power of two) take a radix-2 FFT in LDS instead (n log n work against
+// n min(n, L + 1) / 4), the polar-cap rings (n = 4k) the folded sums.
 //
 // Legendre sums. lambda_lm by the recurrence in l at fixed m,
 //   lambda_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)) sin^m theta,
@@ -39,6 +41,7 @@
 
 #include "../../include/convsht.h"
 #include "common.h"
+#include "fft.h"
 #include "internal.h"
 
 namespace {
@@ -46,6 +49,7 @@ namespace {
 constexpr int kLegThreads = 512;   // Legendre kernels: 8 waves
 constexpr int kFlush = 8;          // l values between reductions (analysis) and rescale checks
 constexpr int kDftThreads = 256;   // ring sum kernels: 4 waves, one per residue class mod 4
+constexpr int kFftThreads = 512;   // belt ring FFT kernels
 constexpr double kInvScale = 0x1p-600;
 constexpr double kRescaleAbove = 0x1p400;
 constexpr double kLogScale = 600.0 * 0.69314718055994530942;
@@ -87,12 +91,14 @@ __device__ __forceinline__ long long alm_base(int L, int m) {
 }
 
 // ---------------------------------------------------------------------------- ring sums (analysis)
+// rings [skip0, skip0 + nskip) are left to the FFT kernels
 template <typename T>
 __global__ __launch_bounds__(kDftThreads) void sht_ring_dft_kernel(const T* __restrict__ x,
                                                                    const ShtRing* __restrict__ rings,
-                                                                   int nrings, int L, double2* __restrict__ G) {
+                                                                   int nrings, int L, double2* __restrict__ G,
+                                                                   int skip0, int nskip) {
   extern __shared__ double s_fold[];   // s0[k], s2[k], then (d, e) pairs [k]
-  const int r = blockIdx.x;
+  const int r = static_cast<int>(blockIdx.x) < skip0 ? static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x) + nskip;
   const ShtRing R = convreal::ldu_record(rings[r]);
   const int n = R.n, k = n >> 2;
   double* s0 = s_fold;
@@ -146,9 +152,10 @@ __global__ __launch_bounds__(kDftThreads) void sht_ring_dft_kernel(const T* __re
 template <typename T, bool ACC>
 __global__ __launch_bounds__(kDftThreads) void sht_ring_idft_kernel(const double2* __restrict__ F,
                                                                     const ShtRing* __restrict__ rings,
-                                                                    int nrings, int L, T* __restrict__ y) {
+                                                                    int nrings, int L, T* __restrict__ y,
+                                                                    int skip0, int nskip) {
   extern __shared__ double2 s_b[];     // residue class c at s_b[c * nq + j / 4]
-  const int r = blockIdx.x;
+  const int r = static_cast<int>(blockIdx.x) < skip0 ? static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x) + nskip;
   const ShtRing R = convreal::ldu_record(rings[r]);
   const int n = R.n, k = n >> 2;
   const int nk = n < L + 1 ? n : L + 1;
@@ -206,6 +213,69 @@ __global__ __launch_bounds__(kDftThreads) void sht_ring_idft_kernel(const double
       else
         *dst = static_cast<T>(v);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------- ring FFTs (belt rings)
+// Rings ring0 .. ring0 + gridDim.x - 1, each of n = 2^logn pixels, one workgroup each (n x 16 bytes
+// of LDS). Analysis: X = FFT(x) (the ring in the real part), G_m = e^{-i m pi c / n} X[m mod n].
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void sht_belt_fft_kernel(const T* __restrict__ x,
+                                                                   const ShtRing* __restrict__ rings, int nrings,
+                                                                   int ring0, int L, int logn,
+                                                                   const double2* __restrict__ tw,
+                                                                   double2* __restrict__ G) {
+  extern __shared__ double2 s_fft[];
+  const int r = ring0 + static_cast<int>(blockIdx.x);
+  const ShtRing R = convreal::ldu_record(rings[r]);
+  const int n = R.n;
+  const T* xr = x + R.start;
+  for (int a = threadIdx.x; a < n; a += blockDim.x)
+    s_fft[convreal::bitrev(a, logn)] = double2{static_cast<double>(xr[a]), 0.0};
+  __syncthreads();
+  convreal::fft_stages(s_fft, n, tw);
+  for (int m = threadIdx.x; m <= L; m += blockDim.x) {
+    const double2 X = s_fft[m & (n - 1)];
+    const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
+    double ps, pc;
+    sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+    G[static_cast<size_t>(m) * nrings + r] = double2{X.x * pc - X.y * ps, X.x * ps + X.y * pc};
+  }
+}
+
+// Synthesis: B[j] = sum_{m = j mod n} w_m F_m e^{i m pi c / n}, y_a = Re sum_j B[j] e^{2 pi i j a / n}
+// = Re FFT(conj B)[a].
+template <typename T, bool ACC>
+__global__ __launch_bounds__(kFftThreads) void sht_belt_ifft_kernel(const double2* __restrict__ F,
+                                                                    const ShtRing* __restrict__ rings, int nrings,
+                                                                    int ring0, int L, int logn,
+                                                                    const double2* __restrict__ tw,
+                                                                    T* __restrict__ y) {
+  extern __shared__ double2 s_fft[];
+  const int r = ring0 + static_cast<int>(blockIdx.x);
+  const ShtRing R = convreal::ldu_record(rings[r]);
+  const int n = R.n;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double br = 0.0, bi = 0.0;
+    for (int m = j; m <= L; m += n) {
+      const double2 f = F[static_cast<size_t>(m) * nrings + r];
+      const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
+      double ps, pc;
+      sincospi(static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+      const double w = m == 0 ? 1.0 : 2.0;
+      br += w * (f.x * pc - f.y * ps);
+      bi += w * (f.x * ps + f.y * pc);
+    }
+    s_fft[convreal::bitrev(j, logn)] = double2{br, -bi};
+  }
+  __syncthreads();
+  convreal::fft_stages(s_fft, n, tw);
+  T* yr = y + R.start;
+  for (int a = threadIdx.x; a < n; a += blockDim.x) {
+    if (ACC)
+      yr[a] = static_cast<T>(static_cast<double>(yr[a]) + s_fft[a].x);
+    else
+      yr[a] = static_cast<T>(s_fft[a].x);
   }
 }
 
@@ -450,6 +520,10 @@ struct conv_sht_plan {
   double2* d_G = nullptr;
   double2* d_alm = nullptr;       // workspace of conv_sht_convolve and the hybrid apply
   double2* d_partial = nullptr;   // nblk > 1: per-block partial sums of the analysis
+  int fft_ring0 = 0;              // belt rings ring0 .. ring0 + fft_nrings - 1 by FFT (power-of-two Nside)
+  int fft_nrings = 0;
+  int fft_logn = 0;
+  double2* d_tw = nullptr;        // n / 2 twiddles exp(-2 pi i m / n), n = 4 Nside
   hipEvent_t ev_in = nullptr, ev_real = nullptr, ev_done = nullptr;
   std::vector<void*> owned;
 };
@@ -507,6 +581,17 @@ hipError_t set_lds_attributes(int nside, int L) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, std::max(s, 65536));
     if (e != hipSuccess) return e;
   }
+  const int nf = std::max(static_cast<int>(16 * 4 * static_cast<size_t>(nside)), 65536);
+  const void* ff[] = {reinterpret_cast<const void*>(&sht_belt_fft_kernel<double>),
+                      reinterpret_cast<const void*>(&sht_belt_fft_kernel<float>),
+                      reinterpret_cast<const void*>(&sht_belt_ifft_kernel<double, false>),
+                      reinterpret_cast<const void*>(&sht_belt_ifft_kernel<double, true>),
+                      reinterpret_cast<const void*>(&sht_belt_ifft_kernel<float, false>),
+                      reinterpret_cast<const void*>(&sht_belt_ifft_kernel<float, true>)};
+  for (const void* f : ff) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, nf);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
@@ -541,32 +626,64 @@ hipError_t launch_synthesis_legendre(const conv_sht_plan* p, const double2* alm,
 
 hipError_t launch_analysis(const conv_sht_plan* p, const void* map, int dtype, double2* alm, hipStream_t st) {
   const size_t lds = dft_lds(p->nside);
+  const unsigned nh = static_cast<unsigned>(p->nrings - p->fft_nrings);
   if (dtype == CONV_SHT_F64)
-    hipLaunchKernelGGL(sht_ring_dft_kernel<double>, dim3(p->nrings), dim3(kDftThreads), lds, st,
-                       static_cast<const double*>(map), p->d_rings, p->nrings, p->L, p->d_G);
+    hipLaunchKernelGGL(sht_ring_dft_kernel<double>, dim3(nh), dim3(kDftThreads), lds, st,
+                       static_cast<const double*>(map), p->d_rings, p->nrings, p->L, p->d_G, p->fft_ring0,
+                       p->fft_nrings);
   else
-    hipLaunchKernelGGL(sht_ring_dft_kernel<float>, dim3(p->nrings), dim3(kDftThreads), lds, st,
-                       static_cast<const float*>(map), p->d_rings, p->nrings, p->L, p->d_G);
+    hipLaunchKernelGGL(sht_ring_dft_kernel<float>, dim3(nh), dim3(kDftThreads), lds, st,
+                       static_cast<const float*>(map), p->d_rings, p->nrings, p->L, p->d_G, p->fft_ring0,
+                       p->fft_nrings);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (p->fft_nrings > 0) {
+    const size_t lf = sizeof(double2) * (static_cast<size_t>(1) << p->fft_logn);
+    const dim3 g(static_cast<unsigned>(p->fft_nrings)), b(kFftThreads);
+    if (dtype == CONV_SHT_F64)
+      hipLaunchKernelGGL(sht_belt_fft_kernel<double>, g, b, lf, st, static_cast<const double*>(map), p->d_rings,
+                         p->nrings, p->fft_ring0, p->L, p->fft_logn, p->d_tw, p->d_G);
+    else
+      hipLaunchKernelGGL(sht_belt_fft_kernel<float>, g, b, lf, st, static_cast<const float*>(map), p->d_rings,
+                         p->nrings, p->fft_ring0, p->L, p->fft_logn, p->d_tw, p->d_G);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   return launch_analysis_legendre(p, alm, st);
 }
 
 hipError_t launch_ring_synthesis(const conv_sht_plan* p, void* map, int dtype, int accumulate, hipStream_t st) {
   const size_t lds = idft_lds(p->nside, p->L);
-  const dim3 g(p->nrings), b(kDftThreads);
+  const dim3 g(static_cast<unsigned>(p->nrings - p->fft_nrings)), b(kDftThreads);
+  const int s0 = p->fft_ring0, ns = p->fft_nrings;
   if (dtype == CONV_SHT_F64) {
     double* y = static_cast<double*>(map);
     if (accumulate)
-      hipLaunchKernelGGL((sht_ring_idft_kernel<double, true>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y);
+      hipLaunchKernelGGL((sht_ring_idft_kernel<double, true>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y, s0, ns);
     else
-      hipLaunchKernelGGL((sht_ring_idft_kernel<double, false>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y);
+      hipLaunchKernelGGL((sht_ring_idft_kernel<double, false>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y, s0, ns);
   } else {
     float* y = static_cast<float*>(map);
     if (accumulate)
-      hipLaunchKernelGGL((sht_ring_idft_kernel<float, true>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y);
+      hipLaunchKernelGGL((sht_ring_idft_kernel<float, true>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y, s0, ns);
     else
-      hipLaunchKernelGGL((sht_ring_idft_kernel<float, false>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y);
+      hipLaunchKernelGGL((sht_ring_idft_kernel<float, false>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y, s0, ns);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ns == 0) return e;
+  const size_t lf = sizeof(double2) * (static_cast<size_t>(1) << p->fft_logn);
+  const dim3 gf(static_cast<unsigned>(ns)), bf(kFftThreads);
+  if (dtype == CONV_SHT_F64) {
+    double* y = static_cast<double*>(map);
+    if (accumulate)
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, p->d_tw, y);
+    else
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, p->d_tw, y);
+  } else {
+    float* y = static_cast<float*>(map);
+    if (accumulate)
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, p->d_tw, y);
+    else
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, p->d_tw, y);
   }
   return hipGetLastError();
 }
@@ -641,9 +758,25 @@ int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
                                    std::sqrt((dl1 * dl1 - mm) / (4.0 * dl1 * dl1 - 1.0))};
     }
   }
+  // belt rings (i = N..3N, n = 4N) by FFT when 4N is a power of two (and at least 16)
+  std::vector<double2> tw;
+  if ((nside & (nside - 1)) == 0 && nside >= 4) {
+    const int n = 4 * nside;
+    p->fft_ring0 = nside - 1;
+    p->fft_nrings = 2 * nside + 1;
+    while ((1 << p->fft_logn) < n) ++p->fft_logn;
+    tw.resize(n / 2);
+    for (int m = 0; m < n / 2; ++m) {
+      const double ang = 2.0 * M_PI * static_cast<double>(m) / static_cast<double>(n);
+      tw[m] = double2{std::cos(ang), -std::sin(ang)};
+    }
+  }
   DeviceGuard guard;
   hipError_t e = guard.enter(dev);
   if (e == hipSuccess) e = set_lds_attributes(nside, lmax);
+  if (e == hipSuccess && !tw.empty()) e = sht_alloc(p, &p->d_tw, tw.size());
+  if (e == hipSuccess && !tw.empty())
+    e = hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = sht_alloc(p, &p->d_rings, rings.size());
   if (e == hipSuccess) e = hipMemcpy(p->d_rings, rings.data(), rings.size() * sizeof(ShtRing), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = sht_alloc(p, &p->d_coef, coef.size());

@@ -40,8 +40,9 @@ def _close(got, ref, rtol):
 
 
 # (nside, L): L above 4 nside folds frequencies of the small polar rings (m >= n); L = 3 nside - 1
-# is the usual band limit
-CASES = [(1, 6), (2, 17), (4, 11), (8, 23), (16, 40), (32, 95)]
+# is the usual band limit; power-of-two grids from Nside 4 take the belt rings through FFTs, Nside 12
+# and the smallest grids through the folded sums
+CASES = [(1, 6), (2, 17), (4, 11), (8, 23), (12, 40), (16, 40), (32, 95)]
 
 
 @pytest.mark.parametrize("nside,L", CASES)
