@@ -102,10 +102,17 @@ int conv_split_compensation(conv_split_ctx* ctx, const double* k_ell, int ell_cu
 /* Largest compensation the search accepts (max_comp >= 0; 0, the default, accepts any). */
 int conv_split_set_max_compensation(conv_split_ctx* ctx, double max_comp);
 
+/* Largest l_cut / lmax the search accepts for a split with a real-space part (0 < frac <= 1; 1, the
+ * default, accepts any): a real-space part that carries only multipoles near the grid's resolution
+ * meets the error model on paper but not on the pixel grid (measured errors 7-100x the Eq. 6 estimate
+ * above l_cut = 0.5 lmax, at most 4.6x below 0.45 lmax). */
+int conv_split_set_max_ell_fraction(conv_split_ctx* ctx, double frac);
+
 /* The split search (the paper's scan): for each theta in theta_grid (n_theta values in
  * (0, theta_max]), the smallest ell_cut in {0, s, 2s, ..., lmax} (s = ell_step >= 1) whose Eq. 6
- * error is <= bound, found by bisection (the error falls as ell_cut grows); if its compensation
- * exceeds the context's limit, that theta keeps only ell_cut = lmax (all harmonic, error 0); among
+ * error is <= bound, found by bisection (the error falls as ell_cut grows); if it exceeds the
+ * context's l_cut limit or its compensation exceeds the context's compensation limit, that theta keeps
+ * only ell_cut = lmax (all harmonic, error 0); among
  * these, the pair of least modelled wall time (ties: the smaller theta). Returns CONV_REAL_OK with
  * the pair, or CONV_SPLIT_INFEASIBLE (outputs untouched). Outputs may be NULL. */
 int conv_split_search(conv_split_ctx* ctx, const double* k_ell, int nside, double bound, double alpha,

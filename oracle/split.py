@@ -185,10 +185,11 @@ def compensation(K_ell, K_hat, K_tilde) -> float:
 
 
 def split_search(K_ell, C_in, bound: float, theta_grid, t_gpu, t_cpu, alpha: float = 5.0,
-                 sv_cut: float = 1e-6, solver=None, max_comp: float = 0.0):
+                 sv_cut: float = 1e-6, solver=None, max_comp: float = 0.0, max_ell_frac: float = 1.0):
     """Scan theta_cut; binary-search the smallest feasible l_cut for each; keep the cheapest.
-    solver is the least-squares split to use (default: the full solve of Eq. 3). With max_comp > 0,
-    a theta whose smallest feasible split has a compensation above max_comp keeps only l_cut = lmax.
+    solver is the least-squares split to use (default: the full solve of Eq. 3). A theta whose
+    smallest feasible l_cut below lmax exceeds max_ell_frac lmax, or (max_comp > 0) whose split has a
+    compensation above max_comp, keeps only l_cut = lmax.
     Returns (theta_cut, ell_cut, wall, error) or None if no pair meets the bound."""
     lmax = len(K_ell) - 1
     solve = lsq_split if solver is None else solver
@@ -214,7 +215,7 @@ def split_search(K_ell, C_in, bound: float, theta_grid, t_gpu, t_cpu, alpha: flo
                 hi = mid
             else:
                 lo = mid
-        if max_comp > 0 and hi < lmax and comp(hi, tc) > max_comp:
+        if hi < lmax and (hi > max_ell_frac * lmax or (max_comp > 0 and comp(hi, tc) > max_comp)):
             hi = lmax
         wall = wall_time(t_gpu(tc), t_cpu(hi))
         if best is None or wall < best[2]:

@@ -148,6 +148,7 @@ struct conv_split_ctx {
   double theta_max = 0.0;
   double sv_cut = 1e-6;
   double max_comp = 0.0;   // search: largest accepted max_{l <= l_cut} |(P x)_l| / max_l |K_l| (0: no limit)
+  double max_ell_frac = 1.0;  // search: largest accepted l_cut / lmax below lmax itself (1: no limit)
   std::vector<double> W;   // (2l + 1) C_l
   std::vector<double> z, w;
   int nmax = 0;
@@ -332,7 +333,8 @@ bool search_one(conv_split_ctx* c, const double* K, int nside, double bound, dou
     // a split whose harmonic part must cancel more than max_comp of the kernel's scale at low l is not
     // trusted (the pixel-grid sum cannot reproduce such large low-l content to the error model's
     // precision): this theta then keeps only the all-harmonic split
-    if (c->max_comp > 0.0 && lc < lmax && compensation_of(c, K, lc, th) > c->max_comp) {
+    if (lc < lmax && (static_cast<double>(lc) > c->max_ell_frac * lmax ||
+                      (c->max_comp > 0.0 && compensation_of(c, K, lc, th) > c->max_comp))) {
       lc = lmax;
       sig_hi = 0.0;
     }
@@ -567,6 +569,16 @@ int conv_split_set_max_compensation(conv_split_ctx* ctx, double max_comp) {
     return CONV_REAL_EINVAL;
   }
   ctx->max_comp = max_comp;
+  return CONV_REAL_OK;
+}
+
+int conv_split_set_max_ell_fraction(conv_split_ctx* ctx, double frac) {
+  if (int e = check_ctx(ctx, "conv_split_set_max_ell_fraction")) return e;
+  if (!(frac > 0.0) || !(frac <= 1.0)) {
+    set_error("conv_split_set_max_ell_fraction: frac must be in (0, 1]");
+    return CONV_REAL_EINVAL;
+  }
+  ctx->max_ell_frac = frac;
   return CONV_REAL_OK;
 }
 

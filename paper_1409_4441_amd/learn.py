@@ -35,6 +35,9 @@ ALPHA = 5.0
 # largest compensation (max_{l <= l_cut} |(P x)_l| / max |K_l|) a split may need: the paper's fits
 # adjust the harmonic kernel at the percent level; splits needing more are not trusted
 MAX_COMP = 1e-2
+# largest l_cut / lmax of a split with a real-space part: above it the measured errors exceed the
+# error model's (the real-space part then carries only multipoles near the grid's resolution)
+MAX_ELL_FRAC = 0.45
 # network answers l_cut / lmax at or above this are taken as the all-harmonic split; answers in
 # [UNCERTAIN_FRAC, ALL_HARMONIC_FRAC) are left to the search
 ALL_HARMONIC_FRAC = 0.95
@@ -211,7 +214,7 @@ def eval_grid():
 def _contexts():
     """One split context per Nside (lmax = 2 Nside), wide enough for the largest scan angle."""
     theta_max = max(THETA_SIGMAS) * sigma_of(FWHM_RANGE[1]) * 1.0001
-    return {ns: _split.Context(2 * ns, theta_max, max_comp=MAX_COMP) for ns in NSIDES}
+    return {ns: _split.Context(2 * ns, theta_max, max_comp=MAX_COMP, max_ell_frac=MAX_ELL_FRAC) for ns in NSIDES}
 
 
 def scan(nside, fwhm, eps, model, ctxs=None, nthreads: int = 0):
@@ -302,14 +305,17 @@ class Predictor:
 
     def judge(self, nside: int, fwhm: float, eps: float, theta_cut: float, ell_cut: int):
         """Eq. 6 error of a split and whether it is accepted: it meets eps, and it is all harmonic or
-        its compensation is at most MAX_COMP (the search's own conditions)."""
+        has l_cut <= MAX_ELL_FRAC lmax and a compensation of at most MAX_COMP (the search's own
+        conditions)."""
         if int(ell_cut) < 0:           # the network left this triple to the search
             return float("nan"), False
         ctx = self.ctxs[int(nside)]
         th = min(max(float(theta_cut), 1e-9), ctx.theta_max)
         K = kernel_ell(2 * int(nside), fwhm)
         _, sig = ctx.error(K, int(ell_cut), th, alpha=ALPHA)
-        ok = sig <= eps and (int(ell_cut) >= 2 * int(nside) or ctx.compensation(K, int(ell_cut), th) <= MAX_COMP)
+        lmax = 2 * int(nside)
+        ok = sig <= eps and (int(ell_cut) >= lmax or (int(ell_cut) <= MAX_ELL_FRAC * lmax and
+                                                        ctx.compensation(K, int(ell_cut), th) <= MAX_COMP))
         return sig, ok
 
     def predict(self, nside: int, fwhm: float, eps: float):

@@ -9,7 +9,8 @@ Kernels K_l = sqrt(C_l) B_l (Eq. 9; C_l = 1/(l(l+1)) standing in for WMAP, Gauss
 C^in = S^2 / (S + N) (text after Eq. 2) for the beam-smoothed signal S_l = C_l B_l^2 and white noise N
 equal to S at a crossover multipole l_n (noise dominates above it). For each case the split scan
 (theta_cut 30'..390' in steps of 30', the range of Table 1; the smallest l_cut meeting the bound by
-bisection; compensation limit 1e-2; alpha = 5; bound 1e-5) picks the cheapest split under
+bisection; compensation limit 1e-2 and l_cut <= 0.45 lmax for a split with a real-space part;
+alpha = 5; bound 1e-5) picks the cheapest split under
 
 * the paper's cost models (Eqs. 7-8: GTX 480 real-space convolver, one CPU core for the harmonic part):
   speedup = 160 s / max(t_gpu, t_cpu), the ratio the paper quotes;
@@ -36,6 +37,7 @@ LMAX = 4096
 NSIDE = 2048
 THETAS = tuple(30.0 * k for k in range(1, 14))   # arcmin
 MAX_COMP = 1e-2
+MAX_ELL_FRAC = 0.45
 
 
 def paper_cost(theta_arcmin: float, ell_cut: int):
@@ -59,7 +61,8 @@ def wiener_weights(fwhm_arcmin: float, ell_n: int | None):
 
 def scan(ctx, K, bound, cost, alpha=5.0, step=8):
     """For each theta, the smallest l_cut (multiple of step, or lmax) whose Eq. 6 error meets the
-    bound, bisected; if its compensation exceeds MAX_COMP, only the all-harmonic split; the cheapest
+    bound, bisected; above MAX_ELL_FRAC lmax or with a compensation above MAX_COMP, only the
+    all-harmonic split; the cheapest
     pair by cost(theta_arcmin, l_cut)[2]. Returns (theta_arcmin, l_cut, wall, sigma)."""
     cands = list(range(0, LMAX, step)) + [LMAX]
     best = None
@@ -80,7 +83,7 @@ def scan(ctx, K, bound, cost, alpha=5.0, step=8):
                 else:
                     lo = mid
         lc = cands[hi]
-        if lc < LMAX and ctx.compensation(K, lc, tc) > MAX_COMP:
+        if lc < LMAX and (lc > MAX_ELL_FRAC * LMAX or ctx.compensation(K, lc, tc) > MAX_COMP):
             lc = LMAX
         s = 0.0 if lc == LMAX else ctx.error(K, lc, tc, alpha=alpha)[1]
         wall = cost(th, lc)[2]

@@ -22,7 +22,7 @@ INFEASIBLE = 1
 # Every entry point that include/convsplit.h declares.
 EXPORTS = ("conv_split_create", "conv_split_destroy", "conv_split_nodes", "conv_split_lsq", "conv_split_error",
            "conv_cost_pairs", "conv_cost_fit", "conv_cost_eval", "conv_split_search", "conv_split_search_many",
-           "conv_split_compensation", "conv_split_set_max_compensation")
+           "conv_split_compensation", "conv_split_set_max_compensation", "conv_split_set_max_ell_fraction")
 
 _c_int, _c_double, _c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
 _dptr_t = ctypes.POINTER(ctypes.c_double)
@@ -41,6 +41,7 @@ def _bind():
     lib.conv_split_error.argtypes = [_c_void_p, _dptr_t, _c_int, _c_double, _c_double, _dptr_t, _dptr_t]
     lib.conv_split_compensation.argtypes = [_c_void_p, _dptr_t, _c_int, _c_double, _dptr_t]
     lib.conv_split_set_max_compensation.argtypes = [_c_void_p, _c_double]
+    lib.conv_split_set_max_ell_fraction.argtypes = [_c_void_p, _c_double]
     lib.conv_cost_pairs.argtypes = [_c_int, _c_double]
     lib.conv_cost_pairs.restype = _c_double
     lib.conv_cost_fit.argtypes = [_dptr_t, _dptr_t, _c_int, _dptr_t, _dptr_t, _c_int, ctypes.POINTER(_Cost)]
@@ -53,7 +54,7 @@ def _bind():
                                            _dptr_t]
     for f in ("conv_split_create", "conv_split_destroy", "conv_split_nodes", "conv_split_lsq", "conv_split_error",
               "conv_cost_fit", "conv_cost_eval", "conv_split_search", "conv_split_search_many",
-              "conv_split_compensation", "conv_split_set_max_compensation"):
+              "conv_split_compensation", "conv_split_set_max_compensation", "conv_split_set_max_ell_fraction"):
         getattr(lib, f).restype = _c_int
 
 
@@ -125,9 +126,11 @@ def pairs_estimate(nside: int, theta_cut: float) -> float:
 
 class Context:
     """Split model for one lmax and input weighting C_in (None: flat), theta_cut <= theta_max; the
-    search accepts splits of compensation <= max_comp (0: any)."""
+    search accepts splits of compensation <= max_comp (0: any) and l_cut <= max_ell_frac lmax (or
+    l_cut = lmax)."""
 
-    def __init__(self, lmax: int, theta_max: float, c_in=None, sv_cut: float = 1e-6, max_comp: float = 0.0):
+    def __init__(self, lmax: int, theta_max: float, c_in=None, sv_cut: float = 1e-6, max_comp: float = 0.0,
+                 max_ell_frac: float = 1.0):
         self.lmax = int(lmax)
         self.theta_max = float(theta_max)
         c = None if c_in is None else _f64(c_in, self.lmax + 1, "c_in")
@@ -137,6 +140,8 @@ class Context:
         self._h = h
         if max_comp:
             _check(lib.conv_split_set_max_compensation(h, float(max_comp)), "conv_split_set_max_compensation")
+        if max_ell_frac < 1.0:
+            _check(lib.conv_split_set_max_ell_fraction(h, float(max_ell_frac)), "conv_split_set_max_ell_fraction")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value and lib is not None:

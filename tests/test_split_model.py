@@ -244,3 +244,29 @@ def test_wiener_weights_match_oracle_and_relax_the_split():
         rw = cw.search(K, 256, 1e-5, [tc], m)
         rf = cf.search(K, 256, 1e-5, [tc], m)
         assert rw is not None and rf is not None and rw[1] <= rf[1]
+
+
+def test_search_with_ell_cut_limit_matches_oracle():
+    # a 100' beam at lmax 256 splits best at 5 sigma with l_cut 243 (0.95 lmax); with the limit that
+    # cut keeps only the all-harmonic split, while a 120' beam's split at l_cut 57 is untouched; the
+    # library's scan equals the oracle's in every case
+    lmax, nside = 256, 128
+    C = np.ones(lmax + 1)
+    m = split.CostModel(1e-4, 1e-14, 1e-9)
+    t_gpu = lambda tc: m.a + m.b * osplit.pairs_estimate(nside, tc)   # noqa: E731
+    t_cpu = lambda lc: m.c * lc * lc * lmax                             # noqa: E731
+    answers = {}
+    for fwhm in (100.0, 120.0):
+        K = _paper_kernel(lmax, fwhm)
+        sig = fwhm * ARCMIN / math.sqrt(8 * math.log(2))
+        grid = [k * sig for k in (1.0, 1.5, 2.0, 3.0, 5.0, 8.0)]
+        for frac in (1.0, 0.45):
+            with split.Context(lmax, max(grid), max_ell_frac=frac) as ctx:
+                got = ctx.search(K, nside, 1e-3, grid, m)
+            want = osplit.split_search(K, C, 1e-3, grid, t_gpu, t_cpu, solver=osplit.lsq_split_reduced,
+                                       max_ell_frac=frac)
+            assert got[:2] == want[:2], (fwhm, frac, got, want)
+            assert got[1] == lmax or got[1] <= frac * lmax
+            answers[fwhm, frac] = got[1]
+    assert answers[100.0, 1.0] > 0.45 * lmax and answers[100.0, 0.45] == lmax
+    assert answers[120.0, 1.0] == answers[120.0, 0.45] <= 0.45 * lmax
