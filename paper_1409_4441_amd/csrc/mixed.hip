@@ -601,14 +601,16 @@ struct CapLane {
 };
 
 // ---------------------------------------------------------------- cap weight store
-// Store tiles are kStoreBlocks blocks of 16 rows (one wave each). Layout, per store tile: per
-// cap-touching ring pair (in list order), per block and per row of the block inside the fundamental
-// domain, the row's weights in groups of 4 inputs, group g covering inputs b0 + 4g .. b0 + 4g + 3 of
-// ring j (b0: start of the tile's union window), 16 bytes each: the 4 weights x s_w rounded to FP16
-// (hi), then the FP16 residues (lo). A row keeps the groups that meet its window [lo, hi], zeros
-// inside them outside the window. Nothing about the layout is stored besides the first group of
-// every tile: the apply recomputes the same windows, and 16-lane prefix sums of the rows' group
-// counts give every lane its addresses. Weights are read through a buffer resource over the tile's
+// Store tiles are kStoreBlocks blocks of 16 rows (one wave each). A row of the tile keeps, per
+// cap-touching ring pair, the groups of 4 inputs that meet its window [lo, hi] (group g covers inputs
+// b0 + 4g .. b0 + 4g + 3 of ring j, b0: start of the tile's union window), 16 bytes each: the 4
+// weights x s_w rounded to FP16 (hi), then the FP16 residues (lo), zeros inside a group outside the
+// window. Layout, per store tile: per ring pair (in list order), per 32-input step and per half of
+// the step (the two load instructions of the apply, see the K order below), the stored groups of
+// the lanes in lane order. Every load instruction of the apply thus reads one contiguous run of at
+// most 1 KB. Nothing about the layout is stored besides the first group of every tile: the apply
+// recomputes the same windows, and a ballot of the lanes whose group is stored, counted below each
+// lane, gives every lane its offset. Weights are read through a buffer resource over the tile's
 // block: a lane whose group is not stored gives an offset past the resource's range, which the
 // hardware answers with zeros without a memory access, so every load instruction is issued
 // unconditionally (and lands in the register that the matrix cores read later) while only stored
@@ -624,11 +626,8 @@ constexpr int kStoreRows = 16 * kStoreBlocks;
 // (half 1) of the step's 32, i.e. weight groups 8q + kgrp and 8q + 4 + kgrp, so that each load
 // instruction reads 64 contiguous bytes per row of weights and per image of inputs.
 struct StorePair {
-  int rbase[kStoreBlocks];   // offset (groups) from the tile's block of group 0 of the lane's row
-  int glo[kStoreBlocks];     // the row's stored groups glo .. glo + gn - 1 (gn = 0: none)
+  int glo[kStoreBlocks];     // the lane's row stores groups glo .. glo + gn - 1 (gn = 0: none)
   int gn[kStoreBlocks];
-  int slo[kStoreBlocks];     // the steps in which the block has stored groups (uniform)
-  int shi[kStoreBlocks];
   unsigned xofs;             // map index of the lowest pixel of the lane's step-0 half-0 inputs
   int nk;                    // 32-input steps over the union window (uniform)
 };
@@ -643,11 +642,26 @@ struct StoreStep {
   bool last;      // last step of its ring pair
 };
 
-// byte offset in the tile's block of group g of the lane's row of block b (kNoLoad if not stored)
-__device__ __forceinline__ unsigned group_offset(const StorePair& S, int b, int g) {
-  return static_cast<unsigned>(g - S.glo[b]) < static_cast<unsigned>(S.gn[b])
-             ? static_cast<unsigned>(S.rbase[b] + g) * 16u
-             : kNoLoad;
+// number of lanes below this one whose bit is set in the wave mask m
+__device__ __forceinline__ unsigned lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(m), 0u));
+}
+
+// Byte offsets in the tile's block of the lane's two groups of step q of block b (kNoLoad where not
+// stored); pos: the step's first group, advanced past the step's groups. Uniform control flow only
+// (a ballot).
+__device__ __forceinline__ bool step_offsets(const StorePair& S, int b, int q, int kgrp, int& pos, unsigned& oa,
+                                             unsigned& ob) {
+  const bool fa = static_cast<unsigned>(8 * q + kgrp - S.glo[b]) < static_cast<unsigned>(S.gn[b]);
+  const bool fb = static_cast<unsigned>(8 * q + 4 + kgrp - S.glo[b]) < static_cast<unsigned>(S.gn[b]);
+  const unsigned long long ma = __builtin_amdgcn_ballot_w64(fa);
+  const unsigned long long mb = __builtin_amdgcn_ballot_w64(fb);
+  const int na = __builtin_popcountll(ma);
+  oa = fa ? static_cast<unsigned>(pos + static_cast<int>(lanes_below(ma))) * 16u : kNoLoad;
+  ob = fb ? static_cast<unsigned>(pos + na + static_cast<int>(lanes_below(mb))) * 16u : kNoLoad;
+  pos += na + __builtin_popcountll(mb);
+  return (ma | mb) != 0ull;
 }
 
 __device__ __forceinline__ u32x4 load_group(__amdgpu_buffer_rsrc_t tile, unsigned off) {
@@ -704,21 +718,20 @@ struct StoreIter {
   __amdgpu_buffer_rsrc_t tile;   // over the tile's block
   convreal::CapPair Pn;        // record kk, loaded one pair ahead of its use
   long long kk, k1;
-  int pos;                     // next pair's first group, from the tile's block
+  int pos;                     // next step's first group, from the tile's block
   int q;
   StorePair S;
 
-  // Set up ring pair P and advance pos past its block. Returns the pair's step count, 0 if it has no
-  // stored weight for the tile. A pair whose inputs wrap around ring j for some lane (the first
-  // tiles of a ring, rings of fewer than 8 pixels) is done here at once, without prefetch, and
-  // also returns 0.
+  // Set up ring pair P. Returns the pair's step count, 0 if it has no stored weight for the tile. A
+  // pair whose inputs wrap around ring j for some lane (the first tiles of a ring, rings of fewer
+  // than 8 pixels) is done here at once, without prefetch, and also returns 0.
   __device__ __forceinline__ int setup(const convreal::CapPair& P, const CapLane& L, const float* __restrict__ xm,
                                        float sx, CapAcc& A) {
     int b0, bend;
     tile_union(P, L.u_first, L.u_last, L.ni, L.inv_2ni, b0, bend);
     if (bend < b0) return 0;
     const int nk = (bend - b0 + 32) >> 5;
-    const int pos0 = pos;
+    int stored = 0;
 #pragma unroll
     for (int b = 0; b < kStoreBlocks; ++b) {
       int lo, hi;
@@ -727,17 +740,12 @@ struct StoreIter {
       const int glo = (lo - b0) >> 2;
       const int gn = in ? ((hi - b0) >> 2) - glo + 1 : 0;
       int total;
-      const int off = scan16(gn, total);
-      S.rbase[b] = pos + off - glo;
+      scan16(gn, total);
       S.glo[b] = glo;
       S.gn[b] = gn;
-      // the block's windows run from its first row's start to its last row's end
-      const int lo0 = __builtin_amdgcn_readlane(lo, 0), hi15 = __builtin_amdgcn_readlane(hi, 15);
-      S.slo[b] = total > 0 ? max(0, ((lo0 - b0) >> 2) >> 3) : 1;
-      S.shi[b] = total > 0 ? min(nk - 1, ((hi15 - b0) >> 2) >> 3) : 0;
-      pos += total;
+      stored += total;
     }
-    if (pos == pos0) return 0;
+    if (stored == 0) return 0;
     const int nj = P.nj;
     const long long xoff = L.ch ? P.xoff_m : P.xoff;
     const int pofs = L.pofs(nj, P.cj);
@@ -767,9 +775,10 @@ struct StoreIter {
       split_fp16<8>(v, xhi, xlo);
 #pragma unroll
       for (int b = 0; b < kStoreBlocks; ++b) {
-        if (q < S.slo[b] || q > S.shi[b]) continue;
-        const u32x4 wa = load_group(tile, group_offset(S, b, 8 * q + L.kgrp));
-        const u32x4 wb = load_group(tile, group_offset(S, b, 8 * q + 4 + L.kgrp));
+        unsigned oa, ob;
+        if (!step_offsets(S, b, q, L.kgrp, pos, oa, ob)) continue;
+        const u32x4 wa = load_group(tile, oa);
+        const u32x4 wb = load_group(tile, ob);
         block_mfma(A.acc[b], xhi, xlo, wa, wb);
       }
     }
@@ -801,11 +810,8 @@ struct StoreIter {
     for (int b = 0; b < kStoreBlocks; ++b) oa[b] = ob[b] = kNoLoad;
     if (ok) {
 #pragma unroll
-      for (int b = 0; b < kStoreBlocks; ++b) {
-        oa[b] = group_offset(S, b, 8 * q + L.kgrp);
-        ob[b] = group_offset(S, b, 8 * q + 4 + L.kgrp);
-        if (q >= S.slo[b] && q <= S.shi[b]) blocks |= 1 << b;
-      }
+      for (int b = 0; b < kStoreBlocks; ++b)
+        if (step_offsets(S, b, q, L.kgrp, pos, oa[b], ob[b])) blocks |= 1 << b;
       xa = S.xofs + static_cast<unsigned>(L.dir * 32 * q);
       xc = xa + static_cast<unsigned>(L.dir * 16);
       ++q;
@@ -1052,31 +1058,46 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
     int b0, bend;
     tile_union(P, L.u_first, L.u_last, L.ni, L.inv_2ni, b0, bend);
     if (bend < b0) continue;
+    const int nk = (bend - b0 + 32) >> 5;
+    StorePair S;
+    int lo[kStoreBlocks], hi[kStoreBlocks], stored = 0;
+#pragma unroll
     for (int b = 0; b < kStoreBlocks; ++b) {
-      const int u_row = L.u_row + 32 * b;
-      int lo, hi;
-      row_window(P, u_row, L.ni, L.inv_2ni, lo, hi);
-      const bool in = L.a0 + 16 * b + L.row < L.F && hi >= lo;
-      const int glo = (lo - b0) >> 2, ghi = (hi - b0) >> 2;
+      row_window(P, L.u_row + 32 * b, L.ni, L.inv_2ni, lo[b], hi[b]);
+      const bool in = L.a0 + 16 * b + L.row < L.F && hi[b] >= lo[b];
+      S.glo[b] = (lo[b] - b0) >> 2;
+      S.gn[b] = in ? ((hi[b] - b0) >> 2) - S.glo[b] + 1 : 0;
       int total;
-      const int off = scan16(in ? ghi - glo + 1 : 0, total);
-      if (FILL && in) {
-        const LongForm lf(P, L.ni, ih2);
-        for (int g = glo + L.kgrp; g <= ghi; g += 4) {
-          const int bA = b0 + 4 * g;
+      scan16(S.gn[b], total);
+      stored += total;
+    }
+    if (!FILL || stored == 0) {
+      pos += stored;
+      continue;
+    }
+    // the apply's order: step, block, half, lanes in lane order
+    const LongForm lf(P, L.ni, ih2);
+    for (int q = 0; q < nk; ++q) {
+#pragma unroll
+      for (int b = 0; b < kStoreBlocks; ++b) {
+        unsigned oa, ob;
+        step_offsets(S, b, q, L.kgrp, pos, oa, ob);
+        for (int h = 0; h < 2; ++h) {
+          const unsigned o = h ? ob : oa;
+          if (o == kNoLoad) continue;
+          const int bA = b0 + 4 * (8 * q + 4 * h + L.kgrp);
           double qv[4];
-          lf.q<4>(u_row, bA, L.ni, P.nj, P.cj, qv);
+          lf.q<4>(L.u_row + 32 * b, bA, L.ni, P.nj, P.cj, qv);
           float w[4];
           weights_of<4>(qv, qcut, seg_max, s_coef, w);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) w[e] = (bA + e >= lo && bA + e <= hi) ? w[e] : 0.0f;
+          for (int e = 0; e < 4; ++e) w[e] = (bA + e >= lo[b] && bA + e <= hi[b]) ? w[e] : 0.0f;
           half4 wh, wl;
           split_fp16<4>(w, wh, wl);
           const u32x2 ph = __builtin_bit_cast(u32x2, wh), pl = __builtin_bit_cast(u32x2, wl);
-          tile[pos + off + (g - glo)] = u32x4{ph.x, ph.y, pl.x, pl.y};
+          tile[o / 16u] = u32x4{ph.x, ph.y, pl.x, pl.y};
         }
       }
-      pos += total;
     }
   }
   if (!FILL && (threadIdx.x & 63) == 0) offsets[t] = pos;
