@@ -615,6 +615,13 @@ int set_weight_store(conv_real_plan* p, int mode) {
       return hip_fail(e, "weight store: count");
     }
     release(p, counts);
+    // the count pass flags tiles whose inputs wrap around a ring in the high bits; the offsets keep
+    // the flag beside the first group
+    std::vector<long long> wraps(static_cast<size_t>(p->n_citems));
+    for (int t = 0; t < p->n_citems; ++t) {
+      wraps[t] = off[t + 1] & convreal::kTileWraps;
+      off[t + 1] &= convreal::kTileOffsetMask;
+    }
     for (int t = 0; t < p->n_citems; ++t) off[t + 1] += off[t];
     const long long n = off[p->n_citems];
     // 16-byte groups, every one written by the fill (at least one, so that the store is never empty)
@@ -628,6 +635,7 @@ int set_weight_store(conv_real_plan* p, int mode) {
     }
     if (build) {
       off.pop_back();
+      for (int t = 0; t < p->n_citems; ++t) off[t] |= wraps[t];
       if ((e = dev_alloc(p, &p->d_wstore, static_cast<size_t>(std::max(n, 1LL)))) != hipSuccess) {
         // the automatic mode falls back to evaluating on the fly
         if (mode == CONV_REAL_STORE_AUTO)

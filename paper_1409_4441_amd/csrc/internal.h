@@ -74,9 +74,13 @@ constexpr int kMaxChunks = 16; // work-queue chunks
 // wider windows of one input ring are split into several blocks
 constexpr int kBeltBlockChunks = 4;
 // 16-row blocks per cap tile when the plan holds a weight store: the blocks of a tile share every
-// step's inputs and every ring pair's set-up, but each block adds its weight registers to every
-// pipeline slot; two blocks exceed the register file at two waves per SIMD and were measured slower
-constexpr int kStoreBlocks = 1;
+// step's inputs and every ring pair's set-up (the cap items are bound by vector instruction issue),
+// and each block adds its weight registers to every pipeline slot
+constexpr int kStoreBlocks = 2;
+// per cap store tile: first group (low bits) and a flag for tiles where some ring pair's inputs
+// wrap around the input ring for some lane (the apply takes them one step at a time)
+constexpr long long kTileWraps = 1LL << 62;
+constexpr long long kTileOffsetMask = kTileWraps - 1;
 // the per-pair kernel stages the table as cubic coefficients (4 doubles per segment, 64 KB of LDS)
 // up to this many segments, as nodes beyond
 constexpr int kCoefMaxSegs = 2048;

@@ -668,6 +668,45 @@ __device__ __forceinline__ u32x4 load_group(__amdgpu_buffer_rsrc_t tile, unsigne
   return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(tile, off, 0, 0));
 }
 
+// Ring pair P over a store tile: the union window [b0, bend] of its rows (steps of 32 inputs from
+// b0), each lane's stored groups per block (S.glo, S.gn) and the pair's stored group count. The
+// fill, the count and both apply paths take the layout from here.
+struct PairWin {
+  int b0, nk, stored;
+};
+__device__ __forceinline__ PairWin pair_windows(const convreal::CapPair& P, const CapLane& L, StorePair& S,
+                                                int (&lo)[kStoreBlocks], int (&hi)[kStoreBlocks]) {
+  PairWin w;
+  int bend;
+  tile_union(P, L.u_first, L.u_last, L.ni, L.inv_2ni, w.b0, bend);
+  w.stored = 0;
+  w.nk = bend < w.b0 ? 0 : (bend - w.b0 + 32) >> 5;
+  if (w.nk == 0) return w;
+#pragma unroll
+  for (int b = 0; b < kStoreBlocks; ++b) {
+    row_window(P, L.u_row + 32 * b, L.ni, L.inv_2ni, lo[b], hi[b]);
+    const bool in = L.a0 + 16 * b + L.row < L.F && hi[b] >= lo[b];
+    S.glo[b] = (lo[b] - w.b0) >> 2;
+    S.gn[b] = in ? ((hi[b] - w.b0) >> 2) - S.glo[b] + 1 : 0;
+    int total;
+    scan16(S.gn[b], total);
+    w.stored += total;
+  }
+  return w;
+}
+
+// The lane's inputs of the pair over all its steps lie in b0 + 4 kgrp + [0, span), pixels
+// pofs + dir b (mod nj) of ring j (half h of step q starts at b0 + 4 kgrp + 32 q + 16 h). Returns
+// whether they cross the ring's start; low: the lowest pixel (mod nj).
+__device__ __forceinline__ bool pair_wraps(const convreal::CapPair& P, const CapLane& L, int b0, int nk, int& low) {
+  const int nj = P.nj;
+  const int pofs = L.pofs(nj, P.cj);
+  const float rcp_n = __builtin_amdgcn_rcpf(static_cast<float>(nj));
+  const int first = b0 + 4 * L.kgrp, span = 32 * (nk - 1) + 20;
+  low = mod_any(L.dir > 0 ? pofs + first : pofs - (first + span - 1), nj, rcp_n);
+  return low + span > nj;
+}
+
 // w_hi x_hi + w_lo x_hi + w_hi x_lo of one block on the step's split inputs
 __device__ __forceinline__ void block_mfma(floatx4& acc, const half8& xhi, const half8& xlo, const u32x4& wa,
                                            const u32x4& wb) {
@@ -722,75 +761,24 @@ struct StoreIter {
   int q;
   StorePair S;
 
-  // Set up ring pair P. Returns the pair's step count, 0 if it has no stored weight for the tile. A
-  // pair whose inputs wrap around ring j for some lane (the first tiles of a ring, rings of fewer
-  // than 8 pixels) is done here at once, without prefetch, and also returns 0.
-  __device__ __forceinline__ int setup(const convreal::CapPair& P, const CapLane& L, const float* __restrict__ xm,
-                                       float sx, CapAcc& A) {
-    int b0, bend;
-    tile_union(P, L.u_first, L.u_last, L.ni, L.inv_2ni, b0, bend);
-    if (bend < b0) return 0;
-    const int nk = (bend - b0 + 32) >> 5;
-    int stored = 0;
-#pragma unroll
-    for (int b = 0; b < kStoreBlocks; ++b) {
-      int lo, hi;
-      row_window(P, L.u_row + 32 * b, L.ni, L.inv_2ni, lo, hi);
-      const bool in = L.a0 + 16 * b + L.row < L.F && hi >= lo;
-      const int glo = (lo - b0) >> 2;
-      const int gn = in ? ((hi - b0) >> 2) - glo + 1 : 0;
-      int total;
-      scan16(gn, total);
-      S.glo[b] = glo;
-      S.gn[b] = gn;
-      stored += total;
-    }
-    if (stored == 0) return 0;
-    const int nj = P.nj;
+  // Set up ring pair P. Returns the pair's step count, 0 if it has no stored weight for the tile.
+  // Tiles where some pair's inputs wrap around ring j never come here.
+  __device__ __forceinline__ int setup(const convreal::CapPair& P, const CapLane& L) {
+    int lo[kStoreBlocks], hi[kStoreBlocks];
+    const PairWin w = pair_windows(P, L, S, lo, hi);
+    if (w.stored == 0) return 0;
+    int low;
+    (void)pair_wraps(P, L, w.b0, w.nk, low);
     const long long xoff = L.ch ? P.xoff_m : P.xoff;
-    const int pofs = L.pofs(nj, P.cj);
-    const float rcp_n = __builtin_amdgcn_rcpf(static_cast<float>(nj));
-    // the lane's inputs over all steps lie in b0 + 4 kgrp + [0, span), pixels pofs + dir b (mod nj);
-    // half h of step q starts at b0 + 4 kgrp + 32 q + 16 h
-    const int first = b0 + 4 * L.kgrp, span = 32 * (nk - 1) + 20;
-    const int low = mod_any(L.dir > 0 ? pofs + first : pofs - (first + span - 1), nj, rcp_n);
-    if (__all(low + span <= nj)) {
-      S.xofs = static_cast<unsigned>(xoff + (L.dir > 0 ? low : low + span - 4));
-      return nk;
-    }
-    const float* xj = xm + xoff;
-    for (int q = 0; q < nk; ++q) {
-      // indices first, then all loads, then the scaling; the scheduling barrier keeps the compiler
-      // from pairing each load with its use, so that the 8 loads are in flight together
-      int ix[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) ix[e] = mod_any(pofs + L.dir * (first + 32 * q + 16 * (e >> 2) + (e & 3)), nj, rcp_n);
-      float v[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = xj[ix[e]];
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] *= sx;
-      half8 xhi, xlo;
-      split_fp16<8>(v, xhi, xlo);
-#pragma unroll
-      for (int b = 0; b < kStoreBlocks; ++b) {
-        unsigned oa, ob;
-        if (!step_offsets(S, b, q, L.kgrp, pos, oa, ob)) continue;
-        const u32x4 wa = load_group(tile, oa);
-        const u32x4 wb = load_group(tile, ob);
-        block_mfma(A.acc[b], xhi, xlo, wa, wb);
-      }
-    }
-    A.pair_done();
-    return 0;
+    S.xofs = static_cast<unsigned>(xoff + (L.dir > 0 ? low : low + 32 * (w.nk - 1) + 16));
+    return w.nk;
   }
 
   // Load the next step into R (R.live = false once the tile has no step left). Every call issues
   // the same loads, an ended sequence reading no weight (zeros) and the map's first pixels, so that
   // the compiler can count the loads in flight and wait for the oldest only.
   __device__ __forceinline__ void next(const convreal::CapPair* __restrict__ cpair, const CapLane& L,
-                                       const float* __restrict__ xm, float sx, CapAcc& A, StoreStep& R) {
+                                       const float* __restrict__ xm, StoreStep& R) {
     bool ok = true;
     while (q >= S.nk) {
       if (kk >= k1) {
@@ -801,7 +789,7 @@ struct StoreIter {
       ++kk;
       if (kk < k1) Pn = ldu_record(cpair[kk]);
       q = 0;
-      S.nk = setup(P, L, xm, sx, A);
+      S.nk = setup(P, L);
     }
     unsigned oa[kStoreBlocks], ob[kStoreBlocks], xa = 0, xc = 0;
     int blocks = 0;
@@ -836,21 +824,64 @@ struct StoreIter {
   }
 };
 
-constexpr int kStoreSlots = 4;   // steps in flight per wave
+constexpr int kStoreSlots = 3;   // steps in flight per wave
+
+// A store tile where some ring pair's inputs wrap around ring j for some lane (the first tile of a
+// ring, rings of a few pixels near the poles): every pair at once, step after step, the inputs
+// gathered pixel by pixel (ring indices mod n_j).
+__device__ __forceinline__ void cap_rows_wrap(__amdgpu_buffer_rsrc_t tile, long long k0, long long k1,
+                                              const convreal::CapPair* __restrict__ cpair, const CapLane& L,
+                                              const float* __restrict__ xm, float sx, CapAcc& A) {
+  int pos = 0;
+  for (long long kk = k0; kk < k1; ++kk) {
+    const convreal::CapPair P = ldu_record(cpair[kk]);
+    StorePair S;
+    int lo[kStoreBlocks], hi[kStoreBlocks];
+    const PairWin w = pair_windows(P, L, S, lo, hi);
+    if (w.stored == 0) continue;
+    const int nj = P.nj;
+    const float* xj = xm + (L.ch ? P.xoff_m : P.xoff);
+    const int pofs = L.pofs(nj, P.cj);
+    const float rcp_n = __builtin_amdgcn_rcpf(static_cast<float>(nj));
+    const int first = w.b0 + 4 * L.kgrp;
+    for (int q = 0; q < w.nk; ++q) {
+      // indices first, then all loads, then the scaling; the scheduling barrier keeps the compiler
+      // from pairing each load with its use, so that the 8 loads are in flight together
+      int ix[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ix[e] = mod_any(pofs + L.dir * (first + 32 * q + 16 * (e >> 2) + (e & 3)), nj, rcp_n);
+      float v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = xj[ix[e]];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] *= sx;
+      half8 xhi, xlo;
+      split_fp16<8>(v, xhi, xlo);
+#pragma unroll
+      for (int b = 0; b < kStoreBlocks; ++b) {
+        unsigned oa, ob;
+        if (!step_offsets(S, b, q, L.kgrp, pos, oa, ob)) continue;
+        const u32x4 wa = load_group(tile, oa);
+        const u32x4 wb = load_group(tile, ob);
+        block_mfma(A.acc[b], xhi, xlo, wa, wb);
+      }
+    }
+    A.pair_done();
+  }
+}
 
 // all cap-touching pairs of a store tile, all blocks
 __device__ __forceinline__ void cap_rows_store(const convreal::MixedDesc* __restrict__ d, int t, const CapLane& L,
                                                const float* __restrict__ xm, float sx,
                                                double (&accd)[kStoreBlocks][4]) {
-  StoreIter it;
-  it.tile = buffer_resource(reinterpret_cast<const unsigned char*>(ldu(d->wstore)) + 16 * ldu(ldu(d->wtile_off)[t]));
-  it.kk = ldu(ldu(d->rest_off)[L.r]);
-  it.k1 = ldu(ldu(d->rest_off)[L.r + 1]);
-  it.pos = 0;
-  it.q = 0;
-  it.S.nk = 0;
+  // the tile's first group, and whether some pair wraps (set by the count pass)
+  const long long wo = ldu(ldu(d->wtile_off)[t]);
+  const __amdgpu_buffer_rsrc_t tile =
+      buffer_resource(reinterpret_cast<const unsigned char*>(ldu(d->wstore)) + 16 * (wo & convreal::kTileOffsetMask));
+  const long long k0 = ldu(ldu(d->rest_off)[L.r]);
+  const long long k1 = ldu(ldu(d->rest_off)[L.r + 1]);
   const convreal::CapPair* cpair = ldu(d->cpair);
-  if (it.kk < it.k1) it.Pn = ldu_record(cpair[it.kk]);
   CapAcc A;
 #pragma unroll
   for (int b = 0; b < kStoreBlocks; ++b) {
@@ -859,19 +890,31 @@ __device__ __forceinline__ void cap_rows_store(const convreal::MixedDesc* __rest
     for (int u = 0; u < 4; ++u) A.accd[b][u] = 0.0;
   }
   A.nfold = 0;
-  StoreStep R[kStoreSlots];
+  if (wo & convreal::kTileWraps) {
+    cap_rows_wrap(tile, k0, k1, cpair, L, xm, sx, A);
+  } else {
+    StoreIter it;
+    it.tile = tile;
+    it.kk = k0;
+    it.k1 = k1;
+    it.pos = 0;
+    it.q = 0;
+    it.S.nk = 0;
+    if (it.kk < it.k1) it.Pn = ldu_record(cpair[it.kk]);
+    StoreStep R[kStoreSlots];
 #pragma unroll
-  for (int s = 0; s < kStoreSlots; ++s) it.next(cpair, L, xm, sx, A, R[s]);
-  // Rounds over the slots: slot s holds step n + s; each live slot is used and every slot is
-  // refilled at once, so the oldest slot is live exactly while steps remain.
-  while (R[0].live) {
+    for (int s = 0; s < kStoreSlots; ++s) it.next(cpair, L, xm, R[s]);
+    // Rounds over the slots: slot s holds step n + s; each live slot is used and every slot is
+    // refilled at once, so the oldest slot is live exactly while steps remain.
+    while (R[0].live) {
 #pragma unroll
-    for (int s = 0; s < kStoreSlots; ++s) {
-      if (R[s].live) {
-        store_compute(A, R[s], L.dir, sx);
-        if (R[s].last) A.pair_done();
+      for (int s = 0; s < kStoreSlots; ++s) {
+        if (R[s].live) {
+          store_compute(A, R[s], L.dir, sx);
+          if (R[s].last) A.pair_done();
+        }
+        it.next(cpair, L, xm, R[s]);
       }
-      it.next(cpair, L, xm, sx, A, R[s]);
     }
   }
 #pragma unroll
@@ -1051,33 +1094,24 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
   const convreal::CapPair* cpair = ldu(d->cpair);
   const long long k0 = ldu(rest_off[L.r]);
   const long long k1 = ldu(rest_off[L.r + 1]);
-  u32x4* tile = FILL ? store + offsets[t] : nullptr;
+  u32x4* tile = FILL ? store + (offsets[t] & convreal::kTileOffsetMask) : nullptr;
   int pos = 0;
+  bool wraps = false;
   for (long long kk = k0; kk < k1; ++kk) {
     const convreal::CapPair P = ldu_record(cpair[kk]);
-    int b0, bend;
-    tile_union(P, L.u_first, L.u_last, L.ni, L.inv_2ni, b0, bend);
-    if (bend < b0) continue;
-    const int nk = (bend - b0 + 32) >> 5;
     StorePair S;
-    int lo[kStoreBlocks], hi[kStoreBlocks], stored = 0;
-#pragma unroll
-    for (int b = 0; b < kStoreBlocks; ++b) {
-      row_window(P, L.u_row + 32 * b, L.ni, L.inv_2ni, lo[b], hi[b]);
-      const bool in = L.a0 + 16 * b + L.row < L.F && hi[b] >= lo[b];
-      S.glo[b] = (lo[b] - b0) >> 2;
-      S.gn[b] = in ? ((hi[b] - b0) >> 2) - S.glo[b] + 1 : 0;
-      int total;
-      scan16(S.gn[b], total);
-      stored += total;
-    }
-    if (!FILL || stored == 0) {
-      pos += stored;
+    int lo[kStoreBlocks], hi[kStoreBlocks];
+    const PairWin w = pair_windows(P, L, S, lo, hi);
+    if (w.stored == 0) continue;
+    if (!FILL) {
+      int low;
+      wraps = wraps || __any(pair_wraps(P, L, w.b0, w.nk, low));
+      pos += w.stored;
       continue;
     }
     // the apply's order: step, block, half, lanes in lane order
     const LongForm lf(P, L.ni, ih2);
-    for (int q = 0; q < nk; ++q) {
+    for (int q = 0; q < w.nk; ++q) {
 #pragma unroll
       for (int b = 0; b < kStoreBlocks; ++b) {
         unsigned oa, ob;
@@ -1085,22 +1119,22 @@ __global__ __launch_bounds__(kBlock) void cap_store_kernel(const convreal::Mixed
         for (int h = 0; h < 2; ++h) {
           const unsigned o = h ? ob : oa;
           if (o == kNoLoad) continue;
-          const int bA = b0 + 4 * (8 * q + 4 * h + L.kgrp);
+          const int bA = w.b0 + 4 * (8 * q + 4 * h + L.kgrp);
           double qv[4];
           lf.q<4>(L.u_row + 32 * b, bA, L.ni, P.nj, P.cj, qv);
-          float w[4];
-          weights_of<4>(qv, qcut, seg_max, s_coef, w);
+          float wv[4];
+          weights_of<4>(qv, qcut, seg_max, s_coef, wv);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) w[e] = (bA + e >= lo[b] && bA + e <= hi[b]) ? w[e] : 0.0f;
+          for (int e = 0; e < 4; ++e) wv[e] = (bA + e >= lo[b] && bA + e <= hi[b]) ? wv[e] : 0.0f;
           half4 wh, wl;
-          split_fp16<4>(w, wh, wl);
+          split_fp16<4>(wv, wh, wl);
           const u32x2 ph = __builtin_bit_cast(u32x2, wh), pl = __builtin_bit_cast(u32x2, wl);
           tile[o / 16u] = u32x4{ph.x, ph.y, pl.x, pl.y};
         }
       }
     }
   }
-  if (!FILL && (threadIdx.x & 63) == 0) offsets[t] = pos;
+  if (!FILL && (threadIdx.x & 63) == 0) offsets[t] = pos | (wraps ? convreal::kTileWraps : 0);
 }
 
 // ---------------------------------------------------------------- persistent queue kernel
