@@ -658,8 +658,13 @@ __device__ __forceinline__ bool step_offsets(const StorePair& S, int b, int q, i
   const unsigned long long ma = __builtin_amdgcn_ballot_w64(fa);
   const unsigned long long mb = __builtin_amdgcn_ballot_w64(fb);
   const int na = __builtin_popcountll(ma);
-  oa = fa ? static_cast<unsigned>(pos + static_cast<int>(lanes_below(ma))) * 16u : kNoLoad;
-  ob = fb ? static_cast<unsigned>(pos + na + static_cast<int>(lanes_below(mb))) * 16u : kNoLoad;
+  unsigned ra = static_cast<unsigned>(pos) + lanes_below(ma);
+  unsigned rb = static_cast<unsigned>(pos + na) + lanes_below(mb);
+  // counted in every lane: an empty asm keeps the compiler from moving the counts into
+  // exec-masked branches of their own (selects are cheaper than the branching)
+  asm volatile("" : "+v"(ra), "+v"(rb));
+  oa = fa ? ra * 16u : kNoLoad;
+  ob = fb ? rb * 16u : kNoLoad;
   pos += na + __builtin_popcountll(mb);
   return (ma | mb) != 0ull;
 }
@@ -756,7 +761,7 @@ __device__ __forceinline__ void store_compute(CapAcc& A, const StoreStep& R, int
 struct StoreIter {
   __amdgpu_buffer_rsrc_t tile;   // over the tile's block
   convreal::CapPair Pn;        // record kk, loaded one pair ahead of its use
-  long long kk, k1;
+  int kk, k1;                  // ring pair indices (below 2^31: at most (4 N)^2 ring pairs)
   int pos;                     // next step's first group, from the tile's block
   int q;
   StorePair S;
@@ -895,8 +900,8 @@ __device__ __forceinline__ void cap_rows_store(const convreal::MixedDesc* __rest
   } else {
     StoreIter it;
     it.tile = tile;
-    it.kk = k0;
-    it.k1 = k1;
+    it.kk = static_cast<int>(k0);
+    it.k1 = static_cast<int>(k1);
     it.pos = 0;
     it.q = 0;
     it.S.nk = 0;
