@@ -218,7 +218,7 @@ int conv_real_set_weight_store(conv_real_plan* plan, int mode);
 int conv_real_get_weight_store(const conv_real_plan* plan, int* active, long long* bytes);
 
 /*
- * Method of an FP64 plan (CONV_REAL_F64). The paper's real-space convolver costs time linear in
+ * Method of an FP64 or mixed plan. The paper's real-space convolver costs time linear in
  * theta_cut (Eq. 7; Results section), which a per-pair sum (quadratic) cannot match at the wide cuts
  * its optimal splits choose (Table 1). For two rings of the equatorial belt (4 Nside pixels each)
  * the pair sum is a circular convolution along the ring, so it can run in Fourier space:
@@ -232,8 +232,16 @@ int conv_real_get_weight_store(const conv_real_plan* plan, int* active, long lon
  *                              matrix cores). Same pairs and kernel values as DIRECT; results differ
  *                              by FP64 rounding only. Requires a power-of-two nside <= 2048 (EINVAL
  *                              otherwise) and a device that can hold the spectra (ENOMEM).
+ *                              Mixed plans (FP32 maps): the belt ring pairs the same way (FP64
+ *                              spectra and transforms), the cap-touching ring pairs on the plan's
+ *                              split-FP16 cap tiles (weight store or on the fly) added to the belt
+ *                              rings; within the mixed path's bound of the direct method (the belt
+ *                              part is FP64 instead of split FP16). EINVAL for a mixed plan whose
+ *                              belt windows cover whole rings or whose table has over 4098 nodes.
  * Synchronous and allocating (not while an apply on the plan may run); conv_real_apply then uses the
- * method, one map at a time for the belt part. FP64 plans only (EINVAL otherwise).
+ * method, one map at a time for the belt part. FP64 and mixed plans (EINVAL for F32 plans). A plan
+ * on the ring-FFT method takes no part in batches (conv_real_batch_create: EINVAL) and in
+ * conv_real_apply_noalloc (EINVAL).
  */
 #define CONV_REAL_METHOD_DIRECT   0
 #define CONV_REAL_METHOD_RING_FFT 1

@@ -190,7 +190,8 @@ class Plan:
         return bool(a.value), int(b.value)
 
     def set_method(self, method: str):
-        """"direct" or "ring_fft" (FP64 plans): pair sums, or belt ring pairs through ring FFTs."""
+        """"direct" or "ring_fft" (FP64 and mixed plans): pair sums, or belt ring pairs through ring
+        FFTs (the cap-touching pairs stay on the plan's own cap path)."""
         _check(lib.conv_real_set_method(self._h, _METHODS.get(method, -1)), "conv_real_set_method")
 
     def method(self) -> str:

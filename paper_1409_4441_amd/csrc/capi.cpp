@@ -166,9 +166,11 @@ struct QueueItem {
 };
 
 // The plan's belt items (band-major) and cap items (ring-major, 4 tiles each) with their costs.
+// with_belt = false: cap items only (a mixed plan on the ring-FFT method, whose belt ring pairs go
+// through the ring FFTs).
 void plan_items(const conv_real_plan* p, const convreal::Tuning& t, std::vector<QueueItem>& belt,
-                std::vector<QueueItem>& cap) {
-  if (p->belt_enabled) {
+                std::vector<QueueItem>& cap, bool with_belt = true) {
+  if (p->belt_enabled && with_belt) {
     const int nsegs = (4 * p->nside + t.seg - 1) / t.seg;
     for (int b = 0; b < p->belt_nbands; ++b)
       for (int s = 0; s < nsegs; ++s) belt.push_back({p->cost_belt[b] * (t.seg / 64), 0, b * nsegs + s});
@@ -289,7 +291,7 @@ void release(conv_real_plan* p, void* ptr) {
 
 hipError_t build_items(conv_real_plan* p) {
   std::vector<QueueItem> belt, cap, q;
-  plan_items(p, p->tune, belt, cap);
+  plan_items(p, p->tune, belt, cap, p->method == CONV_REAL_METHOD_DIRECT);
   const std::vector<int> off = order_queue(belt, cap, p->tune.order, [](const QueueItem& e) { return e.cost; },
                                            [](const QueueItem& e) { return e.kind; }, q);
   std::vector<int2> items(q.size());
@@ -899,9 +901,11 @@ void release_ring_fft(conv_real_plan* p) {
   p->fft_npairs = 0;
 }
 
-// Ring-FFT set-up of an FP64 plan: the belt ring pairs (output ring major), the list of the other
-// ring pairs for the per-pair kernel, twiddles, workspace, and the spectra of the belt pairs' kernels.
+// Ring-FFT set-up: the belt ring pairs (output ring major), twiddles, workspace, and the spectra of
+// the belt pairs' kernels; for an FP64 plan also the list of the other ring pairs and their records
+// for the FP64 cap kernel (a mixed plan keeps its own cap tiles for them).
 hipError_t build_ring_fft(conv_real_plan* p) {
+  const bool f64 = p->precision == CONV_REAL_F64;
   const int N = p->nside;
   const convreal::RingGrid g = convreal::make_ring_grid(N);
   std::vector<int> jlo, jhi;
@@ -944,7 +948,7 @@ hipError_t build_ring_fft(conv_real_plan* p) {
   std::vector<long long> roff(g.nrings + 1, 0), ridx;
   std::vector<convreal::CapPair64> rrec;   // the listed pairs as the FP64 cap kernel reads them
   std::vector<int> rtile_ring, rtile_a0;
-  for (int r = 0; r < g.nrings; ++r) {
+  for (int r = 0; r < g.nrings && f64; ++r) {
     const bool belt_row = r >= blo && r <= bhi;
     for (long long k = poff[r]; k < poff[r + 1]; ++k) {
       const int j = jlo[r] + static_cast<int>(k - poff[r]);
@@ -971,7 +975,7 @@ hipError_t build_ring_fft(conv_real_plan* p) {
   }
   // the cap-touching pairs by symmetry: fundamental domains of the north-half rings that have them
   std::vector<int> mtile_ring, mtile_a0;
-  for (int r = 0; r <= (g.nrings - 1) / 2; ++r) {
+  for (int r = 0; r <= (g.nrings - 1) / 2 && f64; ++r) {
     if (roff[r + 1] == roff[r]) continue;
     const int F = (g.n[r] / 4 - g.c[r]) / 2 + 1;
     for (int a0 = 0; a0 < F; a0 += 16) {
@@ -993,30 +997,35 @@ hipError_t build_ring_fft(conv_real_plan* p) {
   p->fft_n = n;
   p->fft_logn = logn;
   p->fft_npairs = static_cast<long long>(fi.size());
-  release(p, p->d_rest_off);
-  release(p, p->d_rest_idx);
-  release(p, p->d_rtile_ring);
-  release(p, p->d_rtile_a0);
-  p->n_rtiles = static_cast<int>(rtile_ring.size());
-  p->n_mtiles = static_cast<int>(mtile_ring.size());
-  if ((e = dev_upload(p, &p->d_rest_off, roff)) != hipSuccess ||
-      (e = dev_upload(p, &p->d_rest_idx, ridx)) != hipSuccess ||
-      (e = dev_upload(p, &p->d_fft_cpair, rrec)) != hipSuccess ||
-      (e = dev_upload(p, &p->d_rtile_ring, rtile_ring)) != hipSuccess ||
-      (e = dev_upload(p, &p->d_rtile_a0, rtile_a0)) != hipSuccess ||
-      (e = dev_upload(p, &p->d_mtile_ring, mtile_ring)) != hipSuccess ||
-      (e = dev_upload(p, &p->d_mtile_a0, mtile_a0)) != hipSuccess ||
-      (e = dev_upload(p, &p->d_fft_tw, tw)) != hipSuccess || (e = dev_upload(p, &p->d_fft_pi, fi)) != hipSuccess ||
+  if (f64) {
+    release(p, p->d_rest_off);
+    release(p, p->d_rest_idx);
+    release(p, p->d_rtile_ring);
+    release(p, p->d_rtile_a0);
+    p->n_rtiles = static_cast<int>(rtile_ring.size());
+    p->n_mtiles = static_cast<int>(mtile_ring.size());
+    if ((e = dev_upload(p, &p->d_rest_off, roff)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_rest_idx, ridx)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_fft_cpair, rrec)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_rtile_ring, rtile_ring)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_rtile_a0, rtile_a0)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_mtile_ring, mtile_ring)) != hipSuccess ||
+        (e = dev_upload(p, &p->d_mtile_a0, mtile_a0)) != hipSuccess)
+      return e;
+  }
+  if ((e = dev_upload(p, &p->d_fft_tw, tw)) != hipSuccess || (e = dev_upload(p, &p->d_fft_pi, fi)) != hipSuccess ||
       (e = dev_upload(p, &p->d_fft_pj, fj)) != hipSuccess || (e = dev_upload(p, &p->d_fft_pA, fA)) != hipSuccess ||
       (e = dev_upload(p, &p->d_fft_pB, fB)) != hipSuccess || (e = dev_upload(p, &p->d_fft_boff, boff)) != hipSuccess ||
       (e = dev_alloc(p, &p->d_fft_K, nbins * fi.size())) != hipSuccess ||
       (e = dev_alloc(p, &p->d_fft_X, nbins * static_cast<size_t>(bhi - blo + 1))) != hipSuccess ||
       (e = dev_alloc(p, &p->d_fft_Y, nbins * static_cast<size_t>(bhi - blo + 1))) != hipSuccess ||
-      (e = convreal::ring_fft_spectra(p)) != hipSuccess ||
-      (e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
-      (e = convreal::launch_pair_count(p, true, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess)
+      (e = convreal::ring_fft_spectra(p)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess)
     return e;
   p->fft_work_bytes = static_cast<long long>(2 * sizeof(double2) * nbins * static_cast<size_t>(bhi - blo + 1));
+  if (!f64) return hipSuccess;   // the mixed plan counted its cap-touching pairs at set-up
+  if ((e = hipMemset(p->d_count, 0, sizeof(unsigned long long))) != hipSuccess ||
+      (e = convreal::launch_pair_count(p, true, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess)
+    return e;
   unsigned long long cnt = 0;
   if ((e = hipMemcpy(&cnt, p->d_count, sizeof(cnt), hipMemcpyDeviceToHost)) != hipSuccess) return e;
   p->pairs_rest = static_cast<long long>(cnt);
@@ -1027,8 +1036,8 @@ hipError_t build_ring_fft(conv_real_plan* p) {
 
 int conv_real_set_method(conv_real_plan* plan, int method) {
   if (!plan || plan->magic != kMagic) { set_error("conv_real_set_method: invalid plan"); return CONV_REAL_EINVAL; }
-  if (plan->precision != CONV_REAL_F64) {
-    set_error("conv_real_set_method: FP64 plans only");
+  if (plan->precision == CONV_REAL_F32) {
+    set_error("conv_real_set_method: FP64 and mixed plans only");
     return CONV_REAL_EINVAL;
   }
   if (method != CONV_REAL_METHOD_DIRECT && method != CONV_REAL_METHOD_RING_FFT) {
@@ -1040,6 +1049,12 @@ int conv_real_set_method(conv_real_plan* plan, int method) {
     set_error("conv_real_set_method: the ring FFTs need a power-of-two nside <= 2048");
     return CONV_REAL_EINVAL;
   }
+  const bool mixed = plan->precision == CONV_REAL_MIXED;
+  if (mixed && method == CONV_REAL_METHOD_RING_FFT && (!plan->belt_enabled || !plan->cap_mode)) {
+    set_error("conv_real_set_method: this mixed plan has no belt ring pairs on the matrix cores (windows that "
+              "cover whole belt rings) or no cap tiles (kernel table over 4098 nodes)");
+    return CONV_REAL_EINVAL;
+  }
   DeviceGuard guard;
   hipError_t e = guard.enter(plan->device);
   if (e != hipSuccess) return hip_fail(e, "conv_real_set_method: hipSetDevice");
@@ -1047,6 +1062,8 @@ int conv_real_set_method(conv_real_plan* plan, int method) {
   if (method == CONV_REAL_METHOD_DIRECT) {
     release_ring_fft(plan);
     plan->method = method;
+    // a mixed plan's queue takes its belt items back
+    if (mixed && (e = build_items(plan)) != hipSuccess) return hip_fail(e, "conv_real_set_method: work queue");
     return CONV_REAL_OK;
   }
   if (!plan->d_fft_K && (e = build_ring_fft(plan)) != hipSuccess) {
@@ -1055,6 +1072,13 @@ int conv_real_set_method(conv_real_plan* plan, int method) {
     return hip_fail(e, "conv_real_set_method: ring-FFT set-up");
   }
   plan->method = method;
+  // a mixed plan's queue keeps only the cap items: the ring FFTs do the belt ring pairs
+  if (mixed && (e = build_items(plan)) != hipSuccess) {
+    release_ring_fft(plan);
+    plan->method = CONV_REAL_METHOD_DIRECT;
+    (void)build_items(plan);
+    return hip_fail(e, "conv_real_set_method: work queue");
+  }
   return CONV_REAL_OK;
 }
 
@@ -1094,7 +1118,7 @@ int conv_real_apply_noalloc(conv_real_plan* plan, const void* maps_in, void* map
   if (!plan || plan->magic != kMagic) { set_error("conv_real_apply_noalloc: invalid plan"); return CONV_REAL_EINVAL; }
   if (!maps_in || !maps_out) { set_error("conv_real_apply_noalloc: NULL map pointer"); return CONV_REAL_EINVAL; }
   if (nmaps < 1) { set_error("conv_real_apply_noalloc: nmaps must be >= 1"); return CONV_REAL_EINVAL; }
-  if (plan->precision != CONV_REAL_MIXED && plan->method == CONV_REAL_METHOD_RING_FFT) {
+  if (plan->method == CONV_REAL_METHOD_RING_FFT) {
     set_error("conv_real_apply_noalloc: the ring-FFT method needs " + std::to_string(plan->fft_work_bytes) +
               " bytes of spectrum workspace, beyond the " +
               std::to_string(sizeof(unsigned) * convreal::kNoallocScratchWords) +
@@ -1365,6 +1389,10 @@ int conv_real_batch_create(conv_real_batch** batch, conv_real_plan* const* plans
     const conv_real_plan* p = plans[k];
     if (!p || p->magic != kMagic || p->precision != CONV_REAL_MIXED || !p->cap_mode || p->device != plans[0]->device) {
       set_error("conv_real_batch_create: every plan must be a mixed plan on one device with n_tab <= 4098");
+      return CONV_REAL_EINVAL;
+    }
+    if (p->method != CONV_REAL_METHOD_DIRECT) {
+      set_error("conv_real_batch_create: a batch applies the direct method; set it on every plan first");
       return CONV_REAL_EINVAL;
     }
   }

@@ -332,13 +332,16 @@ hipError_t launch_cap_mfma64(const conv_real_plan* p, const double* x, double* y
 // ring-FFT method: spectra of the belt pairs' kernels (set-up), and an apply of FP64 maps
 hipError_t ring_fft_spectra(const conv_real_plan* p);
 hipError_t launch_ring_fft(const conv_real_plan* p, const void* x, void* y, int nmaps, hipStream_t st);
+// the belt ring pairs of one FP32 map through the ring FFTs (a mixed plan on the ring-FFT method):
+// writes the belt rings of y
+hipError_t ring_fft_belt_f32(const conv_real_plan* p, const float* x, float* y, hipStream_t st);
 hipError_t build_belt_weights(conv_real_plan* p);
 size_t belt_stage_bytes(int seg);
 hipError_t set_lds_limits(int nseg);
 hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, int nslots, const int2* items,
                               int n_items, int nrep, const int* chunk_off, int n_chunks, unsigned* amax,
                               unsigned* counter, const Tuning& tune, int max_nseg, long long npix_max,
-                              long long pairs, bool fly, hipStream_t st);
+                              long long pairs, bool fly, hipStream_t st, bool zero_rows = true);
 hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st);
 // the same apply with its per-launch scratch (max |x| per map slot, then the work-queue counters)
 // at `amax` (kMaxSlots words) and `counter` (kMaxChunks words) instead of the plan's own

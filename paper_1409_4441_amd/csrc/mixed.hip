@@ -96,9 +96,9 @@ __global__ void zero_state_kernel(unsigned* amax, int n, unsigned* counter, int 
 }
 
 // per slot: |x| maximum (atomicMax on the bit pattern: non-negative floats order like their bits),
-// and zero of the rows that will receive two atomic adds. 16-byte loads where the map is 16-byte
-// aligned (N_pix = 12 N^2 is a multiple of 4), a plain loop otherwise.
-__global__ __launch_bounds__(256) void prep_kernel(convreal::Slots S, unsigned* __restrict__ amax) {
+// and (zero_rows) zero of the rows that will receive two atomic adds. 16-byte loads where the map is
+// 16-byte aligned (N_pix = 12 N^2 is a multiple of 4), a plain loop otherwise.
+__global__ __launch_bounds__(256) void prep_kernel(convreal::Slots S, unsigned* __restrict__ amax, int zero_rows) {
   const int slot = blockIdx.y;
   const convreal::MixedDesc* d = S.desc[slot];
   const long long npix = d->npix;
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void prep_kernel(convreal::Slots S, unsigned* 
     for (int k = 1; k < 256 / 64; ++k) m = fmaxf(m, wmax[k]);
     atomicMax(amax + slot, __float_as_uint(m));
   }
-  for (int z = 0; z < 2; ++z) {
+  for (int z = 0; z < 2 && zero_rows; ++z) {
     const long long z0 = d->zero_lo[z], z1 = d->zero_hi[z];
     for (long long i = z0 + t0; i < z1; i += stride) y[i] = 0.0f;
   }
@@ -1277,14 +1277,14 @@ hipError_t build_belt_weights(conv_real_plan* p) {
 hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, int nslots, const int2* items,
                               int n_items, int nrep, const int* chunk_off, int n_chunks, unsigned* amax,
                               unsigned* counter, const Tuning& tune, int max_nseg, long long npix_max,
-                              long long pairs, bool fly, hipStream_t st) {
+                              long long pairs, bool fly, hipStream_t st, bool zero_rows) {
   if (n_chunks < 1 || n_chunks > kMaxChunks) return hipErrorInvalidValue;
   hipLaunchKernelGGL(zero_state_kernel, dim3(1), dim3(kMaxSlots), 0, st, amax, nslots, counter, n_chunks);
   mark(mark_plan, st, "zero_state_kernel", 0);
   // at least 8 float4 per thread, at most 1024 workgroups (and atomics) per map
   const long long want = (npix_max / 4 + 2047) / 2048;
   const unsigned gx = static_cast<unsigned>(want < 1 ? 1 : (want < 1024 ? want : 1024));
-  hipLaunchKernelGGL(prep_kernel, dim3(gx, nslots), dim3(256), 0, st, S, amax);
+  hipLaunchKernelGGL(prep_kernel, dim3(gx, nslots), dim3(256), 0, st, S, amax, zero_rows ? 1 : 0);
   mark(mark_plan, st, "prep_kernel", 0);
   if (n_items > 0 && nrep > 0) {
     const size_t coef_off = (belt_stage_bytes(tune.seg) + 15) / 16 * 16;
@@ -1361,8 +1361,17 @@ hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int n
 
 hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int nmaps, hipStream_t st,
                         unsigned* amax, unsigned* counter) {
+  // ring-FFT method: the belt rings of each map are written by the ring FFTs first; the queue then
+  // holds the cap items only, and rows with cap contributions add to what the FFTs wrote (so the
+  // prep pass zeroes nothing)
+  const bool fft = p->method == CONV_REAL_METHOD_RING_FFT;
   for (int m0 = 0; m0 < nmaps; m0 += kMaxSlots) {
     const int nm = nmaps - m0 < kMaxSlots ? nmaps - m0 : kMaxSlots;
+    for (int k = 0; k < nm && fft; ++k) {
+      const size_t off = static_cast<size_t>(m0 + k) * p->npix;
+      const hipError_t e = ring_fft_belt_f32(p, x + off, y + off, st);
+      if (e != hipSuccess) return e;
+    }
     Slots S;
     for (int k = 0; k < nm; ++k) {
       S.desc[k] = p->d_desc;
@@ -1370,8 +1379,8 @@ hipError_t launch_mixed(const conv_real_plan* p, const float* x, float* y, int n
       S.y[k] = y + static_cast<size_t>(m0 + k) * p->npix;
     }
     hipError_t e = launch_mixed_queue(p, S, nm, p->d_items, p->n_items, nm, p->d_qchunk_off, p->n_qchunks, amax,
-                                      counter, p->tune, p->cap_nseg, p->npix, p->pairs * nm,
-                                      p->cap_mode && !p->d_wstore, st);
+                                      counter, p->tune, p->cap_nseg, p->npix,
+                                      (fft ? p->pairs_rest : p->pairs) * nm, p->cap_mode && !p->d_wstore, st, !fft);
     if (e != hipSuccess) return e;
     if (!p->cap_mode) {
       // table too large for the LDS coefficient form: cap-touching pairs per pair in FP64, added to

@@ -333,6 +333,10 @@ hipError_t ring_fft_apply_one(const conv_real_plan* p, const T* x, T* y, hipStre
   return hipSuccess;
 }
 
+hipError_t ring_fft_belt_f32(const conv_real_plan* p, const float* x, float* y, hipStream_t st) {
+  return ring_fft_apply_one(p, x, y, st);
+}
+
 // Belt ring pairs of every map through the ring FFTs (one map at a time: the spectra of x are a
 // per-plan workspace), then the cap-touching pairs over the symmetry group's fundamental domain,
 // added to the belt rings.

@@ -3,7 +3,8 @@ spectra, cap-touching pairs per pair. Same pairs and kernel values as the per-pa
 result meets the oracle at the FP64 bound (rel rms <= 1e-12, max error <= 1e-12 max |y|) on grids
 where every ring is a belt ring (Nside 1), where windows cover whole rings and every pair is kept
 (theta_cut = pi), and at cuts below the pixel spacing; it equals the direct method to rounding at a
-larger grid; switching methods keeps results; only FP64 plans of power-of-two Nside <= 2048 take it."""
+larger grid; switching methods keeps results; only FP64 and mixed plans of power-of-two Nside <= 2048
+take it (mixed plans: tests/test_gpu_ringfft_mixed.py)."""
 import math
 
 import numpy as np
@@ -106,9 +107,6 @@ def test_ring_fft_ring_groups(cuda_device, nside):
 def test_ring_fft_only_where_defined(cuda_device):
     T = _table(3 * DEG, 9 * DEG)
     with cr.Plan(8, T, 9 * DEG, "f32") as plan:
-        with pytest.raises(cr.ConvRealError):
-            plan.set_method("ring_fft")
-    with cr.Plan(8, T, 9 * DEG, "mixed") as plan:
         with pytest.raises(cr.ConvRealError):
             plan.set_method("ring_fft")
     with cr.Plan(6, T, 9 * DEG, "f64") as plan:       # 24-pixel belt rings: not a power of two
