@@ -205,8 +205,9 @@ int conv_real_get_tuning(const conv_real_plan* plan, conv_real_tuning* t);
  *   CONV_REAL_STORE_AUTO  build it if it needs at most 64 GiB and 40% of the free device memory
  * A new mixed plan takes CONV_REAL_STORE_AUTO. Unless the plan's launch configuration was set by
  * conv_real_set_tuning or conv_real_autotune, changing the store also picks its default: seg 256,
- * 3 workgroups per compute unit and order 3 with a store (the kernel is then built for three waves
- * per SIMD), seg 256, 2 workgroups and order 0 without.
+ * 3 workgroups per compute unit and order 3 with or without a store (the kernel is then built for
+ * three waves per SIMD; without a store the cap items' coefficient table shares the LDS of the belt
+ * stage).
  * conv_real_set_weight_store is synchronous (not while an apply on the plan may still run) and
  * allocates; applies never allocate. conv_real_get_weight_store reports whether a store is held
  * and its size in bytes. Mixed plans only (EINVAL otherwise).

@@ -668,12 +668,15 @@ int set_weight_store(conv_real_plan* p, int mode) {
   // table in LDS, so three workgroups with 256-pixel belt items fit a compute unit (and the kernel
   // is built for three waves per SIMD), one of them starting on belt items and two on cap items so
   // that every CU runs both kinds (at Nside 2048 7% faster than alternating the kinds in one queue,
-  // 14% faster than by cost alone); without a store the table leaves room for two workgroups, and
-  // the order makes no difference.
+  // 14% faster than by cost alone). Without a store the cap items need the coefficient table in
+  // LDS; with three workgroups per CU it shares the belt stage's LDS (a workgroup reads it again after
+  // a belt item), which keeps three workgroups per CU for tables up to 3413 segments and two up to
+  // 4096 (after the stage, the table leaves room for two up to 2416 segments and one beyond): at
+  // Nside 2048 with a 4096-node table, 30' 4.3 ms against 7.5 ms, 240' 109 ms against 171 ms.
   if (!p->tune_user) {
     p->tune.seg = 256;
-    p->tune.wg_per_cu = p->d_wstore ? 3 : 2;
-    p->tune.order = p->d_wstore ? 3 : 0;
+    p->tune.wg_per_cu = 3;
+    p->tune.order = 3;
   }
   if ((e = hipMemcpy(p->d_desc, &p->h_desc, sizeof(p->h_desc), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = build_items(p)) != hipSuccess)

@@ -164,8 +164,8 @@ struct Slots {
 // Launch configuration of the persistent kernel (see conv_real_tuning).
 struct Tuning {
   int seg = 256;       // belt output pixels per work item: 256 or 512
-  int wg_per_cu = 2;   // resident workgroups per compute unit
-  int order = 0;       // 0: all items by decreasing cost; 1: belt and cap items alternating;
+  int wg_per_cu = 3;   // resident workgroups per compute unit
+  int order = 3;       // 0: all items by decreasing cost; 1: belt and cap items alternating;
                        // 2: one chunk per XCD of neighbouring rings, each by decreasing cost;
                        // 3: roles (a belt chunk, two cap chunks); 4: roles with the cap items in one
                        // chunk of neighbouring rings per XCD
@@ -337,6 +337,7 @@ hipError_t launch_ring_fft(const conv_real_plan* p, const void* x, void* y, int 
 hipError_t ring_fft_belt_f32(const conv_real_plan* p, const float* x, float* y, hipStream_t st);
 hipError_t build_belt_weights(conv_real_plan* p);
 size_t belt_stage_bytes(int seg);
+size_t shared_lds_bytes(int nseg);
 hipError_t set_lds_limits(int nseg);
 hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, int nslots, const int2* items,
                               int n_items, int nrep, const int* chunk_off, int n_chunks, unsigned* amax,

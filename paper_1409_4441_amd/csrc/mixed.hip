@@ -1212,6 +1212,8 @@ __global__ __launch_bounds__(kBlock, WAVES) void mixed_persistent_kernel(convrea
     if (kind == 0) {
       // three rings in flight, two where the registers are sized for three waves per SIMD
       belt_item<SEG, (WAVES >= 3 ? 2 : 3)>(d, idx, S.x[slot], S.y[slot], sx, stage);
+      // a coefficient table inside the belt stage is gone (read again by the next cap item)
+      if (FLY && coef_offset_bytes == 0 && threadIdx.x == 0) s_coef_owner = nullptr;
     } else {
       if (FLY && owner != d) {
         const float4* coef = reinterpret_cast<const float4*>(ldu(d->coef));
@@ -1246,6 +1248,13 @@ size_t belt_stage_bytes(int seg) {
 size_t persistent_lds_bytes(int seg, int nseg) {
   const size_t coef_off = (belt_stage_bytes(seg) + 15) / 16 * 16;
   return coef_off + sizeof(float4) * static_cast<size_t>(nseg > 0 ? nseg : 1);
+}
+
+// Dynamic LDS with the coefficient table inside the 256-pixel belt stage (read again after every
+// belt item): the larger of the two.
+size_t shared_lds_bytes(int nseg) {
+  const size_t stage = belt_stage_bytes(256), coef = sizeof(float4) * static_cast<size_t>(nseg > 0 ? nseg : 1);
+  return stage > coef ? stage : coef;
 }
 
 hipError_t build_belt_weights(conv_real_plan* p) {
@@ -1287,9 +1296,11 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
   hipLaunchKernelGGL(prep_kernel, dim3(gx, nslots), dim3(256), 0, st, S, amax, zero_rows ? 1 : 0);
   mark(mark_plan, st, "prep_kernel", 0);
   if (n_items > 0 && nrep > 0) {
-    const size_t coef_off = (belt_stage_bytes(tune.seg) + 15) / 16 * 16;
-    // the coefficient table is only read when some slot evaluates cap weights on the fly
-    const size_t lds = persistent_lds_bytes(tune.seg, fly ? max_nseg : 0);
+    // the coefficient table is only read when some slot evaluates cap weights on the fly; three
+    // workgroups per CU fit when it shares the belt stage's LDS (a workgroup uses one at a time)
+    const bool fly3 = fly && tune.seg == 256 && tune.wg_per_cu >= 3;
+    const size_t coef_off = fly3 ? 0 : (belt_stage_bytes(tune.seg) + 15) / 16 * 16;
+    const size_t lds = fly3 ? shared_lds_bytes(max_nseg) : persistent_lds_bytes(tune.seg, fly ? max_nseg : 0);
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     long long total = static_cast<long long>(n_items) * nrep;
@@ -1305,6 +1316,8 @@ hipError_t launch_mixed_queue(const conv_real_plan* mark_plan, const Slots& S, i
       hipLaunchKernelGGL((mixed_persistent_kernel<512, true, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);
     else if (tune.seg == 512)
       hipLaunchKernelGGL((mixed_persistent_kernel<512, false, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);
+    else if (fly3)
+      hipLaunchKernelGGL((mixed_persistent_kernel<256, true, 3>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);
     else if (fly)
       hipLaunchKernelGGL((mixed_persistent_kernel<256, true, 2>), g, blk, lds, st, S, items, n_items, nrep, chunk_off, n_chunks, home_div, amax, counter, co);
     else if (tune.wg_per_cu >= 3)
@@ -1329,6 +1342,7 @@ hipError_t set_lds_limits(int nseg) {
   if (need > static_cast<size_t>(optin)) return hipErrorInvalidValue;
   const int bytes = static_cast<int>(need);
   const void* fns[] = {reinterpret_cast<const void*>(&mixed_persistent_kernel<256, true, 2>),
+                       reinterpret_cast<const void*>(&mixed_persistent_kernel<256, true, 3>),
                        reinterpret_cast<const void*>(&mixed_persistent_kernel<256, false, 2>),
                        reinterpret_cast<const void*>(&mixed_persistent_kernel<256, false, 3>),
                        reinterpret_cast<const void*>(&mixed_persistent_kernel<512, true, 2>),
