@@ -37,6 +37,7 @@
 #include <cmath>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/convsht.h"
@@ -48,7 +49,10 @@ namespace {
 
 constexpr int kLegThreads = 512;   // Legendre kernels: 8 waves
 constexpr int kFlush = 8;          // l values between reductions (analysis) and rescale checks
+constexpr int kLegChunk = kLegThreads;   // values of l whose coefficients (and alm) are staged in LDS at a time
+static_assert(kLegChunk % 8 == 0, "groups of kFlush values of l never straddle a chunk");
 constexpr int kDftThreads = 256;   // ring sum kernels: 4 waves, one per residue class mod 4
+constexpr int kDftChains = 4;      // frequencies per lane at a time in the analysis ring sums
 constexpr int kFftThreads = 512;   // belt ring FFT kernels
 constexpr double kInvScale = 0x1p-600;
 constexpr double kRescaleAbove = 0x1p400;
@@ -76,15 +80,6 @@ struct LegArgs {
   int nnorth;              // rings 0 .. nnorth - 1 are the north half, the last one the equator
   double omega;
 };
-
-// wave-uniform load of a complex value (scalar load; plan tables and alm are read-only here)
-struct Pair64 {
-  double x, y;
-};
-__device__ __forceinline__ double2 ldu2(const double2& ref) {
-  const Pair64 v = convreal::ldu_record(reinterpret_cast<const Pair64&>(ref));
-  return double2{v.x, v.y};
-}
 
 __device__ __forceinline__ long long alm_base(int L, int m) {
   return static_cast<long long>(m) * (2 * L + 3 - m) / 2;
@@ -116,34 +111,52 @@ __global__ __launch_bounds__(kDftThreads) void sht_ring_dft_kernel(const T* __re
   const int nk = n < L + 1 ? n : L + 1;
   const int kappa = threadIdx.x >> 6;          // the wave's residue class j mod 4
   const int lane = threadIdx.x & 63;
-  for (int jq = lane; 4 * jq + kappa < nk; jq += 64) {
-    const int j = 4 * jq + kappa;
-    double zs, zc;
-    sincospi(-2.0 * static_cast<double>(j) / static_cast<double>(n), &zs, &zc);
-    double ar = 0.0, ai = 0.0;
+  // kDftChains frequencies per lane at a time (j = 4 jq + kappa, jq = jq0 + 64 t): independent Horner
+  // chains that share each folded value, so that their latencies overlap
+  for (int jq0 = lane; 4 * jq0 + kappa < nk; jq0 += 64 * kDftChains) {
+    double zs[kDftChains], zc[kDftChains], ar[kDftChains], ai[kDftChains];
+#pragma unroll
+    for (int t = 0; t < kDftChains; ++t) {
+      const int j = 4 * (jq0 + 64 * t) + kappa;
+      sincospi(-2.0 * static_cast<double>(j < nk ? j : 4 * jq0 + kappa) / static_cast<double>(n), &zs[t], &zc[t]);
+      ar[t] = 0.0;
+      ai[t] = 0.0;
+    }
     if (kappa == 0 || kappa == 2) {
       const double* cs = kappa == 0 ? s0 : s2;
       for (int a = k - 1; a >= 0; --a) {
-        const double nr = fma(ar, zc, fma(-ai, zs, cs[a]));
-        ai = fma(ar, zs, ai * zc);
-        ar = nr;
+        const double c = cs[a];
+#pragma unroll
+        for (int t = 0; t < kDftChains; ++t) {
+          const double nr = fma(ar[t], zc[t], fma(-ai[t], zs[t], c));
+          ai[t] = fma(ar[t], zs[t], ai[t] * zc[t]);
+          ar[t] = nr;
+        }
       }
     } else {
       // kappa 1: (x0 - x2) - i (x1 - x3); kappa 3: (x0 - x2) + i (x1 - x3)
       const double sg = kappa == 1 ? -1.0 : 1.0;
       for (int a = k - 1; a >= 0; --a) {
         const double2 c = de[a];
-        const double nr = fma(ar, zc, fma(-ai, zs, c.x));
-        ai = fma(ar, zs, fma(ai, zc, sg * c.y));
-        ar = nr;
+#pragma unroll
+        for (int t = 0; t < kDftChains; ++t) {
+          const double nr = fma(ar[t], zc[t], fma(-ai[t], zs[t], c.x));
+          ai[t] = fma(ar[t], zs[t], fma(ai[t], zc[t], sg * c.y));
+          ar[t] = nr;
+        }
       }
     }
     // G_m = e^{-i m pi c / n} X[j] for every m = j mod n up to L
-    for (int m = j; m <= L; m += n) {
-      const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
-      double ps, pc;
-      sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
-      G[static_cast<size_t>(m) * nrings + r] = double2{ar * pc - ai * ps, ar * ps + ai * pc};
+#pragma unroll
+    for (int t = 0; t < kDftChains; ++t) {
+      const int j = 4 * (jq0 + 64 * t) + kappa;
+      if (j >= nk) continue;
+      for (int m = j; m <= L; m += n) {
+        const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
+        double ps, pc;
+        sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+        G[static_cast<size_t>(m) * nrings + r] = double2{ar[t] * pc - ai[t] * ps, ar[t] * ps + ai[t] * pc};
+      }
     }
   }
 }
@@ -180,23 +193,27 @@ __global__ __launch_bounds__(kDftThreads) void sht_ring_idft_kernel(const double
   for (int ap = threadIdx.x; ap < k; ap += blockDim.x) {
     double zs, zc;
     sincospi(2.0 * static_cast<double>(ap) / static_cast<double>(k), &zs, &zc);
+    // the four residue classes' Horner sums in one loop (independent chains); a class with fewer
+    // than nq terms reads zeros first (s_b is cleared up to nq per class), which leaves its chain at
+    // exactly zero until its own terms start
+    double ar[4] = {0.0, 0.0, 0.0, 0.0}, ai[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int jq = nq - 1; jq >= 0; --jq) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double2 v = s_b[c * nq + jq];
+        const double nr = fma(ar[c], zc, fma(-ai[c], zs, v.x));
+        ai[c] = fma(ar[c], zs, fma(ai[c], zc, v.y));
+        ar[c] = nr;
+      }
+    }
     double ur[4], ui[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int cnt = nk > c ? (nk - c + 3) >> 2 : 0;   // j = 4 j' + c < nk
-      const double2* b = s_b + c * nq;
-      double ar = 0.0, ai = 0.0;
-      for (int jq = cnt - 1; jq >= 0; --jq) {
-        const double2 v = b[jq];
-        const double nr = fma(ar, zc, fma(-ai, zs, v.x));
-        ai = fma(ar, zs, fma(ai, zc, v.y));
-        ar = nr;
-      }
       // times e^{2 pi i c a' / n}
       double ps, pc;
       sincospi(2.0 * static_cast<double>(c * ap) / static_cast<double>(n), &ps, &pc);
-      ur[c] = ar * pc - ai * ps;
-      ui[c] = ar * ps + ai * pc;
+      ur[c] = ar[c] * pc - ai[c] * ps;
+      ui[c] = ar[c] * ps + ai[c] * pc;
     }
     // pixel q k + a': Re sum_c i^{c q} U_c
 #pragma unroll
@@ -293,6 +310,7 @@ __device__ __forceinline__ void start_value(double logpre_m, int m, double s, do
 template <int R>
 __global__ __launch_bounds__(kLegThreads) void sht_analysis_legendre_kernel(LegArgs a, int nblk, double2* partial) {
   __shared__ double2 s_red[kFlush][kLegThreads];
+  __shared__ double2 s_ab[kLegChunk];
   const int item = blockIdx.x;
   const int m = item / nblk;
   const int blk = item - m * nblk;
@@ -323,33 +341,37 @@ __global__ __launch_bounds__(kLegThreads) void sht_analysis_legendre_kernel(LegA
   const double2* coef = a.coef + base;
   double2* out = nblk == 1 ? a.alm + base : partial + static_cast<size_t>(blk) * ((a.L + 1LL) * (a.L + 2) / 2) + base;
   const double scale = nblk == 1 ? a.omega : 1.0;
-  for (int l0 = m; l0 <= a.L; l0 += kFlush) {
+  // One group: l = l0 .. l0 + kFlush - 1 (l0 - m a multiple of kFlush), the recurrence coefficients
+  // from the chunk staged in LDS at c0 (CHECK: tests for l = m, with no recurrence step, and l > L).
+  auto group = [&](int l0, int c0, auto check_tag) {
+    constexpr bool CHECK = decltype(check_tag)::value;
 #pragma unroll
     for (int u = 0; u < kFlush; ++u) {
       const int l = l0 + u;
-      double tr = 0.0, ti = 0.0;
-      if (l <= a.L) {
-        if (l > m) {
-          const double2 ab = ldu2(coef[l - m]);
-#pragma unroll
-          for (int j = 0; j < R; ++j) {
-            const double p2 = ab.x * fma(z[j], p1[j], -ab.y * p0[j]);
-            p0[j] = p1[j];
-            p1[j] = p2;
-          }
-        }
+      if (CHECK && l > a.L) break;
+      if (!CHECK || l > m) {
+        const double2 ab = s_ab[l - c0];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          // l - m has the parity of u (l0 - m is a multiple of kFlush)
-          tr = fma(p1[j], (u & 1) ? sor[j] : ser[j], tr);
-          ti = fma(p1[j], (u & 1) ? soi[j] : sei[j], ti);
+          const double p2 = ab.x * fma(z[j], p1[j], -ab.y * p0[j]);
+          p0[j] = p1[j];
+          p1[j] = p2;
         }
       }
-      s_red[u][tid] = double2{tr, ti};
+      // two accumulators per part (rings of even and odd j), so that the sums' chains are half as long
+      double tr[2] = {0.0, 0.0}, ti[2] = {0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        // l - m has the parity of u (l0 - m is a multiple of kFlush)
+        tr[j & 1] = fma(p1[j], (u & 1) ? sor[j] : ser[j], tr[j & 1]);
+        ti[j & 1] = fma(p1[j], (u & 1) ? soi[j] : sei[j], ti[j & 1]);
+      }
+      s_red[u][tid] = double2{tr[0] + tr[1], ti[0] + ti[1]};
     }
     __syncthreads();
     {
-      // wave w adds the kLegThreads partial sums of l = l0 + w
+      // wave w adds the kLegThreads partial sums of l = l0 + w (rows past L hold stale values and are
+      // not written)
       const int w = tid >> 6, lane = tid & 63;
       double sr = 0.0, si = 0.0;
 #pragma unroll
@@ -383,6 +405,17 @@ __global__ __launch_bounds__(kLegThreads) void sht_analysis_legendre_kernel(LegA
         }
       }
     }
+  };
+  // the coefficients in chunks of kLegChunk values of l (a multiple of kFlush, so groups never
+  // straddle a chunk), loaded by all threads at once
+  for (int c0 = m; c0 <= a.L; c0 += kLegChunk) {
+    const int cn = min(kLegChunk, a.L + 1 - c0);
+    if (tid < cn) s_ab[tid] = coef[c0 - m + tid];
+    __syncthreads();
+    // every group checks its bounds: with 8 rings per thread (one ring block per order at Nside 2048,
+    // so one reduction per l) an unchecked copy of the group exceeds the register file
+    for (int l0 = c0; l0 < c0 + cn; l0 += kFlush) group(l0, c0, std::true_type{});
+    // the groups end with a barrier: the next chunk may overwrite s_ab
   }
 }
 
@@ -402,6 +435,8 @@ __global__ void sht_reduce_kernel(const double2* __restrict__ partial, int nblk,
 
 template <int R>
 __global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(LegArgs a, int nblk) {
+  __shared__ double2 s_ab[kLegChunk];
+  __shared__ double2 s_al[kLegChunk];
   const int item = blockIdx.x;
   const int m = item / nblk;
   const int blk = item - m * nblk;
@@ -423,30 +458,32 @@ __global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(Leg
   const long long base = alm_base(a.L, m);
   const double2* coef = a.coef + base;
   const double2* alm = a.alm + base;
-  for (int l0 = m; l0 <= a.L; l0 += kFlush) {
+  // one group l0 .. l0 + kFlush - 1 (as in the analysis kernel: CHECK for the groups that hold l = m
+  // or run past L), coefficients and alm from the chunk staged in LDS at c0
+  auto group = [&](int l0, int c0, auto check_tag) {
+    constexpr bool CHECK = decltype(check_tag)::value;
 #pragma unroll
     for (int u = 0; u < kFlush; ++u) {
       const int l = l0 + u;
-      if (l <= a.L) {
-        if (l > m) {
-          const double2 ab = ldu2(coef[l - m]);
-#pragma unroll
-          for (int j = 0; j < R; ++j) {
-            const double p2 = ab.x * fma(z[j], p1[j], -ab.y * p0[j]);
-            p0[j] = p1[j];
-            p1[j] = p2;
-          }
-        }
-        const double2 b = ldu2(alm[l - m]);
+      if (CHECK && l > a.L) break;
+      if (!CHECK || l > m) {
+        const double2 ab = s_ab[l - c0];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          if (u & 1) {
-            forr[j] = fma(p1[j], b.x, forr[j]);
-            foi[j] = fma(p1[j], b.y, foi[j]);
-          } else {
-            fer[j] = fma(p1[j], b.x, fer[j]);
-            fei[j] = fma(p1[j], b.y, fei[j]);
-          }
+          const double p2 = ab.x * fma(z[j], p1[j], -ab.y * p0[j]);
+          p0[j] = p1[j];
+          p1[j] = p2;
+        }
+      }
+      const double2 b = s_al[l - c0];
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (u & 1) {
+          forr[j] = fma(p1[j], b.x, forr[j]);
+          foi[j] = fma(p1[j], b.y, foi[j]);
+        } else {
+          fer[j] = fma(p1[j], b.x, fer[j]);
+          fei[j] = fma(p1[j], b.y, fei[j]);
         }
       }
     }
@@ -461,6 +498,21 @@ __global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(Leg
           e[j] -= 1;
         }
       }
+    }
+  };
+  for (int c0 = m; c0 <= a.L; c0 += kLegChunk) {
+    const int cn = min(kLegChunk, a.L + 1 - c0);
+    __syncthreads();   // the previous chunk's values are read by every thread
+    if (tid < cn) {
+      s_ab[tid] = coef[c0 - m + tid];
+      s_al[tid] = alm[c0 - m + tid];
+    }
+    __syncthreads();
+    for (int l0 = c0; l0 < c0 + cn; l0 += kFlush) {
+      if (l0 > m && l0 + kFlush - 1 <= a.L)
+        group(l0, c0, std::false_type{});
+      else
+        group(l0, c0, std::true_type{});
     }
   }
   double2* Fm = a.G + static_cast<size_t>(m) * a.nrings;
@@ -511,8 +563,10 @@ struct conv_sht_plan {
   int nnorth = 0;
   long long npix = 0;
   long long nalm = 0;
-  int R = 1;                 // north rings per thread in the Legendre kernels
-  int nblk = 1;              // ring blocks per order
+  int R = 1;                 // north rings per thread in the synthesis Legendre kernel
+  int nblk = 1;              // its ring blocks per order
+  int Ra = 1;                // the same for the analysis kernel, whose blocks each reduce over rings
+  int nblk_a = 1;
   double omega = 0.0;
   ShtRing* d_rings = nullptr;
   double2* d_coef = nullptr;
@@ -597,17 +651,17 @@ hipError_t set_lds_attributes(int nside, int L) {
 
 hipError_t launch_analysis_legendre(const conv_sht_plan* p, double2* alm, hipStream_t st) {
   LegArgs a{p->d_rings, p->d_coef, p->d_logpre, p->d_G, alm, p->L, p->nrings, p->nnorth, p->omega};
-  const dim3 g(static_cast<unsigned>((p->L + 1) * p->nblk)), b(kLegThreads);
-  switch (p->R) {
-    case 1: hipLaunchKernelGGL(sht_analysis_legendre_kernel<1>, g, b, 0, st, a, p->nblk, p->d_partial); break;
-    case 2: hipLaunchKernelGGL(sht_analysis_legendre_kernel<2>, g, b, 0, st, a, p->nblk, p->d_partial); break;
-    case 4: hipLaunchKernelGGL(sht_analysis_legendre_kernel<4>, g, b, 0, st, a, p->nblk, p->d_partial); break;
-    default: hipLaunchKernelGGL(sht_analysis_legendre_kernel<8>, g, b, 0, st, a, p->nblk, p->d_partial); break;
+  const dim3 g(static_cast<unsigned>((p->L + 1) * p->nblk_a)), b(kLegThreads);
+  switch (p->Ra) {
+    case 1: hipLaunchKernelGGL(sht_analysis_legendre_kernel<1>, g, b, 0, st, a, p->nblk_a, p->d_partial); break;
+    case 2: hipLaunchKernelGGL(sht_analysis_legendre_kernel<2>, g, b, 0, st, a, p->nblk_a, p->d_partial); break;
+    case 4: hipLaunchKernelGGL(sht_analysis_legendre_kernel<4>, g, b, 0, st, a, p->nblk_a, p->d_partial); break;
+    default: hipLaunchKernelGGL(sht_analysis_legendre_kernel<8>, g, b, 0, st, a, p->nblk_a, p->d_partial); break;
   }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || p->nblk == 1) return e;
+  if (e != hipSuccess || p->nblk_a == 1) return e;
   const unsigned gr = static_cast<unsigned>((p->nalm + 255) / 256);
-  hipLaunchKernelGGL(sht_reduce_kernel, dim3(gr), dim3(256), 0, st, p->d_partial, p->nblk, p->nalm, p->omega, alm);
+  hipLaunchKernelGGL(sht_reduce_kernel, dim3(gr), dim3(256), 0, st, p->d_partial, p->nblk_a, p->nalm, p->omega, alm);
   return hipGetLastError();
 }
 
@@ -618,8 +672,7 @@ hipError_t launch_synthesis_legendre(const conv_sht_plan* p, const double2* alm,
   switch (p->R) {
     case 1: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<1>, g, b, 0, st, a, p->nblk); break;
     case 2: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<2>, g, b, 0, st, a, p->nblk); break;
-    case 4: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<4>, g, b, 0, st, a, p->nblk); break;
-    default: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<8>, g, b, 0, st, a, p->nblk); break;
+    default: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<4>, g, b, 0, st, a, p->nblk); break;
   }
   return hipGetLastError();
 }
@@ -733,10 +786,17 @@ int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
   p->npix = 12LL * nside * nside;
   p->nalm = (static_cast<long long>(lmax) + 1) * (lmax + 2) / 2;
   p->omega = 4.0 * M_PI / static_cast<double>(p->npix);
+  // synthesis: up to 4 rings per thread (8 exceed the register file once the unrolled steps keep
+  // their values in registers), more rings in several ring blocks per order; analysis: up to 8, since
+  // every block reduces over its rings for every l (fewer blocks, fewer reductions)
   p->R = 1;
-  while (p->R < 8 && static_cast<long long>(p->R) * kLegThreads < p->nnorth) p->R *= 2;
+  while (p->R < 4 && static_cast<long long>(p->R) * kLegThreads < p->nnorth) p->R *= 2;
   p->nblk = static_cast<int>((p->nnorth + static_cast<long long>(p->R) * kLegThreads - 1) /
                              (static_cast<long long>(p->R) * kLegThreads));
+  p->Ra = 1;
+  while (p->Ra < 8 && static_cast<long long>(p->Ra) * kLegThreads < p->nnorth) p->Ra *= 2;
+  p->nblk_a = static_cast<int>((p->nnorth + static_cast<long long>(p->Ra) * kLegThreads - 1) /
+                               (static_cast<long long>(p->Ra) * kLegThreads));
 
   // rings from the grid's exact integer numerators
   const convreal::RingGrid g = convreal::make_ring_grid(nside);
@@ -785,7 +845,7 @@ int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
   if (e == hipSuccess) e = hipMemcpy(p->d_logpre, logpre.data(), logpre.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = sht_alloc(p, &p->d_G, static_cast<size_t>(lmax + 1) * p->nrings);
   if (e == hipSuccess) e = sht_alloc(p, &p->d_alm, static_cast<size_t>(p->nalm));
-  if (e == hipSuccess && p->nblk > 1) e = sht_alloc(p, &p->d_partial, static_cast<size_t>(p->nalm) * p->nblk);
+  if (e == hipSuccess && p->nblk_a > 1) e = sht_alloc(p, &p->d_partial, static_cast<size_t>(p->nalm) * p->nblk_a);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_real, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming);
