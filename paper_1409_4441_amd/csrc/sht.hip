@@ -28,7 +28,8 @@
 // its exponent is 0 (scaled values are true values times 2^(600 e) <= 2^-144: dropped). The mirror
 // ring (z -> -z) has lambda_lm(-z) = (-1)^(l+m) lambda_lm(z), so one recurrence serves a ring pair:
 // analysis sums G(north) +- G(south), synthesis splits into the even and odd l + m parts.
-// A workgroup of 512 threads takes one order m and up to 512 R north rings (R per thread); analysis
+// A workgroup of 512 threads (synthesis; 256 in the analysis) takes one order m and up to 512 R
+// (256 R) north rings (R per thread); analysis
 // reduces over rings every 8 values of l through LDS (each thread first adds its R rings), synthesis
 // needs no reduction.
 #include <hip/hip_runtime.h>
@@ -47,10 +48,12 @@
 
 namespace {
 
-constexpr int kLegThreads = 512;   // Legendre kernels: 8 waves
+constexpr int kLegThreads = 512;   // Legendre synthesis: 8 waves
+constexpr int kLegThreadsA = 256;  // Legendre analysis: 4 waves (two workgroups per CU overlap their reductions' barriers)
 constexpr int kFlush = 8;          // l values between reductions (analysis) and rescale checks
 constexpr int kLegChunk = kLegThreads;   // values of l whose coefficients (and alm) are staged in LDS at a time
 static_assert(kLegChunk % 8 == 0, "groups of kFlush values of l never straddle a chunk");
+static_assert(kFlush % (kLegThreadsA / 64) == 0, "the analysis waves share each flush's reductions evenly");
 constexpr int kDftThreads = 256;   // ring sum kernels: 4 waves, one per residue class mod 4
 constexpr int kDftChains = 4;      // frequencies per lane at a time in the analysis ring sums
 constexpr int kFftThreads = 512;   // belt ring FFT kernels
@@ -58,7 +61,6 @@ constexpr double kInvScale = 0x1p-600;
 constexpr double kRescaleAbove = 0x1p400;
 constexpr double kLogScale = 600.0 * 0.69314718055994530942;
 constexpr double kLogFloor = -650.0;
-static_assert(kFlush == kLegThreads / 64, "one wave reduces each l of a flush");
 static_assert(kDftThreads == 256, "four waves: one per residue class mod 4");
 
 struct ShtRing {
@@ -308,8 +310,8 @@ __device__ __forceinline__ void start_value(double logpre_m, int m, double s, do
 }
 
 template <int R>
-__global__ __launch_bounds__(kLegThreads) void sht_analysis_legendre_kernel(LegArgs a, int nblk, double2* partial) {
-  __shared__ double2 s_red[kFlush][kLegThreads];
+__global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(LegArgs a, int nblk, double2* partial) {
+  __shared__ double2 s_red[kFlush][kLegThreadsA];
   __shared__ double2 s_ab[kLegChunk];
   const int item = blockIdx.x;
   const int m = item / nblk;
@@ -321,7 +323,7 @@ __global__ __launch_bounds__(kLegThreads) void sht_analysis_legendre_kernel(LegA
   const double logpre = convreal::ldu(a.logpre[m]);
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    const int rn = (blk * R + j) * kLegThreads + tid;
+    const int rn = (blk * R + j) * kLegThreadsA + tid;
     ring[j] = rn;
     z[j] = 0.0; ser[j] = sei[j] = sor[j] = soi[j] = 0.0; p0[j] = p1[j] = 0.0; e[j] = 0;
     if (rn < a.nnorth) {
@@ -369,14 +371,15 @@ __global__ __launch_bounds__(kLegThreads) void sht_analysis_legendre_kernel(LegA
       s_red[u][tid] = double2{tr[0] + tr[1], ti[0] + ti[1]};
     }
     __syncthreads();
-    {
-      // wave w adds the kLegThreads partial sums of l = l0 + w (rows past L hold stale values and are
-      // not written)
-      const int w = tid >> 6, lane = tid & 63;
+    // wave w adds the kLegThreadsA partial sums of l = l0 + w and l0 + w + 4 (rows past L hold stale
+    // values and are not written)
+#pragma unroll
+    for (int h = 0; h < kFlush / (kLegThreadsA / 64); ++h) {
+      const int w = (tid >> 6) + h * (kLegThreadsA / 64), lane = tid & 63;
       double sr = 0.0, si = 0.0;
 #pragma unroll
-      for (int q = 0; q < kLegThreads / 64; ++q) {
-        const double2 v = s_red[w][lane * (kLegThreads / 64) + q];
+      for (int q = 0; q < kLegThreadsA / 64; ++q) {
+        const double2 v = s_red[w][lane * (kLegThreadsA / 64) + q];
         sr += v.x;
         si += v.y;
       }
@@ -386,7 +389,7 @@ __global__ __launch_bounds__(kLegThreads) void sht_analysis_legendre_kernel(LegA
         si += __shfl_xor(si, off);
       }
       const int l = l0 + w;
-      if (lane == 0 && w < kFlush && l <= a.L) out[l - m] = double2{scale * sr, scale * si};
+      if (lane == 0 && l <= a.L) out[l - m] = double2{scale * sr, scale * si};
     }
     __syncthreads();
     // bring scaled values back towards the FP64 range; a ring joins the sums once it is unscaled
@@ -410,10 +413,10 @@ __global__ __launch_bounds__(kLegThreads) void sht_analysis_legendre_kernel(LegA
   // straddle a chunk), loaded by all threads at once
   for (int c0 = m; c0 <= a.L; c0 += kLegChunk) {
     const int cn = min(kLegChunk, a.L + 1 - c0);
-    if (tid < cn) s_ab[tid] = coef[c0 - m + tid];
+    for (int i = tid; i < cn; i += kLegThreadsA) s_ab[i] = coef[c0 - m + i];
     __syncthreads();
-    // every group checks its bounds: with 8 rings per thread (one ring block per order at Nside 2048,
-    // so one reduction per l) an unchecked copy of the group exceeds the register file
+    // every group checks its bounds: with 8 rings per thread an unchecked copy of the group exceeds
+    // the register file
     for (int l0 = c0; l0 < c0 + cn; l0 += kFlush) group(l0, c0, std::true_type{});
     // the groups end with a barrier: the next chunk may overwrite s_ab
   }
@@ -651,7 +654,7 @@ hipError_t set_lds_attributes(int nside, int L) {
 
 hipError_t launch_analysis_legendre(const conv_sht_plan* p, double2* alm, hipStream_t st) {
   LegArgs a{p->d_rings, p->d_coef, p->d_logpre, p->d_G, alm, p->L, p->nrings, p->nnorth, p->omega};
-  const dim3 g(static_cast<unsigned>((p->L + 1) * p->nblk_a)), b(kLegThreads);
+  const dim3 g(static_cast<unsigned>((p->L + 1) * p->nblk_a)), b(kLegThreadsA);
   switch (p->Ra) {
     case 1: hipLaunchKernelGGL(sht_analysis_legendre_kernel<1>, g, b, 0, st, a, p->nblk_a, p->d_partial); break;
     case 2: hipLaunchKernelGGL(sht_analysis_legendre_kernel<2>, g, b, 0, st, a, p->nblk_a, p->d_partial); break;
@@ -794,9 +797,9 @@ int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
   p->nblk = static_cast<int>((p->nnorth + static_cast<long long>(p->R) * kLegThreads - 1) /
                              (static_cast<long long>(p->R) * kLegThreads));
   p->Ra = 1;
-  while (p->Ra < 8 && static_cast<long long>(p->Ra) * kLegThreads < p->nnorth) p->Ra *= 2;
-  p->nblk_a = static_cast<int>((p->nnorth + static_cast<long long>(p->Ra) * kLegThreads - 1) /
-                               (static_cast<long long>(p->Ra) * kLegThreads));
+  while (p->Ra < 8 && static_cast<long long>(p->Ra) * kLegThreadsA < p->nnorth) p->Ra *= 2;
+  p->nblk_a = static_cast<int>((p->nnorth + static_cast<long long>(p->Ra) * kLegThreadsA - 1) /
+                               (static_cast<long long>(p->Ra) * kLegThreadsA));
 
   // rings from the grid's exact integer numerators
   const convreal::RingGrid g = convreal::make_ring_grid(nside);
