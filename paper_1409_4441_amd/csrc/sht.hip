@@ -789,11 +789,12 @@ int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
   p->npix = 12LL * nside * nside;
   p->nalm = (static_cast<long long>(lmax) + 1) * (lmax + 2) / 2;
   p->omega = 4.0 * M_PI / static_cast<double>(p->npix);
-  // synthesis: up to 4 rings per thread (8 exceed the register file once the unrolled steps keep
-  // their values in registers), more rings in several ring blocks per order; analysis: up to 8, since
-  // every block reduces over its rings for every l (fewer blocks, fewer reductions)
+  // synthesis: up to 2 rings per thread, more rings in several ring blocks per order (more waves per
+  // SIMD; at Nside 2048 1-5% faster than 4, while 8 exceed the register file once the unrolled steps
+  // keep their values in registers); analysis: up to 8, since every block reduces over its rings for
+  // every l (fewer blocks, fewer reductions)
   p->R = 1;
-  while (p->R < 4 && static_cast<long long>(p->R) * kLegThreads < p->nnorth) p->R *= 2;
+  while (p->R < 2 && static_cast<long long>(p->R) * kLegThreads < p->nnorth) p->R *= 2;
   p->nblk = static_cast<int>((p->nnorth + static_cast<long long>(p->R) * kLegThreads - 1) /
                              (static_cast<long long>(p->R) * kLegThreads));
   p->Ra = 1;
