@@ -268,9 +268,10 @@ __global__ __launch_bounds__(kTile * kGroups) void pair_accumulate_kernel(PairAr
 // cap rings y =. One FP64 map per launch.
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 // tiles per workgroup (the table is staged once for all of them): the 64 KB table allows two
-// workgroups per CU, so 12 waves each give 6 waves per SIMD (register budget 80; 16 waves gave 4, and
-// 10 waves 5; 12 was fastest at Nside 2048, 14 (7 per SIMD, 72 registers) spilled and lost 19%)
-constexpr int kMfmaWaves = 12;
+// workgroups per CU, so 8 waves each give 4 waves per SIMD (register budget 128, 102 used, no spills;
+// 12 waves at 6 per SIMD spilled 20-26 registers and took 4.5% longer at Nside 2048 / 30', 14
+// spilled more and lost 19%)
+constexpr int kMfmaWaves = 8;
 
 template <bool kCoef>
 __global__ __launch_bounds__(64 * kMfmaWaves, kMfmaWaves / 2) void cap_mfma64_kernel(PairArgs a, const double* __restrict__ x,
