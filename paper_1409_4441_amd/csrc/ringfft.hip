@@ -279,12 +279,22 @@ int fft_threads(int n) { return n / 2 < kFftMaxThreads ? (n / 2 < 64 ? 64 : n / 
 namespace convreal {
 
 hipError_t ring_fft_spectra(const conv_real_plan* p) {
+  const size_t lds = sizeof(double2) * static_cast<size_t>(p->fft_n);
+  // the LDS limits of every transform kernel, set here (plan set-up) so that applies make no
+  // attribute calls (they may run under stream capture); the limit is per kernel, not per plan, so
+  // it is the largest any plan needs (8192-point rings at Nside 2048)
+  const int lds_max = static_cast<int>(sizeof(double2) * 8192);
+  const void* fns[] = {reinterpret_cast<const void*>(&ring_fft_spectra_kernel),
+                       reinterpret_cast<const void*>(&ring_fft_forward_kernel<double>),
+                       reinterpret_cast<const void*>(&ring_fft_forward_kernel<float>),
+                       reinterpret_cast<const void*>(&ring_fft_inverse_kernel<double>),
+                       reinterpret_cast<const void*>(&ring_fft_inverse_kernel<float>)};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    if (e != hipSuccess) return e;
+  }
   if (p->fft_npairs == 0) return hipSuccess;
   const FftArgs a = make_fft_args(p);
-  const size_t lds = sizeof(double2) * static_cast<size_t>(p->fft_n);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_fft_spectra_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(ring_fft_spectra_kernel, dim3(static_cast<unsigned>(p->fft_npairs)), dim3(fft_threads(p->fft_n)),
                      lds, nullptr, a);
   return hipGetLastError();
@@ -296,12 +306,7 @@ hipError_t ring_fft_apply_one(const conv_real_plan* p, const T* x, T* y, hipStre
   const size_t lds = sizeof(double2) * static_cast<size_t>(p->fft_n);
   const unsigned nbelt = static_cast<unsigned>(p->belt_hi - p->belt_lo + 1);
   const unsigned nnorth = static_cast<unsigned>((p->nrings - 1) / 2 - p->belt_lo + 1);   // through the equator
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_fft_forward_kernel<T>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&ring_fft_inverse_kernel<T>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  if (e != hipSuccess) return e;
+  hipError_t e;
   hipLaunchKernelGGL(ring_fft_forward_kernel<T>, dim3((nbelt + 1) / 2), dim3(fft_threads(p->fft_n)), lds, st, a, x);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   mark(p, st, "ring_fft_forward_kernel", 0);

@@ -4,7 +4,8 @@ store or evaluated on the fly), the FFTs writing the belt rings and the cap tile
 Checked against the oracle at the mixed path's bound (rel rms <= 1e-6) on full maps of small grids
 and on sampled pixels (polar, cap-edge and belt-edge rings included) at Nside 512 and 2048, against
 the direct method, with and without the weight store; switching back to the direct method restores
-its result bit for bit; batches and the no-allocation entry point refuse such plans."""
+its result bit for bit; batches and the no-allocation entry point refuse such plans; applies of
+both FP64 and mixed plans on the method replay from a HIP graph bit for bit."""
 import math
 
 import numpy as np
@@ -119,3 +120,35 @@ def test_mixed_ring_fft_refusals(cuda_device):
         with pytest.raises(cr.ConvRealError):
             plan.set_method("ring_fft")
         assert plan.method() == "direct"
+
+
+@pytest.mark.parametrize("precision", ["mixed", "f64"])
+def test_ring_fft_graph_capture(cuda_device, precision):
+    """An apply on the ring-FFT method recorded in a HIP graph (the transforms' LDS limits are set at
+    plan set-up, so applies make no attribute calls): every replay, with eager work between them,
+    equals the eager result bit for bit."""
+    nside, sigma = 32, 1.5 * DEG
+    tc = 5 * sigma
+    T = ok.tabulate(synth.gaussian_beam_sigma(96, sigma), tc, 1024)
+    dtype = np.float32 if precision == "mixed" else np.float64
+    x = torch.from_numpy(synth.white_noise(nside, 2, seed=77, dtype=dtype)).to("cuda:0")
+    with cr.Plan(nside, T, tc, precision) as plan:
+        plan.set_method("ring_fft")
+        ref = plan.apply(x).clone()
+        y = torch.empty_like(x)
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            plan.apply(x, out=y)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            plan.apply(x, out=y)
+        for rep in range(4):
+            y.fill_(float("nan"))
+            junk = torch.randn(1 << 20, device="cuda:0").sum()     # eager work between replays
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(y, ref), rep
+            del junk
