@@ -16,7 +16,9 @@
 // Horner sums in e^{2 pi i a' / k}, combined with i^{(j mod 4) q} into the four pixels q k + a'.
 // Only the frequencies below min(n, L + 1) are formed. On a grid whose Nside is a power of two the
 // belt rings (n = 4 Nside, a power of two) take a radix-2 FFT in LDS instead (n log n work against
-// n min(n, L + 1) / 4), the polar-cap rings (n = 4k) the folded sums.
+// n min(n, L + 1) / 4). The other rings with k >= kChirpMin (the polar-cap rings, and the belt rings of
+// other grids) take each folded class's k-point DFT as a chirp-z convolution through the same radix-2
+// FFTs (below); the smallest rings keep the folded Horner sums.
 //
 // Legendre sums. lambda_lm by the recurrence in l at fixed m,
 //   lambda_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)) sin^m theta,
@@ -56,7 +58,8 @@ static_assert(kLegChunk % 8 == 0, "groups of kFlush values of l never straddle a
 static_assert(kFlush % (kLegThreadsA / 64) == 0, "the analysis waves share each flush's reductions evenly");
 constexpr int kDftThreads = 256;   // ring sum kernels: 4 waves, one per residue class mod 4
 constexpr int kDftChains = 4;      // frequencies per lane at a time in the analysis ring sums
-constexpr int kFftThreads = 512;   // belt ring FFT kernels
+constexpr int kFftThreads = 512;   // belt ring FFT kernels and chirp-z ring sums
+constexpr int kChirpMin = 16;      // rings with k = n / 4 at least this take the chirp-z ring sums
 constexpr double kInvScale = 0x1p-600;
 constexpr double kRescaleAbove = 0x1p400;
 constexpr double kLogScale = 600.0 * 0.69314718055994530942;
@@ -92,10 +95,10 @@ __device__ __forceinline__ long long alm_base(int L, int m) {
 template <typename T>
 __global__ __launch_bounds__(kDftThreads) void sht_ring_dft_kernel(const T* __restrict__ x,
                                                                    const ShtRing* __restrict__ rings,
-                                                                   int nrings, int L, double2* __restrict__ G,
-                                                                   int skip0, int nskip) {
+                                                                   const int* __restrict__ list, int nrings, int L,
+                                                                   double2* __restrict__ G) {
   extern __shared__ double s_fold[];   // s0[k], s2[k], then (d, e) pairs [k]
-  const int r = static_cast<int>(blockIdx.x) < skip0 ? static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x) + nskip;
+  const int r = list[blockIdx.x];
   const ShtRing R = convreal::ldu_record(rings[r]);
   const int n = R.n, k = n >> 2;
   double* s0 = s_fold;
@@ -110,7 +113,8 @@ __global__ __launch_bounds__(kDftThreads) void sht_ring_dft_kernel(const T* __re
     de[a] = double2{x0 - x2, x1 - x3};
   }
   __syncthreads();
-  const int nk = n < L + 1 ? n : L + 1;
+  const int nk = n < L + 1 ? n : L + 1;   // < 4 kChirpMin: the list holds rings with k < kChirpMin only
+  __shared__ double2 s_x[4 * kChirpMin];
   const int kappa = threadIdx.x >> 6;          // the wave's residue class j mod 4
   const int lane = threadIdx.x & 63;
   // kDftChains frequencies per lane at a time (j = 4 jq + kappa, jq = jq0 + 64 t): independent Horner
@@ -148,47 +152,74 @@ __global__ __launch_bounds__(kDftThreads) void sht_ring_dft_kernel(const T* __re
         }
       }
     }
-    // G_m = e^{-i m pi c / n} X[j] for every m = j mod n up to L
 #pragma unroll
     for (int t = 0; t < kDftChains; ++t) {
       const int j = 4 * (jq0 + 64 * t) + kappa;
-      if (j >= nk) continue;
-      for (int m = j; m <= L; m += n) {
-        const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
-        double ps, pc;
-        sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
-        G[static_cast<size_t>(m) * nrings + r] = double2{ar[t] * pc - ai[t] * ps, ar[t] * ps + ai[t] * pc};
-      }
+      if (j < nk) s_x[j] = double2{ar[t], ai[t]};
     }
   }
+  __syncthreads();
+  // G_m = e^{-i m pi c / n} X[m mod n] for every m up to L (a small ring folds many m onto each j:
+  // the whole workgroup shares them out)
+  for (int m = threadIdx.x; m <= L; m += blockDim.x) {
+    const double2 X = s_x[m % n];
+    const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
+    double ps, pc;
+    sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+    G[static_cast<size_t>(m) * nrings + r] = double2{X.x * pc - X.y * ps, X.x * ps + X.y * pc};
+  }
+}
+
+// threads per frequency when the folded sums of B (each over every m = j mod n up to L) are shared out:
+// the largest power of two up to 64 with 2 nsub nj <= blockDim
+__device__ __forceinline__ int fold_split(int nj) {
+  int nsub = 1;
+  while (nsub < 64 && 2 * nsub * nj <= static_cast<int>(blockDim.x)) nsub *= 2;
+  return nsub;
+}
+
+// B[j] = sum_{m = j mod n, m <= L} w_m F_m e^{i m pi c / n} for one j, its terms split over the nsub
+// lanes of the calling group (aligned, consecutive lanes; sub = lane within the group); every lane of
+// the group gets the sum (fixed-order butterfly)
+__device__ __forceinline__ double2 fold_sum(const double2* __restrict__ F, int nrings, int r, int L, int n, int c,
+                                            int j, int sub, int nsub) {
+  double br = 0.0, bi = 0.0;
+  for (int m = j + sub * n; m <= L; m += nsub * n) {
+    const double2 f = F[static_cast<size_t>(m) * nrings + r];
+    const long long num = (static_cast<long long>(m) * c) % (2LL * n);
+    double ps, pc;
+    sincospi(static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+    const double w = m == 0 ? 1.0 : 2.0;
+    br += w * (f.x * pc - f.y * ps);
+    bi += w * (f.x * ps + f.y * pc);
+  }
+  for (int o = 1; o < nsub; o <<= 1) {
+    br += __shfl_xor(br, o);
+    bi += __shfl_xor(bi, o);
+  }
+  return double2{br, bi};
 }
 
 // ---------------------------------------------------------------------------- ring sums (synthesis)
 template <typename T, bool ACC>
 __global__ __launch_bounds__(kDftThreads) void sht_ring_idft_kernel(const double2* __restrict__ F,
                                                                     const ShtRing* __restrict__ rings,
-                                                                    int nrings, int L, T* __restrict__ y,
-                                                                    int skip0, int nskip) {
+                                                                    const int* __restrict__ list, int nrings, int L,
+                                                                    T* __restrict__ y) {
   extern __shared__ double2 s_b[];     // residue class c at s_b[c * nq + j / 4]
-  const int r = static_cast<int>(blockIdx.x) < skip0 ? static_cast<int>(blockIdx.x) : static_cast<int>(blockIdx.x) + nskip;
+  const int r = list[blockIdx.x];
   const ShtRing R = convreal::ldu_record(rings[r]);
   const int n = R.n, k = n >> 2;
   const int nk = n < L + 1 ? n : L + 1;
   const int nq = (nk + 3) >> 2;
   for (int t = threadIdx.x; t < 4 * nq; t += blockDim.x) s_b[t] = double2{0.0, 0.0};
   __syncthreads();
-  for (int j = threadIdx.x; j < nk; j += blockDim.x) {
-    double br = 0.0, bi = 0.0;
-    for (int m = j; m <= L; m += n) {
-      const double2 f = F[static_cast<size_t>(m) * nrings + r];
-      const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
-      double ps, pc;
-      sincospi(static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
-      const double w = m == 0 ? 1.0 : 2.0;
-      br += w * (f.x * pc - f.y * ps);
-      bi += w * (f.x * ps + f.y * pc);
+  {
+    const int nsub = fold_split(nk), sub = static_cast<int>(threadIdx.x) & (nsub - 1);
+    for (int j = static_cast<int>(threadIdx.x) / nsub; j < nk; j += static_cast<int>(blockDim.x) / nsub) {
+      const double2 b = fold_sum(F, nrings, r, L, n, R.c, j, sub, nsub);
+      if (sub == 0) s_b[(j & 3) * nq + (j >> 2)] = b;
     }
-    s_b[(j & 3) * nq + (j >> 2)] = double2{br, bi};
   }
   __syncthreads();
   T* yr = y + R.start;
@@ -242,17 +273,18 @@ template <typename T>
 __global__ __launch_bounds__(kFftThreads) void sht_belt_fft_kernel(const T* __restrict__ x,
                                                                    const ShtRing* __restrict__ rings, int nrings,
                                                                    int ring0, int L, int logn,
-                                                                   const double2* __restrict__ tw,
                                                                    double2* __restrict__ G) {
   extern __shared__ double2 s_fft[];
+  __shared__ double2 s_twh[64], s_twl[64];
   const int r = ring0 + static_cast<int>(blockIdx.x);
   const ShtRing R = convreal::ldu_record(rings[r]);
   const int n = R.n;
   const T* xr = x + R.start;
+  convreal::lds_twiddles_fill(s_twh, s_twl, n);
   for (int a = threadIdx.x; a < n; a += blockDim.x)
     s_fft[convreal::bitrev(a, logn)] = double2{static_cast<double>(xr[a]), 0.0};
   __syncthreads();
-  convreal::fft_stages(s_fft, n, tw);
+  convreal::fft_stages_tw(s_fft, n, convreal::LdsTwiddles{s_twh, s_twl});
   for (int m = threadIdx.x; m <= L; m += blockDim.x) {
     const double2 X = s_fft[m & (n - 1)];
     const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
@@ -268,12 +300,13 @@ template <typename T, bool ACC>
 __global__ __launch_bounds__(kFftThreads) void sht_belt_ifft_kernel(const double2* __restrict__ F,
                                                                     const ShtRing* __restrict__ rings, int nrings,
                                                                     int ring0, int L, int logn,
-                                                                    const double2* __restrict__ tw,
                                                                     T* __restrict__ y) {
   extern __shared__ double2 s_fft[];
+  __shared__ double2 s_twh[64], s_twl[64];
   const int r = ring0 + static_cast<int>(blockIdx.x);
   const ShtRing R = convreal::ldu_record(rings[r]);
   const int n = R.n;
+  convreal::lds_twiddles_fill(s_twh, s_twl, n);
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     double br = 0.0, bi = 0.0;
     for (int m = j; m <= L; m += n) {
@@ -288,7 +321,7 @@ __global__ __launch_bounds__(kFftThreads) void sht_belt_ifft_kernel(const double
     s_fft[convreal::bitrev(j, logn)] = double2{br, -bi};
   }
   __syncthreads();
-  convreal::fft_stages(s_fft, n, tw);
+  convreal::fft_stages_tw(s_fft, n, convreal::LdsTwiddles{s_twh, s_twl});
   T* yr = y + R.start;
   for (int a = threadIdx.x; a < n; a += blockDim.x) {
     if (ACC)
@@ -296,6 +329,233 @@ __global__ __launch_bounds__(kFftThreads) void sht_belt_ifft_kernel(const double
     else
       yr[a] = static_cast<T>(s_fft[a].x);
   }
+}
+
+// ---------------------------------------------------------------------------- ring sums by chirp-z
+// Rings with k = n / 4 >= kChirpMin that are not belt rings of a power-of-two grid. Each residue
+// class of the folded sums is a k-point DFT, X[4 jq + kappa] = sum_a' d[a'] e^{-2 pi i jq a' / k} with
+// d[a'] = c_kappa[a'] e^{-i pi kappa a' / (2 k)}, needed at jq < Q (Q = ceil((min(n, L + 1) - kappa) / 4)).
+// Bluestein's chirp-z identity jq a' = (jq^2 + a'^2 - (jq - a')^2) / 2 turns it into a convolution: with
+// w(t) = e^{-i pi t^2 / k},
+//   X[4 jq + kappa] = w(jq) sum_a' (d[a'] w(a')) conj(w(jq - a')),
+// a circular convolution of length M (a power of two, M >= k + Q - 1) taken as FFT(d w) . H, then an
+// inverse FFT, where H = FFT(b), b[t] = conj(w(t)) for t in [0, Q), b[M - t] = conj(w(t)) for t in [1, k)
+// and zeros between (written at set-up, one table per k, with w(t) for t < k; t^2 mod 2k in integers).
+// The synthesis ring sums sum_jq B[jq] e^{2 pi i jq a' / k} = conj(w(a')) sum_jq (B[jq] conj(w(jq))) w(a' - jq)
+// for a' < k take the same route with kernel transform conj(H) (that kernel is b mirrored and
+// conjugated). O(M log M) per class instead of k Q multiply-adds. The inverse transform is the forward
+// one between two conjugations.
+struct ChirpTabs {
+  const double2* w;          // per k: w(t), t < k
+  const double2* h;          // per k: H[f], f < M(k)
+  const long long* w_off;    // per k (index k): offset of its w table
+  const long long* h_off;    // per k: offset of its H table
+};
+
+__device__ __forceinline__ double2 cconj(double2 a) { return double2{a.x, -a.y}; }
+
+// log2 of the convolution length of a ring with k = n / 4 pixels per quarter
+__device__ __forceinline__ int chirp_logm(int k, int nk) {
+  const int q0 = (nk + 3) >> 2;
+  const int len = k + q0 - 1;
+  int lg = 1;
+  while ((1 << lg) < len) ++lg;
+  return lg;
+}
+
+// s holds FFT(v) in natural order; leave conj(FFT(v) . H~) in bit-reversed order (H~ = H, or conj(H)
+// for the synthesis), ready for the forward FFT that completes the inverse transform
+__device__ __forceinline__ void chirp_product(double2* s, int M, int logm, const double2* __restrict__ H, bool conj_h) {
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const int j = convreal::bitrev(i, logm);
+    if (i > j) continue;
+    double2 hi = H[i], hj = H[j];
+    if (conj_h) {
+      hi = cconj(hi);
+      hj = cconj(hj);
+    }
+    const double2 vi = convreal::cmul(s[i], hi), vj = convreal::cmul(s[j], hj);
+    s[j] = cconj(vi);
+    s[i] = cconj(vj);
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void sht_ring_dft_chirp_kernel(const T* __restrict__ x,
+                                                                         const ShtRing* __restrict__ rings,
+                                                                         const int* __restrict__ list, int nrings,
+                                                                         int L, ChirpTabs c, double2* __restrict__ G) {
+  extern __shared__ double2 s_fft[];
+  const int r = list[blockIdx.x];
+  const ShtRing R = convreal::ldu_record(rings[r]);
+  const int n = R.n, k = n >> 2;
+  const int nk = n < L + 1 ? n : L + 1;
+  const int logm = chirp_logm(k, nk), M = 1 << logm;
+  const double2* w = c.w + convreal::ldu(c.w_off[k]);
+  const double2* H = c.h + convreal::ldu(c.h_off[k]);
+  __shared__ double2 s_twh[64], s_twl[64];
+  convreal::lds_twiddles_fill(s_twh, s_twl, M);
+  const convreal::LdsTwiddles tw{s_twh, s_twl};
+  const T* xr = x + R.start;
+  const double inv_m = 1.0 / static_cast<double>(M);
+  for (int kappa = 0; kappa < 4 && kappa < nk; ++kappa) {
+    for (int t = threadIdx.x; t < M; t += blockDim.x) {
+      double2 v{0.0, 0.0};
+      if (t < k) {
+        const double x0 = static_cast<double>(xr[t]), x1 = static_cast<double>(xr[t + k]);
+        const double x2 = static_cast<double>(xr[t + 2 * k]), x3 = static_cast<double>(xr[t + 3 * k]);
+        // folded value c_kappa[t] (kappa 1: (x0 - x2) - i (x1 - x3), kappa 3: (x0 - x2) + i (x1 - x3))
+        const double2 cv = kappa == 0 ? double2{(x0 + x2) + (x1 + x3), 0.0}
+                         : kappa == 2 ? double2{(x0 + x2) - (x1 + x3), 0.0}
+                         : double2{x0 - x2, kappa == 1 ? x3 - x1 : x1 - x3};
+        double2 ph = w[t];
+        if (kappa != 0) {
+          double ps, pc;
+          sincospi(-static_cast<double>(kappa * t) / static_cast<double>(2 * k), &ps, &pc);
+          ph = convreal::cmul(double2{pc, ps}, ph);
+        }
+        v = convreal::cmul(cv, ph);
+      }
+      s_fft[convreal::bitrev(t, logm)] = v;
+    }
+    __syncthreads();
+    convreal::fft_stages_tw(s_fft, M, tw);
+    chirp_product(s_fft, M, logm, H, false);
+    convreal::fft_stages_tw(s_fft, M, tw);
+    // G_m = e^{-i m pi c / n} X[m mod n] for every m = kappa (mod 4) up to L (m mod n = 4 jq + kappa
+    // with jq < qk, n being a multiple of 4)
+    for (int u = threadIdx.x; 4 * u + kappa <= L; u += blockDim.x) {
+      const int m = 4 * u + kappa;
+      const int jq = (m % n) >> 2;
+      const double2 sv = s_fft[jq];
+      const double2 X = convreal::cmul(w[jq], double2{sv.x * inv_m, -sv.y * inv_m});
+      const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
+      double ps, pc;
+      sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+      G[static_cast<size_t>(m) * nrings + r] = double2{X.x * pc - X.y * ps, X.x * ps + X.y * pc};
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int kChirpPer = 4;   // a' values per thread in the synthesis (k <= kChirpPer * kFftThreads)
+static_assert(kChirpPer * kFftThreads >= CONV_SHT_MAX_NSIDE, "a ring's quarter fits the synthesis threads");
+
+template <typename T, bool ACC>
+__global__ __launch_bounds__(kFftThreads) void sht_ring_idft_chirp_kernel(const double2* __restrict__ F,
+                                                                          const ShtRing* __restrict__ rings,
+                                                                          const int* __restrict__ list, int nrings,
+                                                                          int L, ChirpTabs c, T* __restrict__ y) {
+  extern __shared__ double2 s_fft[];
+  const int r = list[blockIdx.x];
+  const ShtRing R = convreal::ldu_record(rings[r]);
+  const int n = R.n, k = n >> 2;
+  const int nk = n < L + 1 ? n : L + 1;
+  const int logm = chirp_logm(k, nk), M = 1 << logm;
+  const double2* w = c.w + convreal::ldu(c.w_off[k]);
+  const double2* H = c.h + convreal::ldu(c.h_off[k]);
+  __shared__ double2 s_twh[64], s_twl[64];
+  convreal::lds_twiddles_fill(s_twh, s_twl, M);
+  const convreal::LdsTwiddles tw{s_twh, s_twl};
+  const double inv_m = 1.0 / static_cast<double>(M);
+  double acc[kChirpPer][4];
+#pragma unroll
+  for (int u = 0; u < kChirpPer; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[u][q] = 0.0;
+  for (int kappa = 0; kappa < 4 && kappa < nk; ++kappa) {
+    const int qk = (nk - kappa + 3) >> 2;
+    for (int t = threadIdx.x; t < M; t += blockDim.x) s_fft[t] = double2{0.0, 0.0};
+    __syncthreads();
+    {
+      // B[j], j = 4 t + kappa, times conj(w(t)), in bit-reversed order
+      const int nsub = fold_split(qk), sub = static_cast<int>(threadIdx.x) & (nsub - 1);
+      for (int t = static_cast<int>(threadIdx.x) / nsub; t < qk; t += static_cast<int>(blockDim.x) / nsub) {
+        const double2 b = fold_sum(F, nrings, r, L, n, R.c, 4 * t + kappa, sub, nsub);
+        if (sub == 0) s_fft[convreal::bitrev(t, logm)] = convreal::cmul(b, cconj(w[t]));
+      }
+    }
+    __syncthreads();
+    convreal::fft_stages_tw(s_fft, M, tw);
+    chirp_product(s_fft, M, logm, H, true);
+    convreal::fft_stages_tw(s_fft, M, tw);
+#pragma unroll
+    for (int u = 0; u < kChirpPer; ++u) {
+      const int ap = static_cast<int>(threadIdx.x) + u * static_cast<int>(blockDim.x);
+      if (ap >= k) continue;
+      const double2 sv = s_fft[ap];
+      // U = e^{i pi kappa a' / (2k)} conj(w(a')) conv[a'], conv = conj(FFT(...)) / M
+      double2 U = convreal::cmul(cconj(w[ap]), double2{sv.x * inv_m, -sv.y * inv_m});
+      if (kappa != 0) {
+        double ps, pc;
+        sincospi(static_cast<double>(kappa * ap) / static_cast<double>(2 * k), &ps, &pc);
+        U = convreal::cmul(double2{pc, ps}, U);
+      }
+      // pixel q k + a': Re(i^{kappa q} U)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int p = (kappa * q) & 3;
+        acc[u][q] += p == 0 ? U.x : (p == 1 ? -U.y : (p == 2 ? -U.x : U.y));
+      }
+    }
+    __syncthreads();
+  }
+  T* yr = y + R.start;
+#pragma unroll
+  for (int u = 0; u < kChirpPer; ++u) {
+    const int ap = static_cast<int>(threadIdx.x) + u * static_cast<int>(blockDim.x);
+    if (ap >= k) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      T* dst = yr + q * k + ap;
+      if (ACC)
+        *dst = static_cast<T>(static_cast<double>(*dst) + acc[u][q]);
+      else
+        *dst = static_cast<T>(acc[u][q]);
+    }
+  }
+}
+
+// set-up, one workgroup per chirp length k (klist): w(t) for t < k, and H = FFT(b) in natural order
+__global__ __launch_bounds__(kFftThreads) void sht_chirp_setup_kernel(const int* __restrict__ klist, int L,
+                                                                      const long long* __restrict__ w_off,
+                                                                      const long long* __restrict__ h_off,
+                                                                      double2* __restrict__ w_tab,
+                                                                      double2* __restrict__ h_tab) {
+  extern __shared__ double2 s_fft[];
+  __shared__ double2 s_twh[64], s_twl[64];
+  const int k = klist[blockIdx.x];
+  const int n = 4 * k;
+  const int nk = n < L + 1 ? n : L + 1;
+  const int q0 = (nk + 3) >> 2;
+  const int logm = chirp_logm(k, nk), M = 1 << logm;
+  double2* w = w_tab + w_off[k];
+  convreal::lds_twiddles_fill(s_twh, s_twl, M);
+  for (int t = threadIdx.x; t < M; t += blockDim.x) {
+    // b[t] = conj(w(t)) on [0, q0) and b[M - t'] = conj(w(t')) on t' in [1, k)
+    int tt = -1;
+    if (t < q0) tt = t;
+    else if (M - t < k) tt = M - t;
+    double2 v{0.0, 0.0};
+    if (tt >= 0) {
+      const long long num = (static_cast<long long>(tt) * tt) % (2LL * k);
+      double ps, pc;
+      sincospi(static_cast<double>(num) / static_cast<double>(k), &ps, &pc);
+      v = double2{pc, ps};   // conj(w(tt)) = e^{+i pi tt^2 / k}
+    }
+    s_fft[convreal::bitrev(t, logm)] = v;
+    if (t < k) {
+      const long long num = (static_cast<long long>(t) * t) % (2LL * k);
+      double ps, pc;
+      sincospi(-static_cast<double>(num) / static_cast<double>(k), &ps, &pc);
+      w[t] = double2{pc, ps};
+    }
+  }
+  __syncthreads();
+  convreal::fft_stages_tw(s_fft, M, convreal::LdsTwiddles{s_twh, s_twl});
+  double2* H = h_tab + h_off[k];
+  for (int f = threadIdx.x; f < M; f += blockDim.x) H[f] = s_fft[f];
 }
 
 // ---------------------------------------------------------------------------- Legendre sums
@@ -580,7 +840,17 @@ struct conv_sht_plan {
   int fft_ring0 = 0;              // belt rings ring0 .. ring0 + fft_nrings - 1 by FFT (power-of-two Nside)
   int fft_nrings = 0;
   int fft_logn = 0;
-  double2* d_tw = nullptr;        // n / 2 twiddles exp(-2 pi i m / n), n = 4 Nside
+  int* d_direct = nullptr;        // rings of the folded sums (k < kChirpMin, or every ring left by the FFTs)
+  int n_direct = 0;
+  int* d_chirp = nullptr;         // rings of the chirp-z ring sums
+  int n_chirp = 0;
+  int chirp_logm_max = 0;         // largest convolution length (log2) among them
+  struct ChirpRange { int logm, off, count; };
+  std::vector<ChirpRange> chirp_ranges;   // d_chirp in runs of one convolution length (one launch each)
+  double2* d_chirp_w = nullptr;   // chirp tables (ChirpTabs)
+  double2* d_chirp_h = nullptr;
+  long long* d_chirp_woff = nullptr;
+  long long* d_chirp_hoff = nullptr;
   hipEvent_t ev_in = nullptr, ev_real = nullptr, ev_done = nullptr;
   std::vector<void*> owned;
 };
@@ -649,7 +919,23 @@ hipError_t set_lds_attributes(int nside, int L) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, nf);
     if (e != hipSuccess) return e;
   }
+  // chirp-z convolutions of at most 4096 points (k + Q - 1 <= 2 k - 1 < 4096 for Nside <= 2048)
+  const void* fc[] = {reinterpret_cast<const void*>(&sht_ring_dft_chirp_kernel<double>),
+                      reinterpret_cast<const void*>(&sht_ring_dft_chirp_kernel<float>),
+                      reinterpret_cast<const void*>(&sht_ring_idft_chirp_kernel<double, false>),
+                      reinterpret_cast<const void*>(&sht_ring_idft_chirp_kernel<double, true>),
+                      reinterpret_cast<const void*>(&sht_ring_idft_chirp_kernel<float, false>),
+                      reinterpret_cast<const void*>(&sht_ring_idft_chirp_kernel<float, true>),
+                      reinterpret_cast<const void*>(&sht_chirp_setup_kernel)};
+  for (const void* f : fc) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 16 * 4096);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
+}
+
+ChirpTabs chirp_tabs(const conv_sht_plan* p) {
+  return ChirpTabs{p->d_chirp_w, p->d_chirp_h, p->d_chirp_woff, p->d_chirp_hoff};
 }
 
 hipError_t launch_analysis_legendre(const conv_sht_plan* p, double2* alm, hipStream_t st) {
@@ -681,65 +967,101 @@ hipError_t launch_synthesis_legendre(const conv_sht_plan* p, const double2* alm,
 }
 
 hipError_t launch_analysis(const conv_sht_plan* p, const void* map, int dtype, double2* alm, hipStream_t st) {
-  const size_t lds = dft_lds(p->nside);
-  const unsigned nh = static_cast<unsigned>(p->nrings - p->fft_nrings);
-  if (dtype == CONV_SHT_F64)
-    hipLaunchKernelGGL(sht_ring_dft_kernel<double>, dim3(nh), dim3(kDftThreads), lds, st,
-                       static_cast<const double*>(map), p->d_rings, p->nrings, p->L, p->d_G, p->fft_ring0,
-                       p->fft_nrings);
-  else
-    hipLaunchKernelGGL(sht_ring_dft_kernel<float>, dim3(nh), dim3(kDftThreads), lds, st,
-                       static_cast<const float*>(map), p->d_rings, p->nrings, p->L, p->d_G, p->fft_ring0,
-                       p->fft_nrings);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  if (p->n_direct > 0) {
+    const size_t lds = dft_lds(p->nside);
+    const dim3 g(static_cast<unsigned>(p->n_direct)), b(kDftThreads);
+    if (dtype == CONV_SHT_F64)
+      hipLaunchKernelGGL(sht_ring_dft_kernel<double>, g, b, lds, st, static_cast<const double*>(map), p->d_rings,
+                         p->d_direct, p->nrings, p->L, p->d_G);
+    else
+      hipLaunchKernelGGL(sht_ring_dft_kernel<float>, g, b, lds, st, static_cast<const float*>(map), p->d_rings,
+                         p->d_direct, p->nrings, p->L, p->d_G);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  for (const auto& cr : p->chirp_ranges) {
+    const size_t lds = sizeof(double2) << cr.logm;
+    const dim3 g(static_cast<unsigned>(cr.count)), b(kFftThreads);
+    const int* lst = p->d_chirp + cr.off;
+    if (dtype == CONV_SHT_F64)
+      hipLaunchKernelGGL(sht_ring_dft_chirp_kernel<double>, g, b, lds, st, static_cast<const double*>(map),
+                         p->d_rings, lst, p->nrings, p->L, chirp_tabs(p), p->d_G);
+    else
+      hipLaunchKernelGGL(sht_ring_dft_chirp_kernel<float>, g, b, lds, st, static_cast<const float*>(map),
+                         p->d_rings, lst, p->nrings, p->L, chirp_tabs(p), p->d_G);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (p->fft_nrings > 0) {
     const size_t lf = sizeof(double2) * (static_cast<size_t>(1) << p->fft_logn);
     const dim3 g(static_cast<unsigned>(p->fft_nrings)), b(kFftThreads);
     if (dtype == CONV_SHT_F64)
       hipLaunchKernelGGL(sht_belt_fft_kernel<double>, g, b, lf, st, static_cast<const double*>(map), p->d_rings,
-                         p->nrings, p->fft_ring0, p->L, p->fft_logn, p->d_tw, p->d_G);
+                         p->nrings, p->fft_ring0, p->L, p->fft_logn, p->d_G);
     else
       hipLaunchKernelGGL(sht_belt_fft_kernel<float>, g, b, lf, st, static_cast<const float*>(map), p->d_rings,
-                         p->nrings, p->fft_ring0, p->L, p->fft_logn, p->d_tw, p->d_G);
+                         p->nrings, p->fft_ring0, p->L, p->fft_logn, p->d_G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return launch_analysis_legendre(p, alm, st);
 }
 
 hipError_t launch_ring_synthesis(const conv_sht_plan* p, void* map, int dtype, int accumulate, hipStream_t st) {
-  const size_t lds = idft_lds(p->nside, p->L);
-  const dim3 g(static_cast<unsigned>(p->nrings - p->fft_nrings)), b(kDftThreads);
-  const int s0 = p->fft_ring0, ns = p->fft_nrings;
-  if (dtype == CONV_SHT_F64) {
-    double* y = static_cast<double*>(map);
-    if (accumulate)
-      hipLaunchKernelGGL((sht_ring_idft_kernel<double, true>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y, s0, ns);
-    else
-      hipLaunchKernelGGL((sht_ring_idft_kernel<double, false>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y, s0, ns);
-  } else {
-    float* y = static_cast<float*>(map);
-    if (accumulate)
-      hipLaunchKernelGGL((sht_ring_idft_kernel<float, true>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y, s0, ns);
-    else
-      hipLaunchKernelGGL((sht_ring_idft_kernel<float, false>), g, b, lds, st, p->d_G, p->d_rings, p->nrings, p->L, y, s0, ns);
+  hipError_t e = hipSuccess;
+  if (p->n_direct > 0) {
+    const size_t lds = idft_lds(p->nside, p->L);
+    const dim3 g(static_cast<unsigned>(p->n_direct)), b(kDftThreads);
+    const int* lst = p->d_direct;
+    if (dtype == CONV_SHT_F64) {
+      double* y = static_cast<double*>(map);
+      if (accumulate)
+        hipLaunchKernelGGL((sht_ring_idft_kernel<double, true>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, y);
+      else
+        hipLaunchKernelGGL((sht_ring_idft_kernel<double, false>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, y);
+    } else {
+      float* y = static_cast<float*>(map);
+      if (accumulate)
+        hipLaunchKernelGGL((sht_ring_idft_kernel<float, true>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, y);
+      else
+        hipLaunchKernelGGL((sht_ring_idft_kernel<float, false>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, y);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || ns == 0) return e;
+  for (const auto& cr : p->chirp_ranges) {
+    const size_t lds = sizeof(double2) << cr.logm;
+    const dim3 g(static_cast<unsigned>(cr.count)), b(kFftThreads);
+    const int* lst = p->d_chirp + cr.off;
+    const ChirpTabs c = chirp_tabs(p);
+    if (dtype == CONV_SHT_F64) {
+      double* y = static_cast<double*>(map);
+      if (accumulate)
+        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<double, true>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, y);
+      else
+        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<double, false>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, y);
+    } else {
+      float* y = static_cast<float*>(map);
+      if (accumulate)
+        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<float, true>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, y);
+      else
+        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<float, false>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, y);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int s0 = p->fft_ring0, ns = p->fft_nrings;
+  if (ns == 0) return hipSuccess;
   const size_t lf = sizeof(double2) * (static_cast<size_t>(1) << p->fft_logn);
   const dim3 gf(static_cast<unsigned>(ns)), bf(kFftThreads);
   if (dtype == CONV_SHT_F64) {
     double* y = static_cast<double*>(map);
     if (accumulate)
-      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, p->d_tw, y);
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, y);
     else
-      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, p->d_tw, y);
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, y);
   } else {
     float* y = static_cast<float*>(map);
     if (accumulate)
-      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, p->d_tw, y);
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, y);
     else
-      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, p->d_tw, y);
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, y);
   }
   return hipGetLastError();
 }
@@ -823,24 +1145,82 @@ int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
     }
   }
   // belt rings (i = N..3N, n = 4N) by FFT when 4N is a power of two (and at least 16)
-  std::vector<double2> tw;
   if ((nside & (nside - 1)) == 0 && nside >= 4) {
     const int n = 4 * nside;
     p->fft_ring0 = nside - 1;
     p->fft_nrings = 2 * nside + 1;
     while ((1 << p->fft_logn) < n) ++p->fft_logn;
-    tw.resize(n / 2);
-    for (int m = 0; m < n / 2; ++m) {
-      const double ang = 2.0 * M_PI * static_cast<double>(m) / static_cast<double>(n);
-      tw[m] = double2{std::cos(ang), -std::sin(ang)};
+  }
+  // the other rings: chirp-z ring sums from k = kChirpMin on, folded sums below; one chirp table per k
+  std::vector<int> direct, chirp, klist;
+  std::vector<long long> woff, hoff;
+  long long wtot = 0, htot = 0;
+  {
+    std::vector<char> need(nside + 1, 0);
+    for (int r = 0; r < g.nrings; ++r) {
+      if (r >= p->fft_ring0 && r < p->fft_ring0 + p->fft_nrings) continue;
+      const int k = g.n[r] / 4;
+      if (k >= kChirpMin) {
+        chirp.push_back(r);
+        need[k] = 1;
+      } else {
+        direct.push_back(r);
+      }
+    }
+    woff.assign(nside + 1, 0);
+    hoff.assign(nside + 1, 0);
+    auto logm_of = [lmax](int k) {
+      const int nk = std::min(4 * k, lmax + 1);
+      const int len = k + (nk + 3) / 4 - 1;
+      int lg = 1;
+      while ((1 << lg) < len) ++lg;
+      return lg;
+    };
+    // one launch, largest convolutions first (the shortest rings fill the tail); launches per length
+    // with only the LDS each needs measured slower (each launch's tail idles the device)
+    std::stable_sort(chirp.begin(), chirp.end(),
+                     [&](int a, int b) { return logm_of(g.n[a] / 4) > logm_of(g.n[b] / 4); });
+    if (!chirp.empty())
+      p->chirp_ranges.push_back(conv_sht_plan::ChirpRange{logm_of(g.n[chirp[0]] / 4), 0, static_cast<int>(chirp.size())});
+    for (int k = 1; k <= nside; ++k) {
+      if (!need[k]) continue;
+      const int lg = logm_of(k);
+      woff[k] = wtot;
+      hoff[k] = htot;
+      wtot += k;
+      htot += 1LL << lg;
+      p->chirp_logm_max = std::max(p->chirp_logm_max, lg);
+      klist.push_back(k);
     }
   }
+  p->n_direct = static_cast<int>(direct.size());
+  p->n_chirp = static_cast<int>(chirp.size());
   DeviceGuard guard;
   hipError_t e = guard.enter(dev);
   if (e == hipSuccess) e = set_lds_attributes(nside, lmax);
-  if (e == hipSuccess && !tw.empty()) e = sht_alloc(p, &p->d_tw, tw.size());
-  if (e == hipSuccess && !tw.empty())
-    e = hipMemcpy(p->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !direct.empty()) e = sht_alloc(p, &p->d_direct, direct.size());
+  if (e == hipSuccess && !direct.empty())
+    e = hipMemcpy(p->d_direct, direct.data(), direct.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !chirp.empty()) {
+    int* d_klist = nullptr;
+    if (e == hipSuccess) e = sht_alloc(p, &p->d_chirp, chirp.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_chirp, chirp.data(), chirp.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = sht_alloc(p, &d_klist, klist.size());
+    if (e == hipSuccess) e = hipMemcpy(d_klist, klist.data(), klist.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = sht_alloc(p, &p->d_chirp_woff, woff.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_chirp_woff, woff.data(), woff.size() * sizeof(long long), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = sht_alloc(p, &p->d_chirp_hoff, hoff.size());
+    if (e == hipSuccess) e = hipMemcpy(p->d_chirp_hoff, hoff.data(), hoff.size() * sizeof(long long), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = sht_alloc(p, &p->d_chirp_w, static_cast<size_t>(wtot));
+    if (e == hipSuccess) e = sht_alloc(p, &p->d_chirp_h, static_cast<size_t>(htot));
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(sht_chirp_setup_kernel, dim3(static_cast<unsigned>(klist.size())), dim3(kFftThreads),
+                         sizeof(double2) << p->chirp_logm_max, nullptr, d_klist, lmax, p->d_chirp_woff,
+                         p->d_chirp_hoff, p->d_chirp_w, p->d_chirp_h);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  }
   if (e == hipSuccess) e = sht_alloc(p, &p->d_rings, rings.size());
   if (e == hipSuccess) e = hipMemcpy(p->d_rings, rings.data(), rings.size() * sizeof(ShtRing), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = sht_alloc(p, &p->d_coef, coef.size());
