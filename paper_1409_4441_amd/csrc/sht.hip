@@ -267,67 +267,103 @@ __global__ __launch_bounds__(kDftThreads) void sht_ring_idft_kernel(const double
 }
 
 // ---------------------------------------------------------------------------- ring FFTs (belt rings)
-// Rings ring0 .. ring0 + gridDim.x - 1, each of n = 2^logn pixels, one workgroup each (n x 16 bytes
-// of LDS). Analysis: X = FFT(x) (the ring in the real part), G_m = e^{-i m pi c / n} X[m mod n].
+// Rings ring0 .. ring0 + nr - 1, each of n = 2^logn pixels, two rings a workgroup (n x 16 bytes of
+// LDS): one complex FFT carries both, the first ring in the real part and the second in the imaginary
+// part. Analysis: Z = FFT(x1 + i x2), X1[j] = (Z[j] + conj Z[-j]) / 2, X2[j] = (Z[j] - conj Z[-j]) / 2i,
+// G_m = e^{-i m pi c / n} X[m mod n].
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void sht_belt_fft_kernel(const T* __restrict__ x,
                                                                    const ShtRing* __restrict__ rings, int nrings,
-                                                                   int ring0, int L, int logn,
+                                                                   int ring0, int nr, int L, int logn,
                                                                    double2* __restrict__ G) {
   extern __shared__ double2 s_fft[];
   __shared__ double2 s_twh[64], s_twl[64];
-  const int r = ring0 + static_cast<int>(blockIdx.x);
-  const ShtRing R = convreal::ldu_record(rings[r]);
-  const int n = R.n;
-  const T* xr = x + R.start;
+  const int r1 = ring0 + 2 * static_cast<int>(blockIdx.x);
+  const bool two = r1 + 1 < ring0 + nr;
+  const int r2 = two ? r1 + 1 : r1;
+  const ShtRing R1 = convreal::ldu_record(rings[r1]);
+  const ShtRing R2 = convreal::ldu_record(rings[r2]);
+  const int n = R1.n;
+  const T* x1 = x + R1.start;
+  const T* x2 = x + R2.start;
   convreal::lds_twiddles_fill(s_twh, s_twl, n);
   for (int a = threadIdx.x; a < n; a += blockDim.x)
-    s_fft[convreal::bitrev(a, logn)] = double2{static_cast<double>(xr[a]), 0.0};
+    s_fft[convreal::bitrev(a, logn)] = double2{static_cast<double>(x1[a]), two ? static_cast<double>(x2[a]) : 0.0};
   __syncthreads();
   convreal::fft_stages_tw(s_fft, n, convreal::LdsTwiddles{s_twh, s_twl});
   for (int m = threadIdx.x; m <= L; m += blockDim.x) {
-    const double2 X = s_fft[m & (n - 1)];
-    const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
+    const int j = m & (n - 1);
+    const double2 zj = s_fft[j], zc = s_fft[(n - j) & (n - 1)];   // Z[j], Z[-j]
+    const double2 X1{0.5 * (zj.x + zc.x), 0.5 * (zj.y - zc.y)};
+    const double2 X2{0.5 * (zj.y + zc.y), 0.5 * (zc.x - zj.x)};
     double ps, pc;
-    sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
-    G[static_cast<size_t>(m) * nrings + r] = double2{X.x * pc - X.y * ps, X.x * ps + X.y * pc};
+    sincospi(-static_cast<double>((static_cast<long long>(m) * R1.c) % (2LL * n)) / static_cast<double>(n), &ps, &pc);
+    G[static_cast<size_t>(m) * nrings + r1] = double2{X1.x * pc - X1.y * ps, X1.x * ps + X1.y * pc};
+    if (two) {
+      sincospi(-static_cast<double>((static_cast<long long>(m) * R2.c) % (2LL * n)) / static_cast<double>(n), &ps, &pc);
+      G[static_cast<size_t>(m) * nrings + r2] = double2{X2.x * pc - X2.y * ps, X2.x * ps + X2.y * pc};
+    }
   }
 }
 
-// Synthesis: B[j] = sum_{m = j mod n} w_m F_m e^{i m pi c / n}, y_a = Re sum_j B[j] e^{2 pi i j a / n}
-// = Re FFT(conj B)[a].
+// B[j] = sum_{m = j mod n, m <= L} w_m F_m e^{i m pi c / n} of ring r
+__device__ __forceinline__ double2 belt_fold(const double2* __restrict__ F, int nrings, int r, int L, int n, int c,
+                                             int j) {
+  double br = 0.0, bi = 0.0;
+  for (int m = j; m <= L; m += n) {
+    const double2 f = F[static_cast<size_t>(m) * nrings + r];
+    const long long num = (static_cast<long long>(m) * c) % (2LL * n);
+    double ps, pc;
+    sincospi(static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+    const double w = m == 0 ? 1.0 : 2.0;
+    br += w * (f.x * pc - f.y * ps);
+    bi += w * (f.x * ps + f.y * pc);
+  }
+  return double2{br, bi};
+}
+
+// Synthesis: y_a = Re sum_j B[j] e^{2 pi i j a / n} = Re FFT(u)[a] with u = conj B, which is FFT(C)[a]
+// for the Hermitian C[j] = (u[j] + conj u[-j]) / 2; two rings a workgroup: FFT(C1 + i C2) = y1 + i y2.
 template <typename T, bool ACC>
 __global__ __launch_bounds__(kFftThreads) void sht_belt_ifft_kernel(const double2* __restrict__ F,
                                                                     const ShtRing* __restrict__ rings, int nrings,
-                                                                    int ring0, int L, int logn,
+                                                                    int ring0, int nr, int L, int logn,
                                                                     T* __restrict__ y) {
   extern __shared__ double2 s_fft[];
   __shared__ double2 s_twh[64], s_twl[64];
-  const int r = ring0 + static_cast<int>(blockIdx.x);
-  const ShtRing R = convreal::ldu_record(rings[r]);
-  const int n = R.n;
+  const int r1 = ring0 + 2 * static_cast<int>(blockIdx.x);
+  const bool two = r1 + 1 < ring0 + nr;
+  const int r2 = two ? r1 + 1 : r1;
+  const ShtRing R1 = convreal::ldu_record(rings[r1]);
+  const ShtRing R2 = convreal::ldu_record(rings[r2]);
+  const int n = R1.n;
   convreal::lds_twiddles_fill(s_twh, s_twl, n);
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    double br = 0.0, bi = 0.0;
-    for (int m = j; m <= L; m += n) {
-      const double2 f = F[static_cast<size_t>(m) * nrings + r];
-      const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
-      double ps, pc;
-      sincospi(static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
-      const double w = m == 0 ? 1.0 : 2.0;
-      br += w * (f.x * pc - f.y * ps);
-      bi += w * (f.x * ps + f.y * pc);
+    const int jm = (n - j) & (n - 1);
+    // C[j] = (conj B[j] + B[-j]) / 2
+    const double2 a1 = belt_fold(F, nrings, r1, L, n, R1.c, j), b1 = belt_fold(F, nrings, r1, L, n, R1.c, jm);
+    const double2 c1{0.5 * (a1.x + b1.x), 0.5 * (b1.y - a1.y)};
+    double2 c2{0.0, 0.0};
+    if (two) {
+      const double2 a2 = belt_fold(F, nrings, r2, L, n, R2.c, j), b2 = belt_fold(F, nrings, r2, L, n, R2.c, jm);
+      c2 = double2{0.5 * (a2.x + b2.x), 0.5 * (b2.y - a2.y)};
     }
-    s_fft[convreal::bitrev(j, logn)] = double2{br, -bi};
+    // C1 + i C2
+    s_fft[convreal::bitrev(j, logn)] = double2{c1.x - c2.y, c1.y + c2.x};
   }
   __syncthreads();
   convreal::fft_stages_tw(s_fft, n, convreal::LdsTwiddles{s_twh, s_twl});
-  T* yr = y + R.start;
+  T* y1 = y + R1.start;
+  T* y2 = y + R2.start;
   for (int a = threadIdx.x; a < n; a += blockDim.x) {
-    if (ACC)
-      yr[a] = static_cast<T>(static_cast<double>(yr[a]) + s_fft[a].x);
-    else
-      yr[a] = static_cast<T>(s_fft[a].x);
+    const double2 v = s_fft[a];
+    if (ACC) {
+      y1[a] = static_cast<T>(static_cast<double>(y1[a]) + v.x);
+      if (two) y2[a] = static_cast<T>(static_cast<double>(y2[a]) + v.y);
+    } else {
+      y1[a] = static_cast<T>(v.x);
+      if (two) y2[a] = static_cast<T>(v.y);
+    }
   }
 }
 
@@ -993,13 +1029,13 @@ hipError_t launch_analysis(const conv_sht_plan* p, const void* map, int dtype, d
   }
   if (p->fft_nrings > 0) {
     const size_t lf = sizeof(double2) * (static_cast<size_t>(1) << p->fft_logn);
-    const dim3 g(static_cast<unsigned>(p->fft_nrings)), b(kFftThreads);
+    const dim3 g(static_cast<unsigned>((p->fft_nrings + 1) / 2)), b(kFftThreads);
     if (dtype == CONV_SHT_F64)
       hipLaunchKernelGGL(sht_belt_fft_kernel<double>, g, b, lf, st, static_cast<const double*>(map), p->d_rings,
-                         p->nrings, p->fft_ring0, p->L, p->fft_logn, p->d_G);
+                         p->nrings, p->fft_ring0, p->fft_nrings, p->L, p->fft_logn, p->d_G);
     else
       hipLaunchKernelGGL(sht_belt_fft_kernel<float>, g, b, lf, st, static_cast<const float*>(map), p->d_rings,
-                         p->nrings, p->fft_ring0, p->L, p->fft_logn, p->d_G);
+                         p->nrings, p->fft_ring0, p->fft_nrings, p->L, p->fft_logn, p->d_G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return launch_analysis_legendre(p, alm, st);
@@ -1049,19 +1085,19 @@ hipError_t launch_ring_synthesis(const conv_sht_plan* p, void* map, int dtype, i
   const int s0 = p->fft_ring0, ns = p->fft_nrings;
   if (ns == 0) return hipSuccess;
   const size_t lf = sizeof(double2) * (static_cast<size_t>(1) << p->fft_logn);
-  const dim3 gf(static_cast<unsigned>(ns)), bf(kFftThreads);
+  const dim3 gf(static_cast<unsigned>((ns + 1) / 2)), bf(kFftThreads);
   if (dtype == CONV_SHT_F64) {
     double* y = static_cast<double*>(map);
     if (accumulate)
-      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, y);
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, ns, p->L, p->fft_logn, y);
     else
-      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, y);
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<double, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, ns, p->L, p->fft_logn, y);
   } else {
     float* y = static_cast<float*>(map);
     if (accumulate)
-      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, y);
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, true>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, ns, p->L, p->fft_logn, y);
     else
-      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, p->L, p->fft_logn, y);
+      hipLaunchKernelGGL((sht_belt_ifft_kernel<float, false>), gf, bf, lf, st, p->d_G, p->d_rings, p->nrings, s0, ns, p->L, p->fft_logn, y);
   }
   return hipGetLastError();
 }
