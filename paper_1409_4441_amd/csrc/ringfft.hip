@@ -102,6 +102,8 @@ __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_spectra_kernel(FftArg
 template <typename T>
 __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_forward_kernel(FftArgs a, const T* __restrict__ x) {
   extern __shared__ double2 s_fft[];
+  __shared__ double2 s_twh[64], s_twl[64];
+  convreal::lds_twiddles_fill(s_twh, s_twl, a.n);
   const int ra = 2 * static_cast<int>(blockIdx.x);
   const bool two = ra + 1 < a.nbelt;
   const T* xa = x + a.rstart[a.belt_lo + ra];
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_forward_kernel(FftArg
   for (int m = threadIdx.x; m < a.n; m += blockDim.x)
     s_fft[bitrev(m, a.logn)] = double2{static_cast<double>(xa[m]), two ? static_cast<double>(xb[m]) : 0.0};
   __syncthreads();
-  fft_stages(s_fft, a.n, a.tw);
+  convreal::fft_stages_tw(s_fft, a.n, convreal::LdsTwiddles{s_twh, s_twl});
   double2* oa = a.X + static_cast<long long>(ra) * a.nbins;
   double2* ob = oa + a.nbins;
   for (int f = threadIdx.x; f < a.nbins; f += blockDim.x) {
@@ -218,6 +220,8 @@ __global__ __launch_bounds__(kAccThreads) void ring_fft_accumulate_kernel(FftArg
 template <typename T>
 __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_inverse_kernel(FftArgs a, T* __restrict__ y) {
   extern __shared__ double2 s_fft[];
+  __shared__ double2 s_twh[64], s_twl[64];
+  convreal::lds_twiddles_fill(s_twh, s_twl, a.n);
   const int ib = static_cast<int>(blockIdx.x);
   const int i = a.belt_lo + ib, mi = a.nrings - 1 - i;
   const int half = a.n / 2;
@@ -233,7 +237,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void ring_fft_inverse_kernel(FftArg
     }
   }
   __syncthreads();
-  fft_stages(s_fft, a.n, a.tw);
+  convreal::fft_stages_tw(s_fft, a.n, convreal::LdsTwiddles{s_twh, s_twl});
   const double scale = a.omega / static_cast<double>(a.n);
   T* yr = y + a.rstart[i];
   T* ym = y + a.rstart[mi];
