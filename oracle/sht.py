@@ -129,6 +129,41 @@ def synthesis(nside: int, alm: np.ndarray, L: int) -> np.ndarray:
     return y
 
 
+def analysis_orders(nside: int, x, L: int, orders) -> dict:
+    """a_lm for l = m..L of the listed orders m only ({m: array}): the sums of analysis() restricted
+    to those orders, for checks on grids where the whole transform takes too long here."""
+    x = np.asarray(x, dtype=np.float64)
+    z, st, n, start, phi0, dphi = _rings(nside)
+    omega = geometry.pixel_area(nside)
+    ms = np.asarray(list(orders), dtype=np.int64)
+    G = np.zeros((len(ms), len(z)), dtype=np.complex128)
+    for r in range(len(z)):
+        a = np.arange(n[r])
+        phi = phi0[r] + a * dphi[r]
+        G[:, r] = np.exp(-1j * np.outer(ms, phi)) @ x[start[r]: start[r] + n[r]]
+    return {int(m): omega * (lambda_lm(L, int(m), z, st) @ G[i]) for i, m in enumerate(ms)}
+
+
+def synthesis_rings(nside: int, alm: np.ndarray, L: int, rings) -> dict:
+    """The pixels of the listed rings only ({ring: array}, 0-based ring index): the sums of
+    synthesis() restricted to those rings."""
+    alm = np.asarray(alm, dtype=np.complex128)
+    z, st, n, start, phi0, dphi = _rings(nside)
+    rs = np.asarray(list(rings), dtype=np.int64)
+    F = np.zeros((L + 1, len(rs)), dtype=np.complex128)
+    for m in range(L + 1):
+        i0 = alm_index(L, m, m)
+        F[m] = alm[i0: i0 + L - m + 1] @ lambda_lm(L, m, z[rs], st[rs])
+    ms = np.arange(L + 1)
+    out = {}
+    for i, r in enumerate(rs):
+        a = np.arange(n[r])
+        phi = phi0[r] + a * dphi[r]
+        e = np.exp(1j * np.outer(phi, ms))
+        out[int(r)] = F[0, i].real + 2.0 * (e[:, 1:] @ F[1:, i]).real
+    return out
+
+
 def multiply(alm: np.ndarray, k_ell: np.ndarray, L: int) -> np.ndarray:
     """b_lm = k_l a_lm."""
     out = np.array(alm, dtype=np.complex128)

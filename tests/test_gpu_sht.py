@@ -2,9 +2,9 @@
 spectrum) and of the hybrid apply, against the FP64 oracle (oracle/sht.py, oracle/convolve.py).
 
 Tolerances (FP64 arithmetic on both sides, different summation orders and ring-sum forms):
-transforms of FP64 maps agree to 1e-11 of the largest coefficient or pixel value (the GPU sums ring
-DFTs by Horner's rule, the oracle by explicit exponentials); FP32 maps are promoted exactly, so the
-same bound holds. The hybrid apply adds the real-space part, at that part's own tolerance (1e-12 for
+transforms of FP64 maps agree to 1e-11 of the largest coefficient or pixel value (the GPU takes ring
+DFTs by FFT, chirp-z convolution or Horner's rule, the oracle by explicit exponentials); FP32 maps are
+promoted exactly, so the same bound holds. The hybrid apply adds the real-space part, at that part's own tolerance (1e-12 for
 FP64 plans, 1e-6 relative rms for the mixed path).
 """
 import math
@@ -89,6 +89,37 @@ def test_polar_orders_below_fp64_range(cuda_device):
         got_y = t.synthesis(torch.from_numpy(a).to(cuda_device)).cpu().numpy()
     _close(got, ref, 1e-11)
     _close(got_y, ref_y, 1e-11)
+
+
+def test_transforms_at_nside_2048_sampled(cuda_device):
+    # the workload's grid: chirp-z convolutions up to 4096 points (polar rings up to 2047 pixels per
+    # quarter), belt rings of 8192 pixels two per FFT; the oracle restricted to a few orders (analysis)
+    # or rings (synthesis: first polar rings, the first chirp-z ring, the last polar ring, the first belt
+    # rings, the equator, the south pole's ring)
+    from oracle import geometry
+    nside, L = 2048, 1500
+    x = np.random.default_rng(21).standard_normal(12 * nside * nside)
+    orders = [0, 1, 1024, 1500]
+    ref = osht.analysis_orders(nside, x, L, orders)
+    with sht.Sht(nside, L) as t:
+        got = t.analysis(torch.from_numpy(x).to(cuda_device)).cpu().numpy()
+    scale = max(float(np.max(np.abs(v))) for v in ref.values())
+    for m in orders:
+        i0 = osht.alm_index(L, m, m)
+        err = float(np.max(np.abs(got[i0: i0 + L - m + 1] - ref[m])))
+        assert err <= 1e-11 * scale, (m, err, scale)
+    Ls = 600
+    a = _rand_alm(Ls, 5)
+    rings = [0, 1, 15, 16, 1500, 2046, 2047, 2048, 4095, 8190]
+    ref_y = osht.synthesis_rings(nside, a, Ls, rings)
+    with sht.Sht(nside, Ls) as t:
+        got_y = t.synthesis(torch.from_numpy(a).to(cuda_device)).cpu().numpy()
+    rt = geometry.ring_table(nside)
+    scale_y = max(float(np.max(np.abs(v))) for v in ref_y.values())
+    for r in rings:
+        g = got_y[rt["start"][r]: rt["start"][r] + rt["n"][r]]
+        err = float(np.max(np.abs(g - ref_y[r])))
+        assert err <= 1e-11 * scale_y, (r, err, scale_y)
 
 
 @pytest.mark.parametrize("nside,L", [(8, 20), (32, 64)])

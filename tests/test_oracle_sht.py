@@ -74,6 +74,33 @@ def test_synthesis_and_analysis_match_direct_sums(nside, L):
     assert np.allclose(a, ref, rtol=1e-11, atol=1e-12 * np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("nside,L", [(4, 10), (8, 20)])
+def test_restricted_transforms_match_direct_sums(nside, L):
+    # analysis_orders / synthesis_rings (the transforms restricted to a few orders or rings, for
+    # checks on large grids) against the same direct sums over Y_lm
+    z, st, phi, _ = geometry.pixel_angles(nside)
+    Y = _Y(L, np.arctan2(st, z), phi)
+    x = synth.white_noise(nside, 1, seed=3 * nside)[0]
+    ref = geometry.pixel_area(nside) * (np.conj(Y) @ x)
+    orders = [0, 1, L // 2, L]
+    got = sht.analysis_orders(nside, x, L, orders)
+    for m in orders:
+        i0 = sht.alm_index(L, m, m)
+        r = ref[i0: i0 + L - m + 1]
+        assert np.allclose(got[m], r, rtol=1e-11, atol=1e-12 * np.max(np.abs(ref))), m
+    alm = synth.draw_alm(np.ones(L + 1), 200 + nside)
+    w = np.ones(sht.alm_size(L))
+    for ell in range(L + 1):
+        w[sht.alm_index(L, ell, 0)] = 0.5
+    direct = 2.0 * np.real((w * alm) @ Y)
+    rt = geometry.ring_table(nside)
+    rings = [0, nside - 1, 2 * nside - 1, 4 * nside - 2]
+    got_y = sht.synthesis_rings(nside, alm, L, rings)
+    for r in rings:
+        d = direct[rt["start"][r]: rt["start"][r] + rt["n"][r]]
+        assert np.allclose(got_y[r], d, rtol=1e-12, atol=1e-12 * np.max(np.abs(direct))), r
+
+
 @pytest.mark.parametrize("nside,L,q", [(4, 16, 5), (8, 24, 100), (16, 40, 1500)])
 def test_convolution_of_a_delta_is_the_kernel_profile(nside, L, q):
     k_ell = synth.gaussian_beam_sigma(L, 0.3)
