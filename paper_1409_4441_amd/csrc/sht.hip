@@ -26,7 +26,7 @@
 //   a_lm = sqrt((4 l^2 - 1) / (l^2 - m^2)), b_lm = sqrt(((l-1)^2 - m^2) / (4 (l-1)^2 - 1)),
 // with (a_lm, b_lm) from a table written at set-up (read with scalar loads: the same for a whole
 // workgroup). lambda_mm below about e^-650 starts scaled by 2^(600 e) with the exponent e kept beside
-// it; every 8 steps a scaled value above 2^400 is brought down by 2^-600, and a ring contributes once
+// it; every 8 steps (synthesis; 16 in the analysis) a scaled value above 2^400 is brought down by 2^-600, and a ring contributes once
 // its exponent is 0 (scaled values are true values times 2^(600 e) <= 2^-144: dropped). The mirror
 // ring (z -> -z) has lambda_lm(-z) = (-1)^(l+m) lambda_lm(z), so one recurrence serves a ring pair:
 // analysis sums G(north) +- G(south), synthesis splits into the even and odd l + m parts.
@@ -52,10 +52,12 @@ namespace {
 
 constexpr int kLegThreads = 512;   // Legendre synthesis: 8 waves
 constexpr int kLegThreadsA = 256;  // Legendre analysis: 4 waves (two workgroups per CU overlap their reductions' barriers)
-constexpr int kFlush = 8;          // l values between reductions (analysis) and rescale checks
+constexpr int kFlush = 8;          // l values between rescale checks (synthesis)
+constexpr int kFlushA = 16;        // l values between reductions and rescale checks (analysis)
 constexpr int kLegChunk = kLegThreads;   // values of l whose coefficients (and alm) are staged in LDS at a time
-static_assert(kLegChunk % 8 == 0, "groups of kFlush values of l never straddle a chunk");
-static_assert(kFlush % (kLegThreadsA / 64) == 0, "the analysis waves share each flush's reductions evenly");
+static_assert(kLegChunk % kFlush == 0 && kLegChunk % kFlushA == 0, "groups of l values never straddle a chunk");
+static_assert(kFlushA * (kLegThreadsA / kFlushA) == kLegThreadsA && kLegThreadsA / kFlushA <= 64,
+              "the analysis reduces each group's values of l with kLegThreadsA / kFlushA lanes of one wave each");
 constexpr int kDftThreads = 256;   // ring sum kernels: 4 waves, one per residue class mod 4
 constexpr int kDftChains = 4;      // frequencies per lane at a time in the analysis ring sums
 constexpr int kFftThreads = 512;   // belt ring FFT kernels and chirp-z ring sums
@@ -607,7 +609,7 @@ __device__ __forceinline__ void start_value(double logpre_m, int m, double s, do
 
 template <int R>
 __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(LegArgs a, int nblk, double2* partial) {
-  __shared__ double2 s_red[kFlush][kLegThreadsA];
+  __shared__ double2 s_red[kFlushA][kLegThreadsA];
   __shared__ double2 s_ab[kLegChunk];
   const int item = blockIdx.x;
   const int m = item / nblk;
@@ -639,12 +641,12 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
   const double2* coef = a.coef + base;
   double2* out = nblk == 1 ? a.alm + base : partial + static_cast<size_t>(blk) * ((a.L + 1LL) * (a.L + 2) / 2) + base;
   const double scale = nblk == 1 ? a.omega : 1.0;
-  // One group: l = l0 .. l0 + kFlush - 1 (l0 - m a multiple of kFlush), the recurrence coefficients
+  // One group: l = l0 .. l0 + kFlushA - 1 (l0 - m a multiple of kFlushA), the recurrence coefficients
   // from the chunk staged in LDS at c0 (CHECK: tests for l = m, with no recurrence step, and l > L).
   auto group = [&](int l0, int c0, auto check_tag) {
     constexpr bool CHECK = decltype(check_tag)::value;
 #pragma unroll
-    for (int u = 0; u < kFlush; ++u) {
+    for (int u = 0; u < kFlushA; ++u) {
       const int l = l0 + u;
       if (CHECK && l > a.L) break;
       if (!CHECK || l > m) {
@@ -660,32 +662,32 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
       double tr[2] = {0.0, 0.0}, ti[2] = {0.0, 0.0};
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        // l - m has the parity of u (l0 - m is a multiple of kFlush)
+        // l - m has the parity of u (l0 - m is a multiple of kFlushA)
         tr[j & 1] = fma(p1[j], (u & 1) ? sor[j] : ser[j], tr[j & 1]);
         ti[j & 1] = fma(p1[j], (u & 1) ? soi[j] : sei[j], ti[j & 1]);
       }
       s_red[u][tid] = double2{tr[0] + tr[1], ti[0] + ti[1]};
     }
     __syncthreads();
-    // wave w adds the kLegThreadsA partial sums of l = l0 + w and l0 + w + 4 (rows past L hold stale
-    // values and are not written)
-#pragma unroll
-    for (int h = 0; h < kFlush / (kLegThreadsA / 64); ++h) {
-      const int w = (tid >> 6) + h * (kLegThreadsA / 64), lane = tid & 63;
+    // S = kLegThreadsA / kFlushA threads per l: thread (u, seg) adds the partial sums seg, seg + S, ...
+    // of l = l0 + u, then a butterfly over the S (rows past L hold stale values and are not written)
+    {
+      constexpr int S = kLegThreadsA / kFlushA;
+      const int u = tid / S, seg = tid % S;
       double sr = 0.0, si = 0.0;
 #pragma unroll
-      for (int q = 0; q < kLegThreadsA / 64; ++q) {
-        const double2 v = s_red[w][lane * (kLegThreadsA / 64) + q];
+      for (int q = 0; q < kLegThreadsA / S; ++q) {
+        const double2 v = s_red[u][seg + S * q];
         sr += v.x;
         si += v.y;
       }
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
+      for (int off = S / 2; off >= 1; off >>= 1) {
         sr += __shfl_xor(sr, off);
         si += __shfl_xor(si, off);
       }
-      const int l = l0 + w;
-      if (lane == 0 && l <= a.L) out[l - m] = double2{scale * sr, scale * si};
+      const int l = l0 + u;
+      if (seg == 0 && l <= a.L) out[l - m] = double2{scale * sr, scale * si};
     }
     __syncthreads();
     // bring scaled values back towards the FP64 range; a ring joins the sums once it is unscaled
@@ -705,7 +707,7 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
       }
     }
   };
-  // the coefficients in chunks of kLegChunk values of l (a multiple of kFlush, so groups never
+  // the coefficients in chunks of kLegChunk values of l (a multiple of kFlushA, so groups never
   // straddle a chunk), loaded by all threads at once
   for (int c0 = m; c0 <= a.L; c0 += kLegChunk) {
     const int cn = min(kLegChunk, a.L + 1 - c0);
@@ -713,7 +715,7 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
     __syncthreads();
     // every group checks its bounds: with 8 rings per thread an unchecked copy of the group exceeds
     // the register file
-    for (int l0 = c0; l0 < c0 + cn; l0 += kFlush) group(l0, c0, std::true_type{});
+    for (int l0 = c0; l0 < c0 + cn; l0 += kFlushA) group(l0, c0, std::true_type{});
     // the groups end with a barrier: the next chunk may overwrite s_ab
   }
 }
