@@ -24,15 +24,19 @@
 //   lambda_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)) sin^m theta,
 //   lambda_lm = a_lm (z lambda_{l-1,m} - b_lm lambda_{l-2,m}),
 //   a_lm = sqrt((4 l^2 - 1) / (l^2 - m^2)), b_lm = sqrt(((l-1)^2 - m^2) / (4 (l-1)^2 - 1)),
-// with (a_lm, b_lm) from a table written at set-up (read with scalar loads: the same for a whole
-// workgroup). lambda_mm below about e^-650 starts scaled by 2^(600 e) with the exponent e kept beside
-// it; every 8 steps (synthesis; 16 in the analysis) a scaled value above 2^400 is brought down by 2^-600, and a ring contributes once
-// its exponent is 0 (scaled values are true values times 2^(600 e) <= 2^-144: dropped). The mirror
+// carried within each group of kFlush values of l as mu_l = lambda_l / C_l (C_l the product of the
+// a's since the group started), which turns a step into mu_l = z mu_{l-1} - e_l mu_{l-2}: one multiply
+// and one multiply-add, with (e_l, C_l) from a table written at set-up and staged in LDS; C_l is folded
+// into the output coefficients (analysis) or the staged a_lm (synthesis), and the last two values of a
+// group go back to lambda before the next. lambda_mm below about e^-600 starts scaled by 2^(600 e)
+// with the exponent e kept beside it (C_l <= 2^85 then keeps mu above the FP64 normal range); after
+// every group a scaled value above 2^400 is brought down by 2^-600, and a ring contributes once its
+// exponent is 0 (scaled values are true values times 2^(600 e) <= 2^-144: dropped). The mirror
 // ring (z -> -z) has lambda_lm(-z) = (-1)^(l+m) lambda_lm(z), so one recurrence serves a ring pair:
 // analysis sums G(north) +- G(south), synthesis splits into the even and odd l + m parts.
 // A workgroup of 512 threads (synthesis; 256 in the analysis) takes one order m and up to 512 R
 // (256 R) north rings (R per thread); analysis
-// reduces over rings every 8 values of l through LDS (each thread first adds its R rings), synthesis
+// reduces over rings after every group through LDS (each thread first adds its R rings), synthesis
 // needs no reduction.
 #include <hip/hip_runtime.h>
 
@@ -52,12 +56,13 @@ namespace {
 
 constexpr int kLegThreads = 512;   // Legendre synthesis: 8 waves
 constexpr int kLegThreadsA = 256;  // Legendre analysis: 4 waves (two workgroups per CU overlap their reductions' barriers)
-constexpr int kFlush = 8;          // l values between rescale checks (synthesis)
-constexpr int kFlushA = 16;        // l values between reductions and rescale checks (analysis)
+constexpr int kFlush = 16;         // l values per group: recurrence scaling, rescale checks, analysis reductions
+constexpr int kFlushS = 8;         // l values per unrolled step group of the synthesis (two per kFlush group)
+static_assert(kFlush % kFlushS == 0 && kFlush / kFlushS == 2, "the synthesis converts back every second unit");
 constexpr int kLegChunk = kLegThreads;   // values of l whose coefficients (and alm) are staged in LDS at a time
-static_assert(kLegChunk % kFlush == 0 && kLegChunk % kFlushA == 0, "groups of l values never straddle a chunk");
-static_assert(kFlushA * (kLegThreadsA / kFlushA) == kLegThreadsA && kLegThreadsA / kFlushA <= 64,
-              "the analysis reduces each group's values of l with kLegThreadsA / kFlushA lanes of one wave each");
+static_assert(kLegChunk % kFlush == 0, "groups of l values never straddle a chunk");
+static_assert(kFlush * (kLegThreadsA / kFlush) == kLegThreadsA && kLegThreadsA / kFlush <= 64,
+              "the analysis reduces each group's values of l with kLegThreadsA / kFlush lanes of one wave each");
 constexpr int kDftThreads = 256;   // ring sum kernels: 4 waves, one per residue class mod 4
 constexpr int kDftChains = 4;      // frequencies per lane at a time in the analysis ring sums
 constexpr int kFftThreads = 512;   // belt ring FFT kernels and chirp-z ring sums
@@ -65,7 +70,7 @@ constexpr int kChirpMin = 16;      // rings with k = n / 4 at least this take th
 constexpr double kInvScale = 0x1p-600;
 constexpr double kRescaleAbove = 0x1p400;
 constexpr double kLogScale = 600.0 * 0.69314718055994530942;
-constexpr double kLogFloor = -650.0;
+constexpr double kLogFloor = -600.0;
 static_assert(kDftThreads == 256, "four waves: one per residue class mod 4");
 
 struct ShtRing {
@@ -609,7 +614,7 @@ __device__ __forceinline__ void start_value(double logpre_m, int m, double s, do
 
 template <int R>
 __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(LegArgs a, int nblk, double2* partial) {
-  __shared__ double2 s_red[kFlushA][kLegThreadsA];
+  __shared__ double2 s_red[kFlush][kLegThreadsA];
   __shared__ double2 s_ab[kLegChunk];
   const int item = blockIdx.x;
   const int m = item / nblk;
@@ -641,19 +646,19 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
   const double2* coef = a.coef + base;
   double2* out = nblk == 1 ? a.alm + base : partial + static_cast<size_t>(blk) * ((a.L + 1LL) * (a.L + 2) / 2) + base;
   const double scale = nblk == 1 ? a.omega : 1.0;
-  // One group: l = l0 .. l0 + kFlushA - 1 (l0 - m a multiple of kFlushA), the recurrence coefficients
+  // One group: l = l0 .. l0 + kFlush - 1 (l0 - m a multiple of kFlush), the recurrence coefficients
   // from the chunk staged in LDS at c0 (CHECK: tests for l = m, with no recurrence step, and l > L).
   auto group = [&](int l0, int c0, auto check_tag) {
     constexpr bool CHECK = decltype(check_tag)::value;
 #pragma unroll
-    for (int u = 0; u < kFlushA; ++u) {
+    for (int u = 0; u < kFlush; ++u) {
       const int l = l0 + u;
       if (CHECK && l > a.L) break;
       if (!CHECK || l > m) {
-        const double2 ab = s_ab[l - c0];
+        const double el = s_ab[l - c0].x;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          const double p2 = ab.x * fma(z[j], p1[j], -ab.y * p0[j]);
+          const double p2 = fma(z[j], p1[j], -el * p0[j]);
           p0[j] = p1[j];
           p1[j] = p2;
         }
@@ -662,17 +667,17 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
       double tr[2] = {0.0, 0.0}, ti[2] = {0.0, 0.0};
 #pragma unroll
       for (int j = 0; j < R; ++j) {
-        // l - m has the parity of u (l0 - m is a multiple of kFlushA)
+        // l - m has the parity of u (l0 - m is a multiple of kFlush)
         tr[j & 1] = fma(p1[j], (u & 1) ? sor[j] : ser[j], tr[j & 1]);
         ti[j & 1] = fma(p1[j], (u & 1) ? soi[j] : sei[j], ti[j & 1]);
       }
       s_red[u][tid] = double2{tr[0] + tr[1], ti[0] + ti[1]};
     }
     __syncthreads();
-    // S = kLegThreadsA / kFlushA threads per l: thread (u, seg) adds the partial sums seg, seg + S, ...
+    // S = kLegThreadsA / kFlush threads per l: thread (u, seg) adds the partial sums seg, seg + S, ...
     // of l = l0 + u, then a butterfly over the S (rows past L hold stale values and are not written)
     {
-      constexpr int S = kLegThreadsA / kFlushA;
+      constexpr int S = kLegThreadsA / kFlush;
       const int u = tid / S, seg = tid % S;
       double sr = 0.0, si = 0.0;
 #pragma unroll
@@ -687,7 +692,19 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
         si += __shfl_xor(si, off);
       }
       const int l = l0 + u;
-      if (seg == 0 && l <= a.L) out[l - m] = double2{scale * sr, scale * si};
+      if (seg == 0 && l <= a.L) {
+        const double sc = scale * s_ab[l - c0].y;   // the sums are of mu_l = lambda_l / C_l
+        out[l - m] = double2{sc * sr, sc * si};
+      }
+    }
+    // back to lambda for the next group (the last group may end past L: nothing follows it)
+    if (l0 + kFlush - 1 <= a.L) {
+      const double c1 = s_ab[l0 + kFlush - 1 - c0].y, c0v = s_ab[l0 + kFlush - 2 - c0].y;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        p1[j] *= c1;
+        p0[j] *= c0v;
+      }
     }
     __syncthreads();
     // bring scaled values back towards the FP64 range; a ring joins the sums once it is unscaled
@@ -707,7 +724,7 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
       }
     }
   };
-  // the coefficients in chunks of kLegChunk values of l (a multiple of kFlushA, so groups never
+  // the coefficients in chunks of kLegChunk values of l (a multiple of kFlush, so groups never
   // straddle a chunk), loaded by all threads at once
   for (int c0 = m; c0 <= a.L; c0 += kLegChunk) {
     const int cn = min(kLegChunk, a.L + 1 - c0);
@@ -715,7 +732,7 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
     __syncthreads();
     // every group checks its bounds: with 8 rings per thread an unchecked copy of the group exceeds
     // the register file
-    for (int l0 = c0; l0 < c0 + cn; l0 += kFlushA) group(l0, c0, std::true_type{});
+    for (int l0 = c0; l0 < c0 + cn; l0 += kFlush) group(l0, c0, std::true_type{});
     // the groups end with a barrier: the next chunk may overwrite s_ab
   }
 }
@@ -759,24 +776,26 @@ __global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(Leg
   const long long base = alm_base(a.L, m);
   const double2* coef = a.coef + base;
   const double2* alm = a.alm + base;
-  // one group l0 .. l0 + kFlush - 1 (as in the analysis kernel: CHECK for the groups that hold l = m
-  // or run past L), coefficients and alm from the chunk staged in LDS at c0
+  // one unit l0 .. l0 + kFlushS - 1 (CHECK for the units that hold l = m or run past L), coefficients
+  // and alm from the chunk staged in LDS at c0; the scaled recurrence goes back to lambda after the
+  // second unit of each kFlush group (the rescale test between may see mu <= lambda: it then acts one
+  // unit later, far inside the FP64 range)
   auto group = [&](int l0, int c0, auto check_tag) {
     constexpr bool CHECK = decltype(check_tag)::value;
 #pragma unroll
-    for (int u = 0; u < kFlush; ++u) {
+    for (int u = 0; u < kFlushS; ++u) {
       const int l = l0 + u;
       if (CHECK && l > a.L) break;
       if (!CHECK || l > m) {
-        const double2 ab = s_ab[l - c0];
+        const double el = s_ab[l - c0].x;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-          const double p2 = ab.x * fma(z[j], p1[j], -ab.y * p0[j]);
+          const double p2 = fma(z[j], p1[j], -el * p0[j]);
           p0[j] = p1[j];
           p1[j] = p2;
         }
       }
-      const double2 b = s_al[l - c0];
+      const double2 b = s_al[l - c0];   // b_lm C_l: the recurrence carries mu_l = lambda_l / C_l
 #pragma unroll
       for (int j = 0; j < R; ++j) {
         if (u & 1) {
@@ -786,6 +805,15 @@ __global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(Leg
           fer[j] = fma(p1[j], b.x, fer[j]);
           fei[j] = fma(p1[j], b.y, fei[j]);
         }
+      }
+    }
+    // back to lambda at the end of a kFlush group (the last group may end past L: nothing follows it)
+    if (((l0 - m) % kFlush) == kFlush - kFlushS && l0 + kFlushS - 1 <= a.L) {
+      const double c1 = s_ab[l0 + kFlushS - 1 - c0].y, c0v = s_ab[l0 + kFlushS - 2 - c0].y;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        p1[j] *= c1;
+        p0[j] *= c0v;
       }
     }
     // rings still scaled drop what they added (true values below 2^-144 of the scaled ones)
@@ -805,12 +833,13 @@ __global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(Leg
     const int cn = min(kLegChunk, a.L + 1 - c0);
     __syncthreads();   // the previous chunk's values are read by every thread
     if (tid < cn) {
-      s_ab[tid] = coef[c0 - m + tid];
-      s_al[tid] = alm[c0 - m + tid];
+      const double2 cf = coef[c0 - m + tid], b = alm[c0 - m + tid];
+      s_ab[tid] = cf;
+      s_al[tid] = double2{b.x * cf.y, b.y * cf.y};
     }
     __syncthreads();
-    for (int l0 = c0; l0 < c0 + cn; l0 += kFlush) {
-      if (l0 > m && l0 + kFlush - 1 <= a.L)
+    for (int l0 = c0; l0 < c0 + cn; l0 += kFlushS) {
+      if (l0 > m && l0 + kFlushS - 1 <= a.L)
         group(l0, c0, std::false_type{});
       else
         group(l0, c0, std::true_type{});
@@ -1166,7 +1195,11 @@ int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
   const convreal::RingGrid g = convreal::make_ring_grid(nside);
   std::vector<ShtRing> rings(g.nrings);
   for (int r = 0; r < g.nrings; ++r) rings[r] = ShtRing{g.z[r], g.s[r], g.start[r], g.n[r], g.c[r]};
-  // recurrence coefficients and l = m normalisations
+  // recurrence coefficients in the scaled form of the kernels, and l = m normalisations. Within a group
+  // of kFlush values of l (l0 - m a multiple of kFlush) the kernels carry mu_l = lambda_l / C_l with
+  // C_l = a_l C_{l-1} (C = 1 for the two values entering the group, and at l = m), so that
+  // lambda_l = a_l (z lambda_{l-1} - b_l lambda_{l-2}) becomes mu_l = z mu_{l-1} - e_l mu_{l-2},
+  // e_l = b_l C_{l-2} / C_{l-1}: one multiply and one multiply-add a step; the table holds (e_l, C_l).
   std::vector<double2> coef(static_cast<size_t>(p->nalm));
   std::vector<double> logpre(lmax + 1);
   double acc = 0.0;
@@ -1174,12 +1207,20 @@ int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
     if (m > 0) acc += std::log((2.0 * m - 1.0) / (2.0 * m));
     logpre[m] = 0.5 * (std::log((2.0 * m + 1.0) / (4.0 * M_PI)) + acc);
     const long long base = static_cast<long long>(m) * (2 * lmax + 3 - m) / 2;
-    coef[base] = double2{0.0, 0.0};
+    coef[base] = double2{0.0, 1.0};
     const double mm = static_cast<double>(m) * m;
+    double c1 = 1.0, c2 = 1.0;   // C_{l-1}, C_{l-2} within the group
     for (int l = m + 1; l <= lmax; ++l) {
+      const int u = (l - m) % kFlush;
+      if (u == 0) c1 = c2 = 1.0;
+      if (u == 1) c2 = 1.0;
       const double dl = l, dl1 = l - 1.0;
-      coef[base + l - m] = double2{std::sqrt((4.0 * dl * dl - 1.0) / (dl * dl - mm)),
-                                   std::sqrt((dl1 * dl1 - mm) / (4.0 * dl1 * dl1 - 1.0))};
+      const double al = std::sqrt((4.0 * dl * dl - 1.0) / (dl * dl - mm));
+      const double bl = std::sqrt((dl1 * dl1 - mm) / (4.0 * dl1 * dl1 - 1.0));
+      const double cl = al * c1;
+      coef[base + l - m] = double2{bl * c2 / c1, cl};
+      c2 = c1;
+      c1 = cl;
     }
   }
   // belt rings (i = N..3N, n = 4N) by FFT when 4N is a power of two (and at least 16)
