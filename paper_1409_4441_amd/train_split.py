@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 TRAIN_SEED = 14094441 + 50
 TEST_SEED = 14094441 + 51
 INIT_SEED = 14094441 + 52
-SCHEDULE = ((3000, 3e-3), (2000, 1e-3), (1000, 3e-4))
+SCHEDULE = ((3000, 3e-3), (3000, 1e-3), (2000, 3e-4))
 
 
 def labels(triples, model):
