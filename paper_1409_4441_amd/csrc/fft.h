@@ -44,14 +44,15 @@ __device__ inline void lds_twiddles_fill(double2* hi, double2* lo, int n) {
 // in-place forward FFT of s[0, n) held in bit-reversed order (natural order out): radix-2 stages of
 // span len = 2, 4, ..., n, taken two at a time (spans len and 2 len in one pass over LDS, each thread
 // on the 4 points that the two stages connect; the same butterflies and twiddles as one stage at a
-// time), and a last single stage when log2 n is odd; tw(m) = exp(-2 pi i m / n)
+// time), and a last single stage when log2 n is odd; tw(m) = exp(-2 pi i m / n). total (a multiple of
+// n): s holds total / n sequences back to back, transformed together (every pass and barrier shared).
 template <typename TW>
-__device__ inline void fft_stages_tw(double2* s, int n, TW tw) {
+__device__ inline void fft_stages_tw(double2* s, int n, TW tw, int total) {
   int len = 2;
   for (; 2 * len <= n; len <<= 2) {
     const int h = len >> 1;
     const int step1 = n / len, step2 = step1 >> 1;
-    for (int t = threadIdx.x; t < n / 4; t += blockDim.x) {
+    for (int t = threadIdx.x; t < total / 4; t += blockDim.x) {
       const int k = t & (h - 1);
       const int base = (t - k) * 4 + k;
       const double2 w1 = tw(k * step1);
@@ -68,7 +69,7 @@ __device__ inline void fft_stages_tw(double2* s, int n, TW tw) {
   }
   if (len <= n) {
     const int h = len >> 1;
-    for (int t = threadIdx.x; t < n / 2; t += blockDim.x) {
+    for (int t = threadIdx.x; t < total / 2; t += blockDim.x) {
       const int k = t & (h - 1);
       const int i0 = (t - k) * 2 + k;
       const double2 b = cmul(s[i0 + h], tw(k));
@@ -80,9 +81,14 @@ __device__ inline void fft_stages_tw(double2* s, int n, TW tw) {
   }
 }
 
+template <typename TW>
+__device__ inline void fft_stages_tw(double2* s, int n, TW tw) {
+  fft_stages_tw(s, n, tw, n);
+}
+
 // the same with the twiddles from a table in memory (n / 2 entries)
 __device__ inline void fft_stages(double2* s, int n, const double2* __restrict__ tw) {
-  fft_stages_tw(s, n, [tw](int m) { return tw[m]; });
+  fft_stages_tw(s, n, [tw](int m) { return tw[m]; }, n);
 }
 
 }  // namespace convreal

@@ -406,10 +406,13 @@ __device__ __forceinline__ int chirp_logm(int k, int nk) {
   return lg;
 }
 
-// s holds FFT(v) in natural order; leave conj(FFT(v) . H~) in bit-reversed order (H~ = H, or conj(H)
-// for the synthesis), ready for the forward FFT that completes the inverse transform
-__device__ __forceinline__ void chirp_product(double2* s, int M, int logm, const double2* __restrict__ H, bool conj_h) {
-  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+// s holds FFT(v) of total / M sequences in natural order; leave conj(FFT(v) . H~) of each in bit-reversed
+// order (H~ = H, or conj(H) for the synthesis), ready for the forward FFT that completes the inverse
+// transform
+__device__ __forceinline__ void chirp_product(double2* s, int M, int logm, const double2* __restrict__ H, bool conj_h,
+                                              int total) {
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int i = t & (M - 1), base = t - i;
     const int j = convreal::bitrev(i, logm);
     if (i > j) continue;
     double2 hi = H[i], hj = H[j];
@@ -417,9 +420,9 @@ __device__ __forceinline__ void chirp_product(double2* s, int M, int logm, const
       hi = cconj(hi);
       hj = cconj(hj);
     }
-    const double2 vi = convreal::cmul(s[i], hi), vj = convreal::cmul(s[j], hj);
-    s[j] = cconj(vi);
-    s[i] = cconj(vj);
+    const double2 vi = convreal::cmul(s[base + i], hi), vj = convreal::cmul(s[base + j], hj);
+    s[base + j] = cconj(vi);
+    s[base + i] = cconj(vj);
   }
   __syncthreads();
 }
@@ -428,7 +431,8 @@ template <typename T>
 __global__ __launch_bounds__(kFftThreads) void sht_ring_dft_chirp_kernel(const T* __restrict__ x,
                                                                          const ShtRing* __restrict__ rings,
                                                                          const int* __restrict__ list, int nrings,
-                                                                         int L, ChirpTabs c, double2* __restrict__ G) {
+                                                                         int L, ChirpTabs c, int lds_elems,
+                                                                         double2* __restrict__ G) {
   extern __shared__ double2 s_fft[];
   const int r = list[blockIdx.x];
   const ShtRing R = convreal::ldu_record(rings[r]);
@@ -442,41 +446,54 @@ __global__ __launch_bounds__(kFftThreads) void sht_ring_dft_chirp_kernel(const T
   const convreal::LdsTwiddles tw{s_twh, s_twl};
   const T* xr = x + R.start;
   const double inv_m = 1.0 / static_cast<double>(M);
-  for (int kappa = 0; kappa < 4 && kappa < nk; ++kappa) {
-    for (int t = threadIdx.x; t < M; t += blockDim.x) {
-      double2 v{0.0, 0.0};
-      if (t < k) {
-        const double x0 = static_cast<double>(xr[t]), x1 = static_cast<double>(xr[t + k]);
-        const double x2 = static_cast<double>(xr[t + 2 * k]), x3 = static_cast<double>(xr[t + 3 * k]);
-        // folded value c_kappa[t] (kappa 1: (x0 - x2) - i (x1 - x3), kappa 3: (x0 - x2) + i (x1 - x3))
-        const double2 cv = kappa == 0 ? double2{(x0 + x2) + (x1 + x3), 0.0}
-                         : kappa == 2 ? double2{(x0 + x2) - (x1 + x3), 0.0}
-                         : double2{x0 - x2, kappa == 1 ? x3 - x1 : x1 - x3};
-        double2 ph = w[t];
-        if (kappa != 0) {
-          double ps, pc;
-          sincospi(-static_cast<double>(kappa * t) / static_cast<double>(2 * k), &ps, &pc);
-          ph = convreal::cmul(double2{pc, ps}, ph);
+  // classes transformed at once: as many M-point sequences as the LDS buffer holds (every FFT pass and
+  // barrier shared), up to all four
+  const int nc = min(4, lds_elems >> logm);
+  for (int k0 = 0; k0 < 4 && k0 < nk; k0 += nc) {
+    const int ncb = min(nc, 4 - k0);
+    for (int ci = 0; ci < ncb; ++ci) {
+      const int kappa = k0 + ci;
+      double2* sb = s_fft + ci * M;
+      for (int t = threadIdx.x; t < M; t += blockDim.x) {
+        double2 v{0.0, 0.0};
+        if (t < k && kappa < nk) {
+          const double x0 = static_cast<double>(xr[t]), x1 = static_cast<double>(xr[t + k]);
+          const double x2 = static_cast<double>(xr[t + 2 * k]), x3 = static_cast<double>(xr[t + 3 * k]);
+          // folded value c_kappa[t] (kappa 1: (x0 - x2) - i (x1 - x3), kappa 3: (x0 - x2) + i (x1 - x3))
+          const double2 cv = kappa == 0 ? double2{(x0 + x2) + (x1 + x3), 0.0}
+                           : kappa == 2 ? double2{(x0 + x2) - (x1 + x3), 0.0}
+                           : double2{x0 - x2, kappa == 1 ? x3 - x1 : x1 - x3};
+          double2 ph = w[t];
+          if (kappa != 0) {
+            double ps, pc;
+            sincospi(-static_cast<double>(kappa * t) / static_cast<double>(2 * k), &ps, &pc);
+            ph = convreal::cmul(double2{pc, ps}, ph);
+          }
+          v = convreal::cmul(cv, ph);
         }
-        v = convreal::cmul(cv, ph);
+        sb[convreal::bitrev(t, logm)] = v;
       }
-      s_fft[convreal::bitrev(t, logm)] = v;
     }
     __syncthreads();
-    convreal::fft_stages_tw(s_fft, M, tw);
-    chirp_product(s_fft, M, logm, H, false);
-    convreal::fft_stages_tw(s_fft, M, tw);
-    // G_m = e^{-i m pi c / n} X[m mod n] for every m = kappa (mod 4) up to L (m mod n = 4 jq + kappa
-    // with jq < qk, n being a multiple of 4)
-    for (int u = threadIdx.x; 4 * u + kappa <= L; u += blockDim.x) {
-      const int m = 4 * u + kappa;
-      const int jq = (m % n) >> 2;
-      const double2 sv = s_fft[jq];
-      const double2 X = convreal::cmul(w[jq], double2{sv.x * inv_m, -sv.y * inv_m});
-      const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
-      double ps, pc;
-      sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
-      G[static_cast<size_t>(m) * nrings + r] = double2{X.x * pc - X.y * ps, X.x * ps + X.y * pc};
+    convreal::fft_stages_tw(s_fft, M, tw, ncb * M);
+    chirp_product(s_fft, M, logm, H, false, ncb * M);
+    convreal::fft_stages_tw(s_fft, M, tw, ncb * M);
+    for (int ci = 0; ci < ncb; ++ci) {
+      const int kappa = k0 + ci;
+      if (kappa >= nk) break;
+      const double2* sb = s_fft + ci * M;
+      // G_m = e^{-i m pi c / n} X[m mod n] for every m = kappa (mod 4) up to L (m mod n = 4 jq + kappa
+      // with jq < qk, n being a multiple of 4)
+      for (int u = threadIdx.x; 4 * u + kappa <= L; u += blockDim.x) {
+        const int m = 4 * u + kappa;
+        const int jq = (m % n) >> 2;
+        const double2 sv = sb[jq];
+        const double2 X = convreal::cmul(w[jq], double2{sv.x * inv_m, -sv.y * inv_m});
+        const long long num = (static_cast<long long>(m) * R.c) % (2LL * n);
+        double ps, pc;
+        sincospi(-static_cast<double>(num) / static_cast<double>(n), &ps, &pc);
+        G[static_cast<size_t>(m) * nrings + r] = double2{X.x * pc - X.y * ps, X.x * ps + X.y * pc};
+      }
     }
     __syncthreads();
   }
@@ -489,7 +506,8 @@ template <typename T, bool ACC>
 __global__ __launch_bounds__(kFftThreads) void sht_ring_idft_chirp_kernel(const double2* __restrict__ F,
                                                                           const ShtRing* __restrict__ rings,
                                                                           const int* __restrict__ list, int nrings,
-                                                                          int L, ChirpTabs c, T* __restrict__ y) {
+                                                                          int L, ChirpTabs c, int lds_elems,
+                                                                          T* __restrict__ y) {
   extern __shared__ double2 s_fft[];
   const int r = list[blockIdx.x];
   const ShtRing R = convreal::ldu_record(rings[r]);
@@ -507,39 +525,50 @@ __global__ __launch_bounds__(kFftThreads) void sht_ring_idft_chirp_kernel(const 
   for (int u = 0; u < kChirpPer; ++u)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[u][q] = 0.0;
-  for (int kappa = 0; kappa < 4 && kappa < nk; ++kappa) {
-    const int qk = (nk - kappa + 3) >> 2;
-    for (int t = threadIdx.x; t < M; t += blockDim.x) s_fft[t] = double2{0.0, 0.0};
+  // classes transformed at once, as in the analysis
+  const int nc = min(4, lds_elems >> logm);
+  for (int k0 = 0; k0 < 4 && k0 < nk; k0 += nc) {
+    const int ncb = min(nc, 4 - k0);
+    for (int t = threadIdx.x; t < ncb * M; t += blockDim.x) s_fft[t] = double2{0.0, 0.0};
     __syncthreads();
-    {
+    for (int ci = 0; ci < ncb; ++ci) {
+      const int kappa = k0 + ci;
+      if (kappa >= nk) break;
+      const int qk = (nk - kappa + 3) >> 2;
+      double2* sb = s_fft + ci * M;
       // B[j], j = 4 t + kappa, times conj(w(t)), in bit-reversed order
       const int nsub = fold_split(qk), sub = static_cast<int>(threadIdx.x) & (nsub - 1);
       for (int t = static_cast<int>(threadIdx.x) / nsub; t < qk; t += static_cast<int>(blockDim.x) / nsub) {
         const double2 b = fold_sum(F, nrings, r, L, n, R.c, 4 * t + kappa, sub, nsub);
-        if (sub == 0) s_fft[convreal::bitrev(t, logm)] = convreal::cmul(b, cconj(w[t]));
+        if (sub == 0) sb[convreal::bitrev(t, logm)] = convreal::cmul(b, cconj(w[t]));
       }
     }
     __syncthreads();
-    convreal::fft_stages_tw(s_fft, M, tw);
-    chirp_product(s_fft, M, logm, H, true);
-    convreal::fft_stages_tw(s_fft, M, tw);
-#pragma unroll
-    for (int u = 0; u < kChirpPer; ++u) {
-      const int ap = static_cast<int>(threadIdx.x) + u * static_cast<int>(blockDim.x);
-      if (ap >= k) continue;
-      const double2 sv = s_fft[ap];
-      // U = e^{i pi kappa a' / (2k)} conj(w(a')) conv[a'], conv = conj(FFT(...)) / M
-      double2 U = convreal::cmul(cconj(w[ap]), double2{sv.x * inv_m, -sv.y * inv_m});
-      if (kappa != 0) {
-        double ps, pc;
-        sincospi(static_cast<double>(kappa * ap) / static_cast<double>(2 * k), &ps, &pc);
-        U = convreal::cmul(double2{pc, ps}, U);
-      }
-      // pixel q k + a': Re(i^{kappa q} U)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int p = (kappa * q) & 3;
-        acc[u][q] += p == 0 ? U.x : (p == 1 ? -U.y : (p == 2 ? -U.x : U.y));
+    convreal::fft_stages_tw(s_fft, M, tw, ncb * M);
+    chirp_product(s_fft, M, logm, H, true, ncb * M);
+    convreal::fft_stages_tw(s_fft, M, tw, ncb * M);
+    for (int ci = 0; ci < ncb; ++ci) {
+      const int kappa = k0 + ci;
+      if (kappa >= nk) break;
+      const double2* sb = s_fft + ci * M;
+  #pragma unroll
+      for (int u = 0; u < kChirpPer; ++u) {
+        const int ap = static_cast<int>(threadIdx.x) + u * static_cast<int>(blockDim.x);
+        if (ap >= k) continue;
+        const double2 sv = sb[ap];
+        // U = e^{i pi kappa a' / (2k)} conj(w(a')) conv[a'], conv = conj(FFT(...)) / M
+        double2 U = convreal::cmul(cconj(w[ap]), double2{sv.x * inv_m, -sv.y * inv_m});
+        if (kappa != 0) {
+          double ps, pc;
+          sincospi(static_cast<double>(kappa * ap) / static_cast<double>(2 * k), &ps, &pc);
+          U = convreal::cmul(double2{pc, ps}, U);
+        }
+        // pixel q k + a': Re(i^{kappa q} U)
+  #pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int p = (kappa * q) & 3;
+          acc[u][q] += p == 0 ? U.x : (p == 1 ? -U.y : (p == 2 ? -U.x : U.y));
+        }
       }
     }
     __syncthreads();
@@ -596,7 +625,7 @@ __global__ __launch_bounds__(kFftThreads) void sht_chirp_setup_kernel(const int*
     }
   }
   __syncthreads();
-  convreal::fft_stages_tw(s_fft, M, convreal::LdsTwiddles{s_twh, s_twl});
+  convreal::fft_stages_tw(s_fft, M, convreal::LdsTwiddles{s_twh, s_twl}, M);
   double2* H = h_tab + h_off[k];
   for (int f = threadIdx.x; f < M; f += blockDim.x) H[f] = s_fft[f];
 }
@@ -913,7 +942,8 @@ struct conv_sht_plan {
   int n_chirp = 0;
   int chirp_logm_max = 0;         // largest convolution length (log2) among them
   struct ChirpRange { int logm, off, count; };
-  std::vector<ChirpRange> chirp_ranges;   // d_chirp in runs of one convolution length (one launch each)
+  std::vector<ChirpRange> chirp_ranges;   // launches over d_chirp (one, largest convolutions first; logm
+                                          // sizes its LDS buffer, which shorter rings fill with several classes)
   double2* d_chirp_w = nullptr;   // chirp tables (ChirpTabs)
   double2* d_chirp_h = nullptr;
   long long* d_chirp_woff = nullptr;
@@ -1052,10 +1082,10 @@ hipError_t launch_analysis(const conv_sht_plan* p, const void* map, int dtype, d
     const int* lst = p->d_chirp + cr.off;
     if (dtype == CONV_SHT_F64)
       hipLaunchKernelGGL(sht_ring_dft_chirp_kernel<double>, g, b, lds, st, static_cast<const double*>(map),
-                         p->d_rings, lst, p->nrings, p->L, chirp_tabs(p), p->d_G);
+                         p->d_rings, lst, p->nrings, p->L, chirp_tabs(p), 1 << cr.logm, p->d_G);
     else
       hipLaunchKernelGGL(sht_ring_dft_chirp_kernel<float>, g, b, lds, st, static_cast<const float*>(map),
-                         p->d_rings, lst, p->nrings, p->L, chirp_tabs(p), p->d_G);
+                         p->d_rings, lst, p->nrings, p->L, chirp_tabs(p), 1 << cr.logm, p->d_G);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (p->fft_nrings > 0) {
@@ -1101,15 +1131,15 @@ hipError_t launch_ring_synthesis(const conv_sht_plan* p, void* map, int dtype, i
     if (dtype == CONV_SHT_F64) {
       double* y = static_cast<double*>(map);
       if (accumulate)
-        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<double, true>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, y);
+        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<double, true>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, 1 << cr.logm, y);
       else
-        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<double, false>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, y);
+        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<double, false>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, 1 << cr.logm, y);
     } else {
       float* y = static_cast<float*>(map);
       if (accumulate)
-        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<float, true>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, y);
+        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<float, true>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, 1 << cr.logm, y);
       else
-        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<float, false>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, y);
+        hipLaunchKernelGGL((sht_ring_idft_chirp_kernel<float, false>), g, b, lds, st, p->d_G, p->d_rings, lst, p->nrings, p->L, c, 1 << cr.logm, y);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
