@@ -43,8 +43,10 @@ def _close(got, ref, rtol):
 # is the usual band limit; power-of-two grids from Nside 4 take the belt rings through FFTs, Nside 12
 # and the smallest grids through the folded sums; rings of 16 pixels or more per quarter take the
 # chirp-z sums (polar rings from Nside 32, every ring but the smallest at Nside 24 and 48; at Nside 64 /
-# L 300 every such ring also folds frequencies, at Nside 48 / L 60 the band limit cuts each class short)
-CASES = [(1, 6), (2, 17), (4, 11), (8, 23), (12, 40), (16, 40), (32, 95), (24, 71), (48, 60), (64, 300)]
+# L 300 every such ring also folds frequencies, at Nside 48 / L 60 the band limit cuts each class short;
+# L 2 and 0 leave residue classes without a frequency)
+CASES = [(1, 6), (2, 17), (4, 11), (8, 23), (12, 40), (16, 40), (32, 95), (24, 71), (48, 60), (64, 300),
+         (32, 2), (48, 0)]
 
 
 @pytest.mark.parametrize("nside,L", CASES)
