@@ -67,14 +67,18 @@ int conv_split_lsq(conv_split_ctx* ctx, const double* k_ell, int ell_cut, double
 int conv_split_error(conv_split_ctx* ctx, const double* k_ell, int ell_cut, double theta_cut, double alpha,
                      double* sigma_rms, double* sigma);
 
-/* Cost model of a split (the paper's Eqs. 7-8 in form, constants measured here):
- *   t_real = a + b * pairs(nside, theta_cut)    real-space convolution of one map
- *   t_sht  = c * ell_cut^2 * lmax               harmonic-space convolution of one map
- *   wall   = max(t_real, t_sht)                 the two run concurrently */
+/* Cost model of a split (the paper's Eqs. 7-8 in form, constants measured here, with two terms that
+ * Eq. 8 does not carry: the transforms' fixed launch cost and their ring sums, which grow with the
+ * pixel count rather than with ell_cut; c0 = c1 = 0 is Eq. 8's form):
+ *   t_real = a + b * pairs(nside, theta_cut)                   real-space convolution of one map
+ *   t_sht  = c0 + c1 * 12 nside^2 + c * ell_cut^2 * lmax       harmonic-space convolution of one map
+ *   wall   = max(t_real, t_sht)                                the two run concurrently */
 typedef struct conv_cost_model {
-  double a; /* seconds */
-  double b; /* seconds per pixel pair */
-  double c; /* seconds per ell_cut^2 lmax */
+  double a;  /* seconds */
+  double b;  /* seconds per pixel pair */
+  double c;  /* seconds per ell_cut^2 lmax */
+  double c0; /* seconds per harmonic convolution */
+  double c1; /* seconds per map pixel of a harmonic convolution */
 } conv_cost_model;
 
 /* Estimated pixel pairs of one map: Npix^2 (1 - cos theta_cut) / 2 (each pixel sees the fraction
@@ -82,11 +86,15 @@ typedef struct conv_cost_model {
 double conv_cost_pairs(int nside, double theta_cut);
 
 /* Least-squares fit of (a, b) to n_real measured real-space times t_real[k] at pairs[k] (n_real >= 2;
- * with one point a = 0), and of c to n_sht harmonic times t_sht[k] at work_sht[k] = ell_cut^2 lmax
- * (through the origin, n_sht >= 1), both on relative residuals (model / t - 1), so that runs of very
- * different length weigh alike. Times must be > 0. Inputs are host arrays. */
-int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const double* work_sht,
-                  const double* t_sht, int n_sht, conv_cost_model* m);
+ * with one point a = 0), and of (c0, c1, c) to n_sht harmonic times t_sht[k] at npix_sht[k] map pixels
+ * and work_sht[k] = ell_cut^2 lmax, both on relative residuals (model / t - 1), so that runs of very
+ * different length weigh alike. The harmonic coefficients are kept non-negative: every non-empty subset
+ * of the three terms with no more terms than points is fitted, and the one with all coefficients >= 0
+ * and the smallest residual wins (the others are 0; a subset with more terms must lower the residual
+ * by more than 1e-9 relative and 1e-20 absolute). Times must be > 0, work > 0.
+ * Inputs are host arrays. */
+int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const double* npix_sht,
+                  const double* work_sht, const double* t_sht, int n_sht, conv_cost_model* m);
 
 /* The model's times for one split; outputs may be NULL. */
 int conv_cost_eval(const conv_cost_model* m, int nside, int lmax, double theta_cut, int ell_cut, double* t_real,

@@ -30,6 +30,7 @@ Readings (the paper is silent or garbled on these):
 from __future__ import annotations
 
 import functools
+import itertools
 import math
 
 import numpy as np
@@ -160,21 +161,39 @@ def pairs_estimate(nside: int, theta_cut: float) -> float:
     return npix * npix * (1.0 - math.cos(theta_cut)) / 2.0
 
 
-def cost_fit(pairs, t_real, work_sht, t_sht):
-    """Measured-constant cost model in the form of Eqs. 7-8: t_real = a + b pairs, t_sht = c ell_cut^2
-    lmax (through the origin), each fitted by least squares on relative residuals (model / t - 1;
-    a = 0 from a single point)."""
+def cost_fit(pairs, t_real, npix_sht, work_sht, t_sht):
+    """Measured-constant cost model: t_real = a + b pairs (the form of Eq. 7) and t_sht = c0 + c1 npix +
+    c ell_cut^2 lmax (Eq. 8's term plus a fixed and a per-pixel term), each fitted by least squares on
+    relative residuals (model / t - 1; a = 0 from a single point). The harmonic coefficients must not
+    be negative: every non-empty subset of the three terms with no more terms than points is fitted,
+    and the subset whose coefficients are all >= 0 with the smallest residual is kept (fewer terms unless
+    more lower the residual beyond rounding). Returns (a, b, c, c0, c1)."""
     pairs, t_real = np.asarray(pairs, float), np.asarray(t_real, float)
-    work_sht, t_sht = np.asarray(work_sht, float), np.asarray(t_sht, float)
+    npix, work_sht, t_sht = np.asarray(npix_sht, float), np.asarray(work_sht, float), np.asarray(t_sht, float)
     if len(pairs) == 1:
         a, b = 0.0, t_real[0] / pairs[0]
     else:
         # minimise sum ((a + b p_k) / t_k - 1)^2: ordinary least squares on rows [1/t_k, p_k/t_k]
         M = np.stack([1.0 / t_real, pairs / t_real], axis=1)
         (a, b), *_ = np.linalg.lstsq(M, np.ones(len(pairs)), rcond=None)
-    u = work_sht / t_sht
-    c = float(np.sum(u) / np.dot(u, u))
-    return float(a), float(b), c
+    R = np.stack([np.ones_like(t_sht), npix, work_sht], axis=1) / t_sht[:, None]   # columns c0, c1, c
+    best = None
+    for size in (1, 2, 3):
+        for cols in itertools.combinations(range(3), size):
+            if size > len(t_sht):
+                continue
+            x, *_ = np.linalg.lstsq(R[:, cols], np.ones(len(t_sht)), rcond=None)
+            if np.any(x < 0) or not np.all(np.isfinite(x)):
+                continue
+            res = float(np.sum((R[:, cols] @ x - 1.0) ** 2))
+            # a subset with more terms must lower the residual by more than rounding (1e-9 relative,
+            # 1e-20 absolute: an exact fit of fewer terms stays)
+            if best is None or res < best[0] * (1.0 - 1e-9) - 1e-20:
+                coef = np.zeros(3)
+                coef[list(cols)] = x
+                best = (res, coef)
+    c0, c1, c = best[1]
+    return float(a), float(b), float(c), float(c0), float(c1)
 
 
 def compensation(K_ell, K_hat, K_tilde) -> float:

@@ -151,7 +151,7 @@ def feasible_cases(cost_path: str):
     from paper_1409_4441_amd import learn, split
     with open(cost_path) as f:
         c = json.load(f)
-    model = split.CostModel(c["a"], c["b"], c["c"])
+    model = split.CostModel.from_dict(c)
     ns, fw, ep = learn.eval_grid()
     th, lc, _, _ = learn.scan(ns, fw, ep, model)
     cases = []

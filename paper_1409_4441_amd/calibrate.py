@@ -7,8 +7,9 @@ beams over Nside 256..2048, FWHM 5'..30' and theta_cut 2..12 sigma (the range th
 visits); times from HIP events around the applies, pair counts exact (conv_real_pairs). Fitted:
 t_real = a + b pairs.
 Harmonic part: the library's harmonic convolution on the GPU (conv_sht_convolve: analysis, product,
-synthesis) with band limit l_cut, at several (Nside, l_cut); fitted: t_sht = c l_cut^2 lmax with
-lmax = 2 Nside (Eq. 8's form). The two halves of a hybrid apply run at the same time on two
+synthesis) with band limit l_cut, at several (Nside, l_cut); fitted: t_sht = c0 + c1 Npix + c l_cut^2
+lmax with lmax = 2 Nside (Eq. 8's form, c l_cut^2 lmax, for the Legendre sums, plus the launches and
+the ring sums, which grow with the pixel count; coefficients >= 0). The two halves of a hybrid apply run at the same time on two
 streams (Fig. 1), so the model's wall time is the slower of the two; a few hybrid applies are timed
 beside the model to show how far that holds on one device.
 """
@@ -90,7 +91,7 @@ def harmonic_points(quick: bool):
             e1.record()
             torch.cuda.synchronize()
             sec = e0.elapsed_time(e1) / reps * 1e-3
-        pts.append({"nside": nside, "ell_cut": lc, "lmax": 2 * nside, "seconds": sec})
+        pts.append({"nside": nside, "ell_cut": lc, "lmax": 2 * nside, "npix": 12 * nside * nside, "seconds": sec})
         print(f"harmonic nside {nside} l_cut {lc}: {sec * 1e3:.2f} ms", flush=True)
     return pts
 
@@ -138,17 +139,18 @@ def main():
     from paper_1409_4441_amd import split
     real = real_space_points(args.quick)
     harm = harmonic_points(args.quick)
-    m = split.CostModel.fit([p["pairs"] for p in real], [p["seconds"] for p in real],
+    m = split.CostModel.fit([p["pairs"] for p in real], [p["seconds"] for p in real], [p["npix"] for p in harm],
                             [p["ell_cut"] ** 2 * p["lmax"] for p in harm], [p["seconds"] for p in harm])
     hyb = hybrid_points(m)
-    out = {"a": m.a, "b": m.b, "c": m.c,
-           "real_space": real, "harmonic": harm, "hybrid": hyb,
-           "note": "t_real = a + b pairs (mixed-precision path, one map); "
-                   "t_sht = c l_cut^2 lmax (GPU harmonic convolution at band limit l_cut); "
-                   "hybrid: measured two-stream applies beside the model"}
+    for p in harm:
+        p["model_seconds"] = m.eval(p["nside"], p["lmax"], 1e-3, p["ell_cut"])[1]
+    out = dict(m.as_dict(), real_space=real, harmonic=harm, hybrid=hyb,
+               note="t_real = a + b pairs (mixed-precision path, one map); "
+                    "t_sht = c0 + c1 npix + c l_cut^2 lmax (GPU harmonic convolution at band limit l_cut); "
+                    "hybrid: measured two-stream applies beside the model")
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
-    print(json.dumps({"a": m.a, "b": m.b, "c": m.c}), flush=True)
+    print(json.dumps(m.as_dict()), flush=True)
 
 
 if __name__ == "__main__":

@@ -377,6 +377,84 @@ int check_search(const conv_split_ctx* c, int nside, double alpha, const double*
   return CONV_REAL_OK;
 }
 
+// Harmonic cost t = c0 + c1 npix + c work on relative residuals, coefficients >= 0: every non-empty
+// subset of the three terms with no more terms than points, by weighted least squares (normal equations
+// of the rows r_j / t_k, columns scaled to unit maximum); the feasible subset with the smallest residual
+// wins (fewer terms unless more lower the residual beyond rounding). coef = {c0, c1, c}.
+bool fit_harmonic(const double* npix, const double* work, const double* t, int n, double (&coef)[3]) {
+  auto reg = [&](int k, int j) { return j == 0 ? 1.0 : (j == 1 ? npix[k] : work[k]); };
+  double scale[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < 3; ++j) scale[j] = std::max(scale[j], reg(k, j) / t[k]);
+  bool found = false;
+  double best = 0.0;
+  // subsets in order of size, then by mask
+  static const int kMasks[7] = {1, 2, 4, 3, 5, 6, 7};
+  for (int mask : kMasks) {
+    int idx[3], p = 0;
+    for (int j = 0; j < 3; ++j)
+      if (mask & (1 << j)) idx[p++] = j;
+    if (p > n) continue;
+    // normal equations N y = v for y_q = x_idx[q] * scale[idx[q]]
+    double N[3][3] = {}, v[3] = {};
+    for (int k = 0; k < n; ++k) {
+      double row[3];
+      for (int q = 0; q < p; ++q) row[q] = reg(k, idx[q]) / t[k] / scale[idx[q]];
+      for (int q = 0; q < p; ++q) {
+        v[q] += row[q];
+        for (int r = 0; r < p; ++r) N[q][r] += row[q] * row[r];
+      }
+    }
+    // Gaussian elimination with partial pivoting
+    bool ok = true;
+    for (int c = 0; c < p && ok; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < p; ++r)
+        if (std::fabs(N[r][c]) > std::fabs(N[piv][c])) piv = r;
+      if (!(std::fabs(N[piv][c]) > 1e-300)) {
+        ok = false;
+        break;
+      }
+      if (piv != c) {
+        for (int q = 0; q < p; ++q) std::swap(N[c][q], N[piv][q]);
+        std::swap(v[c], v[piv]);
+      }
+      for (int r = c + 1; r < p; ++r) {
+        const double f = N[r][c] / N[c][c];
+        for (int q = c; q < p; ++q) N[r][q] -= f * N[c][q];
+        v[r] -= f * v[c];
+      }
+    }
+    if (!ok) continue;
+    double y[3] = {0.0, 0.0, 0.0};
+    for (int c = p - 1; c >= 0; --c) {
+      double acc = v[c];
+      for (int q = c + 1; q < p; ++q) acc -= N[c][q] * y[q];
+      y[c] = acc / N[c][c];
+    }
+    double x[3] = {0.0, 0.0, 0.0};
+    bool feasible = true;
+    for (int q = 0; q < p; ++q) {
+      x[idx[q]] = y[q] / scale[idx[q]];
+      if (!(x[idx[q]] >= 0.0) || !std::isfinite(x[idx[q]])) feasible = false;
+    }
+    if (!feasible) continue;
+    double res = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double d = (x[0] + x[1] * npix[k] + x[2] * work[k]) / t[k] - 1.0;
+      res += d * d;
+    }
+    // subsets come in order of size: a larger one must lower the residual beyond rounding (1e-9
+    // relative, 1e-20 absolute), so that an exact fit of fewer terms stays
+    if (!found || res < best * (1.0 - 1e-9) - 1e-20) {
+      found = true;
+      best = res;
+      for (int j = 0; j < 3; ++j) coef[j] = x[j];
+    }
+  }
+  return found;
+}
+
 }  // namespace
 
 extern "C" {
@@ -489,9 +567,9 @@ double conv_cost_pairs(int nside, double theta_cut) {
   return npix * npix * s * s;
 }
 
-int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const double* work_sht,
-                  const double* t_sht, int n_sht, conv_cost_model* m) {
-  if (!pairs || !t_real || !work_sht || !t_sht || !m || n_real < 1 || n_sht < 1) {
+int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const double* npix_sht,
+                  const double* work_sht, const double* t_sht, int n_sht, conv_cost_model* m) {
+  if (!pairs || !t_real || !npix_sht || !work_sht || !t_sht || !m || n_real < 1 || n_sht < 1) {
     set_error("conv_cost_fit: NULL argument or empty measurement set");
     return CONV_REAL_EINVAL;
   }
@@ -532,19 +610,21 @@ int conv_cost_fit(const double* pairs, const double* t_real, int n_real, const d
     b = (s0 * sxy - sx * sy) / den;
     a = (sy - b * sx) / s0;
   }
-  double sw = 0, swt = 0;
-  for (int k = 0; k < n_sht; ++k) {
-    const double w = 1.0 / (t_sht[k] * t_sht[k]);
-    sw += w * work_sht[k] * work_sht[k];
-    swt += w * work_sht[k] * t_sht[k];
-  }
-  if (!(sw > 0.0)) {
-    set_error("conv_cost_fit: harmonic work must be > 0");
+  for (int k = 0; k < n_sht; ++k)
+    if (!(work_sht[k] > 0.0) || !(npix_sht[k] > 0.0)) {
+      set_error("conv_cost_fit: harmonic work and pixel counts must be > 0");
+      return CONV_REAL_EINVAL;
+    }
+  double coef[3];
+  if (!fit_harmonic(npix_sht, work_sht, t_sht, n_sht, coef)) {
+    set_error("conv_cost_fit: no non-negative fit of the harmonic times");
     return CONV_REAL_EINVAL;
   }
   m->a = a;
   m->b = b;
-  m->c = swt / sw;
+  m->c0 = coef[0];
+  m->c1 = coef[1];
+  m->c = coef[2];
   return CONV_REAL_OK;
 }
 
@@ -555,7 +635,9 @@ int conv_cost_eval(const conv_cost_model* m, int nside, int lmax, double theta_c
     return CONV_REAL_EINVAL;
   }
   const double tr = m->a + m->b * conv_cost_pairs(nside, theta_cut);
-  const double ts = m->c * static_cast<double>(ell_cut) * static_cast<double>(ell_cut) * static_cast<double>(lmax);
+  const double npix = 12.0 * static_cast<double>(nside) * static_cast<double>(nside);
+  const double ts = m->c0 + m->c1 * npix +
+                    m->c * static_cast<double>(ell_cut) * static_cast<double>(ell_cut) * static_cast<double>(lmax);
   if (t_real) *t_real = tr;
   if (t_sht) *t_sht = ts;
   if (wall) *wall = std::max(tr, ts);

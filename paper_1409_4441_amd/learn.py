@@ -289,7 +289,7 @@ class Predictor:
         params, meta = load(path or DEFAULT_MODEL)
         with open(cost_path or DEFAULT_COST) as f:
             c = json.load(f)
-        return cls(params, meta["norm"], _split.CostModel(c["a"], c["b"], c["c"]))
+        return cls(params, meta["norm"], _split.CostModel.from_dict(c))
 
     def close(self):
         self.net.close()

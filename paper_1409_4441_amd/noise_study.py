@@ -96,7 +96,7 @@ def study(cost_json: str, fwhms=(7.0, 8.0, 9.0, 10.0), ell_ns=(None, 3000, 2000,
     from paper_1409_4441_amd import learn, split
     with open(cost_json) as f:
         c = json.load(f)
-    model = split.CostModel(c["a"], c["b"], c["c"])
+    model = split.CostModel.from_dict(c)
     t_full_here = model.eval(NSIDE, LMAX, 1e-3, LMAX)[1]
     rows = []
     for ell_n in ell_ns:

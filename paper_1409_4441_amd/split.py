@@ -4,7 +4,7 @@
     ctx = split.Context(lmax, theta_max)                  # Gauss-Legendre samples, Legendre operator
     k_hat, k_theta, k_real, k_tilde = ctx.lsq(k_ell, ell_cut, theta_cut)   # Eqs. 3-5
     sigma_rms, sigma = ctx.error(k_ell, ell_cut, theta_cut, alpha=5.0)      # Eqs. 2 and 6
-    model = split.CostModel.fit(pairs, t_real, work_sht, t_sht)
+    model = split.CostModel.fit(pairs, t_real, npix_sht, work_sht, t_sht)
     best = ctx.search(k_ell, nside, bound, theta_grid, model)             # the split scan
 
 Everything runs in libconvreal's host code (FP64); no GPU is needed.
@@ -30,7 +30,8 @@ _iptr_t = ctypes.POINTER(ctypes.c_int)
 
 
 class _Cost(ctypes.Structure):
-    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double)]
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double), ("c0", ctypes.c_double),
+                ("c1", ctypes.c_double)]
 
 
 def _bind():
@@ -44,7 +45,7 @@ def _bind():
     lib.conv_split_set_max_ell_fraction.argtypes = [_c_void_p, _c_double]
     lib.conv_cost_pairs.argtypes = [_c_int, _c_double]
     lib.conv_cost_pairs.restype = _c_double
-    lib.conv_cost_fit.argtypes = [_dptr_t, _dptr_t, _c_int, _dptr_t, _dptr_t, _c_int, ctypes.POINTER(_Cost)]
+    lib.conv_cost_fit.argtypes = [_dptr_t, _dptr_t, _c_int, _dptr_t, _dptr_t, _dptr_t, _c_int, ctypes.POINTER(_Cost)]
     lib.conv_cost_eval.argtypes = [ctypes.POINTER(_Cost), _c_int, _c_int, _c_double, _c_int, _dptr_t, _dptr_t,
                                    _dptr_t]
     lib.conv_split_search.argtypes = [_c_void_p, _dptr_t, _c_int, _c_double, _c_double, _dptr_t, _c_int, _c_int,
@@ -73,10 +74,10 @@ def _f64(a, n=None, name="array"):
 
 
 class CostModel:
-    """t_real = a + b pairs, t_sht = c ell_cut^2 lmax, wall = max of the two."""
+    """t_real = a + b pairs, t_sht = c0 + c1 npix + c ell_cut^2 lmax, wall = max of the two."""
 
-    def __init__(self, a: float, b: float, c: float):
-        self._s = _Cost(float(a), float(b), float(c))
+    def __init__(self, a: float, b: float, c: float, c0: float = 0.0, c1: float = 0.0):
+        self._s = _Cost(float(a), float(b), float(c), float(c0), float(c1))
 
     @property
     def a(self):
@@ -90,16 +91,30 @@ class CostModel:
     def c(self):
         return self._s.c
 
+    @property
+    def c0(self):
+        return self._s.c0
+
+    @property
+    def c1(self):
+        return self._s.c1
+
     def as_dict(self):
-        return {"a": self.a, "b": self.b, "c": self.c}
+        return {"a": self.a, "b": self.b, "c": self.c, "c0": self.c0, "c1": self.c1}
 
     @classmethod
-    def fit(cls, pairs, t_real, work_sht, t_sht) -> "CostModel":
+    def from_dict(cls, d) -> "CostModel":
+        """From a dict with a, b, c and optionally c0, c1 (cost_model.json)."""
+        return cls(d["a"], d["b"], d["c"], d.get("c0", 0.0), d.get("c1", 0.0))
+
+    @classmethod
+    def fit(cls, pairs, t_real, npix_sht, work_sht, t_sht) -> "CostModel":
         p, tr = _f64(pairs), _f64(t_real)
-        w, ts = _f64(work_sht), _f64(t_sht)
+        npx, w, ts = _f64(npix_sht), _f64(work_sht), _f64(t_sht)
         m = _Cost()
-        _check(lib.conv_cost_fit(_d(p), _d(tr), len(p), _d(w), _d(ts), len(w), ctypes.byref(m)), "conv_cost_fit")
-        return cls(m.a, m.b, m.c)
+        _check(lib.conv_cost_fit(_d(p), _d(tr), len(p), _d(npx), _d(w), _d(ts), len(w), ctypes.byref(m)),
+               "conv_cost_fit")
+        return cls(m.a, m.b, m.c, m.c0, m.c1)
 
     def eval(self, nside: int, lmax: int, theta_cut: float, ell_cut: int):
         """(t_real, t_sht, wall) in seconds."""

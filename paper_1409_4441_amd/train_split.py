@@ -102,7 +102,7 @@ def main():
     from paper_1409_4441_amd import learn, split
     with open(args.cost) as f:
         c = json.load(f)
-    model = split.CostModel(c["a"], c["b"], c["c"])
+    model = split.CostModel.from_dict(c)
 
     train = learn.draw_triples(args.n_train, TRAIN_SEED)
     test = learn.draw_triples(args.n_test, TEST_SEED)
@@ -132,7 +132,7 @@ def main():
     grid = learn.eval_grid()
     grid_metrics = evaluate(pred, grid, labels(grid, model)[:4], model)
     pred.close()
-    meta = {"norm": norm, "cost_model": {"a": model.a, "b": model.b, "c": model.c},
+    meta = {"norm": norm, "cost_model": model.as_dict(),
             "train": {"n": args.n_train, "seed": TRAIN_SEED, "init_seed": INIT_SEED,
                       "schedule": [list(s) for s in SCHEDULE], "seconds": t_train,
                       "loss_first": float(hist[0]), "loss_last": float(hist[-1]),

@@ -166,12 +166,16 @@ def test_reduced_solve_rows_below_cut_are_exact():
 def test_cost_fit_recovers_linear_model():
     pairs = np.array([1e9, 5e9, 2e10, 4.8e10])
     t_real = 2e-4 + 3e-14 * pairs
-    work = np.array([1e6, 1e8, 1e10]) * 4096
+    npix = np.array([7.9e5, 3.1e6, 1.26e7, 5.03e7])
+    work = np.array([1e6, 1e8, 3e9, 1e10]) * 4096
     t_sht = 2.5e-12 * work
-    a, b, c = split.cost_fit(pairs, t_real, work, t_sht)
+    a, b, c, c0, c1 = split.cost_fit(pairs, t_real, npix, work, t_sht)
     assert a == pytest.approx(2e-4, rel=1e-9) and b == pytest.approx(3e-14, rel=1e-9)
-    assert c == pytest.approx(2.5e-12, rel=1e-12)
-    assert split.cost_fit([4e9], [1e-3], work, t_sht)[:2] == (0.0, pytest.approx(2.5e-13))
+    assert c == pytest.approx(2.5e-12, rel=1e-12) and (c0, c1) == (0.0, 0.0)   # Eq. 8's form exactly
+    t3 = 3e-5 + 2e-11 * npix + 1e-12 * work
+    _, _, c, c0, c1 = split.cost_fit(pairs, t_real, npix, work, t3)
+    assert (c, c0, c1) == (pytest.approx(1e-12, rel=1e-9), pytest.approx(3e-5, rel=1e-9), pytest.approx(2e-11, rel=1e-9))
+    assert split.cost_fit([4e9], [1e-3], npix, work, t_sht)[:2] == (0.0, pytest.approx(2.5e-13))
 
 
 def test_pairs_estimate_tracks_the_exact_count():
@@ -268,27 +272,40 @@ def test_compensation_is_the_real_space_parts_low_l_content():
 
 
 def test_cost_fit_minimises_relative_residuals():
-    # the fit minimises sum (model_k / t_k - 1)^2: at its answer the objective's gradient vanishes and
-    # every small step in (a, b) or c raises it
+    # the fit minimises sum (model_k / t_k - 1)^2, the harmonic coefficients kept >= 0: at its answer
+    # the gradient vanishes along every positive coefficient and does not point into the feasible
+    # side along a zero one (the optimality conditions of this convex problem), and small steps raise it
     g = np.random.default_rng(4)
     pairs = np.array([1e6, 3e7, 1e9, 2e10, 5e11])
     t_real = (4e-5 + 2e-14 * pairs) * (1 + 0.2 * g.standard_normal(5))
-    work = np.array([1e8, 1e9, 3e10, 7e10])
-    t_sht = 1e-12 * work * (1 + 0.2 * g.standard_normal(4))
-    a, b, c = split.cost_fit(pairs, t_real, work, t_sht)
+    npix = np.array([7.9e5, 7.9e5, 3.1e6, 1.26e7, 1.26e7, 5.03e7])
+    work = np.array([1e8, 1e9, 3e10, 7e10, 1e12, 6e13])
+    for scale_c0, scale_c1 in [(1e-4, 2e-11), (0.0, 3e-11), (1e-4, 0.0)]:
+        t_sht = (scale_c0 + scale_c1 * npix + 1e-12 * work) * (1 + 0.2 * g.standard_normal(6))
+        a, b, c, c0, c1 = split.cost_fit(pairs, t_real, npix, work, t_sht)
+        R = np.stack([np.ones(6), npix, work], axis=1) / t_sht[:, None]
+        x = np.array([c0, c1, c])
+        assert np.all(x >= 0)
+        grad = 2 * R.T @ (R @ x - 1.0)
+        f = lambda v: float(np.sum((R @ v - 1.0) ** 2))
+        for j in range(3):
+            if x[j] > 0:
+                assert abs(grad[j]) * x[j] <= 1e-9 * max(f(x), 1e-30) + 1e-12, (j, grad, x)
+                for d in (1e-3, -1e-3):
+                    y = x.copy()
+                    y[j] *= 1 + d
+                    assert f(y) > f(x)
+            else:
+                assert grad[j] >= -1e-9, (j, grad, x)
 
     def f_real(a_, b_):
         return np.sum(((a_ + b_ * pairs) / t_real - 1.0) ** 2)
-
-    def f_sht(c_):
-        return np.sum((c_ * work / t_sht - 1.0) ** 2)
 
     ga = np.sum(2 * ((a + b * pairs) / t_real - 1.0) / t_real)
     gb = np.sum(2 * ((a + b * pairs) / t_real - 1.0) * pairs / t_real)
     assert abs(ga) * abs(a) <= 1e-9 and abs(gb) * abs(b) <= 1e-9
     for da, db in [(1e-3, 0), (-1e-3, 0), (0, 1e-3), (0, -1e-3)]:
         assert f_real(a * (1 + da), b * (1 + db)) > f_real(a, b)
-    assert f_sht(c * 1.001) > f_sht(c) and f_sht(c * 0.999) > f_sht(c)
 
 
 def test_wiener_weights_and_error_normalisation():

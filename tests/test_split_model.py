@@ -72,18 +72,24 @@ def test_node_counts_match_the_rule():
 def test_cost_model_matches_oracle():
     pairs = np.array([2e9, 9e9, 4.8e10])
     t_real = np.array([0.9e-3, 1.7e-3, 4.1e-3])
-    work = np.array([512.0 ** 2 * 1024, 1024.0 ** 2 * 2048, 1500.0 ** 2 * 4096])
-    t_sht = np.array([0.02, 0.2, 1.1])
-    m = split.CostModel.fit(pairs, t_real, work, t_sht)
-    a, b, c = osplit.cost_fit(pairs, t_real, work, t_sht)
-    assert (m.a, m.b, m.c) == (pytest.approx(a, rel=1e-9, abs=1e-15), pytest.approx(b, rel=1e-9),
-                               pytest.approx(c, rel=1e-12))
+    npix = np.array([3.1e6, 1.26e7, 5.03e7, 5.03e7])
+    work = np.array([512.0 ** 2 * 1024, 1024.0 ** 2 * 2048, 512.0 ** 2 * 4096, 1500.0 ** 2 * 4096])
+    t_sht = np.array([0.3e-3, 1.2e-3, 1.8e-3, 4.2e-3])
+    m = split.CostModel.fit(pairs, t_real, npix, work, t_sht)
+    a, b, c, c0, c1 = osplit.cost_fit(pairs, t_real, npix, work, t_sht)
+    assert (m.a, m.b) == (pytest.approx(a, rel=1e-9, abs=1e-15), pytest.approx(b, rel=1e-9))
+    assert (m.c, m.c0, m.c1) == (pytest.approx(c, rel=1e-8, abs=1e-25), pytest.approx(c0, rel=1e-8, abs=1e-15),
+                                 pytest.approx(c1, rel=1e-8, abs=1e-22))
+    assert m.c > 0 and (m.c0 > 0 or m.c1 > 0)   # this data needs more than Eq. 8's term
     for nside, tc in [(2048, 30 * ARCMIN), (256, 2.0 * math.pi / 180), (64, math.pi)]:
         assert split.pairs_estimate(nside, tc) == pytest.approx(osplit.pairs_estimate(nside, tc), rel=1e-12)
     tr, ts, wall = m.eval(2048, 4096, 30 * ARCMIN, 1500)
     assert tr == pytest.approx(a + b * osplit.pairs_estimate(2048, 30 * ARCMIN), rel=1e-12)
-    assert ts == pytest.approx(c * 1500 ** 2 * 4096, rel=1e-12)
+    assert ts == pytest.approx(c0 + c1 * 12 * 2048 ** 2 + c * 1500 ** 2 * 4096, rel=1e-8)
     assert wall == max(tr, ts)
+    # Eq. 8's form alone (c0 = c1 = 0) when the times follow it
+    m2 = split.CostModel.fit(pairs, t_real, npix, work, 1e-12 * work)
+    assert (m2.c, m2.c0, m2.c1) == (pytest.approx(1e-12, rel=1e-12), 0.0, 0.0)
 
 
 def test_search_matches_oracle_scan():
