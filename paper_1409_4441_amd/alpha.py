@@ -1,4 +1,4 @@
-"""Measure alpha of Eq. 6 for this build: the actual error of the split convolution against the
+"""Measure alpha of Eq. 6 for this library: the actual error of the split convolution against the
 full-kernel convolution, divided by the error model's estimate (Eq. 6 with alpha = 1).
 
     python -m paper_1409_4441_amd.alpha [--nside 512] [--paths f64,mixed] [--out alpha_512.json]

@@ -29,7 +29,7 @@ from . import split as _split
 
 N_PARAMS = 4546
 IN, HIDDEN, OUT = 3, 64, 2
-# Eq. 6's alpha: the paper's 5, an upper bound for this build (the measured ratio of the split's
+# Eq. 6's alpha: the paper's 5, an upper bound for this library (the measured ratio of the split's
 # power-spectrum error to Eq. 6 with alpha = 1 is 1.0-4.6 over the splits the search chooses)
 ALPHA = 5.0
 # largest compensation (max_{l <= l_cut} |(P x)_l| / max |K_l|) a split may need: the paper's fits

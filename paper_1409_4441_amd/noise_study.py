@@ -14,7 +14,7 @@ alpha = 5; bound 1e-5) picks the cheapest split under
 
 * the paper's cost models (Eqs. 7-8: GTX 480 real-space convolver, one CPU core for the harmonic part):
   speedup = 160 s / max(t_gpu, t_cpu), the ratio the paper quotes;
-* this build's measured model (cost_model.json: mixed-precision real-space path and the GPU harmonic
+* this library's measured model (cost_model.json: mixed-precision real-space path and the GPU harmonic
   convolution on one MI355X): speedup = t_sht(lmax) / wall.
 The error of every split is the library's (conv_split_error with the case's weights).
 """
