@@ -936,7 +936,7 @@ struct conv_sht_plan {
   int fft_ring0 = 0;              // belt rings ring0 .. ring0 + fft_nrings - 1 by FFT (power-of-two Nside)
   int fft_nrings = 0;
   int fft_logn = 0;
-  int* d_direct = nullptr;        // rings of the folded sums (k < kChirpMin, or every ring left by the FFTs)
+  int* d_direct = nullptr;        // rings of the folded Horner sums (k < kChirpMin)
   int n_direct = 0;
   int* d_chirp = nullptr;         // rings of the chirp-z ring sums
   int n_chirp = 0;
