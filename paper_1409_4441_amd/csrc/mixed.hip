@@ -17,8 +17,8 @@
 // a -> a + n/4, reflection phi -> -phi i.e. a -> n - a - c, north/south mirror i -> 4N - i) leaves
 // every weight invariant when both pixels move together, so one weight row of output pixel a
 // serves its 16 images: y[img_g(a)] = sum_b w(a, b) x[img_g(b)]. A wave takes 16 output pixels of
-// the group's fundamental domain and, per neighbour ring, computes D[16 pixels][16 images] +=
-// W[16][K] X[K][16]. W is either evaluated on the fly: integer azimuth numerator -> alpha = dphi/2,
+// the group's fundamental domain (32 from a weight store: two blocks that share each step's inputs)
+// and, per neighbour ring, computes D[16 pixels][16 images] += W[16][K] X[K][16] per block. W is either evaluated on the fly: integer azimuth numerator -> alpha = dphi/2,
 // sin^2 alpha by a polynomial, d^2 = A + B sin^2 alpha, all in FP64 (the oscillating kernel is
 // sensitive to d at the 1e-8 level near the cut), then the 4-point interpolant in cubic form from
 // an LDS table of per-segment FP32 coefficients; or it is streamed from a weight store built once
