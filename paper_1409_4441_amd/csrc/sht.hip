@@ -71,6 +71,11 @@ constexpr double kInvScale = 0x1p-600;
 constexpr double kRescaleAbove = 0x1p400;
 constexpr double kLogScale = 600.0 * 0.69314718055994530942;
 constexpr double kLogFloor = -600.0;
+// North rings are grouped in chunks of kDeadChunk (ring 0 the northernmost) for skipping, per order m,
+// the polar rings whose scaled Legendre values never come back into the sums before l = L
+constexpr int kDeadChunk = 256;
+static_assert(kLegThreadsA == kDeadChunk && kLegThreads == 2 * kDeadChunk,
+              "a thread's ring ranges are one chunk wide (analysis) or two (synthesis)");
 static_assert(kDftThreads == 256, "four waves: one per residue class mod 4");
 
 struct ShtRing {
@@ -87,6 +92,7 @@ struct LegArgs {
   const double* logpre;    // per m: log of the l = m normalisation
   double2* G;              // [m][ring]: ring sums (analysis input) or F_m (synthesis output)
   double2* alm;            // m-major alm (analysis output, synthesis input)
+  const int* dead;         // per m: leading chunks of kDeadChunk north rings that add nothing
   int L;
   int nrings;
   int nnorth;              // rings 0 .. nnorth - 1 are the north half, the last one the equator
@@ -641,13 +647,57 @@ __device__ __forceinline__ void start_value(double logpre_m, int m, double s, do
   *e = ee;
 }
 
+// Per order m, dead[m]: the number of leading chunks of kDeadChunk north rings whose rings never take
+// part in either transform's sums. A ring adds to the sums once its carried exponent is zero: from the
+// start if log lambda_mm >= kLogFloor, else once the rescaled value has passed kRescaleAbove at a
+// check, i.e. once the true |lambda_lm| exceeds 2^-200 at some l <= L. This pass follows the plain
+// recurrence lambda_l = a_l (z lambda_{l-1} - lambda_{l-2} / a_{l-1}), a_l = sqrt((4l^2-1)/(l^2-m^2)),
+// and calls a ring live once log lambda_mm > kLogFloor - 64 or the true |lambda_lm| passes 2^-300 at
+// any l: margins of 2^64 and 2^100 over the transforms' own tests, far beyond any rounding difference.
+// Below its turning point |lambda_lm| grows with the colatitude, so a chunk whose last (most
+// equatorial) ring is dead is dead throughout; the chunks from the first live one on are all kept.
+__global__ void sht_dead_chunks_kernel(const ShtRing* __restrict__ rings, const double* __restrict__ logpre, int L,
+                                       int nnorth, int* __restrict__ dead) {
+  __shared__ int s_first;
+  const int m = blockIdx.x;
+  const int nchunks = (nnorth + kDeadChunk - 1) / kDeadChunk;
+  if (threadIdx.x == 0) s_first = nchunks;
+  __syncthreads();
+  for (int c = threadIdx.x; c < nchunks; c += blockDim.x) {
+    const ShtRing Rg = rings[min((c + 1) * kDeadChunk, nnorth) - 1];
+    const double lg = m == 0 ? logpre[m] : fma(static_cast<double>(m), log(Rg.s), logpre[m]);
+    bool live = lg > kLogFloor - 64.0;
+    if (!live) {
+      int e = static_cast<int>(ceil((kLogFloor - lg) / kLogScale));   // lambda_mm = p1 2^(-600 e)
+      double p0 = 0.0, p1 = exp(fma(static_cast<double>(e), kLogScale, lg)), a_prev = 1.0;
+      const double mm = static_cast<double>(m) * m;
+      for (int l = m + 1; l <= L && !live; ++l) {
+        const double dl = l;
+        const double al = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - mm));
+        const double p2 = al * (Rg.z * p1 - p0 / a_prev);
+        p0 = p1;
+        p1 = p2;
+        a_prev = al;
+        if (fabs(p1) > kRescaleAbove) {
+          p0 *= kInvScale;
+          p1 *= kInvScale;
+          --e;
+        }
+        live = e <= 0 || (e == 1 && fabs(p1) > 0x1p300);
+      }
+    }
+    if (live) atomicMin(&s_first, c);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) dead[m] = s_first;
+}
+
+// The analysis sums of order m over R rings per thread, rings ring0 + j kLegThreadsA + tid; out and
+// scale: where the sums go (alm, or the block's partial sums) and their factor.
 template <int R>
-__global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(LegArgs a, int nblk, double2* partial) {
-  __shared__ double2 s_red[kFlush][kLegThreadsA];
-  __shared__ double2 s_ab[kLegChunk];
-  const int item = blockIdx.x;
-  const int m = item / nblk;
-  const int blk = item - m * nblk;
+__device__ __forceinline__ void analysis_body(const LegArgs& a, int m, int ring0, double2* __restrict__ out,
+                                              double scale, double2 (&s_red)[kFlush][kLegThreadsA],
+                                              double2 (&s_ab)[kLegChunk]) {
   const int tid = threadIdx.x;
   const double2* Gm = a.G + static_cast<size_t>(m) * a.nrings;
   double z[R], ser[R], sei[R], sor[R], soi[R], p0[R], p1[R];
@@ -655,7 +705,7 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
   const double logpre = convreal::ldu(a.logpre[m]);
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    const int rn = (blk * R + j) * kLegThreadsA + tid;
+    const int rn = ring0 + j * kLegThreadsA + tid;
     ring[j] = rn;
     z[j] = 0.0; ser[j] = sei[j] = sor[j] = soi[j] = 0.0; p0[j] = p1[j] = 0.0; e[j] = 0;
     if (rn < a.nnorth) {
@@ -671,10 +721,7 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
       }
     }
   }
-  const long long base = alm_base(a.L, m);
-  const double2* coef = a.coef + base;
-  double2* out = nblk == 1 ? a.alm + base : partial + static_cast<size_t>(blk) * ((a.L + 1LL) * (a.L + 2) / 2) + base;
-  const double scale = nblk == 1 ? a.omega : 1.0;
+  const double2* coef = a.coef + alm_base(a.L, m);
   // One group: l = l0 .. l0 + kFlush - 1 (l0 - m a multiple of kFlush), the recurrence coefficients
   // from the chunk staged in LDS at c0 (CHECK: tests for l = m, with no recurrence step, and l > L).
   auto group = [&](int l0, int c0, auto check_tag) {
@@ -766,6 +813,40 @@ __global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(Leg
   }
 }
 
+template <int R>
+__global__ __launch_bounds__(kLegThreadsA) void sht_analysis_legendre_kernel(LegArgs a, int nblk, double2* partial) {
+  __shared__ double2 s_red[kFlush][kLegThreadsA];
+  __shared__ double2 s_ab[kLegChunk];
+  const int item = blockIdx.x;
+  const int m = item / nblk;
+  const int blk = item - m * nblk;
+  const long long base = alm_base(a.L, m);
+  double2* out = nblk == 1 ? a.alm + base : partial + static_cast<size_t>(blk) * ((a.L + 1LL) * (a.L + 2) / 2) + base;
+  const double scale = nblk == 1 ? a.omega : 1.0;
+  // thread ring j covers chunk blk R + j: the leading dead ones are left out in pairs (so that the
+  // remaining rings keep the parity of j that picks their accumulator); a block of dead rings only
+  // writes zero sums
+  const int jd = min(max(convreal::ldu(a.dead[m]) - blk * R, 0), R);
+  if (jd == R) {
+    for (int l = m + static_cast<int>(threadIdx.x); l <= a.L; l += kLegThreadsA) out[l - m] = double2{0.0, 0.0};
+    return;
+  }
+  const int j0 = jd & ~1;
+  const int ring0 = (blk * R + j0) * kLegThreadsA;
+  if (j0 == 0) {
+    analysis_body<R>(a, m, ring0, out, scale, s_red, s_ab);
+  } else if constexpr (R == 8) {
+    if (j0 == 2)
+      analysis_body<6>(a, m, ring0, out, scale, s_red, s_ab);
+    else if (j0 == 4)
+      analysis_body<4>(a, m, ring0, out, scale, s_red, s_ab);
+    else
+      analysis_body<2>(a, m, ring0, out, scale, s_red, s_ab);
+  } else if constexpr (R == 4) {
+    analysis_body<2>(a, m, ring0, out, scale, s_red, s_ab);
+  }
+}
+
 // a_lm = Omega sum over ring blocks of the partial sums (several blocks per order)
 __global__ void sht_reduce_kernel(const double2* __restrict__ partial, int nblk, long long nalm, double omega,
                                   double2* __restrict__ alm) {
@@ -780,20 +861,17 @@ __global__ void sht_reduce_kernel(const double2* __restrict__ partial, int nblk,
   alm[i] = double2{omega * sr, omega * si};
 }
 
+// F_m of R rings per thread, rings ring0 + j kLegThreads + tid
 template <int R>
-__global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(LegArgs a, int nblk) {
-  __shared__ double2 s_ab[kLegChunk];
-  __shared__ double2 s_al[kLegChunk];
-  const int item = blockIdx.x;
-  const int m = item / nblk;
-  const int blk = item - m * nblk;
+__device__ __forceinline__ void synthesis_body(const LegArgs& a, int m, int ring0, double2 (&s_ab)[kLegChunk],
+                                               double2 (&s_al)[kLegChunk]) {
   const int tid = threadIdx.x;
   double z[R], fer[R], fei[R], forr[R], foi[R], p0[R], p1[R];
   int e[R];
   const double logpre = convreal::ldu(a.logpre[m]);
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    const int rn = (blk * R + j) * kLegThreads + tid;
+    const int rn = ring0 + j * kLegThreads + tid;
     z[j] = 0.0; p0[j] = p1[j] = 0.0; e[j] = 0;
     fer[j] = fei[j] = forr[j] = foi[j] = 0.0;
     if (rn < a.nnorth) {
@@ -877,13 +955,40 @@ __global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(Leg
   double2* Fm = a.G + static_cast<size_t>(m) * a.nrings;
 #pragma unroll
   for (int j = 0; j < R; ++j) {
-    const int rn = (blk * R + j) * kLegThreads + tid;
+    const int rn = ring0 + j * kLegThreads + tid;
     if (rn < a.nnorth) {
       const int rs = a.nrings - 1 - rn;
       Fm[rn] = double2{fer[j] + forr[j], fei[j] + foi[j]};
       if (rs != rn) Fm[rs] = double2{fer[j] - forr[j], fei[j] - foi[j]};
     }
   }
+}
+
+template <int R>
+__global__ __launch_bounds__(kLegThreads) void sht_synthesis_legendre_kernel(LegArgs a, int nblk) {
+  __shared__ double2 s_ab[kLegChunk];
+  __shared__ double2 s_al[kLegChunk];
+  const int item = blockIdx.x;
+  const int m = item / nblk;
+  const int blk = item - m * nblk;
+  // thread ring j covers chunks 2 (blk R + j) and 2 (blk R + j) + 1: the leading dead ones are left
+  // out, their F_m (both hemispheres) set to zero
+  const int jd = min(max(convreal::ldu(a.dead[m]) / 2 - blk * R, 0), R);
+  double2* Fm = a.G + static_cast<size_t>(m) * a.nrings;
+  for (int j = 0; j < jd; ++j) {
+    const int rn = (blk * R + j) * kLegThreads + static_cast<int>(threadIdx.x);
+    if (rn < a.nnorth) {
+      const int rs = a.nrings - 1 - rn;
+      Fm[rn] = double2{0.0, 0.0};
+      if (rs != rn) Fm[rs] = double2{0.0, 0.0};
+    }
+  }
+  if (jd == R) return;
+  const int ring0 = (blk * R + jd) * kLegThreads;
+  if (jd == 0)
+    synthesis_body<R>(a, m, ring0, s_ab, s_al);
+  else if constexpr (R == 2)
+    synthesis_body<1>(a, m, ring0, s_ab, s_al);
 }
 
 // ---------------------------------------------------------------------------- alm helpers
@@ -933,6 +1038,7 @@ struct conv_sht_plan {
   double2* d_G = nullptr;
   double2* d_alm = nullptr;       // workspace of conv_sht_convolve and the hybrid apply
   double2* d_partial = nullptr;   // nblk > 1: per-block partial sums of the analysis
+  int* d_dead = nullptr;          // per m: leading chunks of polar rings left out of the Legendre sums
   int fft_ring0 = 0;              // belt rings ring0 .. ring0 + fft_nrings - 1 by FFT (power-of-two Nside)
   int fft_nrings = 0;
   int fft_logn = 0;
@@ -1036,7 +1142,7 @@ ChirpTabs chirp_tabs(const conv_sht_plan* p) {
 }
 
 hipError_t launch_analysis_legendre(const conv_sht_plan* p, double2* alm, hipStream_t st) {
-  LegArgs a{p->d_rings, p->d_coef, p->d_logpre, p->d_G, alm, p->L, p->nrings, p->nnorth, p->omega};
+  LegArgs a{p->d_rings, p->d_coef, p->d_logpre, p->d_G, alm, p->d_dead, p->L, p->nrings, p->nnorth, p->omega};
   const dim3 g(static_cast<unsigned>((p->L + 1) * p->nblk_a)), b(kLegThreadsA);
   switch (p->Ra) {
     case 1: hipLaunchKernelGGL(sht_analysis_legendre_kernel<1>, g, b, 0, st, a, p->nblk_a, p->d_partial); break;
@@ -1052,13 +1158,12 @@ hipError_t launch_analysis_legendre(const conv_sht_plan* p, double2* alm, hipStr
 }
 
 hipError_t launch_synthesis_legendre(const conv_sht_plan* p, const double2* alm, hipStream_t st) {
-  LegArgs a{p->d_rings, p->d_coef, p->d_logpre, p->d_G, const_cast<double2*>(alm), p->L, p->nrings, p->nnorth,
-            p->omega};
+  LegArgs a{p->d_rings, p->d_coef, p->d_logpre, p->d_G, const_cast<double2*>(alm), p->d_dead, p->L, p->nrings,
+            p->nnorth, p->omega};
   const dim3 g(static_cast<unsigned>((p->L + 1) * p->nblk)), b(kLegThreads);
   switch (p->R) {
     case 1: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<1>, g, b, 0, st, a, p->nblk); break;
-    case 2: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<2>, g, b, 0, st, a, p->nblk); break;
-    default: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<4>, g, b, 0, st, a, p->nblk); break;
+    default: hipLaunchKernelGGL(sht_synthesis_legendre_kernel<2>, g, b, 0, st, a, p->nblk); break;
   }
   return hipGetLastError();
 }
@@ -1339,6 +1444,13 @@ int conv_sht_init(conv_sht_plan** plan, int nside, int lmax) {
   if (e == hipSuccess) e = sht_alloc(p, &p->d_G, static_cast<size_t>(lmax + 1) * p->nrings);
   if (e == hipSuccess) e = sht_alloc(p, &p->d_alm, static_cast<size_t>(p->nalm));
   if (e == hipSuccess && p->nblk_a > 1) e = sht_alloc(p, &p->d_partial, static_cast<size_t>(p->nalm) * p->nblk_a);
+  if (e == hipSuccess) e = sht_alloc(p, &p->d_dead, static_cast<size_t>(lmax) + 1);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(sht_dead_chunks_kernel, dim3(static_cast<unsigned>(lmax + 1)), dim3(64), 0, nullptr,
+                       p->d_rings, p->d_logpre, lmax, p->nnorth, p->d_dead);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_real, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming);

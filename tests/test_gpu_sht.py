@@ -124,6 +124,28 @@ def test_transforms_at_nside_2048_sampled(cuda_device):
         assert err <= 1e-11 * scale_y, (r, err, scale_y)
 
 
+def test_synthesis_after_analysis_on_one_plan(cuda_device):
+    # polar rings that an order leaves out of the Legendre sums (their scaled values never come back
+    # into the FP64 range before L; chunks of 256 rings from the pole) get F_m = 0 from the synthesis,
+    # also where the plan's ring-sum buffer still holds an analysis's values: rings on both sides of
+    # the chunk edges, in both hemispheres, against the oracle
+    from oracle import geometry
+    nside, L = 2048, 1500
+    x = np.random.default_rng(31).standard_normal(12 * nside * nside)
+    a = _rand_alm(L, 6)
+    rings = [0, 255, 256, 511, 512, 767, 768, 1023, 1024, 1279, 1280, 1535, 1536, 1800, 8190 - 1279, 8190]
+    ref_y = osht.synthesis_rings(nside, a, L, rings)
+    with sht.Sht(nside, L) as t:
+        t.analysis(torch.from_numpy(x).to(cuda_device))
+        got_y = t.synthesis(torch.from_numpy(a).to(cuda_device)).cpu().numpy()
+    rt = geometry.ring_table(nside)
+    scale_y = max(float(np.max(np.abs(v))) for v in ref_y.values())
+    for r in rings:
+        g = got_y[rt["start"][r]: rt["start"][r] + rt["n"][r]]
+        err = float(np.max(np.abs(g - ref_y[r])))
+        assert err <= 1e-11 * scale_y, (r, err, scale_y)
+
+
 @pytest.mark.parametrize("nside,L", [(8, 20), (32, 64)])
 def test_convolve_and_power_spectrum(cuda_device, nside, L):
     x = np.random.default_rng(11).standard_normal(12 * nside * nside)
