@@ -55,8 +55,9 @@ typedef struct conv_sht_plan conv_sht_plan;
  * Allocates the recurrence coefficients ((L+1)(L+2)/2 x 16 bytes), a ring-by-order workspace
  * ((L + 1)(4 nside - 1) x 16 bytes), one alm workspace and the chirp-z tables of the rings with at
  * least 16 pixels per quarter that no power-of-two FFT takes (per ring length k: k + M values of 16 bytes, M the power of two at
- * least k + ceil(min(4k, L + 1) / 4) - 1; 99 MB at nside 2048 / L 1500), which it fills with a kernel.
- * Synchronous.
+ * least k + ceil(min(4k, L + 1) / 4) - 1; 99 MB at nside 2048 / L 1500), which it fills with a kernel,
+ * and per order m the number of leading polar ring chunks that the Legendre sums leave out (L + 1
+ * ints; a second set-up kernel). Synchronous.
  */
 int conv_sht_init(conv_sht_plan** plan, int nside, int lmax);
 
