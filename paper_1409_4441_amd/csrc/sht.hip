@@ -78,6 +78,16 @@ static_assert(kLegThreadsA == kDeadChunk && kLegThreads == 2 * kDeadChunk,
               "a thread's ring ranges are one chunk wide (analysis) or two (synthesis)");
 static_assert(kDftThreads == 256, "four waves: one per residue class mod 4");
 
+// Blocks are dealt round-robin to the 8 XCDs. Within each window of 8 g consecutive blocks (first
+// block w), the g blocks that XCD x receives take items w + g x .. w + g x + g - 1, so that
+// neighbouring rings, whose G / F entries of one order share cache lines, run on one XCD and meet in
+// its L2. A trailing partial window keeps the identity; the map is a bijection on [0, n).
+__device__ __forceinline__ int xcd_group(int b, int n, int g) {
+  const int w = b - b % (8 * g);
+  if (w + 8 * g > n) return b;
+  return w + (b & 7) * g + (b >> 3) % g;
+}
+
 struct ShtRing {
   double z;          // cos theta
   double s;          // sin theta
@@ -291,7 +301,7 @@ __global__ __launch_bounds__(kFftThreads) void sht_belt_fft_kernel(const T* __re
                                                                    double2* __restrict__ G) {
   extern __shared__ double2 s_fft[];
   __shared__ double2 s_twh[64], s_twl[64];
-  const int r1 = ring0 + 2 * static_cast<int>(blockIdx.x);
+  const int r1 = ring0 + 2 * xcd_group(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), 4);
   const bool two = r1 + 1 < ring0 + nr;
   const int r2 = two ? r1 + 1 : r1;
   const ShtRing R1 = convreal::ldu_record(rings[r1]);
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(kFftThreads) void sht_belt_ifft_kernel(const double
                                                                     T* __restrict__ y) {
   extern __shared__ double2 s_fft[];
   __shared__ double2 s_twh[64], s_twl[64];
-  const int r1 = ring0 + 2 * static_cast<int>(blockIdx.x);
+  const int r1 = ring0 + 2 * xcd_group(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), 4);
   const bool two = r1 + 1 < ring0 + nr;
   const int r2 = two ? r1 + 1 : r1;
   const ShtRing R1 = convreal::ldu_record(rings[r1]);
@@ -440,7 +450,7 @@ __global__ __launch_bounds__(kFftThreads) void sht_ring_dft_chirp_kernel(const T
                                                                          int L, ChirpTabs c, int lds_elems,
                                                                          double2* __restrict__ G) {
   extern __shared__ double2 s_fft[];
-  const int r = list[blockIdx.x];
+  const int r = list[xcd_group(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), 8)];
   const ShtRing R = convreal::ldu_record(rings[r]);
   const int n = R.n, k = n >> 2;
   const int nk = n < L + 1 ? n : L + 1;
@@ -515,7 +525,7 @@ __global__ __launch_bounds__(kFftThreads) void sht_ring_idft_chirp_kernel(const 
                                                                           int L, ChirpTabs c, int lds_elems,
                                                                           T* __restrict__ y) {
   extern __shared__ double2 s_fft[];
-  const int r = list[blockIdx.x];
+  const int r = list[xcd_group(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x), 8)];
   const ShtRing R = convreal::ldu_record(rings[r]);
   const int n = R.n, k = n >> 2;
   const int nk = n < L + 1 ? n : L + 1;
