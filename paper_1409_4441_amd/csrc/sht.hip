@@ -18,7 +18,8 @@
 // belt rings (n = 4 Nside, a power of two) take a radix-2 FFT in LDS instead (n log n work against
 // n min(n, L + 1) / 4). The other rings with k >= kChirpMin (the polar-cap rings, and the belt rings of
 // other grids) take each folded class's k-point DFT as a chirp-z convolution through the same radix-2
-// FFTs (below); the smallest rings keep the folded Horner sums.
+// FFTs (below); the smallest rings keep the folded Horner sums. Neighbouring rings run on one XCD
+// (their G / F entries of one order share cache lines).
 //
 // Legendre sums. lambda_lm by the recurrence in l at fixed m,
 //   lambda_mm = (-1)^m sqrt((2m+1)/(4 pi) prod_{k<=m} (2k-1)/(2k)) sin^m theta,
@@ -37,7 +38,8 @@
 // A workgroup of 512 threads (synthesis; 256 in the analysis) takes one order m and up to 512 R
 // (256 R) north rings (R per thread); analysis
 // reduces over rings after every group through LDS (each thread first adds its R rings), synthesis
-// needs no reduction.
+// needs no reduction. Per order, the leading chunks of 256 polar rings whose scaled values never reach
+// the sums before L (they would add exact zeros) are left out; a set-up kernel counts them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
